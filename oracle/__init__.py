@@ -1,0 +1,21 @@
+"""Oracle for the beyond-Limber C_l hot path -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow FP64 CPU code (NumPy / SciPy) that shares no code with the HIP
+path.  Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import it; the product package never does.
+
+Modules
+  geometry    continuous inputs from samples (natural cubic splines), z(chi),
+              clustering and lensing radial kernels (Sec. 2.2, 2.3 of the paper)
+  fftlog      the paper's method, step by step in its own notation: FFTLog
+              coefficients (Sec. 3.1, eq. FFTLog), the analytic power-law Bessel
+              integral (eq. int_jl, corrected), the sum over n per k, the k-sum
+  quadrature  the plain definition: windows by direct quadrature of
+              j_l(k chi), used to pin the FFTLog oracle (method-error floor)
+  limber      the Limber limit (eq. Limber), a high-l check of the quadrature
+  gradients   exact / directional derivatives of C_l for the adjoint tests
+
+Readings of the paper that the oracle fixes are listed in each function's
+docstring; every one is shared, by statement and not by code, with the HIP
+path.
+"""

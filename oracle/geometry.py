@@ -1,0 +1,137 @@
+"""Radial kernels f_i(chi) from sampled inputs (oracle; FP64; test infrastructure).
+
+Paper, Sec. 2.2 (galaxy clustering) and Sec. 2.3 (weak lensing):
+  clustering   Delta_l^{g,D}(k) = b_1 int dchi W^{delta,g}(chi) D j_l(k chi),
+               W^{delta,g}(chi) = n(z(chi)), with int dz n = 1.  The chi integral
+               needs dz/dchi, so the radial kernel is f = b n(z) (dz/dchi) D(z).
+  lensing      Delta_l^gamma(k) = sqrt((l+2)!/(l-2)!) k^-2 int dchi chi^-2 W^{kappa,gamma} D j_l,
+               W^{kappa,gamma}(chi) = (3 Om H0^2 / 2 c^2) int_chi^inf dchi' n(chi') (chi/a) (chi'-chi)/chi'
+               (eq. tomographic lens efficiency).  Written in z:
+               q(chi) = 1.5 Om (H0/c)^2 chi (1+z) int_z^{z_max} dz' n(z') (1 - chi/chi(z')).
+               The radial kernel is f = q D / chi^2 and c(l, k) = F(l) / k^2.
+
+Readings (the paper does not fix them):
+  * every sampled input is continued by a natural cubic spline; n(z) is zero
+    outside its sample range;
+  * z(chi) is the inverse of the chi(z) spline, dz/dchi = 1 / (chi spline)';
+  * the kernels are supported on [chi(z_min), chi(z_max)] of the geometry grid;
+  * D(k, z) = D(z), z_fid = 0 (linear growth).
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.interpolate import CubicSpline
+
+H0_OVER_C = 1.0 / 2997.92458  # h/Mpc
+_GL = np.polynomial.legendre.leggauss(12)
+
+
+class PointGeometry:
+    """Continuous geometry, growth and redshift distributions of one parameter point."""
+
+    def __init__(self, z_geom, chi_z, D_z, omega_m, z_nz, nz, kinds, bias):
+        self.z_geom = np.asarray(z_geom, float)
+        self.z_nz = np.asarray(z_nz, float)
+        self.chi_spl = CubicSpline(self.z_geom, chi_z, bc_type="natural")
+        self.D_spl = CubicSpline(self.z_geom, D_z, bc_type="natural")
+        self.nz = np.asarray(nz, float)
+        self.n_spl = [CubicSpline(self.z_nz, n_t, bc_type="natural") for n_t in self.nz]
+        self.omega_m = float(omega_m)
+        self.kinds = np.asarray(kinds, int)
+        self.bias = np.asarray(bias, float)
+        self.z_min, self.z_max = self.z_geom[0], self.z_geom[-1]
+        self.chi_min = float(self.chi_spl(self.z_min))
+        self.chi_max = float(self.chi_spl(self.z_max))
+        self._lens_tables = {}
+
+    # --- elementary continuous functions -------------------------------------------------
+    def n_of_z(self, t, z):
+        z = np.asarray(z, float)
+        inside = (z >= self.z_nz[0]) & (z <= self.z_nz[-1])
+        return np.where(inside, self.n_spl[t](np.clip(z, self.z_nz[0], self.z_nz[-1])), 0.0)
+
+    def z_of_chi(self, chi):
+        """Invert the chi(z) spline on the geometry range (one root per value)."""
+        chi = np.atleast_1d(np.asarray(chi, float))
+        out = np.empty_like(chi)
+        for i, c in enumerate(chi):
+            r = self.chi_spl.solve(c, extrapolate=False)
+            r = r[(r >= self.z_min - 1e-12) & (r <= self.z_max + 1e-12)]
+            if len(r) != 1:
+                raise ValueError(f"chi={c} is not inside the geometry range")
+            out[i] = r[0]
+        return out
+
+    # --- lensing efficiency ----------------------------------------------------------------
+    def _knots(self):
+        return np.union1d(self.z_geom, self.z_nz[(self.z_nz >= self.z_min) & (self.z_nz <= self.z_max)])
+
+    def lensing_integrals(self, t, z):
+        """I0(z) = int_z^zmax n_t dz',  I1(z) = int_z^zmax n_t / chi(z') dz'.
+
+        Gauss-Legendre (12 points) on every interval between consecutive knots
+        of the geometry and n(z) grids, where the integrand is smooth; the
+        interval holding z is integrated from z to its right end.
+        """
+        knots = self._knots()
+        x, w = _GL
+        a, b = knots[:-1, None], knots[1:, None]
+        nodes = 0.5 * (b - a) * x + 0.5 * (a + b)
+        wts = 0.5 * (b - a) * w
+        nv = self.n_of_z(t, nodes)
+        seg0 = np.sum(wts * nv, axis=1)
+        seg1 = np.sum(wts * nv / self.chi_spl(nodes), axis=1)
+        suf0 = np.concatenate([np.cumsum(seg0[::-1])[::-1], [0.0]])
+        suf1 = np.concatenate([np.cumsum(seg1[::-1])[::-1], [0.0]])
+        z = np.atleast_1d(np.asarray(z, float))
+        i = np.clip(np.searchsorted(knots, z, side="right") - 1, 0, len(knots) - 2)
+        hi = knots[i + 1]
+        pn = 0.5 * (hi - z)[:, None] * x + 0.5 * (hi + z)[:, None]
+        pw = 0.5 * (hi - z)[:, None] * w
+        pv = self.n_of_z(t, pn)
+        I0 = np.sum(pw * pv, axis=1) + suf0[i + 1]
+        I1 = np.sum(pw * pv / self.chi_spl(pn), axis=1) + suf1[i + 1]
+        return I0, I1
+
+    def lensing_q(self, t, z):
+        """q_t at redshift z (units h^2/Mpc^2 * Mpc/h); eq. tomographic lens efficiency in z."""
+        z = np.atleast_1d(np.asarray(z, float))
+        chi = self.chi_spl(z)
+        I0, I1 = self.lensing_integrals(t, z)
+        return 1.5 * self.omega_m * H0_OVER_C ** 2 * chi * (1.0 + z) * (I0 - chi * I1)
+
+    # --- radial kernels ------------------------------------------------------------------
+    def f_of_z(self, t, z):
+        """Radial kernel per unit chi, f_t, evaluated at redshift z (inside the support)."""
+        z = np.atleast_1d(np.asarray(z, float))
+        D = self.D_spl(z)
+        if self.kinds[t] == 0:
+            dzdchi = 1.0 / self.chi_spl(z, 1)
+            return self.bias[t] * self.n_of_z(t, z) * dzdchi * D
+        chi = self.chi_spl(z)
+        return self.lensing_q(t, z) * D / chi ** 2
+
+    def f_of_chi(self, t, chi):
+        """f_t(chi), zero outside [chi(z_min), chi(z_max)]."""
+        chi = np.atleast_1d(np.asarray(chi, float))
+        out = np.zeros_like(chi)
+        inside = (chi >= self.chi_min) & (chi <= self.chi_max)
+        if np.any(inside):
+            z = self.z_of_chi(chi[inside])
+            out[inside] = self.f_of_z(t, z)
+        return out
+
+
+def point_geometry(wl, b):
+    """PointGeometry of parameter point b of a synthetic workload dict."""
+    T = int(wl["n_tracers"][b])
+    return PointGeometry(wl["z_geom"], wl["chi_z"][b], wl["D_z"][b], wl["omega_m"][b], wl["z_nz"],
+                         wl["nz"][b, :T], wl["kind"][b, :T], wl["bias"][b, :T])
+
+
+def ell_prefactor(kind, ell, k):
+    """c(l, k): 1 for clustering, sqrt((l+2)!/(l-2)!) / k^2 for lensing (real l)."""
+    if kind == 0:
+        return np.ones_like(np.asarray(k, float))
+    F = np.sqrt((ell + 2.0) * (ell + 1.0) * ell * (ell - 1.0))
+    return F / np.asarray(k, float) ** 2

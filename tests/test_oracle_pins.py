@@ -1,0 +1,310 @@
+"""Pins of the oracle against what the paper and the mathematics fix (CPU only).
+
+Each test checks the oracle against something other than itself: independent
+numerical quadrature (mpmath), an explicit O(N^2) DFT, the exact integral by
+direct quadrature, the Limber limit, closed-form invariants and finite
+differences.
+"""
+import mpmath
+import numpy as np
+import pytest
+from scipy import integrate
+
+import synth
+from oracle import fftlog, geometry, gradients, limber, quadrature
+
+
+# --- eq. int_jl (corrected denominator) -------------------------------------------------------
+
+def _mp_power_bessel(ell, p):
+    """int_0^inf x^p j_l(x) dx by mpmath oscillatory quadrature (30 digits)."""
+    mpmath.mp.dps = 30
+    p = mpmath.mpc(p)
+    f = lambda x: x ** p * mpmath.sqrt(mpmath.pi / (2 * x)) * mpmath.besselj(ell + 0.5, x)
+    return complex(mpmath.quadosc(f, [0, mpmath.inf], omega=1))
+
+
+@pytest.mark.parametrize("p", [0.5, -0.3, 0.2 + 4j, -0.7 - 1.5j])
+def test_power_bessel_integral_ell0_mellin_sine(p):
+    """l = 0: j_0(x) = sin(x)/x and int_0^inf x^{p-1} sin x dx = Gamma(p) sin(pi p / 2), -1 < Re p < 1."""
+    from scipy.special import gamma
+    k = 1.7
+    ref = complex(gamma(p) * np.sin(np.pi * p / 2)) * k ** (-1 - p)
+    got = complex(fftlog.bessel_power_integral(0.0, p, k))
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+
+
+@pytest.mark.parametrize("ell,p", [(2.0, -0.5), (7.3, -0.9), (2.0, 0.1 + 3j),
+                                   (10.5, -2.0 + 5j), (3.0, -1.5 - 2j)])
+def test_power_bessel_integral_matches_quadrature(ell, p):
+    k = 2.0
+    ref = _mp_power_bessel(ell, p) * k ** (-1 - p)  # substitution x = k chi
+    got = complex(fftlog.bessel_power_integral(ell, p, k))
+    # oscillatory quadrature converges slowly when the integrand decays slowly (Re p near 1)
+    tol = 1e-10 if np.real(p) <= -0.5 else 1e-6
+    assert abs(got - ref) <= tol * abs(ref)
+
+
+def test_printed_denominator_is_a_typo():
+    """The printed Gamma((2+l+p)/2) misses the quadrature value: the oracle uses (2+l-p)/2."""
+    ell, p = 2.0, -0.5
+    ref = _mp_power_bessel(ell, p)
+    from scipy.special import gamma
+    printed = 2 ** (p - 1) * np.sqrt(np.pi) * gamma(0.5 * (1 + ell + p)) / gamma(0.5 * (2 + ell + p))
+    assert abs(printed - ref.real) > 0.05 * abs(ref)
+    assert abs(fftlog.bessel_power_integral(ell, p, 1.0) - ref) < 1e-10 * abs(ref)
+
+
+# --- the DFT step ---------------------------------------------------------------------------------
+
+def test_fftlog_coefficients_brute_force():
+    rng = np.random.default_rng(0)
+    N = 32
+    k = np.geomspace(1e-3, 1.0, 20)
+    m = fftlog.Method(k, N, m0=4)
+    chi0 = 3.0
+    chi = chi0 * np.exp(np.arange(N) * m.delta)
+    F = rng.standard_normal((2, N))
+    b = -0.3
+    n, c = fftlog.fftlog_coefficients(F, chi, chi0, b, m)
+    for t in range(2):
+        for i, nn in enumerate(n):
+            eta = 2 * np.pi * nn / (N * m.delta)
+            ref = sum(F[t, mm] * chi[mm] ** (-b) * chi0 ** (-1j * eta) * np.exp(-2j * np.pi * nn * mm / N)
+                      for mm in range(N)) / N
+            assert abs(c[t, i] - ref) < 1e-13 * np.abs(F).max() * chi.max() ** abs(b)
+    # the series reproduces the samples away from the (dropped) Nyquist term
+    recon = np.array([[np.sum(c[t] * chi[mm] ** (b + 1j * 2 * np.pi * n / (N * m.delta))) for mm in range(N)]
+                      for t in range(2)])
+    nyq = np.array([np.sum(F[t] * chi ** (-b) * (-1.0) ** np.arange(N)) / N for t in range(2)])
+    expect = F - (nyq[:, None] * (-1.0) ** np.arange(N)[None, :]) * chi[None, :] ** b
+    assert np.allclose(recon.real, expect, atol=1e-12 * np.abs(F).max() * chi.max() ** abs(b))
+
+
+# --- the whole FFTLog oracle against the exact integral (method-error floor) ----------------------
+
+def _eps(Ca, Cb):
+    d = np.sqrt(np.abs(np.einsum("ltt->lt", Cb)))
+    return np.abs(Ca - Cb) / (d[:, :, None] * d[:, None, :])
+
+
+def _floor(wl, ell_sel, kstep, method=None):
+    m = method or fftlog.method_for(wl)
+    geo = geometry.point_geometry(wl, 0)
+    ells = fftlog.point_ells(wl, 0)[ell_sel]
+    W = fftlog.windows_point(geo, ells, m)[:, :, ::kstep]
+    Wq = quadrature.windows_quadrature(geo, ells, m.k[::kstep])
+    s = (fftlog.k_weights(m) * wl["pk"][0])[::kstep]
+    Cf = np.einsum("ltj,lsj,j->lts", W, W, s)
+    Cq = np.einsum("ltj,lsj,j->lts", Wq, Wq, s)
+    return _eps(Cf, Cq)
+
+
+def test_method_floor_cfg0(wl0):
+    eps = _floor(wl0, [0, 9, 19], 8)
+    assert eps.max() < 2e-4
+
+
+def test_method_floor_cfg1(wl1):
+    # l = 2 (band 0), l ~ 3.7 (band 1), then bands 2 at low, mid and top l
+    eps = _floor(wl1, [0, 9, 30, 70, 102], 32)
+    assert eps.max() < 3e-5
+
+
+def test_planted_edge_weight_mistake_is_caught(wl1, monkeypatch):
+    """Dropping the half weight of the lower support edge must break the floor pin."""
+    real = fftlog.sampled_kernels
+
+    def wrong(geo, method):
+        chi0, chi, F = real(geo, method)
+        F[:, method.m0] *= 2.0
+        return chi0, chi, F
+
+    monkeypatch.setattr(fftlog, "sampled_kernels", wrong)
+    eps = _floor(wl1, [0, 30], 32)
+    assert eps.max() > 1e-4
+
+
+# --- Limber limit (eq. Limber, error O(1/l)) -------------------------------------------------------
+
+def test_limber_limit_high_ell(wl1):
+    m = fftlog.method_for(wl1)
+    geo = geometry.point_geometry(wl1, 0)
+    ells_all = fftlog.point_ells(wl1, 0)
+    sel = np.nonzero(ells_all >= 300)[0][::4]
+    ells = ells_all[sel]
+    W = fftlog.windows_point(geo, ells, m)
+    s = fftlog.k_weights(m) * wl1["pk"][0]
+    C = np.einsum("ltj,lsj,j->lts", W, W, s)
+    CL = limber.cl_limber(geo, ells, m.k, wl1["pk"][0])
+    T = len(geo.kinds)
+    rel = np.array([[abs(C[i, t, t] / CL[i, t, t] - 1) for t in range(T)] for i in range(len(ells))])
+    clus = rel[:, :10]
+    assert clus[ells >= 500].max() < 1e-2
+    # error shrinks with l: the mean over clustering autos at the top is below the bottom one
+    assert clus[-1].mean() < clus[0].mean()
+    # weak lensing autos (F(l)^2/(l+1/2)^4 inserted) also converge to Limber
+    assert rel[ells >= 1000, 10:].max() < 2e-2
+
+
+# --- invariants of C_l -------------------------------------------------------------------------------
+
+def _full(Cp, T):
+    C = np.zeros(Cp.shape[:-1] + (T, T))
+    iu = np.triu_indices(T)
+    C[..., iu[0], iu[1]] = Cp
+    C[..., iu[1], iu[0]] = Cp
+    return C
+
+
+def test_symmetric_psd_and_homogeneous(wl1):
+    m = fftlog.method_for(wl1)
+    wl = dict(wl1)
+    wl["ell_idx"] = wl1["ell_idx"][:, ::17].copy()
+    wl["n_ell"] = np.array([wl["ell_idx"].shape[1]], np.int32)
+    C, W = fftlog.cl(wl, 0, m, return_windows=True)
+    Cf = _full(C, 15)
+    for Cl in Cf:
+        ev = np.linalg.eigvalsh(Cl)
+        assert ev.min() >= -1e-12 * ev.max()
+    # C(alpha P) = alpha C
+    C2 = fftlog.cl_from_windows(W, 3.0 * wl["pk"][0], m)
+    assert _eps(_full(C2, 15), _full(3.0 * C, 15)).max() < 1e-13
+    # C^{ij} proportional to b_i b_j: doubling bias 0 doubles row 0 and quadruples C^{00}
+    wl["bias"] = wl1["bias"].copy()
+    wl["bias"][0, 0] *= 2.0
+    Cb = _full(fftlog.cl(wl, 0, m), 15)
+    expect = Cf.copy()
+    expect[:, 0, :] *= 2.0
+    expect[:, :, 0] *= 2.0
+    assert _eps(Cb, expect).max() < 1e-12
+
+
+# --- geometry and growth --------------------------------------------------------------------------------
+
+def test_comoving_distance_matches_adaptive_quad():
+    z = np.array([0.01, 0.5, 1.7, 3.0])
+    chi = synth.comoving_distance(z, 0.3)
+    for zi, ci in zip(z, chi):
+        ref = synth.C_OVER_H0 * integrate.quad(lambda x: 1 / synth.e_of_z(x, 0.3), 0, zi,
+                                               epsabs=0, epsrel=1e-13)[0]
+        assert abs(ci / ref - 1) < 1e-11
+
+
+def test_growth_matches_ode_and_einstein_de_sitter():
+    from scipy.integrate import solve_ivp
+    om = 0.3
+    z = np.array([0.0, 0.5, 1.0, 3.0])
+    D = synth.growth_factor(z, om)
+    # D'' + (3/a + dlnE/da) D' - 1.5 Om / (a^5 E^2) D = 0 in a, growing mode D ~ a early on
+    def E(a):
+        return np.sqrt(om / a ** 3 + 1 - om)
+
+    def rhs(a, y):
+        dlnE = -1.5 * om / a ** 4 / E(a) ** 2
+        return [y[1], -(3 / a + dlnE) * y[1] + 1.5 * om / (a ** 5 * E(a) ** 2) * y[0]]
+
+    a0 = 1e-4
+    sol = solve_ivp(rhs, [a0, 1.0], [a0, 1.0], rtol=1e-12, atol=1e-16, dense_output=True)
+    Dode = sol.sol(1 / (1 + z))[0] / sol.sol(1.0)[0]
+    assert np.allclose(D, Dode, rtol=1e-6)
+    Deds = synth.growth_factor(z, 1.0)
+    assert np.allclose(Deds, 1 / (1 + z), rtol=1e-12)
+
+
+def test_lensing_integrals_match_adaptive_quad(wl1):
+    geo = geometry.point_geometry(wl1, 0)
+    for t in (10, 14):
+        for z in (0.05, 0.6, 1.9):
+            I0, I1 = geo.lensing_integrals(t, np.array([z]))
+            f0 = lambda zz: float(geo.n_of_z(t, zz))
+            r0 = integrate.quad(f0, z, geo.z_max, limit=500, points=geo.z_nz[(geo.z_nz > z)][::10],
+                                epsabs=0, epsrel=1e-12)[0]
+            r1 = integrate.quad(lambda zz: f0(zz) / float(geo.chi_spl(zz)), z, geo.z_max, limit=500,
+                                points=geo.z_nz[(geo.z_nz > z)][::10], epsabs=0, epsrel=1e-12)[0]
+            assert abs(I0[0] - r0) < 1e-9 * abs(r0)
+            assert abs(I1[0] - r1) < 1e-9 * abs(r1)
+
+
+def test_lensing_table_converged(wl1):
+    geo = geometry.point_geometry(wl1, 0)
+    z = np.linspace(0.02, 2.9, 777)
+    a = quadrature.LensingTable(geo, refine=16)
+    b = quadrature.LensingTable(geo, refine=32)
+    for t in (10, 12, 14):
+        qa, qb = a(t, z), b(t, z)
+        assert np.max(np.abs(qa - qb)) < 1e-9 * np.max(np.abs(qb))
+        assert np.allclose(qa, geo.lensing_q(t, z), rtol=1e-8, atol=1e-9 * np.abs(qb).max())
+
+
+def test_z_of_chi_round_trip(wl1):
+    geo = geometry.point_geometry(wl1, 0)
+    z = np.array([0.01, 0.3, 1.1, 2.999])
+    assert np.allclose(geo.z_of_chi(geo.chi_spl(z)), z, atol=1e-12)
+
+
+# --- gradients -----------------------------------------------------------------------------------------
+
+def _small(wl, stride=25):
+    w = dict(wl)
+    w["ell_idx"] = wl["ell_idx"][:, ::stride].copy()
+    w["n_ell"] = np.array([w["ell_idx"].shape[1]], np.int32)
+    return w
+
+
+def test_gradients_against_finite_differences(wl2):
+    wl = _small(wl2)
+    m = fftlog.method_for(wl)
+    rng = np.random.default_rng(7)
+    C, W = fftlog.cl(wl, 0, m, return_windows=True)
+    G = rng.standard_normal(C.shape)
+    L = lambda w: float(np.sum(G * fftlog.cl(w, 0, m)))
+    # P: exact form vs central differences on a few nodes
+    gp = gradients.grad_pk(G, W, m)
+    for j in (100, 500, 900):
+        h = 1e-4 * wl["pk"][0, j]
+        wp, wm = dict(wl), dict(wl)
+        wp["pk"] = wl["pk"].copy(); wp["pk"][0, j] += h
+        wm["pk"] = wl["pk"].copy(); wm["pk"][0, j] -= h
+        fd = (float(np.sum(G * fftlog.cl_from_windows(W, wp["pk"][0], m)))
+              - float(np.sum(G * fftlog.cl_from_windows(W, wm["pk"][0], m)))) / (2 * h)
+        assert abs(fd - gp[j]) <= 1e-7 * abs(gp).max()
+    # biases
+    gb = gradients.grad_bias(G, C, wl["kind"][0], wl["bias"][0])
+    for t in (0, 7):
+        h = 1e-4 * wl["bias"][0, t]
+        wp, wm = dict(wl), dict(wl)
+        wp["bias"] = wl["bias"].copy(); wp["bias"][0, t] += h
+        wm["bias"] = wl["bias"].copy(); wm["bias"][0, t] -= h
+        fd = (L(wp) - L(wm)) / (2 * h)
+        assert abs(fd - gb[t]) <= 1e-7 * abs(gb).max()
+    assert np.all(gb[10:] == 0)
+    # n(z) and D(z) directional derivatives vs central differences
+    v = rng.standard_normal(wl["nz"].shape[-1]) * wl["nz"][0, 12].max() * 0.1
+    dn = gradients.directional_nz(wl, 0, G, 12, v, m)
+    eps = 1e-3
+    wp, wm = dict(wl), dict(wl)
+    wp["nz"] = wl["nz"].copy(); wp["nz"][0, 12] += eps * v
+    wm["nz"] = wl["nz"].copy(); wm["nz"][0, 12] -= eps * v
+    fd = (L(wp) - L(wm)) / (2 * eps)
+    assert abs(fd - dn) <= 1e-7 * abs(dn)
+    vD = rng.standard_normal(wl["D_z"].shape[-1]) * 0.01
+    dD = gradients.directional_D(wl, 0, G, vD, m)
+    wp, wm = dict(wl), dict(wl)
+    wp["D_z"] = wl["D_z"] + eps * vD
+    wm["D_z"] = wl["D_z"] - eps * vD
+    fd = (L(wp) - L(wm)) / (2 * eps)
+    assert abs(fd - dD) <= 1e-7 * abs(dD)
+
+
+def test_euler_identities(wl1):
+    """sum_j P_j dC/dP_j = C, and sum_s D_s dC/dD_s = 2C (C is quadratic in D)."""
+    wl = _small(wl1, 34)
+    m = fftlog.method_for(wl)
+    C, W = fftlog.cl(wl, 0, m, return_windows=True)
+    npair = C.shape[1]
+    # P: with G = e_(l,p), dL/dP . P = C[l, p]
+    for (l, p) in [(0, 0), (1, 17), (2, npair - 1)]:
+        G = np.zeros_like(C); G[l, p] = 1.0
+        assert abs(gradients.grad_pk(G, W, m) @ wl["pk"][0] - C[l, p]) < 1e-12 * abs(C[l, p])
+        assert abs(gradients.directional_D(wl, 0, G, wl["D_z"][0], m) - 2 * C[l, p]) < 1e-10 * abs(C[l, p])
