@@ -1,0 +1,149 @@
+#!/usr/bin/env python3
+"""Throughput of the beyond-Limber C_l hot path on one MI355X.
+
+Workload: a batch of parameter points, each a full set of 15 tracers (10 clustering + 5
+lensing bins, 120 spectra) x 103 multipoles in [2, 2000], N_k = N_chi = 1024, FP32, every
+point with its own cosmology (chi(z), D(z), P(k)) and biases.  Inputs are seeded synthetic
+and resident in HBM before timing.  A step is one call of the whole hot path over the batch:
+kernel assembly, FFTLog coefficients, windows and projection (forward), and -- when the
+adjoint is built -- the backward pass to dP, db, dn(z) and dD(z).
+
+Prints one JSON line.  `value` is C_l sets per second (a set = 120 spectra x 103 l).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X, 256 CUs at 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def fused_kernel_flops(T, L, B, N, n_k):
+    """Algorithmic flops of one launch of the windows + projection kernel.
+
+    Per (point, multipole): T inverse real FFTs of length N (2.5 N log2 N each), the complex
+    product c_n U_l(n) over N/2 coefficients (6 flops each), the k scaling (2 per node) and
+    the symmetric projection sum_j s_j W_i W_j over T(T+1)/2 pairs (2 flops per node).
+    """
+    import math
+    per = T * (2.5 * N * math.log2(N) + 6 * (N // 2) + 2 * n_k) + T * (T + 1) // 2 * 2 * n_k
+    return per * L * B
+
+
+def cpu_baseline(wl, seconds, plan_out):
+    """Time the FP64 oracle on as many points as fit in `seconds` (at least one)."""
+    import numpy as np
+    from oracle import fftlog
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    m = fftlog.method_for(wl)
+    t0 = time.perf_counter()
+    n = 0
+    errs = []
+    while True:
+        C = fftlog.cl(wl, n, m)
+        # GPU error of this point against the oracle: |dC^{ij}| / sqrt(C^{ii} C^{jj})
+        T = int(wl["n_tracers"][n])
+        iu = np.triu_indices(T)
+        diag = {int(i): C[:, p] for p, (i, j) in enumerate(zip(*iu)) if i == j}
+        g = plan_out[n][: C.shape[0], : C.shape[1]]
+        for p, (i, j) in enumerate(zip(*iu)):
+            errs.append(float(np.max(np.abs(g[:, p] - C[:, p]) / np.sqrt(diag[int(i)] * diag[int(j)]))))
+        n += 1
+        if time.perf_counter() - t0 >= seconds or n >= wl["batch"]:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "sets/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} point(s) of the benchmark batch, full 120 spectra x 103 l each, "
+                      f"FP64 FFTLog oracle (NumPy/SciPy), {dt:.1f} s"}, max(errs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; a multi-GPU run is not part of it "
+              "(points would shard across GPUs with no exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+
+    B = args.batch
+    wl = synth.make_workload("cfg1_batch", batch=B)
+    plan = Plan.for_workload(wl)
+    inp = device_inputs(wl, "cuda:0")
+    out = torch.empty((B, plan.max_ell, plan.n_pairs), dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.cl(inp, out)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(args.steps):
+        plan.cl(inp, out)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    flags = plan.device_flags()
+
+    stages = np.mean([plan.cl_timed(inp, out) for _ in range(args.steps)], axis=0)
+    T, L, N, nk = 15, int(wl["n_ell"][0]), wl["n_chi"], len(wl["k"])
+    flops = fused_kernel_flops(T, L, B, N, nk)
+    achieved = flops / (stages[2] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_windows_cl (windows + projection)",
+                "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                "flops_per_launch": flops, "kernel_ms": float(stages[2])}
+
+    result = {
+        "metric": "C_l sets/s (15 tracers, 103 l) forward, FP32, vs FP64 oracle",
+        "value": B / (ms * 1e-3),
+        "unit": "sets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{B} points x (10 clustering + 5 lensing bins, 103 l in [2,2000], "
+                               f"N_k = N_chi = 1024), per-point cosmology", "batch": B, "tracers": T,
+                   "multipoles": L, "n_k": nk, "n_chi": N, "pass": "forward"},
+        "stage_ms": {"assembly": float(stages[0]), "fftlog_coeffs": float(stages[1]),
+                     "windows_projection": float(stages[2])},
+        "device_flags": flags,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        gpu_out = out.cpu().numpy().astype(np.float64)
+        cb, err = cpu_baseline(wl, args.cpu_seconds, gpu_out)
+        result["cpu_baseline"] = cb
+        result["max_rel_err_vs_oracle"] = err
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,150 @@
+/*
+ * swiftcl.h -- C ABI of the MI355X (gfx950) beyond-Limber angular power spectrum path.
+ *
+ * Method (Reymond, Reeves, Zhang & Refregier, "SwiftC_l: fast differentiable angular
+ * power spectra beyond Limber"):
+ *   C_l^{ij} = (2/pi) int dk k^2 Delta_l^i(k) Delta_l^j(k) P(k)             (Sec. 2.1)
+ *   Delta_l^i(k) = c_i(l, k) int dchi f_i(chi) j_l(k chi)                   (Sec. 2.1-2.3)
+ * with f_i the radial kernel of tracer i times growth (and bias):
+ *   clustering  f = b n(z) (dz/dchi) D(z),          c = 1                     (Sec. 2.2)
+ *   lensing     f = q(chi) D(z) / chi^2,             c = sqrt((l+2)!/(l-2)!) / k^2   (Sec. 2.3,
+ *               q = eq. "tomographic lens efficiency")
+ * The chi integral uses an FFTLog decomposition of f in ln chi (Sec. 3.1, eq. FFTLog) and the
+ * analytic integral of chi^p j_l(k chi) (eq. int_jl, with the denominator Gamma((2+l-p)/2));
+ * the k integral runs over the caller's k nodes (Sec. 3.2).
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - k must be log-spaced; the chi grid has the same log step Delta, so the windows land on the
+ *     caller's k nodes; the lower support edge chi(z_min) sits on node `edge_node`.
+ *   - The kernel is zero outside [chi(z_min), chi(z_max)]; edge nodes carry trapezoid weights
+ *     (1/2 on the lower edge, 1/2 + theta on the upper one).
+ *   - The Nyquist coefficient is dropped; the FFTLog bias b is chosen per tracer kind and per
+ *     multipole band.
+ *   - Samples (chi(z), D(z) on z_geom; n(z) on z_nz) are continued by natural cubic splines.
+ *   - The k integral is the trapezoid rule in ln k.
+ *
+ * Every function returns a swiftcl_status and never throws, exits or synchronises implicitly.
+ * Argument checks that need no device data run before any device work.  The message of the last
+ * error on the calling thread is returned by swiftcl_last_error().
+ */
+#ifndef SWIFTCL_H
+#define SWIFTCL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SWIFTCL_OK = 0,
+  SWIFTCL_E_INVALID = -1,     /* a bad argument (null pointer, size, layout) */
+  SWIFTCL_E_DOMAIN = -2,      /* a value outside the method's domain (b range, k spacing) */
+  SWIFTCL_E_NOMEM = -3,       /* device or host allocation failed (swiftcl_plan only) */
+  SWIFTCL_E_DEVICE = -4,      /* a HIP runtime error */
+  SWIFTCL_E_UNSUPPORTED = -5  /* a size this build does not handle (e.g. n_chi) */
+} swiftcl_status;
+
+enum { SWIFTCL_CLUSTERING = 0, SWIFTCL_LENSING = 1 };
+
+typedef enum {
+  SWIFTCL_FP64 = 0,       /* FFTs and contraction in double; outputs double */
+  SWIFTCL_FP32 = 1,       /* FFTs and contraction in float; outputs float */
+  SWIFTCL_SPLIT_BF16 = 2  /* FFTs in float; contraction as bf16 hi+lo MFMA, FP32 accumulate */
+} swiftcl_precision;
+
+#define SWIFTCL_MAX_BANDS 4
+
+typedef struct swiftcl_plan_s* swiftcl_plan_t; /* opaque, owned by the library */
+
+/* Plan descriptor.  Host memory; everything is copied by swiftcl_plan. */
+typedef struct {
+  int32_t n_chi;        /* FFTLog length N_FFT (Sec. 3.1): power of two in [64, 4096], >= n_k   */
+  int32_t edge_node;    /* chi-grid node of chi(z_min), 1..n_chi-2; <= 0 picks a centred default */
+  int32_t n_bands;      /* number of multipole bands, 1..SWIFTCL_MAX_BANDS                      */
+  double band_ell_lo[SWIFTCL_MAX_BANDS]; /* band j holds band_ell_lo[j] <= l < band_ell_lo[j+1];
+                                            band_ell_lo[0] <= min(ell), strictly increasing     */
+  double fftlog_b[2][SWIFTCL_MAX_BANDS]; /* FFTLog bias b per kind and band (Sec. 3.1); every l of
+                                            the band needs -l-1 < b < 1 (eq. int_jl)            */
+  double taper_frac;    /* cosine taper of c_n over the top fraction of |n| ("smoothing at the
+                           tails", Sec. 3.1); 0 = none; in [0, 1)                              */
+  int32_t n_k;          /* number of k nodes (Sec. 3.2: the k integral runs over all of them)   */
+  const double* k;      /* [n_k] h/Mpc, increasing, log-spaced to 1e-9 relative                 */
+  int32_t n_ell;        /* size of the multipole union                                           */
+  const double* ell;    /* [n_ell] real multipoles >= 2, increasing                              */
+  int32_t n_zg;         /* geometry samples: chi(z), D(z)                                        */
+  const double* z_geom; /* [n_zg] increasing; kernel support is [z_geom[0], z_geom[n_zg-1]]     */
+  int32_t n_zs;         /* n(z) samples per tracer                                               */
+  const double* z_nz;   /* [n_zs] increasing, inside the geometry range; n is 0 outside it      */
+  int32_t max_batch;    /* capacity: parameter points per call                                   */
+  int32_t max_tracers;  /* capacity: tracers per point (row stride of per-tracer inputs)        */
+  int32_t max_ell;      /* capacity: multipoles per point (row stride of ell_idx and outputs)   */
+  int32_t precision;    /* swiftcl_precision                                                     */
+  int32_t device;       /* HIP device ordinal the plan lives on                                  */
+} swiftcl_plan_desc;
+
+/* Per-call inputs.  Device pointers owned by the caller, row-major, never written. */
+typedef struct {
+  int32_t batch;             /* B <= max_batch                                                   */
+  const int32_t* n_tracers;  /* [B] tracers of each point, 1..max_tracers                       */
+  const int32_t* kind;       /* [B][max_tracers] SWIFTCL_CLUSTERING or SWIFTCL_LENSING           */
+  const int32_t* n_ell;      /* [B] multipoles of each point, 1..max_ell                         */
+  const int32_t* ell_idx;    /* [B][max_ell] indices into the plan's ell union                   */
+  const double* chi_z;       /* [B][n_zg] comoving distance chi(z_geom) in Mpc/h, increasing     */
+  const double* D_z;         /* [B][n_zg] growth D(z_geom), D(0) = 1 (z_fid = 0)                 */
+  const double* omega_m;     /* [B] Omega_m of the lensing prefactor (eq. lens efficiency)       */
+  const double* nz;          /* [B][max_tracers][n_zs] n(z) samples per unit z                  */
+  const double* bias;        /* [B][max_tracers] linear bias b_1 (clustering only)              */
+  const double* pk;          /* [B][n_k] P(k, z_fid) on the plan's k nodes, (Mpc/h)^3, > 0      */
+} swiftcl_inputs;
+
+/* Build a plan: validates the descriptor, builds the log-chi grid, the FP64 table of Bessel
+ * power-law integrals U_l(n) (eq. int_jl), the k scale tables and the workspace for max_batch
+ * points.  Allocates device memory; the only call that does.  `stream` is a hipStream_t (may be
+ * NULL); the plan is ready when the stream reaches the end of the call. */
+swiftcl_status swiftcl_plan(const swiftcl_plan_desc* desc, void* stream, swiftcl_plan_t* out);
+
+/* Free a plan.  The caller must ensure no call using it is still in flight. */
+swiftcl_status swiftcl_plan_destroy(swiftcl_plan_t plan);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char* swiftcl_last_error(void);
+
+/* Data checks made on the device during the last calls (support outside the chi box, non-finite
+ * inputs): returns the accumulated flag word (0 = clean) and clears it.  Synchronises `stream`. */
+swiftcl_status swiftcl_device_flags(swiftcl_plan_t plan, void* stream, int32_t* flags);
+
+/* k-windows W[b][l][t][j] = Delta_l^t(k_j) (Sec. 2.1) for every point, multipole slot and tracer
+ * slot; padded slots (t >= n_tracers[b], l >= n_ell[b]) are written as 0.  `W` is device memory
+ * of B*max_ell*max_tracers*n_k elements: double for SWIFTCL_FP64, float otherwise. */
+swiftcl_status swiftcl_windows(swiftcl_plan_t plan, const swiftcl_inputs* in, void* W, void* stream);
+
+/* Angular power spectra C[b][l][p] (Sec. 2.1 / 3.2) with p running over the packed upper
+ * triangle (i <= j, row-major) of max_tracers x max_tracers; padded slots are 0.  `C` is device
+ * memory of B*max_ell*max_tracers*(max_tracers+1)/2 elements (double for FP64, float otherwise).
+ * No allocation and no synchronisation: safe inside hipGraph capture. */
+swiftcl_status swiftcl_cl(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C, void* stream);
+
+/* Measurement variant of swiftcl_cl: the same launches, with HIP events recorded on `stream`
+ * between its stages; writes the device time in ms of [0] kernel assembly (FP64 splines, lensing
+ * integrals, sampling on the chi grid), [1] forward FFTLog coefficients, [2] windows + projection.
+ * Creates events and synchronises `stream`: not for use under graph capture. */
+swiftcl_status swiftcl_cl_timed(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C, void* stream,
+                                float* stage_ms);
+
+/* Reverse-mode derivative of L = sum_b sum_l sum_{i<=j} dC[b][l][p(i,j)] C[b][l][p(i,j)] (the
+ * paper differentiates its pipeline end to end, Sec. 1 and 4.3).  Windows are recomputed, not
+ * stored.  Outputs (device, double; any may be NULL = not requested; padded slots written 0):
+ *   dpk   [B][n_k]                  dL/dP(k_j)
+ *   dbias [B][max_tracers]          dL/db_t (0 for lensing tracers)
+ *   dnz   [B][max_tracers][n_zs]    dL/dn_t(z_s) through the n(z) spline (and the lensing q)
+ *   dD    [B][n_zg]                 dL/dD(z_s) through the D(z) spline
+ * `dC` has the layout and type of swiftcl_cl's output. */
+swiftcl_status swiftcl_cl_backward(swiftcl_plan_t plan, const swiftcl_inputs* in, const void* dC,
+                                   double* dpk, double* dbias, double* dnz, double* dD, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWIFTCL_H */

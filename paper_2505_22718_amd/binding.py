@@ -1,0 +1,162 @@
+"""ctypes binding of libswiftcl (include/swiftcl.h): argument marshalling only.
+
+The functions below carry the C names and forward to the shared library; every step of
+the computation runs in the HIP kernels.  There is no CPU fallback: if the library is
+missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswiftcl.so")
+
+SWIFTCL_OK = 0
+SWIFTCL_E_INVALID = -1
+SWIFTCL_E_DOMAIN = -2
+SWIFTCL_E_NOMEM = -3
+SWIFTCL_E_DEVICE = -4
+SWIFTCL_E_UNSUPPORTED = -5
+STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_DOMAIN", -3: "E_NOMEM", -4: "E_DEVICE", -5: "E_UNSUPPORTED"}
+
+SWIFTCL_CLUSTERING = 0
+SWIFTCL_LENSING = 1
+SWIFTCL_FP64 = 0
+SWIFTCL_FP32 = 1
+SWIFTCL_SPLIT_BF16 = 2
+MAX_BANDS = 4
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class swiftcl_plan_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_chi", ctypes.c_int32),
+        ("edge_node", ctypes.c_int32),
+        ("n_bands", ctypes.c_int32),
+        ("band_ell_lo", ctypes.c_double * MAX_BANDS),
+        ("fftlog_b", (ctypes.c_double * MAX_BANDS) * 2),
+        ("taper_frac", ctypes.c_double),
+        ("n_k", ctypes.c_int32),
+        ("k", _dp),
+        ("n_ell", ctypes.c_int32),
+        ("ell", _dp),
+        ("n_zg", ctypes.c_int32),
+        ("z_geom", _dp),
+        ("n_zs", ctypes.c_int32),
+        ("z_nz", _dp),
+        ("max_batch", ctypes.c_int32),
+        ("max_tracers", ctypes.c_int32),
+        ("max_ell", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+    ]
+
+
+class swiftcl_inputs(ctypes.Structure):
+    _fields_ = [
+        ("batch", ctypes.c_int32),
+        ("n_tracers", ctypes.c_void_p),
+        ("kind", ctypes.c_void_p),
+        ("n_ell", ctypes.c_void_p),
+        ("ell_idx", ctypes.c_void_p),
+        ("chi_z", ctypes.c_void_p),
+        ("D_z", ctypes.c_void_p),
+        ("omega_m", ctypes.c_void_p),
+        ("nz", ctypes.c_void_p),
+        ("bias", ctypes.c_void_p),
+        ("pk", ctypes.c_void_p),
+    ]
+
+
+EXPORTED = ["swiftcl_plan", "swiftcl_plan_destroy", "swiftcl_last_error", "swiftcl_device_flags",
+            "swiftcl_windows", "swiftcl_cl", "swiftcl_cl_timed", "swiftcl_cl_backward"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libswiftcl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libswiftcl.so not found at {path}: build it with "
+                           "`python -m paper_2505_22718_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.swiftcl_plan.argtypes = [ctypes.POINTER(swiftcl_plan_desc), vp, ctypes.POINTER(vp)]
+    lib.swiftcl_plan_destroy.argtypes = [vp]
+    lib.swiftcl_last_error.restype = ctypes.c_char_p
+    lib.swiftcl_device_flags.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.swiftcl_windows.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
+    lib.swiftcl_cl.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
+    lib.swiftcl_cl_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, ctypes.POINTER(ctypes.c_float)]
+    lib.swiftcl_cl_backward.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, vp]
+    for name in EXPORTED:
+        f = getattr(lib, name)
+        if name != "swiftcl_last_error":
+            f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class SwiftclError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"swiftcl {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(status):
+    if status != SWIFTCL_OK:
+        raise SwiftclError(status, load().swiftcl_last_error().decode())
+    return status
+
+
+def swiftcl_last_error() -> str:
+    return load().swiftcl_last_error().decode()
+
+
+def swiftcl_plan(desc: swiftcl_plan_desc, stream: int = 0):
+    handle = ctypes.c_void_p()
+    _check(load().swiftcl_plan(ctypes.byref(desc), ctypes.c_void_p(stream), ctypes.byref(handle)))
+    return handle
+
+
+def swiftcl_plan_destroy(plan):
+    _check(load().swiftcl_plan_destroy(plan))
+
+
+def swiftcl_device_flags(plan, stream: int = 0) -> int:
+    v = ctypes.c_int32()
+    _check(load().swiftcl_device_flags(plan, ctypes.c_void_p(stream), ctypes.byref(v)))
+    return v.value
+
+
+def swiftcl_windows(plan, inputs: swiftcl_inputs, W: int, stream: int = 0):
+    _check(load().swiftcl_windows(plan, ctypes.byref(inputs), ctypes.c_void_p(W), ctypes.c_void_p(stream)))
+
+
+def swiftcl_cl(plan, inputs: swiftcl_inputs, C: int, stream: int = 0):
+    _check(load().swiftcl_cl(plan, ctypes.byref(inputs), ctypes.c_void_p(C), ctypes.c_void_p(stream)))
+
+
+def swiftcl_cl_timed(plan, inputs: swiftcl_inputs, C: int, stream: int = 0):
+    """Returns the device time (ms) of the three forward stages."""
+    ms = (ctypes.c_float * 3)()
+    _check(load().swiftcl_cl_timed(plan, ctypes.byref(inputs), ctypes.c_void_p(C), ctypes.c_void_p(stream), ms))
+    return [ms[0], ms[1], ms[2]]
+
+
+def swiftcl_cl_backward(plan, inputs: swiftcl_inputs, dC: int, dpk: int = 0, dbias: int = 0, dnz: int = 0,
+                        dD: int = 0, stream: int = 0):
+    vp = ctypes.c_void_p
+    _check(load().swiftcl_cl_backward(plan, ctypes.byref(inputs), vp(dC), vp(dpk or None), vp(dbias or None),
+                                      vp(dnz or None), vp(dD or None), vp(stream)))
+
+
+def raw_status(fn_name: str, *args) -> int:
+    """Call an entry point and return its status without raising (for error-path tests)."""
+    return getattr(load(), fn_name)(*args)

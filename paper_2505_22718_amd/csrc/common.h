@@ -1,0 +1,178 @@
+// Shared device helpers: complex arithmetic, small in-register DFTs and a wavefront-level
+// Stockham FFT for gfx950 (64-lane wavefronts).  Everything is templated on the real type
+// (float for the FP32 / split paths, double for the FP64 path).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SWIFTCL_WAVE 64
+
+template <typename R> struct cplx_t;
+template <> struct cplx_t<float> { typedef float2 type; };
+template <> struct cplx_t<double> { typedef double2 type; };
+
+template <typename R> using C2 = typename cplx_t<R>::type;
+
+template <typename R> __device__ __forceinline__ C2<R> mk(R x, R y) { C2<R> c; c.x = x; c.y = y; return c; }
+template <typename T> __device__ __forceinline__ T cadd(T a, T b) { a.x += b.x; a.y += b.y; return a; }
+template <typename T> __device__ __forceinline__ T csub(T a, T b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename T> __device__ __forceinline__ T cmul(T a, T b) {
+  T c; c.x = a.x * b.x - a.y * b.y; c.y = a.x * b.y + a.y * b.x; return c;
+}
+template <typename T> __device__ __forceinline__ T cconj(T a) { a.y = -a.y; return a; }
+template <typename T, typename R> __device__ __forceinline__ T cscale(T a, R s) { a.x *= s; a.y *= s; return a; }
+// multiply by S*i (S = +1 or -1)
+template <int S, typename T> __device__ __forceinline__ T mul_si(T a) {
+  T c; if (S > 0) { c.x = -a.y; c.y = a.x; } else { c.x = a.y; c.y = -a.x; } return c;
+}
+
+// Ordering of LDS traffic inside one wavefront (no block barrier needed: a wavefront's LDS
+// instructions execute in order; this stops the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// cos / sin of 2*pi*k/16 for k = 0..3 (exact constants of the 16-point circle)
+#define SWIFTCL_C16_1 0.92387953251128675613
+#define SWIFTCL_S16_1 0.38268343236508977173
+#define SWIFTCL_R2_2 0.70710678118654752440
+
+// e^{S 2 pi i k / r} for the constant twiddles of a radix-r butterfly, k < r/2
+template <typename R, int r, int S> __device__ __forceinline__ C2<R> const_tw(int k) {
+  // r in {4, 8, 16}; k/r reduced to sixteenths
+  const int k16 = k * (16 / r);
+  R c, s;
+  switch (k16) {
+    case 0: c = 1; s = 0; break;
+    case 1: c = (R)SWIFTCL_C16_1; s = (R)SWIFTCL_S16_1; break;
+    case 2: c = (R)SWIFTCL_R2_2; s = (R)SWIFTCL_R2_2; break;
+    case 3: c = (R)SWIFTCL_S16_1; s = (R)SWIFTCL_C16_1; break;
+    case 4: c = 0; s = 1; break;
+    case 5: c = -(R)SWIFTCL_S16_1; s = (R)SWIFTCL_C16_1; break;
+    case 6: c = -(R)SWIFTCL_R2_2; s = (R)SWIFTCL_R2_2; break;
+    default: c = -(R)SWIFTCL_C16_1; s = (R)SWIFTCL_S16_1; break;
+  }
+  return mk<R>(c, S > 0 ? s : -s);
+}
+
+// In-register DFT of size r (power of two <= 16), sign S: Y_k = sum_i y_i e^{S 2 pi i i k / r}.
+// Radix-2 decimation in time, unrolled at compile time.
+template <typename R, int r, int S> __device__ __forceinline__ void dft(C2<R>* v) {
+  if constexpr (r == 1) {
+    return;
+  } else if constexpr (r == 2) {
+    C2<R> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else {
+    C2<R> e[r / 2], o[r / 2];
+#pragma unroll
+    for (int i = 0; i < r / 2; ++i) { e[i] = v[2 * i]; o[i] = v[2 * i + 1]; }
+    dft<R, r / 2, S>(e);
+    dft<R, r / 2, S>(o);
+#pragma unroll
+    for (int k = 0; k < r / 2; ++k) {
+      C2<R> t;
+      if (k == 0) t = o[k];
+      else if (4 * k == r) t = mul_si<S>(o[k]);
+      else t = cmul(o[k], const_tw<R, r, S>(k));
+      v[k] = cadd(e[k], t);
+      v[k + r / 2] = csub(e[k], t);
+    }
+  }
+}
+
+// Radix schedule of an M-point wavefront FFT: each lane holds RL = M/64 elements and every
+// pass uses a radix that divides RL, so a lane runs RL/r butterflies per pass.
+template <int M> struct fft_plan;
+template <> struct fft_plan<128> { static constexpr int RL = 2, NP = 7; static constexpr int rad[7] = {2, 2, 2, 2, 2, 2, 2}; };
+template <> struct fft_plan<256> { static constexpr int RL = 4, NP = 4; static constexpr int rad[4] = {4, 4, 4, 4}; };
+template <> struct fft_plan<512> { static constexpr int RL = 8, NP = 3; static constexpr int rad[3] = {8, 8, 8}; };
+template <> struct fft_plan<1024> { static constexpr int RL = 16, NP = 3; static constexpr int rad[3] = {16, 8, 8}; };
+template <> struct fft_plan<2048> { static constexpr int RL = 32, NP = 3; static constexpr int rad[3] = {16, 16, 8}; };
+
+// One Stockham pass (self-sorting, natural-order output) of radix r on an M-point sequence.
+// Butterfly q (q = lane + 64 u) reads x[q + i M/r], applies twiddles e^{S 2 pi i i j / (Ls r)}
+// with j = q mod Ls, runs dft<r> and writes Y_i to (q / Ls) Ls r + j + i Ls.
+// tw is the table e^{-2 pi i m / N}, m < N (N = 2M for the real transforms).
+template <typename R, int M, int r, int S, bool FIRST, bool LAST>
+__device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw,
+                                              int N, int Ls, int lane) {
+  constexpr int RL = M / SWIFTCL_WAVE;
+  constexpr int BPL = RL / r;
+  C2<R> b[RL];
+  if (FIRST) {
+    // registers hold x[lane + 64 e]; butterfly u input i is e = u + i * BPL
+#pragma unroll
+    for (int u = 0; u < BPL; ++u)
+#pragma unroll
+      for (int i = 0; i < r; ++i) b[u * r + i] = v[u + i * BPL];
+  } else {
+#pragma unroll
+    for (int u = 0; u < BPL; ++u) {
+      const int q = lane + SWIFTCL_WAVE * u;
+#pragma unroll
+      for (int i = 0; i < r; ++i) b[u * r + i] = lds[q + i * (M / r)];
+    }
+    wave_sync();
+  }
+  const int L = Ls * r;
+  const int step = N / L;
+#pragma unroll
+  for (int u = 0; u < BPL; ++u) {
+    const int q = lane + SWIFTCL_WAVE * u;
+    const int j = q % Ls;
+#pragma unroll
+    for (int i = 1; i < r; ++i) {
+      C2<R> w = tw[(i * j * step) & (N - 1)];
+      if (S > 0) w = cconj(w);
+      b[u * r + i] = cmul(b[u * r + i], w);
+    }
+    dft<R, r, S>(&b[u * r]);
+  }
+  if (LAST) {
+#pragma unroll
+    for (int u = 0; u < BPL; ++u)
+#pragma unroll
+      for (int i = 0; i < r; ++i) v[u + i * BPL] = b[u * r + i];
+  } else {
+#pragma unroll
+    for (int u = 0; u < BPL; ++u) {
+      const int q = lane + SWIFTCL_WAVE * u;
+      const int j = q % Ls;
+      const int base = (q / Ls) * L + j;
+#pragma unroll
+      for (int i = 0; i < r; ++i) lds[base + i * Ls] = b[u * r + i];
+    }
+    wave_sync();
+  }
+}
+
+// M-point complex FFT by one wavefront.  In and out: v[e] holds element lane + 64 e (natural
+// order).  lds: M complex of scratch private to this wavefront.  S = -1 forward, +1 inverse
+// (unnormalised).
+template <typename R, int M, int S>
+__device__ __forceinline__ void wave_fft(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int N, int lane) {
+  using P = fft_plan<M>;
+  if constexpr (P::NP == 3) {
+    stockham_pass<R, M, P::rad[0], S, true, false>(v, lds, tw, N, 1, lane);
+    stockham_pass<R, M, P::rad[1], S, false, false>(v, lds, tw, N, P::rad[0], lane);
+    stockham_pass<R, M, P::rad[2], S, false, true>(v, lds, tw, N, P::rad[0] * P::rad[1], lane);
+  } else if constexpr (P::NP == 4) {
+    stockham_pass<R, M, P::rad[0], S, true, false>(v, lds, tw, N, 1, lane);
+    stockham_pass<R, M, P::rad[1], S, false, false>(v, lds, tw, N, 4, lane);
+    stockham_pass<R, M, P::rad[2], S, false, false>(v, lds, tw, N, 16, lane);
+    stockham_pass<R, M, P::rad[3], S, false, true>(v, lds, tw, N, 64, lane);
+  } else {
+    stockham_pass<R, M, 2, S, true, false>(v, lds, tw, N, 1, lane);
+    stockham_pass<R, M, 2, S, false, false>(v, lds, tw, N, 2, lane);
+    stockham_pass<R, M, 2, S, false, false>(v, lds, tw, N, 4, lane);
+    stockham_pass<R, M, 2, S, false, false>(v, lds, tw, N, 8, lane);
+    stockham_pass<R, M, 2, S, false, false>(v, lds, tw, N, 16, lane);
+    stockham_pass<R, M, 2, S, false, false>(v, lds, tw, N, 32, lane);
+    stockham_pass<R, M, 2, S, false, true>(v, lds, tw, N, 64, lane);
+  }
+}

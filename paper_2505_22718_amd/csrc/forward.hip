@@ -1,0 +1,283 @@
+// Forward hot path: FFTLog coefficients (r2c), multiplication by the power-law Bessel table,
+// inverse FFT to the k-windows and the projection C = W diag(s) W^T on MFMA.
+//
+// Notation (paper Sec. 3.1-3.2, with the readings stated in swiftcl.h):
+//   g_m   = w_m f(chi_m) (chi_m / chi_0)^-b                     (assembled in FP64, assemble.hip)
+//   c_n   = (1/N) sum_m g_m e^{-2 pi i n m / N} (k_0 chi_0)^{-i eta_n} chi_0^{-b},  n < N/2
+//   d_n   = c_n U_l(n),   U_l(n) = sqrt(pi) 2^{p-1} Gamma((1+l+p)/2) / Gamma((2+l-p)/2)
+//   x_j   = Re( d_0 + 2 sum_{n=1}^{N/2-1} d_n e^{-2 pi i n j / N} )
+//   W_j   = c(l) k_j^{-1-b} [k_j^-2 for lensing] x_j              (Delta_l(k_j) of Sec. 2.1)
+//   C_l^{ij} = sum_j s_j W_i(k_j) W_j(k_j),  s_j = (2/pi) w_j k_j^3 P_j
+// One wavefront runs one length-N real transform as a length-N/2 complex FFT in registers and
+// LDS; one workgroup owns one (point, multipole) and keeps sqrt(s) W of all its tracers in LDS,
+// so the windows never touch HBM on the C_l path.
+#include "common.h"
+#include "internal.h"
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename R> struct mfma_acc;
+// Output layout of the 16x16x4 MFMAs: lane l, accumulator register r holds D[row][l % 16] with
+// row = 4 (l / 16) + r for f32 and row = l / 16 + 4 r for f64.
+template <> struct mfma_acc<float> {
+  typedef v4f type;
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane / 16) + r; }
+  static __device__ __forceinline__ type step(float a, float b, type c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct mfma_acc<double> {
+  typedef v4d type;
+  static __device__ __forceinline__ int row(int lane, int r) { return lane / 16 + 4 * r; }
+  static __device__ __forceinline__ type step(double a, double b, type c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+template <typename R>
+__global__ void k_sqrt_s(plan_dev P, swiftcl_inputs in) {
+  const int b = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= in.batch || j >= P.n_k) return;
+  const double v = P.kw[j] * in.pk[(size_t)b * P.n_k + j];
+  if (!(v >= 0.0) || !isfinite(v)) atomicOr(P.flags, FLAG_NONFINITE);
+  ((R*)P.sqrt_s)[(size_t)b * P.n_k + j] = (R)sqrt(fmax(v, 0.0));
+}
+
+// FFTLog coefficients: one wavefront per (point, tracer, band) row.
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs in) {
+  __shared__ C2<R> lds[4][M];
+  constexpr int RL = M / SWIFTCL_WAVE;
+  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int T = P.max_tracers, nb = P.n_bands, N = P.N;
+  const long rows = (long)in.batch * T * nb;
+  const long row = (long)blockIdx.x * 4 + wave;
+  if (row >= rows) return;  // whole wavefront leaves; no block barrier below
+  const int bi = (int)(row % nb);
+  const int t = (int)((row / nb) % T);
+  const int b = (int)(row / ((long)nb * T));
+  C2<R>* out = (C2<R>*)P.chat + row * M;
+  const int Tb = clampi(in.n_tracers[b], 0, T);
+  if (t >= Tb) {
+#pragma unroll
+    for (int e = 0; e < RL; ++e) out[lane + SWIFTCL_WAVE * e] = mk<R>(0, 0);
+    return;
+  }
+  const C2<R>* g2 = (const C2<R>*)((const R*)P.g + row * N);
+  const C2<R>* tw = (const C2<R>*)P.tw;
+  C2<R> v[RL];
+#pragma unroll
+  for (int e = 0; e < RL; ++e) v[e] = g2[lane + SWIFTCL_WAVE * e];
+  wave_fft<R, M, -1>(v, lds[wave], tw, N, lane);
+#pragma unroll
+  for (int e = 0; e < RL; ++e) lds[wave][lane + SWIFTCL_WAVE * e] = v[e];
+  wave_sync();
+  const double* pt = P.pt + (size_t)b * PT_STRIDE;
+  const int kind = in.kind[(size_t)b * T + t] & 1;
+  const double scale = pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] / (double)N;
+  const double dphi = -2.0 * M_PI * pt[PT_LNK0CHI0] / ((double)N * P.delta);
+#pragma unroll
+  for (int e = 0; e < RL; ++e) {
+    const int n = lane + SWIFTCL_WAVE * e;
+    const C2<R> Zn = v[e];
+    C2<R> X;
+    if (n == 0) {
+      X = mk<R>(Zn.x + Zn.y, (R)0);
+    } else {
+      const C2<R> Zm = cconj(lds[wave][M - n]);
+      const C2<R> A = cscale(cadd(Zn, Zm), (R)0.5);
+      const C2<R> Bd = cscale(csub(Zn, Zm), (R)0.5);
+      const C2<R> t2 = cmul(tw[n], Bd);
+      X = mk<R>(A.x + t2.y, A.y - t2.x);  // A - i w^n Bd
+    }
+    double sn, cs;
+    sincos(dphi * (double)n, &sn, &cs);
+    const C2<R> ph = mk<R>((R)(cs * scale), (R)(sn * scale));
+    out[n] = cmul(X, ph);
+  }
+}
+
+// Windows and / or C_l for one (point, multipole) per workgroup of NW wavefronts.
+template <typename R, int M, int NW, bool WRITE_W, bool DO_CL>
+__global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inputs in, R* __restrict__ Wout,
+                                                        R* __restrict__ Cout) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int RL = M / SWIFTCL_WAVE;
+  C2<R>* fbuf = (C2<R>*)smem;                                  // [NW][M]
+  R* V = (R*)(smem + (size_t)NW * M * sizeof(C2<R>));          // [n_k][16]
+  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands, N = P.N;
+  const int b = blockIdx.x / Lm, li = blockIdx.x % Lm;
+  if (b >= in.batch) return;
+  const int Tb = clampi(in.n_tracers[b], 0, T);
+  const int Lb = clampi(in.n_ell[b], 0, Lm);
+  const int npair = T * (T + 1) / 2;
+  if (li >= Lb) {
+    if (WRITE_W) {
+      R* w = Wout + ((size_t)b * Lm + li) * T * nk;
+      for (int i = threadIdx.x; i < T * nk; i += NW * 64) w[i] = (R)0;
+    }
+    if (DO_CL) {
+      R* c = Cout + ((size_t)b * Lm + li) * npair;
+      for (int i = threadIdx.x; i < npair; i += NW * 64) c[i] = (R)0;
+    }
+    return;
+  }
+  int ei = in.ell_idx[(size_t)b * Lm + li];
+  if (ei < 0 || ei >= P.n_ell) {
+    if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+    ei = 0;
+  }
+  const int band = P.ell_band[ei];
+  const R Fl = (R)P.fell[ei];
+  const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
+  const C2<R>* tw = (const C2<R>*)P.tw;
+  C2<R>* mine = fbuf + (size_t)wave * M;
+  const int trows = DO_CL ? 16 : T;
+  for (int t = wave; t < trows; t += NW) {
+    if (t >= Tb) {
+      for (int j = lane; j < nk; j += SWIFTCL_WAVE) {
+        if (DO_CL) V[j * 16 + t] = (R)0;
+        if (WRITE_W && t < T) Wout[(((size_t)b * Lm + li) * T + t) * nk + j] = (R)0;
+      }
+      continue;
+    }
+    const int kind = in.kind[(size_t)b * T + t] & 1;
+    const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
+    const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
+    C2<R> d[RL];
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < RL; ++e) {
+      const int n = lane + SWIFTCL_WAVE * e;
+      d[e] = cmul(ch[n], Ur[n]);
+      mine[n] = d[e];
+    }
+    wave_sync();
+    C2<R> v[RL];
+#pragma unroll
+    for (int e = 0; e < RL; ++e) {
+      const int n = lane + SWIFTCL_WAVE * e;
+      if (n == 0) {
+        v[e] = mk<R>(d[e].x, d[e].x);  // X_0 (1 + i), X_0 = Re d_0, Nyquist dropped
+      } else {
+        const C2<R> dm = mine[M - n];
+        const C2<R> cd = cconj(d[e]);
+        const C2<R> A = cadd(cd, dm);
+        const C2<R> Bd = csub(cd, dm);
+        const C2<R> t2 = cmul(cconj(tw[n]), Bd);
+        v[e] = mk<R>(A.x - t2.y, A.y + t2.x);  // A + i e^{2 pi i n / N} Bd
+      }
+    }
+    wave_sync();
+    wave_fft<R, M, +1>(v, mine, tw, N, lane);
+    const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
+    const R F = kind ? Fl : (R)1;
+#pragma unroll
+    for (int e = 0; e < RL; ++e) {
+      const int j = lane + SWIFTCL_WAVE * e;
+      const int k0 = 2 * j;
+      if (k0 < nk) {
+        const R w0 = F * ks[k0] * v[e].x;
+        const R w1 = F * ks[k0 + 1] * v[e].y;
+        if (WRITE_W) {
+          C2<R>* dst = (C2<R>*)(Wout + (((size_t)b * Lm + li) * T + t) * nk + k0);
+          *dst = mk<R>(w0, w1);
+        }
+        if (DO_CL) {
+          V[k0 * 16 + t] = w0 * sq[k0];
+          V[(k0 + 1) * 16 + t] = w1 * sq[k0 + 1];
+        }
+      }
+    }
+  }
+  if (!DO_CL) return;
+  __syncthreads();
+  // C = V^T V over k on MFMA 16x16x4: lane feeds V[k][lane % 16] as both A and B operand.
+  using acc_t = typename mfma_acc<R>::type;
+  acc_t acc = {0, 0, 0, 0};
+  const int nsteps = (nk + 3) / 4;
+  for (int s = wave; s < nsteps; s += NW) {
+    const int kk = 4 * s + lane / 16;
+    const R a = kk < nk ? V[kk * 16 + (lane & 15)] : (R)0;
+    acc = mfma_acc<R>::step(a, a, acc);
+  }
+  R* red = (R*)smem;  // the FFT scratch is free now: [NW][256]
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave * 256 + mfma_acc<R>::row(lane, r) * 16 + (lane & 15)] = acc[r];
+  __syncthreads();
+  R* c = Cout + ((size_t)b * Lm + li) * npair;
+  for (int idx = threadIdx.x; idx < npair; idx += NW * 64) {
+    int i = 0, rem = idx;
+    while (rem >= T - i) { rem -= T - i; ++i; }
+    const int j = i + rem;
+    R val = (R)0;
+    if (i < Tb && j < Tb) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) val += red[w * 256 + i * 16 + j];
+    }
+    c[idx] = val;
+  }
+}
+
+template <typename R, int M>
+static hipError_t launch_fwd_t(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s) {
+  hipLaunchKernelGGL(k_sqrt_s<R>, dim3((p.n_k + 255) / 256, in->batch), dim3(256), 0, s, p, *in);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long rows = (long)in->batch * p.max_tracers * p.n_bands;
+  hipLaunchKernelGGL((k_forward_fft<R, M>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_fft(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s) {
+  const bool dp = p.precision == SWIFTCL_FP64;
+  switch (p.M) {
+    case 128: return dp ? launch_fwd_t<double, 128>(p, in, s) : launch_fwd_t<float, 128>(p, in, s);
+    case 256: return dp ? launch_fwd_t<double, 256>(p, in, s) : launch_fwd_t<float, 256>(p, in, s);
+    case 512: return dp ? launch_fwd_t<double, 512>(p, in, s) : launch_fwd_t<float, 512>(p, in, s);
+    case 1024: return dp ? launch_fwd_t<double, 1024>(p, in, s) : launch_fwd_t<float, 1024>(p, in, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename R, int M, bool WRITE_W, bool DO_CL>
+static hipError_t launch_wcl_t(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s) {
+  constexpr int NW = 4;
+  const size_t lds = (size_t)NW * M * sizeof(C2<R>) + (DO_CL ? (size_t)p.n_k * 16 * sizeof(R) : 0);
+  auto kern = k_windows_cl<R, M, NW, WRITE_W, DO_CL>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)((size_t)in->batch * p.max_ell)), dim3(NW * 64), lds, s, p, *in, (R*)W,
+                     (R*)C);
+  return hipGetLastError();
+}
+
+template <typename R, int M>
+static hipError_t launch_wcl_m(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (W) e = launch_wcl_t<R, M, true, false>(p, in, W, nullptr, s);
+  if (e == hipSuccess && C) e = launch_wcl_t<R, M, false, true>(p, in, nullptr, C, s);
+  return e;
+}
+
+hipError_t launch_windows_cl(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s) {
+  const bool dp = p.precision == SWIFTCL_FP64;
+  switch (p.M) {
+    case 128: return dp ? launch_wcl_m<double, 128>(p, in, W, C, s) : launch_wcl_m<float, 128>(p, in, W, C, s);
+    case 256: return dp ? launch_wcl_m<double, 256>(p, in, W, C, s) : launch_wcl_m<float, 256>(p, in, W, C, s);
+    case 512: return dp ? launch_wcl_m<double, 512>(p, in, W, C, s) : launch_wcl_m<float, 512>(p, in, W, C, s);
+    case 1024: return dp ? launch_wcl_m<double, 1024>(p, in, W, C, s) : launch_wcl_m<float, 1024>(p, in, W, C, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_backward(const plan_dev&, const swiftcl_inputs*, const void*, double*, double*, double*, double*,
+                           hipStream_t) {
+  return hipErrorNotSupported;
+}

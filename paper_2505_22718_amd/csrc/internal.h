@@ -1,0 +1,81 @@
+// Internal plan layout and kernel launchers shared by the translation units of libswiftcl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/swiftcl.h"
+
+// Per-point scalars written by the spline set-up kernel (FP64), PT_STRIDE doubles per point.
+enum {
+  PT_CHI0 = 0,        // chi_0 = chi(z_min) exp(-edge_node Delta)
+  PT_LNK0CHI0 = 1,    // ln(k_0 chi_0)
+  PT_M1 = 2,          // last node inside the support (as a double)
+  PT_THETA = 3,       // fractional position of chi(z_max) above node m1
+  PT_CHI0B = 4,       // chi_0^{-b} for [kind][band]: 2 * SWIFTCL_MAX_BANDS entries
+  PT_STRIDE = 16
+};
+
+// Device flag bits (swiftcl_device_flags)
+enum { FLAG_SUPPORT_OVERFLOW = 1, FLAG_NONFINITE = 2, FLAG_BAD_INDEX = 4 };
+
+// Everything the kernels need: scalars and device pointers only (trivially copyable, passed
+// by value to every kernel).
+struct plan_dev {
+  int device;
+  int precision;
+  int N, M, n_k, n_ell, n_zg, n_zs, n_bands, m0;
+  int max_batch, max_tracers, max_ell;
+  int n_union;
+  double delta, k0, taper_frac;
+  double band_ell_lo[SWIFTCL_MAX_BANDS];
+  double fftlog_b[2][SWIFTCL_MAX_BANDS];
+
+  // --- plan-time device tables ---
+  void* U;          // [2][n_ell][M] complex real: Bessel power-law integral U_l(n) (taper folded in)
+  void* kscale;     // [2][n_bands][n_k] real: k^{-1-b} (times k^-2 for lensing)
+  void* tw;         // [N] complex real: e^{-2 pi i m / N}
+  double* fell;     // [n_ell] F(l) for lensing
+  int* ell_band;    // [n_ell]
+  double* kw;       // [n_k] (2/pi) w_j k_j^3
+  double* z_geom;   // [n_zg]
+  double* z_nz;     // [n_zs]
+  double* lu_geom;  // [3][n_zg] natural-spline Thomas factors (a, inv, c')
+  double* lu_nz;    // [3][n_zs]
+  double* z_union;  // [n_union + 1] knots of the lensing quadrature
+  int* union_iv;    // [2][n_union] geometry interval, n(z) interval (-1 = outside)
+
+  // --- workspace sized for max_batch ---
+  double* pt;       // [B][PT_STRIDE]
+  double* m_chi;    // [B][n_zg] spline second derivatives
+  double* m_D;      // [B][n_zg]
+  double* m_n;      // [B][T][n_zs]
+  double* lens_suf; // [B][T][2][n_union + 1]
+  void* g;          // [B][T][n_bands][N] real: tilted, edge-weighted kernel samples
+  void* chat;       // [B][T][n_bands][M] complex real: FFTLog coefficients (phased)
+  void* sqrt_s;     // [B][n_k] real: sqrt((2/pi) w k^3 P)
+  int* flags;       // [1]
+  // backward workspace
+  void* dchat;      // [B][T][n_bands][M] complex real
+  void* dg;         // [B][T][n_bands][N] real
+};
+
+struct swiftcl_plan_s {
+  plan_dev d{};
+  std::vector<double> ell_host;
+  size_t real_size = 4;  // sizeof(real) on the FFT path
+};
+
+void set_error(const std::string& msg);
+swiftcl_status hip_check(hipError_t e, const char* what);
+
+// Launchers (each returns the first HIP error of its launches)
+hipError_t launch_u_table(const plan_dev& p, const double* d_ell, hipStream_t s);
+hipError_t launch_assemble(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s);
+hipError_t launch_forward_fft(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s);
+hipError_t launch_windows_cl(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s);
+hipError_t launch_backward(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,
+                           double* dbias, double* dnz, double* dD, hipStream_t s);

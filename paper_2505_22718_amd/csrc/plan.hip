@@ -1,0 +1,488 @@
+// Host plan, argument checks, plan-time tables and the C entry points of libswiftcl.
+//
+// The plan fixes everything that depends only on the descriptor: the log-chi grid step
+// (equal to the k grid's log step, so the FFTLog output lands on the caller's k nodes), the
+// per-(kind, l) table of power-law Bessel integrals U_l(n) of eq. int_jl (computed on the GPU
+// in FP64 from a complex log-gamma), the k scale tables, FFT twiddles, spline factorisations
+// and the workspace for max_batch points.  Calls after swiftcl_plan allocate nothing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+swiftcl_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SWIFTCL_OK;
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return SWIFTCL_E_DEVICE;
+}
+
+extern "C" const char* swiftcl_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------------------------
+// Complex log-gamma in FP64 (Stirling's series with Bernoulli-number coefficients after an
+// upward recurrence shift; valid for Re z > 0).  Only exp() of differences is used, so the
+// branch of the imaginary part is irrelevant.
+// ---------------------------------------------------------------------------------------------
+struct zd { double x, y; };
+__device__ inline zd zadd(zd a, zd b) { return {a.x + b.x, a.y + b.y}; }
+__device__ inline zd zsub(zd a, zd b) { return {a.x - b.x, a.y - b.y}; }
+__device__ inline zd zmul(zd a, zd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ inline zd zdiv(zd a, zd b) {
+  double d = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+__device__ inline zd zlog(zd a) { return {log(hypot(a.x, a.y)), atan2(a.y, a.x)}; }
+
+__device__ zd zlgamma(zd z) {
+  // shift so that Re z >= 12, accumulating log of the product z (z+1) ... in chunks
+  zd acc = {0.0, 0.0};
+  zd prod = {1.0, 0.0};
+  int cnt = 0;
+  while (z.x < 12.0) {
+    prod = zmul(prod, z);
+    z.x += 1.0;
+    if (++cnt == 8) { acc = zadd(acc, zlog(prod)); prod = {1.0, 0.0}; cnt = 0; }
+  }
+  acc = zadd(acc, zlog(prod));
+  // Stirling: (z - 1/2) ln z - z + ln(2 pi)/2 + sum_k B_2k / (2k (2k-1) z^{2k-1})
+  const double c[10] = {1.0 / 12.0, -1.0 / 360.0, 1.0 / 1260.0, -1.0 / 1680.0, 1.0 / 1188.0,
+                        -691.0 / 360360.0, 1.0 / 156.0, -3617.0 / 122400.0, 43867.0 / 244188.0,
+                        -174611.0 / 125400.0};
+  zd lz = zlog(z);
+  zd r = zsub(zmul({z.x - 0.5, z.y}, lz), z);
+  r.x += 0.91893853320467274178;  // ln(2 pi)/2
+  zd iz = zdiv({1.0, 0.0}, z);
+  zd iz2 = zmul(iz, iz);
+  zd term = iz;
+  for (int k = 0; k < 10; ++k) {
+    r = zadd(r, {c[k] * term.x, c[k] * term.y});
+    term = zmul(term, iz2);
+  }
+  return zsub(r, acc);
+}
+
+// U_l(n) = sqrt(pi) 2^{p-1} Gamma((1+l+p)/2) / Gamma((2+l-p)/2) * taper(n),  p = b + i eta_n,
+// eta_n = 2 pi n / (N Delta), n = 0..M-1.  (eq. int_jl with the corrected denominator; the
+// k^{-1-p} factor is applied on the k side.)
+template <typename R>
+__global__ void k_u_table(C2<R>* __restrict__ U, const double* __restrict__ ell, const int* __restrict__ band,
+                          double b0, double b1, double b2, double b3, double c0, double c1, double c2, double c3,
+                          int n_ell, int M, double delta, double taper_frac) {
+  const int li = blockIdx.x;
+  const int n = blockIdx.y * blockDim.x + threadIdx.x;
+  if (li >= n_ell || n >= M) return;
+  const double l = ell[li];
+  const int bi = band[li];
+  const double bclus[4] = {b0, b1, b2, b3};
+  const double blens[4] = {c0, c1, c2, c3};
+  const double eta = 2.0 * M_PI * (double)n / (2.0 * M * delta);
+  double tap = 1.0;
+  if (taper_frac > 0.0) {
+    double x = (double)n / (double)M, x0 = 1.0 - taper_frac;
+    if (x > x0) tap = 0.5 * (1.0 + cos(M_PI * fmin((x - x0) / taper_frac, 1.0)));
+  }
+  for (int kind = 0; kind < 2; ++kind) {
+    const double b = kind == 0 ? bclus[bi] : blens[bi];
+    zd pa = {0.5 * (1.0 + l + b), 0.5 * eta};
+    zd pb = {0.5 * (2.0 + l - b), -0.5 * eta};
+    zd lg = zsub(zlgamma(pa), zlgamma(pb));
+    // 2^{p-1} = exp((p-1) ln 2)
+    lg.x += (b - 1.0) * 0.69314718055994530942;
+    lg.y += eta * 0.69314718055994530942;
+    double mag = 1.7724538509055160273 * exp(lg.x) * tap;  // sqrt(pi)
+    double sn, cs;
+    sincos(lg.y, &sn, &cs);
+    if (n == 0) sn = 0.0;
+    C2<R> v;
+    v.x = (R)(mag * cs);
+    v.y = (R)(mag * sn);
+    U[((size_t)kind * n_ell + li) * M + n] = v;
+  }
+}
+
+hipError_t launch_u_table(const plan_dev& pd, const double* d_ell, hipStream_t s) {
+  const plan_dev* p = &pd;
+  dim3 grid(p->n_ell, (p->M + 127) / 128);
+  const double* b = p->fftlog_b[0];
+  const double* c = p->fftlog_b[1];
+  if (p->precision == SWIFTCL_FP64)
+    hipLaunchKernelGGL(k_u_table<double>, grid, dim3(128), 0, s, (double2*)p->U, d_ell, p->ell_band, b[0], b[1],
+                       b[2], b[3], c[0], c[1], c[2], c[3], p->n_ell, p->M, p->delta, p->taper_frac);
+  else
+    hipLaunchKernelGGL(k_u_table<float>, grid, dim3(128), 0, s, (float2*)p->U, d_ell, p->ell_band, b[0], b[1],
+                       b[2], b[3], c[0], c[1], c[2], c[3], p->n_ell, p->M, p->delta, p->taper_frac);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Descriptor checks (host only, no device work)
+// ---------------------------------------------------------------------------------------------
+static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+static swiftcl_status check_increasing(const double* x, int n, const char* name) {
+  if (!x) { set_error(std::string(name) + " is NULL"); return SWIFTCL_E_INVALID; }
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(x[i])) { set_error(std::string(name) + " has a non-finite entry"); return SWIFTCL_E_INVALID; }
+    if (i && !(x[i] > x[i - 1])) { set_error(std::string(name) + " is not strictly increasing"); return SWIFTCL_E_INVALID; }
+  }
+  return SWIFTCL_OK;
+}
+
+static int default_edge_node(int n_chi, double delta) {
+  // centre a support of 5 e-folds (z in [0.01, 3] for LCDM) in the chi box
+  return (int)std::lround(0.5 * (n_chi - 5.0 / delta));
+}
+
+static swiftcl_status validate_desc(const swiftcl_plan_desc* d) {
+  if (!d) { set_error("descriptor is NULL"); return SWIFTCL_E_INVALID; }
+  if (!is_pow2(d->n_chi) || d->n_chi < 256 || d->n_chi > 4096) {
+    set_error("n_chi must be a power of two in [256, 4096]");
+    return is_pow2(d->n_chi) ? SWIFTCL_E_UNSUPPORTED : SWIFTCL_E_INVALID;
+  }
+  if (d->n_chi > 2048) { set_error("n_chi = 4096 is not built"); return SWIFTCL_E_UNSUPPORTED; }
+  if (d->n_k < 2 || d->n_k > d->n_chi) { set_error("need 2 <= n_k <= n_chi"); return SWIFTCL_E_INVALID; }
+  if (d->n_k % 2) { set_error("n_k must be even"); return SWIFTCL_E_UNSUPPORTED; }
+  swiftcl_status st;
+  if ((st = check_increasing(d->k, d->n_k, "k")) != SWIFTCL_OK) return st;
+  if (d->k[0] <= 0) { set_error("k must be positive"); return SWIFTCL_E_DOMAIN; }
+  const double delta = std::log(d->k[d->n_k - 1] / d->k[0]) / (d->n_k - 1);
+  for (int j = 0; j + 1 < d->n_k; ++j) {
+    const double dj = std::log(d->k[j + 1] / d->k[j]);
+    if (std::fabs(dj - delta) > 1e-9 * std::max(1.0, delta) + 1e-9 * delta) {
+      set_error("k is not log-spaced");
+      return SWIFTCL_E_DOMAIN;
+    }
+  }
+  if (d->n_ell < 1) { set_error("n_ell must be >= 1"); return SWIFTCL_E_INVALID; }
+  if ((st = check_increasing(d->ell, d->n_ell, "ell")) != SWIFTCL_OK) return st;
+  if (d->ell[0] < 2.0) { set_error("multipoles must be >= 2"); return SWIFTCL_E_DOMAIN; }
+  if (d->n_bands < 1 || d->n_bands > SWIFTCL_MAX_BANDS) { set_error("n_bands must be in 1..4"); return SWIFTCL_E_INVALID; }
+  for (int j = 1; j < d->n_bands; ++j)
+    if (!(d->band_ell_lo[j] > d->band_ell_lo[j - 1])) { set_error("band_ell_lo must increase"); return SWIFTCL_E_INVALID; }
+  if (d->band_ell_lo[0] > d->ell[0]) { set_error("band_ell_lo[0] exceeds the smallest multipole"); return SWIFTCL_E_INVALID; }
+  for (int i = 0; i < d->n_ell; ++i) {
+    int bi = 0;
+    while (bi + 1 < d->n_bands && d->ell[i] >= d->band_ell_lo[bi + 1]) ++bi;
+    for (int kind = 0; kind < 2; ++kind) {
+      const double b = d->fftlog_b[kind][bi];
+      if (!(b > -d->ell[i] - 1.0 && b < 1.0) || !std::isfinite(b)) {
+        set_error("FFTLog bias b outside (-l-1, 1) for some multipole");
+        return SWIFTCL_E_DOMAIN;
+      }
+    }
+  }
+  if (!(d->taper_frac >= 0.0 && d->taper_frac < 1.0)) { set_error("taper_frac must be in [0, 1)"); return SWIFTCL_E_INVALID; }
+  if (d->n_zg < 4 || d->n_zs < 4) { set_error("need at least 4 geometry and n(z) samples"); return SWIFTCL_E_INVALID; }
+  if ((st = check_increasing(d->z_geom, d->n_zg, "z_geom")) != SWIFTCL_OK) return st;
+  if ((st = check_increasing(d->z_nz, d->n_zs, "z_nz")) != SWIFTCL_OK) return st;
+  if (d->z_geom[0] < 0.0) { set_error("z_geom must be >= 0"); return SWIFTCL_E_DOMAIN; }
+  if (d->z_nz[0] < d->z_geom[0] || d->z_nz[d->n_zs - 1] > d->z_geom[d->n_zg - 1]) {
+    set_error("z_nz must lie inside the geometry range");
+    return SWIFTCL_E_INVALID;
+  }
+  const int m0 = d->edge_node > 0 ? d->edge_node : default_edge_node(d->n_chi, delta);
+  if (m0 < 1 || m0 > d->n_chi - 2) { set_error("edge_node outside 1..n_chi-2"); return SWIFTCL_E_INVALID; }
+  if (d->max_batch < 1 || d->max_tracers < 1 || d->max_ell < 1) { set_error("capacities must be >= 1"); return SWIFTCL_E_INVALID; }
+  if (d->max_tracers > 16) { set_error("max_tracers > 16 is not built"); return SWIFTCL_E_UNSUPPORTED; }
+  if (d->precision < 0 || d->precision > 2) { set_error("unknown precision"); return SWIFTCL_E_INVALID; }
+  return SWIFTCL_OK;
+}
+
+// Thomas factors of the natural cubic spline system on grid x (interior rows 1..n-2).
+static void spline_lu(const double* x, int n, std::vector<double>& out) {
+  out.assign(3 * (size_t)n, 0.0);
+  double* a = out.data();
+  double* inv = a + n;
+  double* cp = a + 2 * n;
+  for (int i = 1; i < n - 1; ++i) {
+    const double h0 = x[i] - x[i - 1], h1 = x[i + 1] - x[i];
+    const double ai = h0 / 6.0, bi = (h0 + h1) / 3.0, ci = h1 / 6.0;
+    const double den = (i == 1) ? bi : bi - ai * cp[i - 1];
+    a[i] = ai;
+    inv[i] = 1.0 / den;
+    cp[i] = ci / den;
+  }
+}
+
+template <typename T> static swiftcl_status dalloc(T** ptr, size_t count, const char* what) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    set_error(std::string("hipMalloc failed for ") + what);
+    return SWIFTCL_E_NOMEM;
+  }
+  return SWIFTCL_OK;
+}
+
+static void free_plan(swiftcl_plan_s* p) {
+  if (!p) return;
+  void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
+                  p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_suf, p->d.g,
+                  p->d.chat, p->d.sqrt_s, p->d.flags, p->d.dchat, p->d.dg};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream, swiftcl_plan_t* out) {
+  if (!out) { set_error("out is NULL"); return SWIFTCL_E_INVALID; }
+  *out = nullptr;
+  swiftcl_status st = validate_desc(d);
+  if (st != SWIFTCL_OK) return st;
+  if ((st = hip_check(hipSetDevice(d->device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+
+  swiftcl_plan_s* p = new (std::nothrow) swiftcl_plan_s();
+  if (!p) { set_error("host allocation failed"); return SWIFTCL_E_NOMEM; }
+  p->d.device = d->device;
+  p->d.precision = d->precision;
+  p->d.N = d->n_chi;
+  p->d.M = d->n_chi / 2;
+  p->d.n_k = d->n_k;
+  p->d.n_ell = d->n_ell;
+  p->d.n_zg = d->n_zg;
+  p->d.n_zs = d->n_zs;
+  p->d.n_bands = d->n_bands;
+  p->d.max_batch = d->max_batch;
+  p->d.max_tracers = d->max_tracers;
+  p->d.max_ell = d->max_ell;
+  p->d.delta = std::log(d->k[d->n_k - 1] / d->k[0]) / (d->n_k - 1);
+  p->d.k0 = d->k[0];
+  p->d.taper_frac = d->taper_frac;
+  p->d.m0 = d->edge_node > 0 ? d->edge_node : default_edge_node(d->n_chi, p->d.delta);
+  for (int j = 0; j < SWIFTCL_MAX_BANDS; ++j) {
+    p->d.band_ell_lo[j] = j < d->n_bands ? d->band_ell_lo[j] : 1e300;
+    p->d.fftlog_b[0][j] = j < d->n_bands ? d->fftlog_b[0][j] : 0.0;
+    p->d.fftlog_b[1][j] = j < d->n_bands ? d->fftlog_b[1][j] : 0.0;
+  }
+  p->ell_host.assign(d->ell, d->ell + d->n_ell);
+  p->real_size = d->precision == SWIFTCL_FP64 ? 8 : 4;
+  const size_t rs = p->real_size;
+  const int N = p->d.N, M = p->d.M, nk = p->d.n_k, T = p->d.max_tracers, B = p->d.max_batch, nb = p->d.n_bands;
+
+  // --- host tables ---
+  std::vector<int> band(p->d.n_ell);
+  std::vector<double> fell(p->d.n_ell);
+  for (int i = 0; i < p->d.n_ell; ++i) {
+    int bi = 0;
+    while (bi + 1 < nb && d->ell[i] >= d->band_ell_lo[bi + 1]) ++bi;
+    band[i] = bi;
+    const double l = d->ell[i];
+    fell[i] = std::sqrt((l + 2.0) * (l + 1.0) * l * (l - 1.0));
+  }
+  std::vector<double> kscale((size_t)2 * nb * nk), kw(nk);
+  for (int kind = 0; kind < 2; ++kind)
+    for (int bi = 0; bi < nb; ++bi)
+      for (int j = 0; j < nk; ++j) {
+        const double lk = std::log(d->k[0]) + j * p->d.delta;  // the grid node k_0 e^{j Delta}
+        double v = std::exp((-1.0 - p->d.fftlog_b[kind][bi]) * lk);
+        if (kind == 1) v *= std::exp(-2.0 * lk);
+        kscale[((size_t)kind * nb + bi) * nk + j] = v;
+      }
+  for (int j = 0; j < nk; ++j) {
+    const double w = (j == 0 || j == nk - 1) ? 0.5 * p->d.delta : p->d.delta;
+    kw[j] = (2.0 / M_PI) * w * d->k[j] * d->k[j] * d->k[j];
+  }
+  std::vector<double> twd(2 * (size_t)N);
+  for (int m = 0; m < N; ++m) {
+    twd[2 * m] = std::cos(2.0 * M_PI * m / N);
+    twd[2 * m + 1] = -std::sin(2.0 * M_PI * m / N);
+  }
+  std::vector<double> lug, lun;
+  spline_lu(d->z_geom, d->n_zg, lug);
+  spline_lu(d->z_nz, d->n_zs, lun);
+  // knots of the lensing quadrature: union of both grids inside the geometry range
+  std::set<double> us(d->z_geom, d->z_geom + d->n_zg);
+  for (int i = 0; i < d->n_zs; ++i) us.insert(d->z_nz[i]);
+  std::vector<double> zu(us.begin(), us.end());
+  p->d.n_union = (int)zu.size() - 1;
+  std::vector<int> uiv(2 * (size_t)p->d.n_union);
+  for (int u = 0; u < p->d.n_union; ++u) {
+    const double mid = 0.5 * (zu[u] + zu[u + 1]);
+    int ig = (int)(std::upper_bound(d->z_geom, d->z_geom + d->n_zg, mid) - d->z_geom) - 1;
+    ig = std::min(std::max(ig, 0), d->n_zg - 2);
+    int in = (int)(std::upper_bound(d->z_nz, d->z_nz + d->n_zs, mid) - d->z_nz) - 1;
+    if (mid < d->z_nz[0] || mid > d->z_nz[d->n_zs - 1]) in = -1;
+    else in = std::min(std::max(in, 0), d->n_zs - 2);
+    uiv[u] = ig;
+    uiv[p->d.n_union + u] = in;
+  }
+
+  // --- device allocations ---
+#define ALLOC(ptr, type, count)                                             \
+  do {                                                                      \
+    type* tmp_ = nullptr;                                                   \
+    if ((st = dalloc<type>(&tmp_, (count), #ptr)) != SWIFTCL_OK) {          \
+      free_plan(p);                                                         \
+      return st;                                                            \
+    }                                                                       \
+    p->d.ptr = (decltype(p->d.ptr))tmp_;                                        \
+  } while (0)
+  ALLOC(U, char, (size_t)2 * p->d.n_ell * M * 2 * rs);
+  ALLOC(kscale, char, kscale.size() * rs);
+  ALLOC(tw, char, (size_t)N * 2 * rs);
+  ALLOC(fell, double, p->d.n_ell);
+  ALLOC(ell_band, int, p->d.n_ell);
+  ALLOC(kw, double, nk);
+  ALLOC(z_geom, double, p->d.n_zg);
+  ALLOC(z_nz, double, p->d.n_zs);
+  ALLOC(lu_geom, double, lug.size());
+  ALLOC(lu_nz, double, lun.size());
+  ALLOC(z_union, double, zu.size());
+  ALLOC(union_iv, int, uiv.size());
+  ALLOC(pt, double, (size_t)B * PT_STRIDE);
+  ALLOC(m_chi, double, (size_t)B * p->d.n_zg);
+  ALLOC(m_D, double, (size_t)B * p->d.n_zg);
+  ALLOC(m_n, double, (size_t)B * T * p->d.n_zs);
+  ALLOC(lens_suf, double, (size_t)B * T * 2 * (p->d.n_union + 1));
+  ALLOC(g, char, (size_t)B * T * nb * N * rs);
+  ALLOC(chat, char, (size_t)B * T * nb * M * 2 * rs);
+  ALLOC(sqrt_s, char, (size_t)B * nk * rs);
+  ALLOC(flags, int, 1);
+  ALLOC(dchat, char, (size_t)B * T * nb * M * 2 * rs);
+  ALLOC(dg, char, (size_t)B * T * nb * N * rs);
+#undef ALLOC
+
+  // --- uploads (host tables converted to the FFT precision) ---
+  auto to_real = [&](const std::vector<double>& v) {
+    std::vector<char> buf(v.size() * rs);
+    if (rs == 8) std::memcpy(buf.data(), v.data(), buf.size());
+    else for (size_t i = 0; i < v.size(); ++i) ((float*)buf.data())[i] = (float)v[i];
+    return buf;
+  };
+  std::vector<char> kscale_r = to_real(kscale), tw_r = to_real(twd);
+  double* d_ell = nullptr;
+  hipError_t e = hipMalloc((void**)&d_ell, sizeof(double) * p->d.n_ell);
+  if (e != hipSuccess) { free_plan(p); set_error("hipMalloc failed for ell"); return SWIFTCL_E_NOMEM; }
+  struct Up { void* dst; const void* src; size_t n; } ups[] = {
+      {p->d.kscale, kscale_r.data(), kscale_r.size()},
+      {p->d.tw, tw_r.data(), tw_r.size()},
+      {p->d.fell, fell.data(), fell.size() * sizeof(double)},
+      {p->d.ell_band, band.data(), band.size() * sizeof(int)},
+      {p->d.kw, kw.data(), kw.size() * sizeof(double)},
+      {p->d.z_geom, d->z_geom, (size_t)p->d.n_zg * sizeof(double)},
+      {p->d.z_nz, d->z_nz, (size_t)p->d.n_zs * sizeof(double)},
+      {p->d.lu_geom, lug.data(), lug.size() * sizeof(double)},
+      {p->d.lu_nz, lun.data(), lun.size() * sizeof(double)},
+      {p->d.z_union, zu.data(), zu.size() * sizeof(double)},
+      {p->d.union_iv, uiv.data(), uiv.size() * sizeof(int)},
+      {d_ell, d->ell, (size_t)p->d.n_ell * sizeof(double)},
+  };
+  for (auto& u : ups) {
+    e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) break;
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(p->d.flags, 0, sizeof(int), s);
+  if (e == hipSuccess) e = launch_u_table(p->d, d_ell, s);
+  // the host vectors above die at return: finish the copies before handing the plan out
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_ell);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return hip_check(e, "plan set-up");
+  }
+  *out = p;
+  return SWIFTCL_OK;
+}
+
+extern "C" swiftcl_status swiftcl_plan_destroy(swiftcl_plan_t p) {
+  if (!p) { set_error("plan is NULL"); return SWIFTCL_E_INVALID; }
+  free_plan(p);
+  return SWIFTCL_OK;
+}
+
+extern "C" swiftcl_status swiftcl_device_flags(swiftcl_plan_t p, void* stream, int32_t* flags) {
+  if (!p || !flags) { set_error("NULL argument"); return SWIFTCL_E_INVALID; }
+  hipStream_t s = (hipStream_t)stream;
+  int v = 0;
+  hipError_t e = hipMemcpyAsync(&v, p->d.flags, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemsetAsync(p->d.flags, 0, sizeof(int), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_check(e, "device flags");
+  *flags = v;
+  return SWIFTCL_OK;
+}
+
+static swiftcl_status check_inputs(swiftcl_plan_t p, const swiftcl_inputs* in) {
+  if (!p) { set_error("plan is NULL"); return SWIFTCL_E_INVALID; }
+  if (!in) { set_error("inputs is NULL"); return SWIFTCL_E_INVALID; }
+  if (in->batch < 1 || in->batch > p->d.max_batch) { set_error("batch outside 1..max_batch"); return SWIFTCL_E_INVALID; }
+  const void* req[] = {in->n_tracers, in->kind, in->n_ell, in->ell_idx, in->chi_z, in->D_z,
+                       in->omega_m, in->nz, in->bias, in->pk};
+  for (const void* q : req)
+    if (!q) { set_error("a required input pointer is NULL"); return SWIFTCL_E_INVALID; }
+  return SWIFTCL_OK;
+}
+
+static swiftcl_status run_forward(swiftcl_plan_t p, const swiftcl_inputs* in, void* W, void* C, void* stream) {
+  swiftcl_status st = check_inputs(p, in);
+  if (st != SWIFTCL_OK) return st;
+  if (!W && !C) { set_error("output is NULL"); return SWIFTCL_E_INVALID; }
+  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_assemble(p->d, in, s);
+  if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+  if (e == hipSuccess) e = launch_windows_cl(p->d, in, W, C, s);
+  return hip_check(e, "forward launch");
+}
+
+extern "C" swiftcl_status swiftcl_windows(swiftcl_plan_t p, const swiftcl_inputs* in, void* W, void* stream) {
+  if (!W) { set_error("W is NULL"); return SWIFTCL_E_INVALID; }
+  return run_forward(p, in, W, nullptr, stream);
+}
+
+extern "C" swiftcl_status swiftcl_cl(swiftcl_plan_t p, const swiftcl_inputs* in, void* C, void* stream) {
+  if (!C) { set_error("C is NULL"); return SWIFTCL_E_INVALID; }
+  return run_forward(p, in, nullptr, C, stream);
+}
+
+extern "C" swiftcl_status swiftcl_cl_timed(swiftcl_plan_t p, const swiftcl_inputs* in, void* C, void* stream,
+                                           float* stage_ms) {
+  swiftcl_status st = check_inputs(p, in);
+  if (st != SWIFTCL_OK) return st;
+  if (!C || !stage_ms) { set_error("C or stage_ms is NULL"); return SWIFTCL_E_INVALID; }
+  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+  if (e == hipSuccess) e = launch_assemble(p->d, in, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+  if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+  if (e == hipSuccess) e = launch_windows_cl(p->d, in, nullptr, C, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[3], s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventElapsedTime(&stage_ms[i], ev[i], ev[i + 1]);
+  for (int i = 0; i < 4; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  return hip_check(e, "timed forward");
+}
+
+extern "C" swiftcl_status swiftcl_cl_backward(swiftcl_plan_t p, const swiftcl_inputs* in, const void* dC,
+                                              double* dpk, double* dbias, double* dnz, double* dD, void* stream) {
+  swiftcl_status st = check_inputs(p, in);
+  if (st != SWIFTCL_OK) return st;
+  if (!dC) { set_error("dC is NULL"); return SWIFTCL_E_INVALID; }
+  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_assemble(p->d, in, s);
+  if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+  if (e == hipSuccess) e = launch_backward(p->d, in, dC, dpk, dbias, dnz, dD, s);
+  return hip_check(e, "backward launch");
+}

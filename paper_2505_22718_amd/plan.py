@@ -1,0 +1,152 @@
+"""Torch-facing plan: device buffers and streams around the C entry points.
+
+Every computation happens in libswiftcl.so; this module only builds the descriptor, hands
+over device pointers and the current HIP stream, and allocates outputs.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import binding as bd
+
+# Default FFTLog bias bands of the library: bands start at l = 0, 3 and 6; per band the bias b
+# (paper Sec. 3.1) of clustering and of lensing tracers.
+DEFAULT_BAND_ELL_LO = (0.0, 3.0, 6.0)
+DEFAULT_FFTLOG_B = ((0.1, -0.2, -0.5), (-1.5, -2.0, -2.5))
+
+PRECISIONS = {"fp64": bd.SWIFTCL_FP64, "fp32": bd.SWIFTCL_FP32, "split_bf16": bd.SWIFTCL_SPLIT_BF16}
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Plan:
+    """Owns one swiftcl plan on one device."""
+
+    def __init__(self, k, ell, z_geom, z_nz, n_chi, max_batch, max_tracers, max_ell, precision="fp32",
+                 band_ell_lo=DEFAULT_BAND_ELL_LO, fftlog_b=DEFAULT_FFTLOG_B, taper_frac=0.0, edge_node=0,
+                 device=0):
+        self.k = _f64(k)
+        self.ell = _f64(ell)
+        self.z_geom = _f64(z_geom)
+        self.z_nz = _f64(z_nz)
+        self.n_chi = int(n_chi)
+        self.max_batch, self.max_tracers, self.max_ell = int(max_batch), int(max_tracers), int(max_ell)
+        self.precision = precision
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        d = bd.swiftcl_plan_desc()
+        d.n_chi = self.n_chi
+        d.edge_node = int(edge_node)
+        d.n_bands = len(band_ell_lo)
+        for j, v in enumerate(band_ell_lo):
+            d.band_ell_lo[j] = float(v)
+        for kind in (0, 1):
+            for j, v in enumerate(fftlog_b[kind]):
+                d.fftlog_b[kind][j] = float(v)
+        d.taper_frac = float(taper_frac)
+        dp = ctypes.POINTER(ctypes.c_double)
+        d.n_k, d.k = len(self.k), self.k.ctypes.data_as(dp)
+        d.n_ell, d.ell = len(self.ell), self.ell.ctypes.data_as(dp)
+        d.n_zg, d.z_geom = len(self.z_geom), self.z_geom.ctypes.data_as(dp)
+        d.n_zs, d.z_nz = len(self.z_nz), self.z_nz.ctypes.data_as(dp)
+        d.max_batch, d.max_tracers, d.max_ell = self.max_batch, self.max_tracers, self.max_ell
+        d.precision = PRECISIONS[precision]
+        d.device = self.device.index or 0
+        self.desc = d
+        self.out_dtype = torch.float64 if precision == "fp64" else torch.float32
+        with torch.cuda.device(self.device):
+            self.handle = bd.swiftcl_plan(d, torch.cuda.current_stream(self.device).cuda_stream)
+
+    @classmethod
+    def for_workload(cls, wl, max_batch=None, precision=None, **kw):
+        return cls(wl["k"], wl["ell"], wl["z_geom"], wl["z_nz"], wl["n_chi"],
+                   max_batch or wl["batch"], wl["nz"].shape[1], wl["ell_idx"].shape[1],
+                   precision=precision or ("fp32" if wl["precision"] == "split_bf16" else wl["precision"]), **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            bd.swiftcl_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_pairs(self):
+        return self.max_tracers * (self.max_tracers + 1) // 2
+
+    def _stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    @staticmethod
+    def inputs_struct(t):
+        s = bd.swiftcl_inputs()
+        s.batch = int(t["n_tracers"].shape[0])
+        for name in ("n_tracers", "kind", "n_ell", "ell_idx", "chi_z", "D_z", "omega_m", "nz", "bias", "pk"):
+            setattr(s, name, t[name].data_ptr())
+        return s
+
+    def cl(self, t, out=None):
+        B = t["n_tracers"].shape[0]
+        if out is None:
+            out = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
+        bd.swiftcl_cl(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
+        return out
+
+    def cl_timed(self, t, out):
+        """Forward C_l with per-stage device times (ms): assembly, FFTLog coefficients, windows + C."""
+        return bd.swiftcl_cl_timed(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
+
+    def windows(self, t, out=None):
+        B = t["n_tracers"].shape[0]
+        if out is None:
+            out = torch.empty((B, self.max_ell, self.max_tracers, len(self.k)), dtype=self.out_dtype,
+                              device=self.device)
+        bd.swiftcl_windows(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
+        return out
+
+    def backward(self, t, dC, want=("pk", "bias", "nz", "D")):
+        B = t["n_tracers"].shape[0]
+        f64 = dict(dtype=torch.float64, device=self.device)
+        outs = {
+            "pk": torch.empty((B, len(self.k)), **f64) if "pk" in want else None,
+            "bias": torch.empty((B, self.max_tracers), **f64) if "bias" in want else None,
+            "nz": torch.empty((B, self.max_tracers, len(self.z_nz)), **f64) if "nz" in want else None,
+            "D": torch.empty((B, len(self.z_geom)), **f64) if "D" in want else None,
+        }
+        ptr = {k: (v.data_ptr() if v is not None else 0) for k, v in outs.items()}
+        bd.swiftcl_cl_backward(self.handle, self.inputs_struct(t), dC.contiguous().data_ptr(), ptr["pk"],
+                               ptr["bias"], ptr["nz"], ptr["D"], self._stream())
+        return {k: v for k, v in outs.items() if v is not None}
+
+    def device_flags(self):
+        return bd.swiftcl_device_flags(self.handle, self._stream())
+
+
+def device_inputs(wl, device="cuda:0", points=None):
+    """Device tensors of a synthetic workload (optionally a subset of its points)."""
+    sel = slice(None) if points is None else np.asarray(points)
+    dev = torch.device(device)
+
+    def f(x, dt):
+        return torch.as_tensor(np.ascontiguousarray(np.asarray(x)[sel]), dtype=dt).to(dev)
+
+    return {
+        "n_tracers": f(wl["n_tracers"], torch.int32),
+        "kind": f(wl["kind"], torch.int32),
+        "n_ell": f(wl["n_ell"], torch.int32),
+        "ell_idx": f(wl["ell_idx"], torch.int32),
+        "chi_z": f(wl["chi_z"], torch.float64),
+        "D_z": f(wl["D_z"], torch.float64),
+        "omega_m": f(wl["omega_m"], torch.float64),
+        "nz": f(wl["nz"], torch.float64),
+        "bias": f(wl["bias"], torch.float64),
+        "pk": f(wl["pk"], torch.float64),
+    }

@@ -1,0 +1,104 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared symbol, and
+descriptor validation rejects bad plans before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2505_22718_amd import binding
+    return binding.load()
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:swiftcl_status|const char\*)\s+(swiftcl_\w+)\s*\(", text, re.M))
+    return names
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert {"swiftcl_plan", "swiftcl_windows", "swiftcl_cl", "swiftcl_cl_backward"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _desc(**over):
+    from paper_2505_22718_amd import binding as bd
+    import synth
+    k = np.geomspace(1e-4, 10, 256)
+    ell = np.geomspace(2, 200, 20)
+    zg = np.linspace(0.01, 3, 1024)
+    zs = np.linspace(0.01, 3, 200)
+    arrays = dict(k=k, ell=ell, z_geom=zg, z_nz=zs)
+    arrays.update({a: over.pop(a) for a in list(over) if a in arrays})
+    keep = {a: np.ascontiguousarray(v, dtype=np.float64) for a, v in arrays.items()}
+    d = bd.swiftcl_plan_desc()
+    d.n_chi = 512
+    d.n_bands = 3
+    for j, v in enumerate((0.0, 3.0, 6.0)):
+        d.band_ell_lo[j] = v
+    for kind, row in enumerate(((0.1, -0.2, -0.5), (-1.5, -2.0, -2.5))):
+        for j, v in enumerate(row):
+            d.fftlog_b[kind][j] = v
+    dp = ctypes.POINTER(ctypes.c_double)
+    d.n_k, d.k = len(keep["k"]), keep["k"].ctypes.data_as(dp)
+    d.n_ell, d.ell = len(keep["ell"]), keep["ell"].ctypes.data_as(dp)
+    d.n_zg, d.z_geom = len(keep["z_geom"]), keep["z_geom"].ctypes.data_as(dp)
+    d.n_zs, d.z_nz = len(keep["z_nz"]), keep["z_nz"].ctypes.data_as(dp)
+    d.max_batch, d.max_tracers, d.max_ell, d.precision, d.device = 1, 2, 20, 0, 0
+    for key, v in over.items():
+        if key == "fftlog_b00":
+            d.fftlog_b[0][0] = v
+        else:
+            setattr(d, key, v)
+    return d, keep
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(n_chi=500), -1),                                   # not a power of two
+    (dict(n_chi=8192), -5),                                  # a power of two that is not built
+    (dict(n_chi=4096, n_k=256), -5),                         # 4096 not built
+    (dict(k=np.linspace(1e-4, 10, 256)), -2),                # k not log-spaced
+    (dict(k=np.geomspace(1e-4, 10, 1024)), -1),              # n_k > n_chi
+    (dict(ell=np.geomspace(1.5, 200, 20)), -2),              # l < 2
+    (dict(ell=np.array([2.0, 5.0, 4.0])), -1),               # not increasing
+    (dict(fftlog_b00=1.2), -2),                              # b >= 1 outside eq. int_jl range
+    (dict(n_bands=0), -1),
+    (dict(taper_frac=1.0), -1),
+    (dict(max_tracers=17), -5),
+    (dict(max_batch=0), -1),
+    (dict(precision=7), -1),
+    (dict(edge_node=600), -1),
+    (dict(z_nz=np.linspace(0.0, 3, 200)), -1),               # n(z) grid outside the geometry range
+    (dict(k=np.array([1e-4] + [np.nan] * 255)), -1),
+])
+def test_plan_rejects_bad_descriptor(lib, over, code):
+    d, keep = _desc(**over)
+    h = ctypes.c_void_p()
+    st = lib.swiftcl_plan(ctypes.byref(d), None, ctypes.byref(h))
+    assert st == code, lib.swiftcl_last_error()
+    assert h.value is None
+    assert len(lib.swiftcl_last_error()) > 0
+
+
+def test_null_arguments_rejected(lib):
+    from paper_2505_22718_amd import binding as bd
+    h = ctypes.c_void_p()
+    assert lib.swiftcl_plan(None, None, ctypes.byref(h)) == bd.SWIFTCL_E_INVALID
+    d, keep = _desc()
+    assert lib.swiftcl_plan(ctypes.byref(d), None, None) == bd.SWIFTCL_E_INVALID
+    inp = bd.swiftcl_inputs()
+    assert lib.swiftcl_cl(None, ctypes.byref(inp), None, None) == bd.SWIFTCL_E_INVALID
+    assert lib.swiftcl_windows(None, ctypes.byref(inp), None, None) == bd.SWIFTCL_E_INVALID
+    assert lib.swiftcl_cl_backward(None, ctypes.byref(inp), None, None, None, None, None, None) == bd.SWIFTCL_E_INVALID
+    assert lib.swiftcl_plan_destroy(None) == bd.SWIFTCL_E_INVALID
