@@ -94,17 +94,25 @@ template <> struct fft_plan<512> { static constexpr int RL = 8, NP = 3; static c
 template <> struct fft_plan<1024> { static constexpr int RL = 16, NP = 3; static constexpr int rad[3] = {16, 8, 8}; };
 template <> struct fft_plan<2048> { static constexpr int RL = 32, NP = 3; static constexpr int rad[3] = {16, 16, 8}; };
 
+// LDS scratch layout of the wave FFT: one padding element every 8 complex values, so the
+// strided writes of the Stockham passes spread over all banks.  A wavefront's scratch holds
+// fft_lds_size(M) complex values.
+__host__ __device__ constexpr int fft_pad(int c) { return c + (c >> 3); }
+__host__ __device__ constexpr int fft_lds_size(int M) { return M + M / 8; }
+
 // One Stockham pass (self-sorting, natural-order output) of radix r on an M-point sequence.
 // Butterfly q (q = lane + 64 u) reads x[q + i M/r], applies twiddles e^{S 2 pi i i j / (Ls r)}
 // with j = q mod Ls, runs dft<r> and writes Y_i to (q / Ls) Ls r + j + i Ls.
-// tw is the table e^{-2 pi i m / N}, m < N (N = 2M for the real transforms).
-template <typename R, int M, int r, int S, bool FIRST, bool LAST>
-__device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw,
-                                              int N, int Ls, int lane) {
+// tw is the table e^{-2 pi i m / N}, m < N, N = 2M (global memory or LDS).
+template <typename R, int M, int r, int Ls, int S, bool FIRST, bool LAST>
+__device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
   constexpr int RL = M / SWIFTCL_WAVE;
   constexpr int BPL = RL / r;
+  constexpr int N = 2 * M;
+  constexpr int L = Ls * r;
+  constexpr int step = N / L;
   C2<R> b[RL];
-  if (FIRST) {
+  if constexpr (FIRST) {
     // registers hold x[lane + 64 e]; butterfly u input i is e = u + i * BPL
 #pragma unroll
     for (int u = 0; u < BPL; ++u)
@@ -115,25 +123,25 @@ __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>*
     for (int u = 0; u < BPL; ++u) {
       const int q = lane + SWIFTCL_WAVE * u;
 #pragma unroll
-      for (int i = 0; i < r; ++i) b[u * r + i] = lds[q + i * (M / r)];
+      for (int i = 0; i < r; ++i) b[u * r + i] = lds[fft_pad(q + i * (M / r))];
     }
     wave_sync();
   }
-  const int L = Ls * r;
-  const int step = N / L;
 #pragma unroll
   for (int u = 0; u < BPL; ++u) {
-    const int q = lane + SWIFTCL_WAVE * u;
-    const int j = q % Ls;
+    if constexpr (Ls > 1) {
+      const int q = lane + SWIFTCL_WAVE * u;
+      const int j = q & (Ls - 1);
 #pragma unroll
-    for (int i = 1; i < r; ++i) {
-      C2<R> w = tw[(i * j * step) & (N - 1)];
-      if (S > 0) w = cconj(w);
-      b[u * r + i] = cmul(b[u * r + i], w);
+      for (int i = 1; i < r; ++i) {
+        C2<R> w = tw[(i * j * step) & (N - 1)];
+        if (S > 0) w = cconj(w);
+        b[u * r + i] = cmul(b[u * r + i], w);
+      }
     }
     dft<R, r, S>(&b[u * r]);
   }
-  if (LAST) {
+  if constexpr (LAST) {
 #pragma unroll
     for (int u = 0; u < BPL; ++u)
 #pragma unroll
@@ -142,37 +150,42 @@ __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>*
 #pragma unroll
     for (int u = 0; u < BPL; ++u) {
       const int q = lane + SWIFTCL_WAVE * u;
-      const int j = q % Ls;
+      const int j = q & (Ls - 1);
       const int base = (q / Ls) * L + j;
 #pragma unroll
-      for (int i = 0; i < r; ++i) lds[base + i * Ls] = b[u * r + i];
+      for (int i = 0; i < r; ++i) lds[fft_pad(base + i * Ls)] = b[u * r + i];
     }
     wave_sync();
   }
 }
 
 // M-point complex FFT by one wavefront.  In and out: v[e] holds element lane + 64 e (natural
-// order).  lds: M complex of scratch private to this wavefront.  S = -1 forward, +1 inverse
-// (unnormalised).
+// order).  lds: fft_lds_size(M) complex of scratch private to this wavefront.  S = -1 forward, +1 inverse
+// (unnormalised).  The twiddle table has N = 2M entries.
 template <typename R, int M, int S>
-__device__ __forceinline__ void wave_fft(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int N, int lane) {
+__device__ __forceinline__ void wave_fft(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
   using P = fft_plan<M>;
   if constexpr (P::NP == 3) {
-    stockham_pass<R, M, P::rad[0], S, true, false>(v, lds, tw, N, 1, lane);
-    stockham_pass<R, M, P::rad[1], S, false, false>(v, lds, tw, N, P::rad[0], lane);
-    stockham_pass<R, M, P::rad[2], S, false, true>(v, lds, tw, N, P::rad[0] * P::rad[1], lane);
+    constexpr int r0 = P::rad[0], r1 = P::rad[1], r2 = P::rad[2];
+    stockham_pass<R, M, r0, 1, S, true, false>(v, lds, tw, lane);
+    stockham_pass<R, M, r1, r0, S, false, false>(v, lds, tw, lane);
+    stockham_pass<R, M, r2, r0 * r1, S, false, true>(v, lds, tw, lane);
   } else if constexpr (P::NP == 4) {
-    stockham_pass<R, M, P::rad[0], S, true, false>(v, lds, tw, N, 1, lane);
-    stockham_pass<R, M, P::rad[1], S, false, false>(v, lds, tw, N, 4, lane);
-    stockham_pass<R, M, P::rad[2], S, false, false>(v, lds, tw, N, 16, lane);
-    stockham_pass<R, M, P::rad[3], S, false, true>(v, lds, tw, N, 64, lane);
+    stockham_pass<R, M, 4, 1, S, true, false>(v, lds, tw, lane);
+    stockham_pass<R, M, 4, 4, S, false, false>(v, lds, tw, lane);
+    stockham_pass<R, M, 4, 16, S, false, false>(v, lds, tw, lane);
+    stockham_pass<R, M, 4, 64, S, false, true>(v, lds, tw, lane);
   } else {
-    stockham_pass<R, M, 2, S, true, false>(v, lds, tw, N, 1, lane);
-    stockham_pass<R, M, 2, S, false, false>(v, lds, tw, N, 2, lane);
-    stockham_pass<R, M, 2, S, false, false>(v, lds, tw, N, 4, lane);
-    stockham_pass<R, M, 2, S, false, false>(v, lds, tw, N, 8, lane);
-    stockham_pass<R, M, 2, S, false, false>(v, lds, tw, N, 16, lane);
-    stockham_pass<R, M, 2, S, false, false>(v, lds, tw, N, 32, lane);
-    stockham_pass<R, M, 2, S, false, true>(v, lds, tw, N, 64, lane);
+    stockham_pass<R, M, 2, 1, S, true, false>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 2, S, false, false>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 4, S, false, false>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 8, S, false, false>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 16, S, false, false>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 32, S, false, false>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 64, S, false, true>(v, lds, tw, lane);
   }
 }
+
+// Number of XCDs (each with its own L2) on MI355X; workgroups are dispatched round-robin over
+// them, so blockIdx % 8 names the XCD.
+#define SWIFTCL_NXCD 8

@@ -50,7 +50,7 @@ __global__ void k_sqrt_s(plan_dev P, swiftcl_inputs in) {
 // FFTLog coefficients: one wavefront per (point, tracer, band) row.
 template <typename R, int M>
 __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs in) {
-  __shared__ C2<R> lds[4][M];
+  __shared__ C2<R> lds[4][fft_lds_size(M)];
   constexpr int RL = M / SWIFTCL_WAVE;
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, nb = P.n_bands, N = P.N;
@@ -72,9 +72,9 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
   C2<R> v[RL];
 #pragma unroll
   for (int e = 0; e < RL; ++e) v[e] = g2[lane + SWIFTCL_WAVE * e];
-  wave_fft<R, M, -1>(v, lds[wave], tw, N, lane);
+  wave_fft<R, M, -1>(v, lds[wave], tw, lane);
 #pragma unroll
-  for (int e = 0; e < RL; ++e) lds[wave][lane + SWIFTCL_WAVE * e] = v[e];
+  for (int e = 0; e < RL; ++e) lds[wave][fft_pad(lane + SWIFTCL_WAVE * e)] = v[e];
   wave_sync();
   const double* pt = P.pt + (size_t)b * PT_STRIDE;
   const int kind = in.kind[(size_t)b * T + t] & 1;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
     if (n == 0) {
       X = mk<R>(Zn.x + Zn.y, (R)0);
     } else {
-      const C2<R> Zm = cconj(lds[wave][M - n]);
+      const C2<R> Zm = cconj(lds[wave][fft_pad(M - n)]);
       const C2<R> A = cscale(cadd(Zn, Zm), (R)0.5);
       const C2<R> Bd = cscale(csub(Zn, Zm), (R)0.5);
       const C2<R> t2 = cmul(tw[n], Bd);
@@ -101,17 +101,26 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
   }
 }
 
-// Windows and / or C_l for one (point, multipole) per workgroup of NW wavefronts.
-template <typename R, int M, int NW, bool WRITE_W, bool DO_CL>
+// Windows and / or C_l for one (point, multipole) per workgroup of NW wavefronts.  Blocks are
+// mapped so that all multipoles of one point run on one XCD (its FFTLog coefficients stay in
+// that XCD's L2): block = ((b / 8) * Lm + l) * 8 + b % 8.
+template <typename R, int M, int NW, bool TW_LDS, bool WRITE_W, bool DO_CL>
 __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inputs in, R* __restrict__ Wout,
                                                         R* __restrict__ Cout) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int RL = M / SWIFTCL_WAVE;
-  C2<R>* fbuf = (C2<R>*)smem;                                  // [NW][M]
-  R* V = (R*)(smem + (size_t)NW * M * sizeof(C2<R>));          // [n_k][16]
+  constexpr int N = 2 * M;
+  constexpr int FL = fft_lds_size(M);
+  constexpr int NTW = TW_LDS ? N : 0;
+  C2<R>* stw_l = (C2<R>*)smem;                                        // [N] twiddles (TW_LDS)
+  C2<R>* fbuf = stw_l + NTW;                                          // [NW][FL]
+  R* V = (R*)(smem + ((size_t)NTW + (size_t)NW * FL) * sizeof(C2<R>));  // [16][n_k + 2]
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
-  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands, N = P.N;
-  const int b = blockIdx.x / Lm, li = blockIdx.x % Lm;
+  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
+  const int xcd = blockIdx.x % SWIFTCL_NXCD;
+  const int rest = blockIdx.x / SWIFTCL_NXCD;
+  const int li = rest % Lm;
+  const int b = (rest / Lm) * SWIFTCL_NXCD + xcd;
   if (b >= in.batch) return;
   const int Tb = clampi(in.n_tracers[b], 0, T);
   const int Lb = clampi(in.n_ell[b], 0, Lm);
@@ -132,16 +141,22 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
     if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
     ei = 0;
   }
+  const C2<R>* stw = TW_LDS ? stw_l : (const C2<R>*)P.tw;
+  if constexpr (TW_LDS) {
+    const C2<R>* gtw = (const C2<R>*)P.tw;
+    for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
+    __syncthreads();
+  }
+  const int vs = nk + 2;  // row stride of V: rows start on distinct banks
   const int band = P.ell_band[ei];
   const R Fl = (R)P.fell[ei];
   const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
-  const C2<R>* tw = (const C2<R>*)P.tw;
-  C2<R>* mine = fbuf + (size_t)wave * M;
+  C2<R>* mine = fbuf + (size_t)wave * FL;
   const int trows = DO_CL ? 16 : T;
   for (int t = wave; t < trows; t += NW) {
     if (t >= Tb) {
       for (int j = lane; j < nk; j += SWIFTCL_WAVE) {
-        if (DO_CL) V[j * 16 + t] = (R)0;
+        if (DO_CL) V[t * vs + j] = (R)0;
         if (WRITE_W && t < T) Wout[(((size_t)b * Lm + li) * T + t) * nk + j] = (R)0;
       }
       continue;
@@ -155,7 +170,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
     for (int e = 0; e < RL; ++e) {
       const int n = lane + SWIFTCL_WAVE * e;
       d[e] = cmul(ch[n], Ur[n]);
-      mine[n] = d[e];
+      mine[fft_pad(n)] = d[e];
     }
     wave_sync();
     C2<R> v[RL];
@@ -165,16 +180,16 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
       if (n == 0) {
         v[e] = mk<R>(d[e].x, d[e].x);  // X_0 (1 + i), X_0 = Re d_0, Nyquist dropped
       } else {
-        const C2<R> dm = mine[M - n];
+        const C2<R> dm = mine[fft_pad(M - n)];
         const C2<R> cd = cconj(d[e]);
         const C2<R> A = cadd(cd, dm);
         const C2<R> Bd = csub(cd, dm);
-        const C2<R> t2 = cmul(cconj(tw[n]), Bd);
+        const C2<R> t2 = cmul(cconj(stw[n]), Bd);
         v[e] = mk<R>(A.x - t2.y, A.y + t2.x);  // A + i e^{2 pi i n / N} Bd
       }
     }
     wave_sync();
-    wave_fft<R, M, +1>(v, mine, tw, N, lane);
+    wave_fft<R, M, +1>(v, mine, stw, lane);
     const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
     const R F = kind ? Fl : (R)1;
 #pragma unroll
@@ -182,32 +197,32 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
       const int j = lane + SWIFTCL_WAVE * e;
       const int k0 = 2 * j;
       if (k0 < nk) {
-        const R w0 = F * ks[k0] * v[e].x;
-        const R w1 = F * ks[k0 + 1] * v[e].y;
+        const C2<R> kk = *(const C2<R>*)(ks + k0);
+        const R w0 = F * kk.x * v[e].x;
+        const R w1 = F * kk.y * v[e].y;
         if (WRITE_W) {
           C2<R>* dst = (C2<R>*)(Wout + (((size_t)b * Lm + li) * T + t) * nk + k0);
           *dst = mk<R>(w0, w1);
         }
         if (DO_CL) {
-          V[k0 * 16 + t] = w0 * sq[k0];
-          V[(k0 + 1) * 16 + t] = w1 * sq[k0 + 1];
+          const C2<R> s2 = *(const C2<R>*)(sq + k0);
+          *(C2<R>*)(V + t * vs + k0) = mk<R>(w0 * s2.x, w1 * s2.y);
         }
       }
     }
   }
   if (!DO_CL) return;
   __syncthreads();
-  // C = V^T V over k on MFMA 16x16x4: lane feeds V[k][lane % 16] as both A and B operand.
+  // C = V V^T over k on MFMA 16x16x4: lane feeds V[lane % 16][k] as both A and B operand.
   using acc_t = typename mfma_acc<R>::type;
   acc_t acc = {0, 0, 0, 0};
   const int nsteps = (nk + 3) / 4;
   for (int s = wave; s < nsteps; s += NW) {
     const int kk = 4 * s + lane / 16;
-    const R a = kk < nk ? V[kk * 16 + (lane & 15)] : (R)0;
+    const R a = kk < nk ? V[(lane & 15) * vs + kk] : (R)0;
     acc = mfma_acc<R>::step(a, a, acc);
   }
-  R* red = (R*)smem;  // the FFT scratch is free now: [NW][256]
-  __syncthreads();
+  R* red = (R*)fbuf;  // the FFT scratch is free now: [NW][256]
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[wave * 256 + mfma_acc<R>::row(lane, r) * 16 + (lane & 15)] = acc[r];
   __syncthreads();
@@ -246,14 +261,28 @@ hipError_t launch_forward_fft(const plan_dev& p, const swiftcl_inputs* in, hipSt
   return hipErrorInvalidValue;
 }
 
+// LDS bytes of the fused kernel (twiddles, per-wave FFT scratch, V)
+size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k) {
+  return ((tw_lds ? 2 * (size_t)M : 0) + (size_t)NW * fft_lds_size(M)) * 2 * rs +
+         (do_cl ? (size_t)16 * (n_k + 2) * rs : 0);
+}
+
+// FP32: 16 wavefronts (one tracer each) and twiddles in LDS; FP64: 2 wavefronts, twiddles
+// read through the cache (V alone is 8 bytes x 16 x n_k).
+template <typename R> struct wcl_shape;
+template <> struct wcl_shape<float> { static constexpr int NW = 16; static constexpr bool TW = true; };
+template <> struct wcl_shape<double> { static constexpr int NW = 2; static constexpr bool TW = false; };
+
 template <typename R, int M, bool WRITE_W, bool DO_CL>
 static hipError_t launch_wcl_t(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s) {
-  constexpr int NW = 4;
-  const size_t lds = (size_t)NW * M * sizeof(C2<R>) + (DO_CL ? (size_t)p.n_k * 16 * sizeof(R) : 0);
-  auto kern = k_windows_cl<R, M, NW, WRITE_W, DO_CL>;
+  constexpr int NW = wcl_shape<R>::NW;
+  constexpr bool TW = wcl_shape<R>::TW;
+  const size_t lds = windows_cl_lds(M, NW, TW, DO_CL, sizeof(R), p.n_k);
+  auto kern = k_windows_cl<R, M, NW, TW, WRITE_W, DO_CL>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)((size_t)in->batch * p.max_ell)), dim3(NW * 64), lds, s, p, *in, (R*)W,
+  const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(groups * p.max_ell * SWIFTCL_NXCD)), dim3(NW * 64), lds, s, p, *in, (R*)W,
                      (R*)C);
   return hipGetLastError();
 }

@@ -43,8 +43,8 @@ struct plan_dev {
   double* kw;       // [n_k] (2/pi) w_j k_j^3
   double* z_geom;   // [n_zg]
   double* z_nz;     // [n_zs]
-  double* lu_geom;  // [3][n_zg] natural-spline Thomas factors (a, inv, c')
-  double* lu_nz;    // [3][n_zs]
+  double* lu_geom;  // [4][n_zg] natural-spline Thomas factors (a, 1/pivot, c') and 1/h
+  double* lu_nz;    // [4][n_zs]
   double* z_union;  // [n_union + 1] knots of the lensing quadrature
   int* union_iv;    // [2][n_union] geometry interval, n(z) interval (-1 = outside)
 
@@ -70,6 +70,8 @@ struct swiftcl_plan_s {
 };
 
 void set_error(const std::string& msg);
+size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k);
+size_t geometry_lds_bytes(const plan_dev& p);
 swiftcl_status hip_check(hipError_t e, const char* what);
 
 // Launchers (each returns the first HIP error of its launches)

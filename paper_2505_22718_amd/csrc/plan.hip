@@ -188,6 +188,7 @@ static swiftcl_status validate_desc(const swiftcl_plan_desc* d) {
   if ((st = check_increasing(d->z_geom, d->n_zg, "z_geom")) != SWIFTCL_OK) return st;
   if ((st = check_increasing(d->z_nz, d->n_zs, "z_nz")) != SWIFTCL_OK) return st;
   if (d->z_geom[0] < 0.0) { set_error("z_geom must be >= 0"); return SWIFTCL_E_DOMAIN; }
+  if (d->n_zg > 1536 || d->n_zs > 1536) { set_error("at most 1536 geometry and n(z) samples"); return SWIFTCL_E_UNSUPPORTED; }
   if (d->z_nz[0] < d->z_geom[0] || d->z_nz[d->n_zs - 1] > d->z_geom[d->n_zg - 1]) {
     set_error("z_nz must lie inside the geometry range");
     return SWIFTCL_E_INVALID;
@@ -200,12 +201,14 @@ static swiftcl_status validate_desc(const swiftcl_plan_desc* d) {
   return SWIFTCL_OK;
 }
 
-// Thomas factors of the natural cubic spline system on grid x (interior rows 1..n-2).
+// Thomas factors of the natural cubic spline system on grid x (interior rows 1..n-2), and 1/h.
 static void spline_lu(const double* x, int n, std::vector<double>& out) {
-  out.assign(3 * (size_t)n, 0.0);
+  out.assign(4 * (size_t)n, 0.0);
   double* a = out.data();
   double* inv = a + n;
   double* cp = a + 2 * n;
+  double* ih = a + 3 * n;
+  for (int i = 0; i + 1 < n; ++i) ih[i] = 1.0 / (x[i + 1] - x[i]);
   for (int i = 1; i < n - 1; ++i) {
     const double h0 = x[i] - x[i - 1], h1 = x[i + 1] - x[i];
     const double ai = h0 / 6.0, bi = (h0 + h1) / 3.0, ci = h1 / 6.0;
@@ -243,6 +246,34 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   swiftcl_status st = validate_desc(d);
   if (st != SWIFTCL_OK) return st;
   if ((st = hip_check(hipSetDevice(d->device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  (void)hipGetLastError();  // drop a stale error of an earlier, unrelated call
+  int lds_max = 0;
+  if ((st = hip_check(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, d->device),
+                      "device attribute")) != SWIFTCL_OK)
+    return st;
+  {
+    const bool dp = d->precision == SWIFTCL_FP64;
+    const size_t need = windows_cl_lds(d->n_chi / 2, dp ? 2 : 16, !dp, true, dp ? 8 : 4, d->n_k);
+    if (need > (size_t)lds_max) {
+      set_error("this n_chi / n_k / precision needs " + std::to_string(need) + " bytes of LDS per workgroup, the device has " +
+                std::to_string(lds_max));
+      return SWIFTCL_E_UNSUPPORTED;
+    }
+  }
+  {
+    // the geometry kernel keeps one point's samples in LDS
+    std::set<double> us(d->z_geom, d->z_geom + d->n_zg);
+    for (int i = 0; i < d->n_zs; ++i) us.insert(d->z_nz[i]);
+    plan_dev probe{};
+    probe.n_zg = d->n_zg;
+    probe.n_zs = d->n_zs;
+    probe.max_tracers = d->max_tracers;
+    probe.n_union = (int)us.size() - 1;
+    if (geometry_lds_bytes(probe) > (size_t)lds_max) {
+      set_error("geometry samples exceed the LDS of one workgroup (n_zg, n_zs, max_tracers too large)");
+      return SWIFTCL_E_UNSUPPORTED;
+    }
+  }
   hipStream_t s = (hipStream_t)stream;
 
   swiftcl_plan_s* p = new (std::nothrow) swiftcl_plan_s();
@@ -433,6 +464,7 @@ static swiftcl_status run_forward(swiftcl_plan_t p, const swiftcl_inputs* in, vo
   if (st != SWIFTCL_OK) return st;
   if (!W && !C) { set_error("output is NULL"); return SWIFTCL_E_INVALID; }
   if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_assemble(p->d, in, s);
   if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
@@ -456,6 +488,7 @@ extern "C" swiftcl_status swiftcl_cl_timed(swiftcl_plan_t p, const swiftcl_input
   if (st != SWIFTCL_OK) return st;
   if (!C || !stage_ms) { set_error("C or stage_ms is NULL"); return SWIFTCL_E_INVALID; }
   if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipError_t e = hipSuccess;
@@ -480,6 +513,7 @@ extern "C" swiftcl_status swiftcl_cl_backward(swiftcl_plan_t p, const swiftcl_in
   if (st != SWIFTCL_OK) return st;
   if (!dC) { set_error("dC is NULL"); return SWIFTCL_E_INVALID; }
   if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_assemble(p->d, in, s);
   if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
