@@ -143,6 +143,15 @@ swiftcl_status swiftcl_cl_timed(swiftcl_plan_t plan, const swiftcl_inputs* in, v
 swiftcl_status swiftcl_cl_backward(swiftcl_plan_t plan, const swiftcl_inputs* in, const void* dC,
                                    double* dpk, double* dbias, double* dnz, double* dD, void* stream);
 
+/* Measurement variant of swiftcl_cl_backward: the same launches with HIP events between its
+ * stages; writes the device time in ms of [0] kernel assembly, [1] forward FFTLog coefficients,
+ * [2] backward windows (recomputed W, G W on MFMA, adjoint FFTs), [3] reduction of the
+ * coefficient cotangents and their inverse transform, [4] chain rule through the kernels.
+ * Creates events and synchronises `stream`: not for use under graph capture. */
+swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t plan, const swiftcl_inputs* in, const void* dC,
+                                         double* dpk, double* dbias, double* dnz, double* dD, void* stream,
+                                         float* stage_ms);
+
 #ifdef __cplusplus
 }
 #endif

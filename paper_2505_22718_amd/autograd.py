@@ -1,0 +1,36 @@
+"""torch.autograd.Function over the hand-written adjoint of libswiftcl.
+
+ClFunction.apply(plan, inputs, pk, bias, nz, D_z) -> C [B, max_ell, npairs]
+with gradients for pk [B, n_k], bias [B, T], nz [B, T, n_zs] and D_z [B, n_zg] (float64
+tensors).  `inputs` supplies the remaining device inputs (tracer and multipole counts,
+kinds, chi(z), Omega_m); the four differentiable tensors replace their entries.  Both
+directions run in the library's HIP kernels; torch provides memory and the stream.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class ClFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, inputs, pk, bias, nz, D_z):
+        t = dict(inputs)
+        t.update(pk=pk.detach().contiguous(), bias=bias.detach().contiguous(), nz=nz.detach().contiguous(),
+                 D_z=D_z.detach().contiguous())
+        C = plan.cl(t)
+        ctx.plan = plan
+        ctx.t = t
+        return C
+
+    @staticmethod
+    def backward(ctx, dC):
+        want = [name for name, need in zip(("pk", "bias", "nz", "D"), ctx.needs_input_grad[2:]) if need]
+        if not want:
+            return None, None, None, None, None, None
+        g = ctx.plan.backward(ctx.t, dC.to(ctx.plan.out_dtype).contiguous(), want=tuple(want))
+        return None, None, g.get("pk"), g.get("bias"), g.get("nz"), g.get("D")
+
+
+def cl(plan, inputs, pk, bias, nz, D_z):
+    """Differentiable C_l (see ClFunction)."""
+    return ClFunction.apply(plan, inputs, pk, bias, nz, D_z)

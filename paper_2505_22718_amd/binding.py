@@ -72,7 +72,8 @@ class swiftcl_inputs(ctypes.Structure):
 
 
 EXPORTED = ["swiftcl_plan", "swiftcl_plan_destroy", "swiftcl_last_error", "swiftcl_device_flags",
-            "swiftcl_windows", "swiftcl_cl", "swiftcl_cl_timed", "swiftcl_cl_backward"]
+            "swiftcl_windows", "swiftcl_cl", "swiftcl_cl_timed", "swiftcl_cl_backward",
+            "swiftcl_cl_backward_timed"]
 
 _lib = None
 
@@ -95,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.swiftcl_cl.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
     lib.swiftcl_cl_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, ctypes.POINTER(ctypes.c_float)]
     lib.swiftcl_cl_backward.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, vp]
+    lib.swiftcl_cl_backward_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, vp,
+                                              ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTED:
         f = getattr(lib, name)
         if name != "swiftcl_last_error":
@@ -155,6 +158,16 @@ def swiftcl_cl_backward(plan, inputs: swiftcl_inputs, dC: int, dpk: int = 0, dbi
     vp = ctypes.c_void_p
     _check(load().swiftcl_cl_backward(plan, ctypes.byref(inputs), vp(dC), vp(dpk or None), vp(dbias or None),
                                       vp(dnz or None), vp(dD or None), vp(stream)))
+
+
+def swiftcl_cl_backward_timed(plan, inputs: swiftcl_inputs, dC: int, dpk: int = 0, dbias: int = 0, dnz: int = 0,
+                              dD: int = 0, stream: int = 0):
+    """Returns the device time (ms) of the five stages of a backward call."""
+    vp = ctypes.c_void_p
+    ms = (ctypes.c_float * 5)()
+    _check(load().swiftcl_cl_backward_timed(plan, ctypes.byref(inputs), vp(dC), vp(dpk or None), vp(dbias or None),
+                                            vp(dnz or None), vp(dD or None), vp(stream), ms))
+    return [ms[i] for i in range(5)]
 
 
 def raw_status(fn_name: str, *args) -> int:

@@ -17,89 +17,6 @@
 #include "geometry.h"
 #include "internal.h"
 
-// Wavefront-parallel natural cubic spline: M'' at the n samples y (LDS), written to Mo (LDS).
-// Thomas factors a, 1/pivot, c' and 1/h of the grid come from the plan (lu, global).
-__device__ void wave_spline(const double* __restrict__ y, const double* __restrict__ lu, int n,
-                            double* __restrict__ Mo, int lane) {
-  const double* a = lu;
-  const double* inv = lu + n;
-  const double* cp = lu + 2 * n;
-  const double* ih = lu + 3 * n;
-  const int rows = n - 2;  // interior rows 1..n-2
-  const int C = (rows + SWIFTCL_WAVE - 1) / SWIFTCL_WAVE;
-  const int lo = 1 + lane * C;
-  const int hi = min(1 + (lane + 1) * C, n - 1);
-  // forward sweep y_i = alpha_i y_{i-1} + beta_i, alpha = -a inv, beta = r inv
-  double A = 1.0, B = 0.0;
-  for (int i = lo; i < hi; ++i) {
-    const double r = (y[i + 1] - y[i]) * ih[i] - (y[i] - y[i - 1]) * ih[i - 1];
-    const double al = -a[i] * inv[i], be = r * inv[i];
-    A = al * A;
-    B = al * B + be;
-  }
-  for (int off = 1; off < SWIFTCL_WAVE; off <<= 1) {
-    const double Ap = __shfl_up(A, off), Bp = __shfl_up(B, off);
-    if (lane >= off) { B = A * Bp + B; A = A * Ap; }
-  }
-  double prev = __shfl_up(B, 1);
-  if (lane == 0) prev = 0.0;
-  for (int i = lo; i < hi; ++i) {
-    const double r = (y[i + 1] - y[i]) * ih[i] - (y[i] - y[i - 1]) * ih[i - 1];
-    prev = (r - a[i] * prev) * inv[i];
-    Mo[i] = prev;
-  }
-  // backward sweep M_i = -c'_i M_{i+1} + r'_i, from M_{n-1} = 0 downwards
-  A = 1.0;
-  B = 0.0;
-  for (int i = hi - 1; i >= lo; --i) {
-    const double g = -cp[i];
-    A = g * A;
-    B = g * B + Mo[i];
-  }
-  for (int off = 1; off < SWIFTCL_WAVE; off <<= 1) {
-    const double Ap = __shfl_down(A, off), Bp = __shfl_down(B, off);
-    if (lane + off < SWIFTCL_WAVE) { B = A * Bp + B; A = A * Ap; }
-  }
-  double next = __shfl_down(B, 1);
-  if (lane == SWIFTCL_WAVE - 1) next = 0.0;
-  for (int i = hi - 1; i >= lo; --i) {
-    next = Mo[i] - cp[i] * next;
-    Mo[i] = next;
-  }
-  if (lane == 0) { Mo[0] = 0.0; Mo[n - 1] = 0.0; }
-}
-
-// In-place suffix sums x[u] <- sum_{v >= u} x[v] over n values in LDS, by the whole block.
-// tmp: 2 * (blockDim / 64) doubles of LDS.
-__device__ void block_suffix_sum(double* x, int n, double* tmp) {
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int wave = tid / SWIFTCL_WAVE, lane = tid % SWIFTCL_WAVE, nw = nth / SWIFTCL_WAVE;
-  const int C = (n + nth - 1) / nth;
-  double loc = 0.0;
-  for (int k = 0; k < C; ++k) {
-    const int r = tid * C + k;
-    if (r < n) loc += x[n - 1 - r];
-  }
-  double incl = loc;
-  for (int off = 1; off < SWIFTCL_WAVE; off <<= 1) {
-    const double p = __shfl_up(incl, off);
-    if (lane >= off) incl += p;
-  }
-  if (lane == SWIFTCL_WAVE - 1) tmp[wave] = incl;
-  __syncthreads();
-  if (tid == 0) {
-    double acc = 0.0;
-    for (int w = 0; w < nw; ++w) { tmp[nw + w] = acc; acc += tmp[w]; }
-  }
-  __syncthreads();
-  double run = incl - loc + tmp[nw + wave];
-  for (int k = 0; k < C; ++k) {
-    const int r = tid * C + k;
-    if (r < n) { run += x[n - 1 - r]; x[n - 1 - r] = run; }
-  }
-  __syncthreads();
-}
-
 size_t geometry_lds_bytes(const plan_dev& p) {
   return sizeof(double) * ((size_t)6 * p.n_zg + (size_t)3 * p.n_zs + (size_t)2 * p.max_tracers * p.n_zs +
                            (size_t)2 * p.n_union + 64);
@@ -241,8 +158,16 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
       seg1[u] = s1;
     }
     __syncthreads();
-    block_suffix_sum(seg0, nu, tmp);
-    block_suffix_sum(seg1, nu, tmp);
+    block_scan(seg0, nu, tmp, false);
+    block_scan(seg1, nu, tmp, false);
+    {
+      // keep the suffix integrals for the adjoint
+      double* suf = P.lens_suf + ((size_t)b * T + t) * 2 * (nu + 1);
+      for (int u = tid; u < nu; u += nth) {
+        suf[u] = seg0[u];
+        suf[(nu + 1) + u] = seg1[u];
+      }
+    }
 #pragma unroll
     for (int k = 0; k < MAXN; ++k) {
       if (!ns[k].active) continue;

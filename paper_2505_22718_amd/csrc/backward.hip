@@ -1,0 +1,537 @@
+// Hand-written adjoint of the hot path: dL/dP(k), dL/db, dL/dn(z samples), dL/dD(z samples) for
+// L = sum_{b,l} sum_{i<=j} dC^{ij} C^{ij}.  Windows are recomputed, never stored.
+//
+// With G the symmetrised cotangent (G_ii = dC^{ii}, G_ij = G_ji = dC^{ij}/2) and
+// C = W diag(s) W^T, s = (2/pi) w k^3 P:
+//   Y = G W,   dP_k = sum_l (2/pi) w_k k_k^3 sum_t W_tk Y_tk,   dW = 2 s Y                (a5)
+//   W = c(l) k^{-1-b} x, x = c2r(conj(c U)) -> dc_n = sum_l h_n conj(r2c(dx)_n) conj(U_l(n))  (a6)
+//      (h_0 = 1, h_n = 2: the Hermitian half counts every n > 0 twice)
+//   c_n = alpha_n r2c(g)_n, alpha_n = (k_0 chi_0)^{-i eta_n} chi_0^{-b} / N
+//      -> dg_m = Re sum_{n<N/2} conj(alpha_n) dc_n e^{+2 pi i n m / N}
+//   g_band = w f e^{-b m Delta} -> df = sum_band w e^{-b m Delta} dg_band, then the chain through
+//   the kernels (bias, n(z) spline, lensing integrals, D(z) spline) in FP64                 (a7)
+#include "common.h"
+#include "geometry.h"
+#include "internal.h"
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename R> struct bmfma;
+template <> struct bmfma<float> {
+  typedef v4f type;
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane / 16) + r; }
+  static __device__ __forceinline__ type step(float a, float b, type c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct bmfma<double> {
+  typedef v4d type;
+  static __device__ __forceinline__ int row(int lane, int r) { return lane / 16 + 4 * r; }
+  static __device__ __forceinline__ type step(double a, double b, type c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ int clampb(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// number of multipole chunks per point: enough workgroups to fill the chip
+int backward_chunks(const plan_dev& p, int batch) {
+  int c = (2 * 256 + batch - 1) / batch;
+  if (c > p.max_ell) c = p.max_ell;
+  return c < 1 ? 1 : c;
+}
+
+// (a5, a6) One workgroup per (point, chunk of multipole slots), NW wavefronts, wave t = tracer t.
+// Per multipole: recompute W (forward FFT), Y = G W on MFMA, dP partial, dx, r2c, accumulate dc.
+// Partial dc per (point, chunk, tracer, band) and partial sum_t W Y per (point, chunk, k) go to
+// the workspace; k_bwd_coeffs and k_bwd_geometry reduce them.
+template <typename R, int M, int NW, bool TW_LDS>
+__global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inputs in, const R* __restrict__ dC,
+                                                         int nchunk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int RL = M / SWIFTCL_WAVE;
+  constexpr int N = 2 * M;
+  constexpr int FL = fft_lds_size(M);
+  constexpr int NTW = TW_LDS ? N : 0;
+  C2<R>* stw_l = (C2<R>*)smem;
+  C2<R>* fbuf = stw_l + NTW;                                           // [NW][FL]
+  R* WY = (R*)(smem + ((size_t)NTW + (size_t)NW * FL) * sizeof(C2<R>));  // [16][n_k + 2]
+  __shared__ R G[16][16];
+  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
+  const int xcd = blockIdx.x % SWIFTCL_NXCD;
+  const int rest = blockIdx.x / SWIFTCL_NXCD;
+  const int chunk = rest % nchunk;
+  const int b = (rest / nchunk) * SWIFTCL_NXCD + xcd;
+  if (b >= in.batch) return;
+  const int Tb = clampb(in.n_tracers[b], 0, T);
+  const int Lb = clampb(in.n_ell[b], 0, Lm);
+  const int l0 = (int)(((long)chunk * Lb) / nchunk), l1 = (int)(((long)(chunk + 1) * Lb) / nchunk);
+  const int vs = nk + 2;
+  const int npair = T * (T + 1) / 2;
+  const C2<R>* stw = TW_LDS ? stw_l : (const C2<R>*)P.tw;
+  if constexpr (TW_LDS) {
+    const C2<R>* gtw = (const C2<R>*)P.tw;
+    for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
+  }
+  const size_t slot = (size_t)b * nchunk + chunk;
+  C2<R>* part = (C2<R>*)P.dchat_part + slot * T * nb * M;
+  for (size_t i = threadIdx.x; i < (size_t)T * nb * M; i += NW * 64) part[i] = mk<R>(0, 0);
+  C2<R>* mine = fbuf + (size_t)wave * FL;
+  const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
+  const int ntiles = (nk + 15) / 16;
+  // this workgroup's slice of the dP partials: column k is owned by one lane of one wavefront
+  R* dpp = (R*)P.dpk_part + slot * nk;
+  for (int k = threadIdx.x; k < nk; k += NW * 64) dpp[k] = (R)0;
+  C2<R> acc[RL];
+#pragma unroll
+  for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
+  int cur_band = -1;
+  __syncthreads();
+
+  for (int li = l0; li < l1; ++li) {
+    int ei = in.ell_idx[(size_t)b * Lm + li];
+    if (ei < 0 || ei >= P.n_ell) {
+      if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+      ei = 0;
+    }
+    const int band = P.ell_band[ei];
+    const R Fl = (R)P.fell[ei];
+    if (NW >= 16 && band != cur_band) {
+      if (cur_band >= 0) {
+        for (int t = wave; t < Tb; t += NW) {
+          C2<R>* dst = part + ((size_t)t * nb + cur_band) * M;
+#pragma unroll
+          for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
+      cur_band = band;
+    }
+    // G of this multipole (symmetrised cotangent)
+    for (int gi = threadIdx.x; gi < 256; gi += NW * 64) {
+      const int i = gi / 16, j = gi % 16;
+      R gv = (R)0;
+      if (i < Tb && j < Tb) {
+        const int a = i < j ? i : j, c = i < j ? j : i;
+        const int p = a * T - a * (a - 1) / 2 + (c - a);
+        gv = dC[((size_t)b * Lm + li) * npair + p];
+        if (i != j) gv *= (R)0.5;
+      }
+      G[i][j] = gv;
+    }
+    // (1) W of every tracer into LDS
+    for (int t = wave; t < 16; t += NW) {
+      if (t >= Tb) {
+        for (int j = lane; j < nk; j += SWIFTCL_WAVE) WY[t * vs + j] = (R)0;
+        continue;
+      }
+      const int kind = in.kind[(size_t)b * T + t] & 1;
+      const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
+      const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
+      C2<R> v[RL];
+      wave_sync();
+#pragma unroll
+      for (int e = 0; e < RL; ++e) {
+        const int n = lane + SWIFTCL_WAVE * e;
+        v[e] = cconj(cmul(ch[n], Ur[n]));
+      }
+      wave_c2r<R, M>(v, mine, stw, lane);
+      const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
+      const R F = kind ? Fl : (R)1;
+#pragma unroll
+      for (int e = 0; e < RL; ++e) {
+        const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
+        if (k0 < nk) {
+          const C2<R> kk = *(const C2<R>*)(ks + k0);
+          *(C2<R>*)(WY + t * vs + k0) = mk<R>(F * kk.x * v[e].x, F * kk.y * v[e].y);
+        }
+      }
+    }
+    __syncthreads();
+    // (2) Y = G W on MFMA, tile by tile of 16 k (each tile owned by one wavefront, in place)
+    using acc_t = typename bmfma<R>::type;
+    for (int tile = wave; tile < ntiles; tile += NW) {
+      const int col = tile * 16 + (lane & 15);
+      acc_t y = {0, 0, 0, 0};
+#pragma unroll
+      for (int j0 = 0; j0 < 16; j0 += 4) {
+        const R a = G[lane & 15][j0 + lane / 16];
+        const R bo = col < nk ? WY[(j0 + lane / 16) * vs + col] : (R)0;
+        y = bmfma<R>::step(a, bo, y);
+      }
+      R s = (R)0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bmfma<R>::row(lane, r);
+        if (col < nk) s += WY[row * vs + col] * y[r];
+      }
+      s += __shfl_xor(s, 16);
+      s += __shfl_xor(s, 32);
+      if (lane < 16 && col < nk) dpp[col] += s;
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bmfma<R>::row(lane, r);
+        if (col < nk) WY[row * vs + col] = y[r];
+      }
+    }
+    __syncthreads();
+    // (3) dx = 2 s F k^{-1-b} Y, r2c, dc += h_n conj(X_n) conj(U_l(n))
+    for (int t = wave; t < Tb; t += NW) {
+      const int kind = in.kind[(size_t)b * T + t] & 1;
+      const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
+      const R F = kind ? Fl : (R)1;
+      C2<R> v[RL];
+#pragma unroll
+      for (int e = 0; e < RL; ++e) {
+        const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
+        if (k0 < nk) {
+          const C2<R> y2 = *(const C2<R>*)(WY + t * vs + k0);
+          const C2<R> kk = *(const C2<R>*)(ks + k0);
+          const C2<R> s2 = *(const C2<R>*)(sq + k0);
+          v[e] = mk<R>((R)2 * s2.x * s2.x * F * kk.x * y2.x, (R)2 * s2.y * s2.y * F * kk.y * y2.y);
+        } else {
+          v[e] = mk<R>(0, 0);
+        }
+      }
+      wave_sync();
+      wave_r2c<R, M>(v, mine, stw, lane);
+      const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
+      if constexpr (NW >= 16) {
+        // one tracer per wavefront: accumulate in registers, flushed when the band changes
+#pragma unroll
+        for (int e = 0; e < RL; ++e) {
+          const int n = lane + SWIFTCL_WAVE * e;
+          const R h = n == 0 ? (R)1 : (R)2;
+          acc[e] = cadd(acc[e], cscale(cmul(cconj(v[e]), cconj(Ur[n])), h));
+        }
+      } else {
+        // a wavefront serves several tracers: add into this workgroup's partial slot directly
+        C2<R>* dst = part + ((size_t)t * nb + band) * M;
+#pragma unroll
+        for (int e = 0; e < RL; ++e) {
+          const int n = lane + SWIFTCL_WAVE * e;
+          const R h = n == 0 ? (R)1 : (R)2;
+          dst[n] = cadd(dst[n], cscale(cmul(cconj(v[e]), cconj(Ur[n])), h));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (NW >= 16 && cur_band >= 0) {
+    for (int t = wave; t < Tb; t += NW) {
+      C2<R>* dst = part + ((size_t)t * nb + cur_band) * M;
+#pragma unroll
+      for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]);
+    }
+  }
+}
+
+// Reduce dc over chunks and take it back through the forward real transform: dg per
+// (point, tracer, band), one wavefront per row.
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_bwd_coeffs(plan_dev P, swiftcl_inputs in, int nchunk) {
+  __shared__ C2<R> lds[4][fft_lds_size(M)];
+  constexpr int RL = M / SWIFTCL_WAVE;
+  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int T = P.max_tracers, nb = P.n_bands, N = P.N;
+  const long rows = (long)in.batch * T * nb;
+  const long row = (long)blockIdx.x * 4 + wave;
+  if (row >= rows) return;
+  const int bi = (int)(row % nb);
+  const int t = (int)((row / nb) % T);
+  const int b = (int)(row / ((long)nb * T));
+  C2<R>* out = (C2<R>*)((R*)P.dg + row * N);
+  const int Tb = clampb(in.n_tracers[b], 0, T);
+  if (t >= Tb) {
+#pragma unroll
+    for (int e = 0; e < RL; ++e) out[lane + SWIFTCL_WAVE * e] = mk<R>(0, 0);
+    return;
+  }
+  C2<R> v[RL];
+#pragma unroll
+  for (int e = 0; e < RL; ++e) v[e] = mk<R>(0, 0);
+  for (int c = 0; c < nchunk; ++c) {
+    const C2<R>* src = (const C2<R>*)P.dchat_part + ((((size_t)b * nchunk + c) * T + t) * nb + bi) * M;
+#pragma unroll
+    for (int e = 0; e < RL; ++e) v[e] = cadd(v[e], src[lane + SWIFTCL_WAVE * e]);
+  }
+  const double* pt = P.pt + (size_t)b * PT_STRIDE;
+  const int kind = in.kind[(size_t)b * T + t] & 1;
+  const double scale = pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] / (double)N;
+  const double dphi = -2.0 * M_PI * pt[PT_LNK0CHI0] / ((double)N * P.delta);
+#pragma unroll
+  for (int e = 0; e < RL; ++e) {
+    const int n = lane + SWIFTCL_WAVE * e;
+    double sn, cs;
+    sincos(dphi * (double)n, &sn, &cs);
+    // e_n = dc_n conj(alpha_n); the c2r doubles n > 0, so pass e_n / 2 there
+    C2<R> en = cmul(v[e], mk<R>((R)(cs * scale), (R)(-sn * scale)));
+    v[e] = n == 0 ? en : cscale(en, (R)0.5);
+  }
+  wave_c2r<R, M>(v, lds[wave], (const C2<R>*)P.tw, lane);
+#pragma unroll
+  for (int e = 0; e < RL; ++e) out[lane + SWIFTCL_WAVE * e] = v[e];
+}
+
+size_t bwd_geometry_lds_bytes(const plan_dev& p) {
+  return sizeof(double) * ((size_t)8 * p.n_zg + (size_t)6 * p.n_zs + (size_t)2 * p.n_union + 64);
+}
+
+// (a7) Chain rule through the kernel assembly, one workgroup of 512 threads per point (FP64).
+template <typename R>
+__global__ __launch_bounds__(512) void k_bwd_geometry(plan_dev P, swiftcl_inputs in, int nchunk, double* dpk,
+                                                       double* dbias, double* dnz, double* dD) {
+  extern __shared__ double sh[];
+  const int b = blockIdx.x;
+  if (b >= in.batch) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int wave = tid / SWIFTCL_WAVE, lane = tid % SWIFTCL_WAVE;
+  const int T = P.max_tracers, nzg = P.n_zg, nzs = P.n_zs, nb = P.n_bands, N = P.N, nu = P.n_union, nk = P.n_k;
+  const int Tb = clampb(in.n_tracers[b], 0, T);
+
+  // dP: reduce the chunk partials, times (2/pi) w k^3
+  if (dpk) {
+    for (int k = tid; k < nk; k += nth) {
+      double s = 0.0;
+      for (int c = 0; c < nchunk; ++c) s += (double)((const R*)P.dpk_part)[((size_t)b * nchunk + c) * nk + k];
+      dpk[(size_t)b * nk + k] = P.kw[k] * s;
+    }
+  }
+  if (!dbias && !dnz && !dD) return;
+
+  double* zg = sh;                       // [nzg]
+  double* zgih = zg + nzg;               // [nzg]
+  double* chi = zgih + nzg;              // [nzg]
+  double* mchi = chi + nzg;              // [nzg]
+  double* Dz = mchi + nzg;               // [nzg]
+  double* mD = Dz + nzg;                 // [nzg]
+  double* dDy = mD + nzg;                // [nzg] cotangent of D samples (value terms)
+  double* dDM = dDy + nzg;               // [nzg] cotangent of D'' (spline terms)
+  double* zs = dDM + nzg;                // [nzs]
+  double* zsih = zs + nzs;               // [nzs]
+  double* dny = zsih + nzs;              // [nzs] cotangent of the current tracer's n samples
+  double* dnM = dny + nzs;               // [nzs]
+  double* nt = dnM + nzs;                // [nzs] the current tracer's n samples
+  double* mt = nt + nzs;                 // [nzs] and their spline second derivatives
+  double* seg0 = mt + nzs;               // [nu]
+  double* seg1 = seg0 + nu;              // [nu]
+  double* tmp = seg1 + nu;               // [64]
+
+  for (int i = tid; i < nzg; i += nth) {
+    zg[i] = P.z_geom[i];
+    zgih[i] = P.lu_geom[3 * nzg + i];
+    chi[i] = in.chi_z[(size_t)b * nzg + i];
+    mchi[i] = P.m_chi[(size_t)b * nzg + i];
+    Dz[i] = in.D_z[(size_t)b * nzg + i];
+    mD[i] = P.m_D[(size_t)b * nzg + i];
+    dDy[i] = 0.0;
+    dDM[i] = 0.0;
+  }
+  for (int i = tid; i < nzs; i += nth) {
+    zs[i] = P.z_nz[i];
+    zsih[i] = P.lu_nz[3 * nzs + i];
+  }
+  const double* pt = P.pt + (size_t)b * PT_STRIDE;
+  const double chi0 = pt[PT_CHI0], theta = pt[PT_THETA];
+  const int m0 = P.m0, m1 = (int)pt[PT_M1];
+  __syncthreads();
+
+  // node positions: z (and its geometry interval) solved once, the rest re-derived where used
+  constexpr int MAXN = 4;  // n_chi <= 2048 with 512 threads
+  double nz_z[MAXN];
+  int nz_ig[MAXN];
+  bool act[MAXN];
+#pragma unroll
+  for (int k = 0; k < MAXN; ++k) {
+    const int m = tid + k * nth;
+    act[k] = m < N && m >= m0 && m <= m1;
+    nz_z[k] = 0.0;
+    nz_ig[k] = 0;
+    if (act[k]) nz_z[k] = node_z(m, m0, chi0, P.delta, zg, zgih, chi, mchi, nzg, &nz_ig[k]);
+  }
+  // df at node slot k of tracer t (kind): sum over bands of dg w e^{-b m Delta}
+  auto df_at = [&](int t, int kind, int k, double w) {
+    const int m = tid + k * nth;
+    double s = 0.0;
+    for (int bi = 0; bi < nb; ++bi)
+      s += (double)((const R*)P.dg)[(((size_t)b * T + t) * nb + bi) * N + m] *
+           exp(-P.fftlog_b[kind][bi] * (double)m * P.delta);
+    return s * w;
+  };
+  const double pref = 1.5 * in.omega_m[b] * SWIFTCL_H0_OVER_C * SWIFTCL_H0_OVER_C;
+  for (int t = 0; t < T; ++t) {
+    if (t >= Tb) {
+      if (tid == 0 && dbias) dbias[(size_t)b * T + t] = 0.0;
+      if (dnz)
+        for (int i = tid; i < nzs; i += nth) dnz[((size_t)b * T + t) * nzs + i] = 0.0;
+      continue;
+    }
+    const int kind = in.kind[(size_t)b * T + t] & 1;
+    for (int i = tid; i < nzs; i += nth) {
+      dny[i] = 0.0;
+      dnM[i] = 0.0;
+      nt[i] = in.nz[((size_t)b * T + t) * nzs + i];
+      mt[i] = P.m_n[((size_t)b * T + t) * nzs + i];
+    }
+    __syncthreads();
+    double dbl = 0.0;
+    if (kind == SWIFTCL_CLUSTERING) {
+      const double bias = in.bias[(size_t)b * T + t];
+#pragma unroll
+      for (int k = 0; k < MAXN; ++k) {
+        if (!act[k]) continue;
+        const int m = tid + k * nth;
+        node_state s;
+        node_fill(s, nz_z[k], nz_ig[k], m, m0, m1, theta, zg, zgih, chi, mchi, Dz, mD, zs, nzs, P.z_union, nu,
+                  P.union_iv);
+        const double df = df_at(t, 0, k, s.w);
+        const double n = s.inz < 0 ? 0.0 : spline_at(zs, zsih, nt, mt, s.inz, s.z, nullptr);
+        dbl += df * n * s.D / s.dchi;
+        if (s.inz >= 0) spline_value_adjoint(zs, zsih, s.inz, s.z, df * bias * s.D / s.dchi, dny, dnM);
+        spline_value_adjoint(zg, zgih, s.ig, s.z, df * bias * n / s.dchi, dDy, dDM);
+      }
+    } else {
+      // the forward's suffix integrals of this tracer (q at every node)
+      const double* suf = P.lens_suf + ((size_t)b * T + t) * 2 * (nu + 1);
+      for (int u = tid; u < nu; u += nth) {
+        seg0[u] = suf[u];
+        seg1[u] = suf[(nu + 1) + u];
+      }
+      __syncthreads();
+      double dI0[MAXN], dI1[MAXN];
+      int uu[MAXN];
+#pragma unroll
+      for (int k = 0; k < MAXN; ++k) {
+        dI0[k] = dI1[k] = 0.0;
+        uu[k] = 0;
+        if (!act[k]) continue;
+        const int m = tid + k * nth;
+        node_state s;
+        node_fill(s, nz_z[k], nz_ig[k], m, m0, m1, theta, zg, zgih, chi, mchi, Dz, mD, zs, nzs, P.z_union, nu,
+                  P.union_iv);
+        uu[k] = s.u;
+        const double df = df_at(t, 1, k, s.w);
+        double p0, p1;
+        lens_interval(s.z, s.zc, s.ugi, s.uni, zg, zgih, chi, mchi, zs, zsih, nt, mt, &p0, &p1);
+        const double I0 = p0 + (s.u + 1 < nu ? seg0[s.u + 1] : 0.0);
+        const double I1 = p1 + (s.u + 1 < nu ? seg1[s.u + 1] : 0.0);
+        const double x = s.chiz;
+        const double q = pref * x * (1.0 + s.z) * (I0 - x * I1);
+        spline_value_adjoint(zg, zgih, s.ig, s.z, df * q / (x * x), dDy, dDM);
+        const double dq = df * s.D / (x * x);
+        dI0[k] = dq * pref * x * (1.0 + s.z);
+        dI1[k] = -dq * pref * x * x * (1.0 + s.z);
+      }
+      __syncthreads();
+      // transpose of I(z_m) = partial(z_m) + suffix(u_m + 1): full intervals u get the sum of
+      // dI over nodes with u_m < u (an exclusive prefix over intervals)
+      for (int u = tid; u < nu; u += nth) { seg0[u] = 0.0; seg1[u] = 0.0; }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < MAXN; ++k) {
+        if (!act[k]) continue;
+        unsafeAtomicAdd(&seg0[uu[k]], dI0[k]);
+        unsafeAtomicAdd(&seg1[uu[k]], dI1[k]);
+      }
+      __syncthreads();
+      block_scan(seg0, nu, tmp, true);
+      block_scan(seg1, nu, tmp, true);
+      for (int u = tid; u < nu; u += nth) {
+        const int iv = P.union_iv[nu + u];
+        if (iv < 0) continue;
+        const double a = P.z_union[u], c = P.z_union[u + 1];
+        const int ig = P.union_iv[u];
+        const double w0 = seg0[u], w1 = seg1[u];
+        for (int qn = 0; qn < 12; ++qn) {
+          const double z = 0.5 * (c - a) * c_gl12_x[qn] + 0.5 * (a + c);
+          const double w = 0.5 * (c - a) * c_gl12_w[qn];
+          const double x = spline_at(zg, zgih, chi, mchi, ig, z, nullptr);
+          spline_value_adjoint(zs, zsih, iv, z, w * (w0 + w1 / x), dny, dnM);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < MAXN; ++k) {
+        if (!act[k]) continue;
+        const int m = tid + k * nth;
+        node_state s;
+        node_fill(s, nz_z[k], nz_ig[k], m, m0, m1, theta, zg, zgih, chi, mchi, Dz, mD, zs, nzs, P.z_union, nu,
+                  P.union_iv);
+        if (s.uni < 0) continue;
+        const double a = s.z, c = s.zc;
+        for (int qn = 0; qn < 12; ++qn) {
+          const double z = 0.5 * (c - a) * c_gl12_x[qn] + 0.5 * (a + c);
+          const double w = 0.5 * (c - a) * c_gl12_w[qn];
+          const double x = spline_at(zg, zgih, chi, mchi, s.ugi, z, nullptr);
+          spline_value_adjoint(zs, zsih, s.uni, z, w * (dI0[k] + dI1[k] / x), dny, dnM);
+        }
+      }
+    }
+    // bias: block reduction
+    for (int off = 32; off >= 1; off >>= 1) dbl += __shfl_xor(dbl, off);
+    if (lane == 0) tmp[wave] = dbl;
+    __syncthreads();
+    if (tid == 0 && dbias) {
+      double s = 0.0;
+      for (int w = 0; w < nth / SWIFTCL_WAVE; ++w) s += tmp[w];
+      dbias[(size_t)b * T + t] = kind == SWIFTCL_CLUSTERING ? s : 0.0;
+    }
+    // n spline transpose
+    if (wave == 0) wave_spline_adjoint(dny, dnM, P.lu_nz, nzs, lane);
+    __syncthreads();
+    if (dnz)
+      for (int i = tid; i < nzs; i += nth) dnz[((size_t)b * T + t) * nzs + i] = dny[i];
+    __syncthreads();
+  }
+  if (dD) {
+    if (wave == 0) wave_spline_adjoint(dDy, dDM, P.lu_geom, nzg, lane);
+    __syncthreads();
+    for (int i = tid; i < nzg; i += nth) dD[(size_t)b * nzg + i] = dDy[i];
+  }
+}
+
+template <typename R, int M>
+static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,
+                               double* dbias, double* dnz, double* dD, hipStream_t s, hipEvent_t* ev) {
+  constexpr bool dp = sizeof(R) == 8;
+  constexpr int NW = dp ? 2 : 16;
+  constexpr bool TW = !dp;
+  const int nchunk = backward_chunks(p, in->batch);
+  const size_t lds = windows_cl_lds(M, NW, TW, true, sizeof(R), p.n_k);
+  auto k1 = k_bwd_windows<R, M, NW, TW>;
+  hipError_t e = hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
+  hipLaunchKernelGGL(k1, dim3((unsigned)(groups * nchunk * SWIFTCL_NXCD)), dim3(NW * 64), lds, s, p, *in,
+                     (const R*)dC, nchunk);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+  const long rows = (long)in->batch * p.max_tracers * p.n_bands;
+  hipLaunchKernelGGL((k_bwd_coeffs<R, M>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in, nchunk);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+  const size_t lg = bwd_geometry_lds_bytes(p);
+  e = hipFuncSetAttribute((const void*)k_bwd_geometry<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lg);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bwd_geometry<R>, dim3(in->batch), dim3(512), lg, s, p, *in, nchunk, dpk, dbias, dnz, dD);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk, double* dbias,
+                           double* dnz, double* dD, hipStream_t s, hipEvent_t* ev) {
+  const bool dp = p.precision == SWIFTCL_FP64;
+  switch (p.M) {
+    case 128: return dp ? launch_bwd_t<double, 128>(p, in, dC, dpk, dbias, dnz, dD, s, ev)
+                        : launch_bwd_t<float, 128>(p, in, dC, dpk, dbias, dnz, dD, s, ev);
+    case 256: return dp ? launch_bwd_t<double, 256>(p, in, dC, dpk, dbias, dnz, dD, s, ev)
+                        : launch_bwd_t<float, 256>(p, in, dC, dpk, dbias, dnz, dD, s, ev);
+    case 512: return dp ? launch_bwd_t<double, 512>(p, in, dC, dpk, dbias, dnz, dD, s, ev)
+                        : launch_bwd_t<float, 512>(p, in, dC, dpk, dbias, dnz, dD, s, ev);
+    case 1024: return dp ? launch_bwd_t<double, 1024>(p, in, dC, dpk, dbias, dnz, dD, s, ev)
+                         : launch_bwd_t<float, 1024>(p, in, dC, dpk, dbias, dnz, dD, s, ev);
+  }
+  return hipErrorInvalidValue;
+}

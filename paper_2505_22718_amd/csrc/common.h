@@ -189,3 +189,56 @@ __device__ __forceinline__ void wave_fft(C2<R>* v, C2<R>* lds, const C2<R>* __re
 // Number of XCDs (each with its own L2) on MI355X; workgroups are dispatched round-robin over
 // them, so blockIdx % 8 names the XCD.
 #define SWIFTCL_NXCD 8
+
+// Real forward transform of length N = 2M by one wavefront.
+// In: v[e] = (x[2j], x[2j+1]), j = lane + 64 e.  Out: v[e] = X_n = sum_m x_m e^{-2 pi i n m / N},
+// n = lane + 64 e < M (X_0 is real).
+template <typename R, int M>
+__device__ __forceinline__ void wave_r2c(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
+  constexpr int RL = M / SWIFTCL_WAVE;
+  wave_fft<R, M, -1>(v, lds, tw, lane);
+#pragma unroll
+  for (int e = 0; e < RL; ++e) lds[fft_pad(lane + SWIFTCL_WAVE * e)] = v[e];
+  wave_sync();
+#pragma unroll
+  for (int e = 0; e < RL; ++e) {
+    const int n = lane + SWIFTCL_WAVE * e;
+    const C2<R> Zn = v[e];
+    if (n == 0) {
+      v[e] = mk<R>(Zn.x + Zn.y, (R)0);
+    } else {
+      const C2<R> Zm = cconj(lds[fft_pad(M - n)]);
+      const C2<R> A = cscale(cadd(Zn, Zm), (R)0.5);
+      const C2<R> Bd = cscale(csub(Zn, Zm), (R)0.5);
+      const C2<R> t2 = cmul(tw[n], Bd);
+      v[e] = mk<R>(A.x + t2.y, A.y - t2.x);  // A - i w^n Bd
+    }
+  }
+  wave_sync();
+}
+
+// Real inverse transform of length N = 2M by one wavefront, from the half spectrum with the
+// Nyquist term dropped: x_m = Re X_0 + 2 Re sum_{n=1}^{M-1} X_n e^{+2 pi i n m / N}.
+// In: v[e] = X_n, n = lane + 64 e (only Re X_0 is used).  Out: v[e] = (x[2j], x[2j+1]).
+template <typename R, int M>
+__device__ __forceinline__ void wave_c2r(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
+  constexpr int RL = M / SWIFTCL_WAVE;
+#pragma unroll
+  for (int e = 0; e < RL; ++e) lds[fft_pad(lane + SWIFTCL_WAVE * e)] = v[e];
+  wave_sync();
+#pragma unroll
+  for (int e = 0; e < RL; ++e) {
+    const int n = lane + SWIFTCL_WAVE * e;
+    if (n == 0) {
+      v[e] = mk<R>(v[e].x, v[e].x);  // X_0 (1 + i)
+    } else {
+      const C2<R> Xm = cconj(lds[fft_pad(M - n)]);  // X_{n+M} = conj(X_{M-n})
+      const C2<R> A = cadd(v[e], Xm);
+      const C2<R> Bd = csub(v[e], Xm);
+      const C2<R> t2 = cmul(cconj(tw[n]), Bd);
+      v[e] = mk<R>(A.x - t2.y, A.y + t2.x);  // A + i e^{2 pi i n / N} Bd
+    }
+  }
+  wave_sync();
+  wave_fft<R, M, +1>(v, lds, tw, lane);
+}

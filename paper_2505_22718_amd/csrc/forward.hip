@@ -72,10 +72,7 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
   C2<R> v[RL];
 #pragma unroll
   for (int e = 0; e < RL; ++e) v[e] = g2[lane + SWIFTCL_WAVE * e];
-  wave_fft<R, M, -1>(v, lds[wave], tw, lane);
-#pragma unroll
-  for (int e = 0; e < RL; ++e) lds[wave][fft_pad(lane + SWIFTCL_WAVE * e)] = v[e];
-  wave_sync();
+  wave_r2c<R, M>(v, lds[wave], tw, lane);
   const double* pt = P.pt + (size_t)b * PT_STRIDE;
   const int kind = in.kind[(size_t)b * T + t] & 1;
   const double scale = pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] / (double)N;
@@ -83,21 +80,9 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
     const int n = lane + SWIFTCL_WAVE * e;
-    const C2<R> Zn = v[e];
-    C2<R> X;
-    if (n == 0) {
-      X = mk<R>(Zn.x + Zn.y, (R)0);
-    } else {
-      const C2<R> Zm = cconj(lds[wave][fft_pad(M - n)]);
-      const C2<R> A = cscale(cadd(Zn, Zm), (R)0.5);
-      const C2<R> Bd = cscale(csub(Zn, Zm), (R)0.5);
-      const C2<R> t2 = cmul(tw[n], Bd);
-      X = mk<R>(A.x + t2.y, A.y - t2.x);  // A - i w^n Bd
-    }
     double sn, cs;
     sincos(dphi * (double)n, &sn, &cs);
-    const C2<R> ph = mk<R>((R)(cs * scale), (R)(sn * scale));
-    out[n] = cmul(X, ph);
+    out[n] = cmul(v[e], mk<R>((R)(cs * scale), (R)(sn * scale)));
   }
 }
 
@@ -164,32 +149,14 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
     const int kind = in.kind[(size_t)b * T + t] & 1;
     const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
     const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
-    C2<R> d[RL];
-    wave_sync();
-#pragma unroll
-    for (int e = 0; e < RL; ++e) {
-      const int n = lane + SWIFTCL_WAVE * e;
-      d[e] = cmul(ch[n], Ur[n]);
-      mine[fft_pad(n)] = d[e];
-    }
-    wave_sync();
     C2<R> v[RL];
+    wave_sync();
 #pragma unroll
     for (int e = 0; e < RL; ++e) {
       const int n = lane + SWIFTCL_WAVE * e;
-      if (n == 0) {
-        v[e] = mk<R>(d[e].x, d[e].x);  // X_0 (1 + i), X_0 = Re d_0, Nyquist dropped
-      } else {
-        const C2<R> dm = mine[fft_pad(M - n)];
-        const C2<R> cd = cconj(d[e]);
-        const C2<R> A = cadd(cd, dm);
-        const C2<R> Bd = csub(cd, dm);
-        const C2<R> t2 = cmul(cconj(stw[n]), Bd);
-        v[e] = mk<R>(A.x - t2.y, A.y + t2.x);  // A + i e^{2 pi i n / N} Bd
-      }
+      v[e] = cconj(cmul(ch[n], Ur[n]));  // X_n = conj(c_n U_l(n))
     }
-    wave_sync();
-    wave_fft<R, M, +1>(v, mine, stw, lane);
+    wave_c2r<R, M>(v, mine, stw, lane);
     const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
     const R F = kind ? Fl : (R)1;
 #pragma unroll
@@ -304,9 +271,4 @@ hipError_t launch_windows_cl(const plan_dev& p, const swiftcl_inputs* in, void* 
     case 1024: return dp ? launch_wcl_m<double, 1024>(p, in, W, C, s) : launch_wcl_m<float, 1024>(p, in, W, C, s);
   }
   return hipErrorInvalidValue;
-}
-
-hipError_t launch_backward(const plan_dev&, const swiftcl_inputs*, const void*, double*, double*, double*, double*,
-                           hipStream_t) {
-  return hipErrorNotSupported;
 }

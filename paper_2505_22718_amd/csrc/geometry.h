@@ -48,28 +48,34 @@ struct node_state {
   double zc;          // right end of the union interval
 };
 
-__device__ __forceinline__ void locate_node(node_state& s, int m, int m0, int m1, double theta, double chi0,
-                                            double delta, const double* zg, const double* zgih, const double* chi,
-                                            const double* mchi, const double* Dz, const double* mD, int nzg,
-                                            const double* zs, int nzs, const double* __restrict__ z_union, int nu,
-                                            const int* __restrict__ union_iv) {
-  double z;
-  int ig;
+// z at chi node m: the lower support edge for m == m0, else the root of chi(z) = chi_0 e^{m Delta}
+// on the geometry spline (Newton from the linear estimate, kept inside the interval); ig returns
+// the geometry interval.
+__device__ __forceinline__ double node_z(int m, int m0, double chi0, double delta, const double* zg,
+                                         const double* zgih, const double* chi, const double* mchi, int nzg, int* ig_out) {
   if (m == m0) {
-    z = zg[0];  // the lower support edge sits on node m0 by construction
-    ig = 0;
-  } else {
-    const double target = fmin(chi0 * exp((double)m * delta), chi[nzg - 1]);
-    ig = find_interval(chi, nzg, target);
-    const double za = zg[ig], zb = zg[ig + 1];
-    z = za + (target - chi[ig]) / (chi[ig + 1] - chi[ig]) * (zb - za);
-    for (int it = 0; it < 6; ++it) {
-      double d;
-      const double v = spline_at(zg, zgih, chi, mchi, ig, z, &d);
-      z -= (v - target) / d;
-      z = fmin(fmax(z, za), zb);
-    }
+    *ig_out = 0;
+    return zg[0];
   }
+  const double target = fmin(chi0 * exp((double)m * delta), chi[nzg - 1]);
+  const int ig = find_interval(chi, nzg, target);
+  const double za = zg[ig], zb = zg[ig + 1];
+  double z = za + (target - chi[ig]) / (chi[ig + 1] - chi[ig]) * (zb - za);
+  for (int it = 0; it < 6; ++it) {
+    double d;
+    const double v = spline_at(zg, zgih, chi, mchi, ig, z, &d);
+    z -= (v - target) / d;
+    z = fmin(fmax(z, za), zb);
+  }
+  *ig_out = ig;
+  return z;
+}
+
+// Everything else at a node from its z and geometry interval.
+__device__ __forceinline__ void node_fill(node_state& s, double z, int ig, int m, int m0, int m1, double theta,
+                                          const double* zg, const double* zgih, const double* chi, const double* mchi,
+                                          const double* Dz, const double* mD, const double* zs, int nzs,
+                                          const double* __restrict__ z_union, int nu, const int* __restrict__ union_iv) {
   s.z = z;
   s.ig = ig;
   s.chiz = spline_at(zg, zgih, chi, mchi, ig, z, &s.dchi);
@@ -82,6 +88,16 @@ __device__ __forceinline__ void locate_node(node_state& s, int m, int m0, int m1
   s.zc = z_union[u + 1];
   s.ugi = union_iv[u];
   s.uni = union_iv[nu + u];
+}
+
+__device__ __forceinline__ void locate_node(node_state& s, int m, int m0, int m1, double theta, double chi0,
+                                            double delta, const double* zg, const double* zgih, const double* chi,
+                                            const double* mchi, const double* Dz, const double* mD, int nzg,
+                                            const double* zs, int nzs, const double* __restrict__ z_union, int nu,
+                                            const int* __restrict__ union_iv) {
+  int ig;
+  const double z = node_z(m, m0, chi0, delta, zg, zgih, chi, mchi, nzg, &ig);
+  node_fill(s, z, ig, m, m0, m1, theta, zg, zgih, chi, mchi, Dz, mD, zs, nzs, z_union, nu, union_iv);
 }
 
 // int_a^c n dz and int_a^c n / chi dz on one union sub-interval (12-point Gauss-Legendre);
@@ -103,4 +119,136 @@ __device__ __forceinline__ void lens_interval(double a, double c, int ig, int iv
   }
   *s0 = r0;
   *s1 = r1;
+}
+
+// Wavefront-parallel solve of the natural-spline tridiagonal system A z = rhs on the interior
+// rows 1..n-2 (A is symmetric; Thomas factors a, 1/pivot, c' of the grid in lu).  x holds rhs on
+// entry and z on exit (LDS); x[0] and x[n-1] are set to 0.  The two Thomas recurrences are
+// affine maps y_i = alpha_i y_{i-1} + beta_i: every lane composes the maps of a contiguous chunk
+// of rows, a shuffle scan composes the chunks, and every lane replays its chunk.
+__device__ inline void wave_tridiag_solve(double* __restrict__ x, const double* __restrict__ lu, int n, int lane) {
+  const double* a = lu;
+  const double* inv = lu + n;
+  const double* cp = lu + 2 * n;
+  const int rows = n - 2;
+  const int C = (rows + SWIFTCL_WAVE - 1) / SWIFTCL_WAVE;
+  const int lo = 1 + lane * C;
+  const int hi = min(1 + (lane + 1) * C, n - 1);
+  double A = 1.0, B = 0.0;
+  for (int i = lo; i < hi; ++i) {
+    const double al = -a[i] * inv[i], be = x[i] * inv[i];
+    A = al * A;
+    B = al * B + be;
+  }
+  for (int off = 1; off < SWIFTCL_WAVE; off <<= 1) {
+    const double Ap = __shfl_up(A, off), Bp = __shfl_up(B, off);
+    if (lane >= off) { B = A * Bp + B; A = A * Ap; }
+  }
+  double prev = __shfl_up(B, 1);
+  if (lane == 0) prev = 0.0;
+  for (int i = lo; i < hi; ++i) {
+    prev = (x[i] - a[i] * prev) * inv[i];
+    x[i] = prev;
+  }
+  A = 1.0;
+  B = 0.0;
+  for (int i = hi - 1; i >= lo; --i) {
+    const double g = -cp[i];
+    A = g * A;
+    B = g * B + x[i];
+  }
+  for (int off = 1; off < SWIFTCL_WAVE; off <<= 1) {
+    const double Ap = __shfl_down(A, off), Bp = __shfl_down(B, off);
+    if (lane + off < SWIFTCL_WAVE) { B = A * Bp + B; A = A * Ap; }
+  }
+  double next = __shfl_down(B, 1);
+  if (lane == SWIFTCL_WAVE - 1) next = 0.0;
+  for (int i = hi - 1; i >= lo; --i) {
+    next = x[i] - cp[i] * next;
+    x[i] = next;
+  }
+  if (lane == 0) { x[0] = 0.0; x[n - 1] = 0.0; }
+}
+
+// Natural cubic spline second derivatives Mo of samples y on the grid of lu (1/h in lu[3n..]).
+__device__ inline void wave_spline(const double* __restrict__ y, const double* __restrict__ lu, int n,
+                                   double* __restrict__ Mo, int lane) {
+  const double* ih = lu + 3 * n;
+  for (int i = 1 + lane; i < n - 1; i += SWIFTCL_WAVE)
+    Mo[i] = (y[i + 1] - y[i]) * ih[i] - (y[i] - y[i - 1]) * ih[i - 1];
+  wave_sync();
+  wave_tridiag_solve(Mo, lu, n, lane);
+  wave_sync();
+}
+
+// Adjoint of wave_spline plus evaluation: given dy (cotangent of the samples through the
+// value terms) and dM (cotangent of the second derivatives), adds the contribution of dM to dy:
+// dy += R^T A^{-1} dM, R the second-difference operator of the right-hand side.  dM is
+// overwritten.
+__device__ inline void wave_spline_adjoint(double* __restrict__ dy, double* __restrict__ dM,
+                                           const double* __restrict__ lu, int n, int lane) {
+  const double* ih = lu + 3 * n;
+  wave_tridiag_solve(dM, lu, n, lane);
+  wave_sync();
+  // dy_j += ih_{j-1} z_{j-1} - (ih_j + ih_{j-1}) z_j + ih_j z_{j+1}, z_0 = z_{n-1} = 0
+  for (int j = lane; j < n; j += SWIFTCL_WAVE) {
+    double acc = 0.0;
+    if (j >= 2) acc += ih[j - 1] * dM[j - 1];
+    if (j >= 1 && j <= n - 2) acc -= (ih[j] + ih[j - 1]) * dM[j];
+    if (j + 1 <= n - 2) acc += ih[j] * dM[j + 1];
+    dy[j] += acc;
+  }
+  wave_sync();
+}
+
+// Cotangent of one spline value v = A y_i + B y_{i+1} + cA M_i + cB M_{i+1} (interval i, point z)
+// accumulated into dy / dM with native LDS FP64 atomic adds (their order, hence the last bit of
+// the sums, may vary from run to run).
+__device__ __forceinline__ void spline_value_adjoint(const double* __restrict__ x, const double* __restrict__ ih,
+                                                     int i, double z, double dv, double* dy, double* dM) {
+  const double h = x[i + 1] - x[i];
+  const double A = (x[i + 1] - z) * ih[i];
+  const double B = (z - x[i]) * ih[i];
+  unsafeAtomicAdd(&dy[i], A * dv);
+  unsafeAtomicAdd(&dy[i + 1], B * dv);
+  unsafeAtomicAdd(&dM[i], (A * A * A - A) * (h * h / 6.0) * dv);
+  unsafeAtomicAdd(&dM[i + 1], (B * B * B - B) * (h * h / 6.0) * dv);
+}
+
+// In-place suffix sums x[u] <- sum_{v >= u} x[v] (prefix = false) or exclusive prefix sums
+// x[u] <- sum_{v < u} x[v] (prefix = true) over n values in LDS, by the whole block.
+// tmp: 2 * (blockDim / 64) doubles of LDS.
+__device__ inline void block_scan(double* x, int n, double* tmp, bool prefix) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int wave = tid / SWIFTCL_WAVE, lane = tid % SWIFTCL_WAVE, nw = nth / SWIFTCL_WAVE;
+  const int C = (n + nth - 1) / nth;
+  // element of rank r (scan order) sits at idx(r)
+  auto idx = [&](int r) { return prefix ? r : n - 1 - r; };
+  double loc = 0.0;
+  for (int k = 0; k < C; ++k) {
+    const int r = tid * C + k;
+    if (r < n) loc += x[idx(r)];
+  }
+  double incl = loc;
+  for (int off = 1; off < SWIFTCL_WAVE; off <<= 1) {
+    const double p = __shfl_up(incl, off);
+    if (lane >= off) incl += p;
+  }
+  if (lane == SWIFTCL_WAVE - 1) tmp[wave] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    double acc = 0.0;
+    for (int w = 0; w < nw; ++w) { tmp[nw + w] = acc; acc += tmp[w]; }
+  }
+  __syncthreads();
+  double run = incl - loc + tmp[nw + wave];
+  for (int k = 0; k < C; ++k) {
+    const int r = tid * C + k;
+    if (r < n) {
+      const double v = x[idx(r)];
+      if (prefix) { x[idx(r)] = run; run += v; }
+      else { run += v; x[idx(r)] = run; }
+    }
+  }
+  __syncthreads();
 }

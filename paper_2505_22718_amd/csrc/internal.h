@@ -59,8 +59,10 @@ struct plan_dev {
   void* sqrt_s;     // [B][n_k] real: sqrt((2/pi) w k^3 P)
   int* flags;       // [1]
   // backward workspace
-  void* dchat;      // [B][T][n_bands][M] complex real
+  void* dchat_part; // [bwd_slots][T][n_bands][M] complex real: dc partials per (point, chunk)
+  void* dpk_part;   // [bwd_slots][n_k] real: sum_t W Y partials per (point, chunk)
   void* dg;         // [B][T][n_bands][N] real
+  int bwd_slots;    // capacity of (point, chunk) slots
 };
 
 struct swiftcl_plan_s {
@@ -72,6 +74,8 @@ struct swiftcl_plan_s {
 void set_error(const std::string& msg);
 size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k);
 size_t geometry_lds_bytes(const plan_dev& p);
+size_t bwd_geometry_lds_bytes(const plan_dev& p);
+int backward_chunks(const plan_dev& p, int batch);
 swiftcl_status hip_check(hipError_t e, const char* what);
 
 // Launchers (each returns the first HIP error of its launches)
@@ -79,5 +83,6 @@ hipError_t launch_u_table(const plan_dev& p, const double* d_ell, hipStream_t s)
 hipError_t launch_assemble(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s);
 hipError_t launch_forward_fft(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s);
 hipError_t launch_windows_cl(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s);
+// ev (optional): two events recorded after the first and second backward kernels
 hipError_t launch_backward(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,
-                           double* dbias, double* dnz, double* dD, hipStream_t s);
+                           double* dbias, double* dnz, double* dD, hipStream_t s, hipEvent_t* ev = nullptr);

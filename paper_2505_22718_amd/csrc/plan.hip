@@ -234,7 +234,7 @@ static void free_plan(swiftcl_plan_s* p) {
   if (!p) return;
   void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_suf, p->d.g,
-                  p->d.chat, p->d.sqrt_s, p->d.flags, p->d.dchat, p->d.dg};
+                  p->d.chat, p->d.sqrt_s, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -269,7 +269,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     probe.n_zs = d->n_zs;
     probe.max_tracers = d->max_tracers;
     probe.n_union = (int)us.size() - 1;
-    if (geometry_lds_bytes(probe) > (size_t)lds_max) {
+    if (geometry_lds_bytes(probe) > (size_t)lds_max || bwd_geometry_lds_bytes(probe) > (size_t)lds_max) {
       set_error("geometry samples exceed the LDS of one workgroup (n_zg, n_zs, max_tracers too large)");
       return SWIFTCL_E_UNSUPPORTED;
     }
@@ -383,7 +383,14 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(chat, char, (size_t)B * T * nb * M * 2 * rs);
   ALLOC(sqrt_s, char, (size_t)B * nk * rs);
   ALLOC(flags, int, 1);
-  ALLOC(dchat, char, (size_t)B * T * nb * M * 2 * rs);
+  {
+    // (point, chunk) slots of the backward partials: the most any batch size asks for
+    long slots = 0;
+    for (int bb = 1; bb <= B; ++bb) slots = std::max(slots, (long)bb * backward_chunks(p->d, bb));
+    p->d.bwd_slots = (int)slots;
+  }
+  ALLOC(dchat_part, char, (size_t)p->d.bwd_slots * T * nb * M * 2 * rs);
+  ALLOC(dpk_part, char, (size_t)p->d.bwd_slots * nk * rs);
   ALLOC(dg, char, (size_t)B * T * nb * N * rs);
 #undef ALLOC
 
@@ -519,4 +526,30 @@ extern "C" swiftcl_status swiftcl_cl_backward(swiftcl_plan_t p, const swiftcl_in
   if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
   if (e == hipSuccess) e = launch_backward(p->d, in, dC, dpk, dbias, dnz, dD, s);
   return hip_check(e, "backward launch");
+}
+
+extern "C" swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t p, const swiftcl_inputs* in, const void* dC,
+                                                    double* dpk, double* dbias, double* dnz, double* dD, void* stream,
+                                                    float* stage_ms) {
+  swiftcl_status st = check_inputs(p, in);
+  if (st != SWIFTCL_OK) return st;
+  if (!dC || !stage_ms) { set_error("dC or stage_ms is NULL"); return SWIFTCL_E_INVALID; }
+  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+  if (e == hipSuccess) e = launch_assemble(p->d, in, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+  if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+  if (e == hipSuccess) e = launch_backward(p->d, in, dC, dpk, dbias, dnz, dD, s, &ev[3]);
+  if (e == hipSuccess) e = hipEventRecord(ev[5], s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+  for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventElapsedTime(&stage_ms[i], ev[i], ev[i + 1]);
+  for (int i = 0; i < 6; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  return hip_check(e, "timed backward");
 }

@@ -126,6 +126,18 @@ class Plan:
                                ptr["bias"], ptr["nz"], ptr["D"], self._stream())
         return {k: v for k, v in outs.items() if v is not None}
 
+    def backward_timed(self, t, dC, outs):
+        """Backward with per-stage device times (ms); outs: dict of preallocated gradient tensors."""
+        ptr = {k: (outs[k].data_ptr() if outs.get(k) is not None else 0) for k in ("pk", "bias", "nz", "D")}
+        return bd.swiftcl_cl_backward_timed(self.handle, self.inputs_struct(t), dC.data_ptr(), ptr["pk"],
+                                            ptr["bias"], ptr["nz"], ptr["D"], self._stream())
+
+    def backward_into(self, t, dC, outs):
+        """Backward into preallocated gradient tensors (no allocation)."""
+        ptr = {k: (outs[k].data_ptr() if outs.get(k) is not None else 0) for k in ("pk", "bias", "nz", "D")}
+        bd.swiftcl_cl_backward(self.handle, self.inputs_struct(t), dC.data_ptr(), ptr["pk"], ptr["bias"],
+                               ptr["nz"], ptr["D"], self._stream())
+
     def device_flags(self):
         return bd.swiftcl_device_flags(self.handle, self._stream())
 

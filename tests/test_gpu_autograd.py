@@ -1,0 +1,102 @@
+"""The adjoint behind torch.autograd against central finite differences of the HIP forward.
+
+FP64 (the 2-bin workload): torch.autograd.gradcheck over P(k), biases, n(z) samples and
+D(z) samples (central differences, eps 1e-6 relative to the input scale).
+FP32 (15 tracers, biases scaled by U(0.9, 1.1)): central differences with a 1e-4 relative step
+along seeded directions that move every entry of P(k) (random signs), of one tracer's n(z) or
+of D(z) (by (0.5 + U(0, 1)) times the entry, so C moves by ~1e-4 relative; a single k node or
+a random-sign n(z) direction moves C by 1e-7..1e-5, too close to FP32 resolution), and on single
+biases.  The
+FP32 forward's roundoff (~6e-8 of C) over a 1e-4 relative change gives the difference quotient
+~1e-3 accuracy, so the tolerance is 1e-2.
+The geometry adjoint sums with FP64 LDS atomics, so repeated backward calls agree to roundoff,
+not bit for bit (gradcheck's reentrancy tolerance is set accordingly).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def test_gradcheck_fp64(dev):
+    from paper_2505_22718_amd.autograd import cl
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    wl = synth.make_workload("cfg0")
+    plan = Plan.for_workload(wl, precision="fp64")
+    t = device_inputs(wl, dev)
+    rng = np.random.default_rng(3)
+    G = torch.as_tensor(rng.standard_normal((1, plan.max_ell, plan.n_pairs)), dtype=torch.float64, device=dev)
+    scale = {"pk": t["pk"].abs().max(), "bias": 1.0, "nz": t["nz"].abs().max(), "D": 1.0}
+
+    def make(name):
+        base = {"pk": t["pk"], "bias": t["bias"], "nz": t["nz"], "D": t["D_z"]}
+
+        def f(x):
+            args = dict(base)
+            args[name] = x * scale[name]
+            return (cl(plan, t, args["pk"], args["bias"], args["nz"], args["D"]) * G).sum()
+        return f, (base[name] / scale[name]).clone().requires_grad_(True)
+
+    for name in ("pk", "bias", "nz", "D"):
+        _say(f"gradcheck {name}")
+        f, x = make(name)
+        scale_f = float(abs(f(x.detach()))) + 1e-300
+        assert torch.autograd.gradcheck(f, (x,), eps=1e-6, atol=1e-9 * scale_f, rtol=1e-5, fast_mode=True,
+                                        nondet_tol=1e-12 * scale_f)
+
+
+def test_central_differences_fp32(dev):
+    from paper_2505_22718_amd.autograd import cl
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    wl = synth.make_workload("cfg2")
+    plan = Plan.for_workload(wl)
+    t = device_inputs(wl, dev)
+    rng = np.random.default_rng(4)
+    G = torch.as_tensor(rng.standard_normal((1, plan.max_ell, plan.n_pairs)), dtype=torch.float32, device=dev)
+    x = {k: t[k].clone().requires_grad_(True) for k in ("pk", "bias", "nz", "D_z")}
+    L = (cl(plan, t, x["pk"], x["bias"], x["nz"], x["D_z"]) * G).sum()
+    L.backward()
+
+    def loss(over):
+        args = {k: v.detach() for k, v in x.items()}
+        args.update(over)
+        with torch.no_grad():
+            return float((cl(plan, t, args["pk"], args["bias"], args["nz"], args["D_z"]).double() * G.double()).sum())
+
+    dirs = rng.standard_normal
+    cases = []
+    vp = torch.as_tensor(dirs(x["pk"].shape), device=dev) * x["pk"].detach()
+    cases.append(("pk", vp))
+    for tr in (2, 12):
+        vn = torch.zeros_like(x["nz"])
+        vn[0, tr] = torch.as_tensor(0.5 + rng.uniform(size=x["nz"].shape[-1]), device=dev) * x["nz"].detach()[0, tr]
+        cases.append(("nz", vn))
+    cases.append(("D_z", torch.as_tensor(0.5 + rng.uniform(size=x["D_z"].shape), device=dev) * x["D_z"].detach()))
+    for tr in (3, 8):
+        vb = torch.zeros_like(x["bias"])
+        vb[0, tr] = x["bias"].detach()[0, tr]
+        cases.append(("bias", vb))
+    for name, v in cases:
+        h = 1e-4
+        base = x[name].detach()
+        fd = (loss({name: base + h * v}) - loss({name: base - h * v})) / (2 * h)
+        ad = float((x[name].grad * v).sum())
+        _say(f"  {name}: adjoint {ad:.6e} central difference {fd:.6e}")
+        assert abs(ad - fd) <= 1e-2 * abs(fd)
