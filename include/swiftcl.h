@@ -143,6 +143,25 @@ swiftcl_status swiftcl_cl_timed(swiftcl_plan_t plan, const swiftcl_inputs* in, v
 swiftcl_status swiftcl_cl_backward(swiftcl_plan_t plan, const swiftcl_inputs* in, const void* dC,
                                    double* dpk, double* dbias, double* dnz, double* dD, void* stream);
 
+/* Launch-shape autotuner (used by batched callers, e.g. many parameter points of uneven tracer and
+ * multipole counts).  Times, on the caller's inputs, the forward projection launched as one
+ * workgroup per (point, multipole slot) or as a persistent grid walking per-XCD compact work
+ * lists, and (if dC is not NULL) the adjoint with 1, 2 or 4 times its base number of multipole
+ * chunks; keeps the fastest in the plan.  With cache_path (may be NULL) the choice is read from,
+ * or appended to, a file with one JSON object per line keyed by architecture and shape.  `C`
+ * (output-shaped scratch, overwritten) and `dC` are device buffers laid out as for swiftcl_cl /
+ * swiftcl_cl_backward.  `report` (may be NULL) receives a one-line summary.  Synchronises `stream`;
+ * call it outside graph capture, then capture or call swiftcl_cl / swiftcl_cl_backward as usual. */
+swiftcl_status swiftcl_autotune(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C, const void* dC,
+                                void* stream, const char* cache_path, char* report, int32_t report_len);
+
+/* Set (values < 0 leave a field unchanged) or read the launch configuration the autotuner chooses:
+ * fwd_mode 0 = one workgroup per (point, multipole slot), 1 = persistent grid over per-XCD compact
+ * work lists; bwd_chunk_mul in {1, 2, 4} scales the adjoint's number of multipole chunks.  Every
+ * configuration computes the same C_l bit for bit. */
+swiftcl_status swiftcl_set_launch(swiftcl_plan_t plan, int32_t fwd_mode, int32_t bwd_chunk_mul);
+swiftcl_status swiftcl_get_launch(swiftcl_plan_t plan, int32_t* fwd_mode, int32_t* bwd_chunk_mul);
+
 /* Measurement variant of swiftcl_cl_backward: the same launches with HIP events between its
  * stages; writes the device time in ms of [0] kernel assembly, [1] forward FFTLog coefficients,
  * [2] backward windows (recomputed W, G W on MFMA, adjoint FFTs), [3] reduction of the

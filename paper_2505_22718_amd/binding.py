@@ -73,7 +73,7 @@ class swiftcl_inputs(ctypes.Structure):
 
 EXPORTED = ["swiftcl_plan", "swiftcl_plan_destroy", "swiftcl_last_error", "swiftcl_device_flags",
             "swiftcl_windows", "swiftcl_cl", "swiftcl_cl_timed", "swiftcl_cl_backward",
-            "swiftcl_cl_backward_timed"]
+            "swiftcl_cl_backward_timed", "swiftcl_autotune", "swiftcl_set_launch", "swiftcl_get_launch"]
 
 _lib = None
 
@@ -96,6 +96,10 @@ def load(path: str = LIB_PATH):
     lib.swiftcl_cl.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
     lib.swiftcl_cl_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, ctypes.POINTER(ctypes.c_float)]
     lib.swiftcl_cl_backward.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, vp]
+    lib.swiftcl_autotune.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, ctypes.c_char_p,
+                                     ctypes.c_char_p, ctypes.c_int32]
+    lib.swiftcl_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    lib.swiftcl_get_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.swiftcl_cl_backward_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, vp,
                                               ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTED:
@@ -168,6 +172,25 @@ def swiftcl_cl_backward_timed(plan, inputs: swiftcl_inputs, dC: int, dpk: int = 
     _check(load().swiftcl_cl_backward_timed(plan, ctypes.byref(inputs), vp(dC), vp(dpk or None), vp(dbias or None),
                                             vp(dnz or None), vp(dD or None), vp(stream), ms))
     return [ms[i] for i in range(5)]
+
+
+def swiftcl_autotune(plan, inputs: swiftcl_inputs, C: int, dC: int = 0, stream: int = 0, cache_path=None) -> str:
+    """Picks the fastest launch shapes for these inputs; returns the one-line report."""
+    buf = ctypes.create_string_buffer(512)
+    path = cache_path.encode() if cache_path else None
+    _check(load().swiftcl_autotune(plan, ctypes.byref(inputs), ctypes.c_void_p(C), ctypes.c_void_p(dC or None),
+                                   ctypes.c_void_p(stream), path, buf, 512))
+    return buf.value.decode()
+
+
+def swiftcl_set_launch(plan, fwd_mode: int = -1, bwd_chunk_mul: int = -1):
+    _check(load().swiftcl_set_launch(plan, fwd_mode, bwd_chunk_mul))
+
+
+def swiftcl_get_launch(plan):
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().swiftcl_get_launch(plan, ctypes.byref(a), ctypes.byref(b)))
+    return {"fwd_mode": a.value, "bwd_chunk_mul": b.value}
 
 
 def raw_status(fn_name: str, *args) -> int:

@@ -188,15 +188,14 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
 
 hipError_t launch_assemble(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s) {
   const size_t lds = geometry_lds_bytes(p);
-  hipError_t e;
-  if (p.precision == SWIFTCL_FP64) {
-    e = hipFuncSetAttribute((const void*)k_geometry<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  if (p.precision == SWIFTCL_FP64)
     hipLaunchKernelGGL(k_geometry<double>, dim3(in->batch), dim3(1024), lds, s, p, *in);
-  } else {
-    e = hipFuncSetAttribute((const void*)k_geometry<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  else
     hipLaunchKernelGGL(k_geometry<float>, dim3(in->batch), dim3(1024), lds, s, p, *in);
-  }
   return hipGetLastError();
+}
+
+hipError_t prepare_assemble(const plan_dev& p) {
+  return p.precision == SWIFTCL_FP64 ? lds_attr_once((const void*)k_geometry<double>)
+                                     : lds_attr_once((const void*)k_geometry<float>);
 }

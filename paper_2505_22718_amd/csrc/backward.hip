@@ -37,7 +37,8 @@ __device__ __forceinline__ int clampb(int v, int lo, int hi) { return v < lo ? l
 
 // number of multipole chunks per point: enough workgroups to fill the chip
 int backward_chunks(const plan_dev& p, int batch) {
-  int c = (2 * 256 + batch - 1) / batch;
+  const int mul = p.bwd_chunk_mul > 0 ? p.bwd_chunk_mul : 1;
+  int c = (2 * 256 * mul + batch - 1) / batch;
   if (c > p.max_ell) c = p.max_ell;
   return c < 1 ? 1 : c;
 }
@@ -502,8 +503,7 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   const int nchunk = backward_chunks(p, in->batch);
   const size_t lds = windows_cl_lds(M, NW, TW, true, sizeof(R), p.n_k);
   auto k1 = k_bwd_windows<R, M, NW, TW>;
-  hipError_t e = hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  hipError_t e;
   const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
   hipLaunchKernelGGL(k1, dim3((unsigned)(groups * nchunk * SWIFTCL_NXCD)), dim3(NW * 64), lds, s, p, *in,
                      (const R*)dC, nchunk);
@@ -514,8 +514,6 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   const size_t lg = bwd_geometry_lds_bytes(p);
-  e = hipFuncSetAttribute((const void*)k_bwd_geometry<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lg);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bwd_geometry<R>, dim3(in->batch), dim3(512), lg, s, p, *in, nchunk, dpk, dbias, dnz, dD);
   return hipGetLastError();
 }
@@ -532,6 +530,25 @@ hipError_t launch_backward(const plan_dev& p, const swiftcl_inputs* in, const vo
                         : launch_bwd_t<float, 512>(p, in, dC, dpk, dbias, dnz, dD, s, ev);
     case 1024: return dp ? launch_bwd_t<double, 1024>(p, in, dC, dpk, dbias, dnz, dD, s, ev)
                          : launch_bwd_t<float, 1024>(p, in, dC, dpk, dbias, dnz, dD, s, ev);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename R, int M>
+static hipError_t prepare_bwd_t() {
+  constexpr bool dp = sizeof(R) == 8;
+  hipError_t e = lds_attr_once((const void*)k_bwd_windows<R, M, dp ? 2 : 16, !dp>);
+  if (e == hipSuccess) e = lds_attr_once((const void*)k_bwd_geometry<R>);
+  return e;
+}
+
+hipError_t prepare_backward(const plan_dev& p) {
+  const bool dp = p.precision == SWIFTCL_FP64;
+  switch (p.M) {
+    case 128: return dp ? prepare_bwd_t<double, 128>() : prepare_bwd_t<float, 128>();
+    case 256: return dp ? prepare_bwd_t<double, 256>() : prepare_bwd_t<float, 256>();
+    case 512: return dp ? prepare_bwd_t<double, 512>() : prepare_bwd_t<float, 512>();
+    case 1024: return dp ? prepare_bwd_t<double, 1024>() : prepare_bwd_t<float, 1024>();
   }
   return hipErrorInvalidValue;
 }

@@ -86,27 +86,16 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
   }
 }
 
-// Windows and / or C_l for one (point, multipole) per workgroup of NW wavefronts.  Blocks are
-// mapped so that all multipoles of one point run on one XCD (its FFTLog coefficients stay in
-// that XCD's L2): block = ((b / 8) * Lm + l) * 8 + b % 8.
-template <typename R, int M, int NW, bool TW_LDS, bool WRITE_W, bool DO_CL>
-__global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inputs in, R* __restrict__ Wout,
-                                                        R* __restrict__ Cout) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// Windows and / or C_l of one (point, multipole slot) by a workgroup of NW wavefronts (wave t
+// handles tracer t); stw: twiddles (LDS or global), fbuf: per-wave FFT scratch, V: sqrt(s) W.
+template <typename R, int M, int NW, bool WRITE_W, bool DO_CL>
+__device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl_inputs& in, R* __restrict__ Wout,
+                                                R* __restrict__ Cout, int b, int li, const C2<R>* stw, C2<R>* fbuf,
+                                                R* V) {
   constexpr int RL = M / SWIFTCL_WAVE;
-  constexpr int N = 2 * M;
   constexpr int FL = fft_lds_size(M);
-  constexpr int NTW = TW_LDS ? N : 0;
-  C2<R>* stw_l = (C2<R>*)smem;                                        // [N] twiddles (TW_LDS)
-  C2<R>* fbuf = stw_l + NTW;                                          // [NW][FL]
-  R* V = (R*)(smem + ((size_t)NTW + (size_t)NW * FL) * sizeof(C2<R>));  // [16][n_k + 2]
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
-  const int xcd = blockIdx.x % SWIFTCL_NXCD;
-  const int rest = blockIdx.x / SWIFTCL_NXCD;
-  const int li = rest % Lm;
-  const int b = (rest / Lm) * SWIFTCL_NXCD + xcd;
-  if (b >= in.batch) return;
   const int Tb = clampi(in.n_tracers[b], 0, T);
   const int Lb = clampi(in.n_ell[b], 0, Lm);
   const int npair = T * (T + 1) / 2;
@@ -125,12 +114,6 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
   if (ei < 0 || ei >= P.n_ell) {
     if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
     ei = 0;
-  }
-  const C2<R>* stw = TW_LDS ? stw_l : (const C2<R>*)P.tw;
-  if constexpr (TW_LDS) {
-    const C2<R>* gtw = (const C2<R>*)P.tw;
-    for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
-    __syncthreads();
   }
   const int vs = nk + 2;  // row stride of V: rows start on distinct banks
   const int band = P.ell_band[ei];
@@ -207,6 +190,83 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
   }
 }
 
+// Launch modes.  PERSIST = false: one workgroup per (point, multipole slot), blocks mapped so that
+// all multipoles of one point run on one XCD (block = ((b / 8) * Lm + l) * 8 + b % 8); padded
+// slots write zeros.  PERSIST = true: a grid sized to the chip; XCD x walks the compact list of
+// (point b = 8 i + x, multipole) items built by k_schedule (ragged multipole counts leave no idle
+// workgroup, and every block loads the twiddles once); padded slots are zeroed by k_zero_padded.
+template <typename R, int M, int NW, bool TW_LDS, bool WRITE_W, bool DO_CL, bool PERSIST>
+__global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inputs in, R* __restrict__ Wout,
+                                                        R* __restrict__ Cout) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int N = 2 * M;
+  constexpr int FL = fft_lds_size(M);
+  constexpr int NTW = TW_LDS ? N : 0;
+  C2<R>* stw_l = (C2<R>*)smem;                                        // [N] twiddles (TW_LDS)
+  C2<R>* fbuf = stw_l + NTW;                                          // [NW][FL]
+  R* V = (R*)(smem + ((size_t)NTW + (size_t)NW * FL) * sizeof(C2<R>));  // [16][n_k + 2]
+  const int xcd = blockIdx.x % SWIFTCL_NXCD;
+  const int rest = blockIdx.x / SWIFTCL_NXCD;
+  const C2<R>* stw = TW_LDS ? stw_l : (const C2<R>*)P.tw;
+  if constexpr (!PERSIST) {
+    const int li = rest % P.max_ell;
+    const int b = (rest / P.max_ell) * SWIFTCL_NXCD + xcd;
+    if (b >= in.batch) return;
+    if constexpr (TW_LDS) {
+      const C2<R>* gtw = (const C2<R>*)P.tw;
+      for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
+      __syncthreads();
+    }
+    windows_cl_item<R, M, NW, WRITE_W, DO_CL>(P, in, Wout, Cout, b, li, stw, fbuf, V);
+  } else {
+    if constexpr (TW_LDS) {
+      const C2<R>* gtw = (const C2<R>*)P.tw;
+      for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
+      __syncthreads();
+    }
+    const int stride = P.sched_stride;
+    const int* offs = P.sched + xcd * stride;
+    const int total = P.sched[SWIFTCL_NXCD * stride + xcd];
+    const int nx = (in.batch - xcd + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
+    const int g8 = gridDim.x / SWIFTCL_NXCD;
+    for (int k = rest; k < total; k += g8) {
+      int lo = 0, hi = nx;  // largest i with offs[i] <= k
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (offs[mid] <= k) lo = mid; else hi = mid;
+      }
+      const int b = lo * SWIFTCL_NXCD + xcd;
+      windows_cl_item<R, M, NW, WRITE_W, DO_CL>(P, in, Wout, Cout, b, k - offs[lo], stw, fbuf, V);
+      __syncthreads();
+    }
+  }
+}
+
+// Per-XCD compact work lists: offs[x][i] = sum of the multipole counts of points 8 j + x, j < i;
+// the totals follow the eight lists.
+__global__ void k_schedule(plan_dev P, swiftcl_inputs in) {
+  const int x = threadIdx.x;
+  if (x >= SWIFTCL_NXCD) return;
+  int* offs = P.sched + x * P.sched_stride;
+  int acc = 0, i = 0;
+  for (int b = x; b < in.batch; b += SWIFTCL_NXCD, ++i) {
+    offs[i] = acc;
+    acc += clampi(in.n_ell[b], 0, P.max_ell);
+  }
+  offs[i] = acc;
+  P.sched[SWIFTCL_NXCD * P.sched_stride + x] = acc;
+}
+
+// Zeros of the padded multipole slots (l >= n_ell[b]) for the persistent launch.
+template <typename R>
+__global__ void k_zero_padded(plan_dev P, swiftcl_inputs in, R* __restrict__ Cout) {
+  const int b = blockIdx.y, li = blockIdx.x;
+  if (b >= in.batch || li < clampi(in.n_ell[b], 0, P.max_ell)) return;
+  const int npair = P.max_tracers * (P.max_tracers + 1) / 2;
+  R* c = Cout + ((size_t)b * P.max_ell + li) * npair;
+  for (int i = threadIdx.x; i < npair; i += blockDim.x) c[i] = (R)0;
+}
+
 template <typename R, int M>
 static hipError_t launch_fwd_t(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s) {
   hipLaunchKernelGGL(k_sqrt_s<R>, dim3((p.n_k + 255) / 256, in->batch), dim3(256), 0, s, p, *in);
@@ -245,9 +305,17 @@ static hipError_t launch_wcl_t(const plan_dev& p, const swiftcl_inputs* in, void
   constexpr int NW = wcl_shape<R>::NW;
   constexpr bool TW = wcl_shape<R>::TW;
   const size_t lds = windows_cl_lds(M, NW, TW, DO_CL, sizeof(R), p.n_k);
-  auto kern = k_windows_cl<R, M, NW, TW, WRITE_W, DO_CL>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  if (DO_CL && !WRITE_W && p.fwd_mode == 1) {
+    hipLaunchKernelGGL(k_schedule, dim3(1), dim3(64), 0, s, p, *in);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_padded<R>, dim3(p.max_ell, in->batch), dim3(128), 0, s, p, *in, (R*)C);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, true>), dim3(p.persist_blocks), dim3(NW * 64), lds, s,
+                       p, *in, (R*)W, (R*)C);
+    return hipGetLastError();
+  }
+  auto kern = k_windows_cl<R, M, NW, TW, WRITE_W, DO_CL, false>;
   const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
   hipLaunchKernelGGL(kern, dim3((unsigned)(groups * p.max_ell * SWIFTCL_NXCD)), dim3(NW * 64), lds, s, p, *in, (R*)W,
                      (R*)C);
@@ -269,6 +337,27 @@ hipError_t launch_windows_cl(const plan_dev& p, const swiftcl_inputs* in, void* 
     case 256: return dp ? launch_wcl_m<double, 256>(p, in, W, C, s) : launch_wcl_m<float, 256>(p, in, W, C, s);
     case 512: return dp ? launch_wcl_m<double, 512>(p, in, W, C, s) : launch_wcl_m<float, 512>(p, in, W, C, s);
     case 1024: return dp ? launch_wcl_m<double, 1024>(p, in, W, C, s) : launch_wcl_m<float, 1024>(p, in, W, C, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename R, int M>
+static hipError_t prepare_fwd_t() {
+  constexpr int NW = wcl_shape<R>::NW;
+  constexpr bool TW = wcl_shape<R>::TW;
+  hipError_t e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, true, false, false>);
+  if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, false, true, false>);
+  if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, false, true, true>);
+  return e;
+}
+
+hipError_t prepare_forward(const plan_dev& p) {
+  const bool dp = p.precision == SWIFTCL_FP64;
+  switch (p.M) {
+    case 128: return dp ? prepare_fwd_t<double, 128>() : prepare_fwd_t<float, 128>();
+    case 256: return dp ? prepare_fwd_t<double, 256>() : prepare_fwd_t<float, 256>();
+    case 512: return dp ? prepare_fwd_t<double, 512>() : prepare_fwd_t<float, 512>();
+    case 1024: return dp ? prepare_fwd_t<double, 1024>() : prepare_fwd_t<float, 1024>();
   }
   return hipErrorInvalidValue;
 }

@@ -63,6 +63,12 @@ struct plan_dev {
   void* dpk_part;   // [bwd_slots][n_k] real: sum_t W Y partials per (point, chunk)
   void* dg;         // [B][T][n_bands][N] real
   int bwd_slots;    // capacity of (point, chunk) slots
+  // launch configuration (autotuned; see swiftcl_autotune)
+  int fwd_mode;       // 0: one workgroup per (point, multipole slot); 1: persistent, per-XCD lists
+  int persist_blocks; // grid of the persistent launch (a multiple of 8)
+  int bwd_chunk_mul;  // multiplier of the backward multipole-chunk count (1, 2 or 4)
+  int* sched;         // [8][sched_stride] + [8] totals: per-XCD work lists of the persistent launch
+  int sched_stride;
 };
 
 struct swiftcl_plan_s {
@@ -72,6 +78,10 @@ struct swiftcl_plan_s {
 };
 
 void set_error(const std::string& msg);
+hipError_t lds_attr_once(const void* kern);
+hipError_t prepare_forward(const plan_dev& p);
+hipError_t prepare_assemble(const plan_dev& p);
+hipError_t prepare_backward(const plan_dev& p);
 size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k);
 size_t geometry_lds_bytes(const plan_dev& p);
 size_t bwd_geometry_lds_bytes(const plan_dev& p);

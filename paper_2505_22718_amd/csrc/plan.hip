@@ -9,7 +9,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -29,6 +33,22 @@ swiftcl_status hip_check(hipError_t e, const char* what) {
 }
 
 extern "C" const char* swiftcl_last_error(void) { return g_last_error.c_str(); }
+
+// Raise a kernel's dynamic-LDS limit to the device maximum, once per kernel and process.  The
+// plan calls it for every kernel it will launch, so the launches themselves make no attribute
+// calls (they can run under hipGraph capture).
+hipError_t lds_attr_once(const void* kern) {
+  static std::mutex mu;
+  static std::set<const void*> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count(kern)) return hipSuccess;
+  int dev = 0, lds = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e == hipSuccess) e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess) done.insert(kern);
+  return e;
+}
 
 // ---------------------------------------------------------------------------------------------
 // Complex log-gamma in FP64 (Stirling's series with Bernoulli-number coefficients after an
@@ -234,7 +254,7 @@ static void free_plan(swiftcl_plan_s* p) {
   if (!p) return;
   void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_suf, p->d.g,
-                  p->d.chat, p->d.sqrt_s, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg};
+                  p->d.chat, p->d.sqrt_s, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -294,6 +314,14 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   p->d.k0 = d->k[0];
   p->d.taper_frac = d->taper_frac;
   p->d.m0 = d->edge_node > 0 ? d->edge_node : default_edge_node(d->n_chi, p->d.delta);
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d->device) != hipSuccess || ncu < 8)
+      ncu = 256;
+    p->d.persist_blocks = (ncu / SWIFTCL_NXCD) * SWIFTCL_NXCD;
+    p->d.fwd_mode = 0;
+    p->d.bwd_chunk_mul = 1;
+  }
   for (int j = 0; j < SWIFTCL_MAX_BANDS; ++j) {
     p->d.band_ell_lo[j] = j < d->n_bands ? d->band_ell_lo[j] : 1e300;
     p->d.fftlog_b[0][j] = j < d->n_bands ? d->fftlog_b[0][j] : 0.0;
@@ -384,11 +412,16 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(sqrt_s, char, (size_t)B * nk * rs);
   ALLOC(flags, int, 1);
   {
-    // (point, chunk) slots of the backward partials: the most any batch size asks for
+    // (point, chunk) slots of the backward partials: the most any batch size and chunk
+    // multiplier ask for
     long slots = 0;
-    for (int bb = 1; bb <= B; ++bb) slots = std::max(slots, (long)bb * backward_chunks(p->d, bb));
+    plan_dev probe = p->d;
+    probe.bwd_chunk_mul = 4;
+    for (int bb = 1; bb <= B; ++bb) slots = std::max(slots, (long)bb * backward_chunks(probe, bb));
     p->d.bwd_slots = (int)slots;
   }
+  p->d.sched_stride = B / SWIFTCL_NXCD + 2;
+  ALLOC(sched, int, (size_t)(SWIFTCL_NXCD + 1) * p->d.sched_stride);
   ALLOC(dchat_part, char, (size_t)p->d.bwd_slots * T * nb * M * 2 * rs);
   ALLOC(dpk_part, char, (size_t)p->d.bwd_slots * nk * rs);
   ALLOC(dg, char, (size_t)B * T * nb * N * rs);
@@ -552,4 +585,147 @@ extern "C" swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t p, const swif
   for (int i = 0; i < 6; ++i)
     if (ev[i]) (void)hipEventDestroy(ev[i]);
   return hip_check(e, "timed backward");
+}
+
+// ---------------------------------------------------------------------------------------------
+// Autotuner: times the launch variants on the caller's inputs and keeps the fastest in the plan.
+// Choices: fwd_mode (one workgroup per slot / persistent per-XCD lists) and bwd_chunk_mul (1, 2,
+// 4 x the base multipole-chunk count of the adjoint).  Results are cached, one JSON object per
+// line, keyed by device architecture and shape.
+// ---------------------------------------------------------------------------------------------
+static std::string tune_key(const swiftcl_plan_s* p, int batch) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, p->d.device) == hipSuccess) arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s|N%d|nk%d|T%d|L%d|B%d|p%d|bands%d", arch.c_str(), p->d.N, p->d.n_k,
+           p->d.max_tracers, p->d.max_ell, batch, p->d.precision, p->d.n_bands);
+  return buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, int* fwd_mode, int* chunk_mul) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  const std::string needle = "\"key\": \"" + key + "\"";
+  while (fgets(line, sizeof(line), f)) {
+    if (!strstr(line, needle.c_str())) continue;
+    const char* a = strstr(line, "\"fwd_mode\": ");
+    const char* b = strstr(line, "\"bwd_chunk_mul\": ");
+    if (a && b) {
+      *fwd_mode = atoi(a + 12);
+      *chunk_mul = atoi(b + 17);
+      found = (*fwd_mode == 0 || *fwd_mode == 1) && (*chunk_mul == 1 || *chunk_mul == 2 || *chunk_mul == 4);
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+static float time_ms(hipStream_t s, const std::function<hipError_t()>& fn, hipError_t* err) {
+  hipEvent_t a = nullptr, b = nullptr;
+  float best = 1e30f;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = fn();  // warm-up
+  for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+    e = hipEventRecord(a, s);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e == hipSuccess && ms < best) best = ms;
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  *err = e;
+  return best;
+}
+
+extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_inputs* in, void* C, const void* dC,
+                                           void* stream, const char* cache_path, char* report, int32_t report_len) {
+  swiftcl_status st = check_inputs(p, in);
+  if (st != SWIFTCL_OK) return st;
+  if (!C) { set_error("C is NULL"); return SWIFTCL_E_INVALID; }
+  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  const std::string key = tune_key(p, in->batch);
+  std::string rep;
+  int fm = 0, cm = 1;
+  if (cache_lookup(cache_path, key, &fm, &cm)) {
+    p->d.fwd_mode = fm;
+    p->d.bwd_chunk_mul = cm;
+    rep = "cached " + key + ": fwd_mode=" + std::to_string(fm) + " bwd_chunk_mul=" + std::to_string(cm);
+  } else {
+    hipError_t e = launch_assemble(p->d, in, s);
+    if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+    float tf[2] = {1e30f, 1e30f};
+    for (int m = 0; m < 2 && e == hipSuccess; ++m) {
+      p->d.fwd_mode = m;
+      tf[m] = time_ms(s, [&]() { return launch_windows_cl(p->d, in, nullptr, C, s); }, &e);
+    }
+    if (e != hipSuccess) { p->d.fwd_mode = 0; return hip_check(e, "autotune forward"); }
+    p->d.fwd_mode = tf[1] < tf[0] ? 1 : 0;
+    float tb[3] = {1e30f, 1e30f, 1e30f};
+    const int muls[3] = {1, 2, 4};
+    if (dC) {
+      for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        p->d.bwd_chunk_mul = muls[i];
+        tb[i] = time_ms(s, [&]() { return launch_backward(p->d, in, dC, nullptr, nullptr, nullptr, nullptr, s); }, &e);
+      }
+      if (e != hipSuccess) { p->d.bwd_chunk_mul = 1; return hip_check(e, "autotune backward"); }
+      int bi = 0;
+      for (int i = 1; i < 3; ++i)
+        if (tb[i] < tb[bi]) bi = i;
+      p->d.bwd_chunk_mul = muls[bi];
+    }
+    char buf[512];
+    snprintf(buf, sizeof(buf),
+             "{\"key\": \"%s\", \"fwd_mode\": %d, \"bwd_chunk_mul\": %d, \"fwd_ms\": [%.4f, %.4f], "
+             "\"bwd_ms\": [%.4f, %.4f, %.4f]}",
+             key.c_str(), p->d.fwd_mode, p->d.bwd_chunk_mul, tf[0], tf[1], dC ? tb[0] : 0.f, dC ? tb[1] : 0.f,
+             dC ? tb[2] : 0.f);
+    rep = buf;
+    if (cache_path) {
+      FILE* f = fopen(cache_path, "a");
+      if (f) {
+        fprintf(f, "%s\n", buf);
+        fclose(f);
+      }
+    }
+  }
+  if (report && report_len > 0) {
+    strncpy(report, rep.c_str(), (size_t)report_len - 1);
+    report[report_len - 1] = '\0';
+  }
+  return SWIFTCL_OK;
+}
+
+extern "C" swiftcl_status swiftcl_set_launch(swiftcl_plan_t p, int32_t fwd_mode, int32_t bwd_chunk_mul) {
+  if (!p) { set_error("plan is NULL"); return SWIFTCL_E_INVALID; }
+  if (fwd_mode >= 0) {
+    if (fwd_mode > 1) { set_error("fwd_mode must be 0 or 1"); return SWIFTCL_E_INVALID; }
+    p->d.fwd_mode = fwd_mode;
+  }
+  if (bwd_chunk_mul >= 0) {
+    if (bwd_chunk_mul != 1 && bwd_chunk_mul != 2 && bwd_chunk_mul != 4) {
+      set_error("bwd_chunk_mul must be 1, 2 or 4");
+      return SWIFTCL_E_INVALID;
+    }
+    p->d.bwd_chunk_mul = bwd_chunk_mul;
+  }
+  return SWIFTCL_OK;
+}
+
+extern "C" swiftcl_status swiftcl_get_launch(swiftcl_plan_t p, int32_t* fwd_mode, int32_t* bwd_chunk_mul) {
+  if (!p || !fwd_mode || !bwd_chunk_mul) { set_error("NULL argument"); return SWIFTCL_E_INVALID; }
+  *fwd_mode = p->d.fwd_mode;
+  *bwd_chunk_mul = p->d.bwd_chunk_mul;
+  return SWIFTCL_OK;
 }

@@ -138,6 +138,21 @@ class Plan:
         bd.swiftcl_cl_backward(self.handle, self.inputs_struct(t), dC.data_ptr(), ptr["pk"], ptr["bias"],
                                ptr["nz"], ptr["D"], self._stream())
 
+    def autotune(self, t, dC=None, cache_path=None):
+        """Choose the launch shapes for inputs like `t` (see swiftcl_autotune); returns the report."""
+        B = t["n_tracers"].shape[0]
+        C = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
+        return bd.swiftcl_autotune(self.handle, self.inputs_struct(t), C.data_ptr(),
+                                   dC.data_ptr() if dC is not None else 0, self._stream(), cache_path)
+
+    def set_launch(self, fwd_mode=None, bwd_chunk_mul=None):
+        """Force a launch configuration (what swiftcl_autotune would choose)."""
+        bd.swiftcl_set_launch(self.handle, -1 if fwd_mode is None else fwd_mode,
+                              -1 if bwd_chunk_mul is None else bwd_chunk_mul)
+
+    def launch_config(self):
+        return bd.swiftcl_get_launch(self.handle)
+
     def device_flags(self):
         return bd.swiftcl_device_flags(self.handle, self._stream())
 
