@@ -17,8 +17,12 @@
 #include "geometry.h"
 #include "internal.h"
 
+// tracers whose n(z) rows sit in LDS at once
+#define GEOM_GROUP 16
+
 size_t geometry_lds_bytes(const plan_dev& p) {
-  return sizeof(double) * ((size_t)6 * p.n_zg + (size_t)3 * p.n_zs + (size_t)2 * p.max_tracers * p.n_zs +
+  const size_t tg = p.max_tracers < GEOM_GROUP ? p.max_tracers : GEOM_GROUP;
+  return sizeof(double) * ((size_t)6 * p.n_zg + (size_t)3 * p.n_zs + (size_t)2 * tg * p.n_zs +
                            (size_t)2 * p.n_union + 64);
 }
 
@@ -44,9 +48,11 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
   double* mD = Dz + nzg;                // [nzg]
   double* zs = mD + nzg;                // [nzs] n(z) grid
   double* zsih = zs + nzs;              // [nzs]
-  double* nzr = zsih + 2 * (size_t)nzs; // [T][nzs] (one spare row of nzs keeps the layout simple)
-  double* mn = nzr + (size_t)T * nzs;   // [T][nzs]
-  double* seg0 = mn + (size_t)T * nzs;  // [nu]
+  const int TG = T < GEOM_GROUP ? T : GEOM_GROUP;
+  double* nzr = zsih + 2 * (size_t)nzs; // [TG][nzs] n(z) rows of the current tracer group (one spare row of
+                                        // nzs before it keeps the layout simple)
+  double* mn = nzr + (size_t)TG * nzs;  // [TG][nzs]
+  double* seg0 = mn + (size_t)TG * nzs; // [nu]
   double* seg1 = seg0 + nu;             // [nu]
   double* tmp = seg1 + nu;              // [64]
 
@@ -62,22 +68,17 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
     zs[i] = P.z_nz[i];
     zsih[i] = P.lu_nz[3 * nzs + i];
   }
-  for (int i = tid; i < Tb * nzs; i += nth) nzr[i] = in.nz[(size_t)b * T * nzs + i];
   __syncthreads();
 
-  // splines: curve 0 chi(z), 1 D(z), 2 + t n_t(z); one wavefront per curve
-  for (int c = wave; c < 2 + Tb; c += nw) {
-    if (c == 0) wave_spline(chi, P.lu_geom, nzg, mchi, lane);
-    else if (c == 1) wave_spline(Dz, P.lu_geom, nzg, mD, lane);
-    else wave_spline(nzr + (size_t)(c - 2) * nzs, P.lu_nz, nzs, mn + (size_t)(c - 2) * nzs, lane);
-  }
+  // splines of chi(z) and D(z), one wavefront each
+  if (wave == 0) wave_spline(chi, P.lu_geom, nzg, mchi, lane);
+  else if (wave == 1) wave_spline(Dz, P.lu_geom, nzg, mD, lane);
   __syncthreads();
   // keep the spline coefficients for the adjoint
   for (int i = tid; i < nzg; i += nth) {
     P.m_chi[(size_t)b * nzg + i] = mchi[i];
     P.m_D[(size_t)b * nzg + i] = mD[i];
   }
-  for (int i = tid; i < Tb * nzs; i += nth) P.m_n[(size_t)b * T * nzs + i] = mn[i];
 
   // per-point scalars
   const double chi_min = chi[0], chi_max = chi[nzg - 1];
@@ -126,17 +127,31 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
     locate_node(ns[k], m, m0, m1, theta, chi0, P.delta, zg, zgih, chi, mchi, Dz, mD, nzg, zs, nzs, P.z_union, nu,
                 P.union_iv);
   }
+  const double pref = 1.5 * in.omega_m[b] * SWIFTCL_H0_OVER_C * SWIFTCL_H0_OVER_C;
+  for (int g0 = 0; g0 < T; g0 += TG) {
+  const int g1 = min(g0 + TG, T);
+  // n(z) rows and their splines for tracers [g0, g1) of this point
+  for (int i = tid; i < (g1 - g0) * nzs; i += nth) {
+    const int tt = g0 + i / nzs;
+    nzr[i] = tt < Tb ? in.nz[((size_t)b * T + g0) * nzs + i] : 0.0;
+  }
+  __syncthreads();
+  for (int c = wave; c < min(g1, Tb) - g0; c += nw)
+    wave_spline(nzr + (size_t)c * nzs, P.lu_nz, nzs, mn + (size_t)c * nzs, lane);
+  __syncthreads();
+  for (int i = tid; i < (min(g1, Tb) - g0) * nzs; i += nth) P.m_n[((size_t)b * T + g0) * nzs + i] = mn[i];
   // clustering tracers and padded slots
 #pragma unroll
   for (int k = 0; k < MAXN; ++k) {
     if (!ns[k].active) continue;
     const int m = tid + k * nth;
-    for (int t = 0; t < T; ++t) {
+    for (int t = g0; t < g1; ++t) {
       if (t < Tb && in.kind[(size_t)b * T + t] != SWIFTCL_CLUSTERING) continue;
       double f = 0.0;
       if (t < Tb) {
         const double n = ns[k].inz < 0 ? 0.0
-                         : spline_at(zs, zsih, nzr + (size_t)t * nzs, mn + (size_t)t * nzs, ns[k].inz, ns[k].z, nullptr);
+                         : spline_at(zs, zsih, nzr + (size_t)(t - g0) * nzs, mn + (size_t)(t - g0) * nzs, ns[k].inz,
+                                     ns[k].z, nullptr);
         f = in.bias[(size_t)b * T + t] * n * ns[k].D / ns[k].dchi;
       }
       for (int bi = 0; bi < nb; ++bi)
@@ -145,11 +160,10 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
     }
   }
   // lensing tracers, one at a time: interval integrals, suffix scan, then q at every node
-  const double pref = 1.5 * in.omega_m[b] * SWIFTCL_H0_OVER_C * SWIFTCL_H0_OVER_C;
-  for (int t = 0; t < Tb; ++t) {
+  for (int t = g0; t < min(g1, Tb); ++t) {
     if (in.kind[(size_t)b * T + t] != SWIFTCL_LENSING) continue;
-    const double* nt = nzr + (size_t)t * nzs;
-    const double* mt = mn + (size_t)t * nzs;
+    const double* nt = nzr + (size_t)(t - g0) * nzs;
+    const double* mt = mn + (size_t)(t - g0) * nzs;
     for (int u = tid; u < nu; u += nth) {
       double s0, s1;
       lens_interval(P.z_union[u], P.z_union[u + 1], P.union_iv[u], P.union_iv[nu + u], zg, zgih, chi, mchi, zs, zsih,
@@ -184,6 +198,8 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
     }
     __syncthreads();
   }
+  __syncthreads();
+  }  // tracer groups
 }
 
 hipError_t launch_assemble(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s) {

@@ -37,6 +37,25 @@ template <> struct mfma_acc<double> {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Split precision: v = hi + lo with hi = bf16(v) and lo = bf16(v - hi), both rounded to nearest
+// even; hi + lo carries 16 significant bits.  Products accumulate in FP32 on the
+// 16x16x32 bf16 MFMA as hi.hi + hi.lo + lo.hi (lo.lo, below 2^-16 relative, is dropped).
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned short v8us __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  const unsigned int u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+__device__ __forceinline__ void split_bf16(float x, unsigned short* hi, unsigned short* lo) {
+  *hi = bf16_rne(x);
+  *lo = bf16_rne(x - bf16_to_float(*hi));
+}
+__device__ __forceinline__ v4f mfma_bf16(v8us a, v8us b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+
 template <typename R>
 __global__ void k_sqrt_s(plan_dev P, swiftcl_inputs in) {
   const int b = blockIdx.y;
@@ -88,7 +107,7 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
 
 // Windows and / or C_l of one (point, multipole slot) by a workgroup of NW wavefronts (wave t
 // handles tracer t); stw: twiddles (LDS or global), fbuf: per-wave FFT scratch, V: sqrt(s) W.
-template <typename R, int M, int NW, bool WRITE_W, bool DO_CL>
+template <typename R, int M, int NW, bool WRITE_W, bool DO_CL, bool SPLIT>
 __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl_inputs& in, R* __restrict__ Wout,
                                                 R* __restrict__ Cout, int b, int li, const C2<R>* stw, C2<R>* fbuf,
                                                 R* V) {
@@ -166,11 +185,30 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
   // C = V V^T over k on MFMA 16x16x4: lane feeds V[lane % 16][k] as both A and B operand.
   using acc_t = typename mfma_acc<R>::type;
   acc_t acc = {0, 0, 0, 0};
-  const int nsteps = (nk + 3) / 4;
-  for (int s = wave; s < nsteps; s += NW) {
-    const int kk = 4 * s + lane / 16;
-    const R a = kk < nk ? V[(lane & 15) * vs + kk] : (R)0;
-    acc = mfma_acc<R>::step(a, a, acc);
+  if constexpr (SPLIT) {
+    // 16x16x32 bf16: lane feeds 8 consecutive k of row lane % 16, split into hi + lo
+    const int nsteps = (nk + 31) / 32;
+    for (int s = wave; s < nsteps; s += NW) {
+      const int k0 = 32 * s + 8 * (lane / 16);
+      v8us hi, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        unsigned short h = 0, l = 0;
+        if (k0 + e < nk) split_bf16((float)V[(lane & 15) * vs + k0 + e], &h, &l);
+        hi[e] = h;
+        lo[e] = l;
+      }
+      acc = mfma_bf16(hi, hi, acc);
+      acc = mfma_bf16(hi, lo, acc);
+      acc = mfma_bf16(lo, hi, acc);
+    }
+  } else {
+    const int nsteps = (nk + 3) / 4;
+    for (int s = wave; s < nsteps; s += NW) {
+      const int kk = 4 * s + lane / 16;
+      const R a = kk < nk ? V[(lane & 15) * vs + kk] : (R)0;
+      acc = mfma_acc<R>::step(a, a, acc);
+    }
   }
   R* red = (R*)fbuf;  // the FFT scratch is free now: [NW][256]
 #pragma unroll
@@ -195,7 +233,7 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
 // slots write zeros.  PERSIST = true: a grid sized to the chip; XCD x walks the compact list of
 // (point b = 8 i + x, multipole) items built by k_schedule (ragged multipole counts leave no idle
 // workgroup, and every block loads the twiddles once); padded slots are zeroed by k_zero_padded.
-template <typename R, int M, int NW, bool TW_LDS, bool WRITE_W, bool DO_CL, bool PERSIST>
+template <typename R, int M, int NW, bool TW_LDS, bool WRITE_W, bool DO_CL, bool PERSIST, bool SPLIT>
 __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inputs in, R* __restrict__ Wout,
                                                         R* __restrict__ Cout) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -217,7 +255,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
       for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
       __syncthreads();
     }
-    windows_cl_item<R, M, NW, WRITE_W, DO_CL>(P, in, Wout, Cout, b, li, stw, fbuf, V);
+    windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT>(P, in, Wout, Cout, b, li, stw, fbuf, V);
   } else {
     if constexpr (TW_LDS) {
       const C2<R>* gtw = (const C2<R>*)P.tw;
@@ -236,7 +274,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
         if (offs[mid] <= k) lo = mid; else hi = mid;
       }
       const int b = lo * SWIFTCL_NXCD + xcd;
-      windows_cl_item<R, M, NW, WRITE_W, DO_CL>(P, in, Wout, Cout, b, k - offs[lo], stw, fbuf, V);
+      windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT>(P, in, Wout, Cout, b, k - offs[lo], stw, fbuf, V);
       __syncthreads();
     }
   }
@@ -294,31 +332,260 @@ size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k
          (do_cl ? (size_t)16 * (n_k + 2) * rs : 0);
 }
 
-// FP32: 16 wavefronts (one tracer each) and twiddles in LDS; FP64: 2 wavefronts, twiddles
-// read through the cache (V alone is 8 bytes x 16 x n_k).
-template <typename R> struct wcl_shape;
-template <> struct wcl_shape<float> { static constexpr int NW = 16; static constexpr bool TW = true; };
-template <> struct wcl_shape<double> { static constexpr int NW = 2; static constexpr bool TW = false; };
+// Workgroup shape: FP32 16 wavefronts (one tracer each), twiddles in LDS up to N = 1024; FP64 2
+// wavefronts with twiddles read through the cache (V alone is 8 bytes x 16 x n_k).
+template <typename R, int M> struct wcl_shape;
+template <int M> struct wcl_shape<float, M> {
+  static constexpr int NW = 16;
+  static constexpr bool TW = M <= 512;
+};
+template <int M> struct wcl_shape<double, M> {
+  static constexpr int NW = 2;
+  static constexpr bool TW = false;
+};
+
+int windows_nw(int precision) { return precision == SWIFTCL_FP64 ? 2 : 16; }
+bool windows_tw_lds(int precision, int M) { return precision != SWIFTCL_FP64 && M <= 512; }
+
+// ---------------------------------------------------------------------------------------------
+// Unfused projection for more than 16 tracers or windows too large for LDS (FP32 / split):
+// k_windows_v writes V = sqrt(s) W of up to 32 tracer slots per (point, multipole) to the
+// workspace, k_contract forms the 32 x 32 Gram matrix from three 16 x 16 MFMA tile pairs
+// (0,0), (0,1), (1,1).  Points are processed in chunks of P.vchunk.
+// ---------------------------------------------------------------------------------------------
+template <int M, int NW, bool TW_LDS, bool SPLIT>
+__global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  typedef float R;
+  constexpr int RL = M / SWIFTCL_WAVE;
+  constexpr int N = 2 * M;
+  constexpr int FL = fft_lds_size(M);
+  constexpr int NTW = TW_LDS ? N : 0;
+  C2<R>* stw_l = (C2<R>*)smem;
+  C2<R>* fbuf = stw_l + NTW;
+  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
+  const int xcd = blockIdx.x % SWIFTCL_NXCD;
+  const int rest = blockIdx.x / SWIFTCL_NXCD;
+  const int li = rest % Lm;
+  const int bl = (rest / Lm) * SWIFTCL_NXCD + xcd;
+  if (bl >= nbp) return;
+  const int b = b0 + bl;
+  const int Tb = clampi(in.n_tracers[b], 0, T);
+  const int Lb = clampi(in.n_ell[b], 0, Lm);
+  const size_t row0 = ((size_t)bl * Lm + li) * 32;
+  const size_t lo_off = (size_t)P.vchunk * Lm * 32 * nk;  // split: lo parts after all hi parts
+  float* vf = (float*)P.vbuf;
+  unsigned short* vh = (unsigned short*)P.vbuf;
+  if (li >= Lb) {
+    for (size_t i = threadIdx.x; i < (size_t)32 * nk; i += NW * 64) {
+      if (SPLIT) { vh[row0 * nk + i] = 0; vh[lo_off + row0 * nk + i] = 0; }
+      else vf[row0 * nk + i] = 0.f;
+    }
+    return;
+  }
+  int ei = in.ell_idx[(size_t)b * Lm + li];
+  if (ei < 0 || ei >= P.n_ell) {
+    if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+    ei = 0;
+  }
+  const C2<R>* stw = TW_LDS ? stw_l : (const C2<R>*)P.tw;
+  if constexpr (TW_LDS) {
+    const C2<R>* gtw = (const C2<R>*)P.tw;
+    for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
+    __syncthreads();
+  }
+  const int band = P.ell_band[ei];
+  const R Fl = (R)P.fell[ei];
+  const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
+  C2<R>* mine = fbuf + (size_t)wave * FL;
+  for (int t = wave; t < 32; t += NW) {
+    const size_t rb = (row0 + t) * nk;
+    if (t >= Tb) {
+      for (int j = lane; j < nk; j += SWIFTCL_WAVE) {
+        if (SPLIT) { vh[rb + j] = 0; vh[lo_off + rb + j] = 0; }
+        else vf[rb + j] = 0.f;
+      }
+      continue;
+    }
+    const int kind = in.kind[(size_t)b * T + t] & 1;
+    const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
+    const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
+    C2<R> v[RL];
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < RL; ++e) {
+      const int n = lane + SWIFTCL_WAVE * e;
+      v[e] = cconj(cmul(ch[n], Ur[n]));
+    }
+    wave_c2r<R, M>(v, mine, stw, lane);
+    const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
+    const R F = kind ? Fl : (R)1;
+#pragma unroll
+    for (int e = 0; e < RL; ++e) {
+      const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
+      if (k0 < nk) {
+        const C2<R> kk = *(const C2<R>*)(ks + k0);
+        const C2<R> s2 = *(const C2<R>*)(sq + k0);
+        const float x0 = F * kk.x * v[e].x * s2.x, x1 = F * kk.y * v[e].y * s2.y;
+        if (SPLIT) {
+          unsigned short h0, l0, h1, l1;
+          split_bf16(x0, &h0, &l0);
+          split_bf16(x1, &h1, &l1);
+          *(unsigned int*)(vh + rb + k0) = (unsigned int)h0 | ((unsigned int)h1 << 16);
+          *(unsigned int*)(vh + lo_off + rb + k0) = (unsigned int)l0 | ((unsigned int)l1 << 16);
+        } else {
+          *(C2<R>*)(vf + rb + k0) = mk<R>(x0, x1);
+        }
+      }
+    }
+  }
+}
+
+// C of one (point, multipole) from the workspace: 4 wavefronts split k; tile pairs (0,0), (0,1),
+// (1,1) of the 32 x 32 Gram matrix.
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void k_contract(plan_dev P, swiftcl_inputs in, float* __restrict__ Cout, int b0,
+                                                  int nbp) {
+  __shared__ float red[4][3][256];
+  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k;
+  const int bl = blockIdx.x / Lm, li = blockIdx.x % Lm;
+  if (bl >= nbp) return;
+  const int b = b0 + bl;
+  const int Tb = clampi(in.n_tracers[b], 0, T);
+  const int Lb = clampi(in.n_ell[b], 0, Lm);
+  const int npair = T * (T + 1) / 2;
+  float* c = Cout + ((size_t)b * Lm + li) * npair;
+  if (li >= Lb) {
+    for (int i = threadIdx.x; i < npair; i += 256) c[i] = 0.f;
+    return;
+  }
+  const size_t row0 = ((size_t)bl * Lm + li) * 32;
+  const size_t lo_off = (size_t)P.vchunk * Lm * 32 * nk;
+  const bool two = Tb > 16;
+  v4f a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
+  const int r = lane & 15;
+  if constexpr (SPLIT) {
+    const unsigned short* vh = (const unsigned short*)P.vbuf;
+    const int nsteps = (nk + 31) / 32;
+    for (int s = wave; s < nsteps; s += 4) {
+      const int k0 = 32 * s + 8 * (lane / 16);
+      v8us h0, l0, h1, l1;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool ok = k0 + e < nk;
+        h0[e] = ok ? vh[(row0 + r) * nk + k0 + e] : 0;
+        l0[e] = ok ? vh[lo_off + (row0 + r) * nk + k0 + e] : 0;
+        h1[e] = ok ? vh[(row0 + 16 + r) * nk + k0 + e] : 0;
+        l1[e] = ok ? vh[lo_off + (row0 + 16 + r) * nk + k0 + e] : 0;
+      }
+      a00 = mfma_bf16(h0, h0, a00);
+      a00 = mfma_bf16(h0, l0, a00);
+      a00 = mfma_bf16(l0, h0, a00);
+      if (two) {
+        a01 = mfma_bf16(h0, h1, a01);
+        a01 = mfma_bf16(h0, l1, a01);
+        a01 = mfma_bf16(l0, h1, a01);
+        a11 = mfma_bf16(h1, h1, a11);
+        a11 = mfma_bf16(h1, l1, a11);
+        a11 = mfma_bf16(l1, h1, a11);
+      }
+    }
+  } else {
+    const float* vf = (const float*)P.vbuf;
+    const int nsteps = (nk + 3) / 4;
+    for (int s = wave; s < nsteps; s += 4) {
+      const int kk = 4 * s + lane / 16;
+      const bool ok = kk < nk;
+      const float x0 = ok ? vf[(row0 + r) * nk + kk] : 0.f;
+      const float x1 = ok ? vf[(row0 + 16 + r) * nk + kk] : 0.f;
+      a00 = mfma_acc<float>::step(x0, x0, a00);
+      if (two) {
+        a01 = mfma_acc<float>::step(x0, x1, a01);
+        a11 = mfma_acc<float>::step(x1, x1, a11);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = mfma_acc<float>::row(lane, q) * 16 + r;
+    red[wave][0][idx] = a00[q];
+    red[wave][1][idx] = a01[q];
+    red[wave][2][idx] = a11[q];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < npair; idx += 256) {
+    int i = 0, rem = idx;
+    while (rem >= T - i) { rem -= T - i; ++i; }
+    const int j = i + rem;
+    float val = 0.f;
+    if (i < Tb && j < Tb) {
+      const int tile = (i < 16) ? (j < 16 ? 0 : 1) : 2;
+      const int e = (i % 16) * 16 + (j % 16);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) val += red[w][tile][e];
+    }
+    c[idx] = val;
+  }
+}
+
+template <int M>
+static hipError_t launch_unfused(const plan_dev& p, const swiftcl_inputs* in, void* C, hipStream_t s) {
+  constexpr int NW = 16;
+  constexpr bool TW = M <= 512;
+  const bool split = p.precision == SWIFTCL_SPLIT_BF16;
+  const size_t lds = windows_cl_lds(M, NW, TW, false, sizeof(float), p.n_k);
+  for (int b0 = 0; b0 < in->batch; b0 += p.vchunk) {
+    const int nbp = in->batch - b0 < p.vchunk ? in->batch - b0 : p.vchunk;
+    const size_t groups = (size_t)(nbp + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
+    const dim3 g1((unsigned)(groups * p.max_ell * SWIFTCL_NXCD));
+    if (split) hipLaunchKernelGGL((k_windows_v<M, NW, TW, true>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
+    else hipLaunchKernelGGL((k_windows_v<M, NW, TW, false>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2((unsigned)((size_t)nbp * p.max_ell));
+    if (split) hipLaunchKernelGGL(k_contract<true>, g2, dim3(256), 0, s, p, *in, (float*)C, b0, nbp);
+    else hipLaunchKernelGGL(k_contract<false>, g2, dim3(256), 0, s, p, *in, (float*)C, b0, nbp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 template <typename R, int M, bool WRITE_W, bool DO_CL>
 static hipError_t launch_wcl_t(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s) {
-  constexpr int NW = wcl_shape<R>::NW;
-  constexpr bool TW = wcl_shape<R>::TW;
+  constexpr int NW = wcl_shape<R, M>::NW;
+  constexpr bool TW = wcl_shape<R, M>::TW;
   const size_t lds = windows_cl_lds(M, NW, TW, DO_CL, sizeof(R), p.n_k);
+  const bool split = p.precision == SWIFTCL_SPLIT_BF16;
   if (DO_CL && !WRITE_W && p.fwd_mode == 1) {
     hipLaunchKernelGGL(k_schedule, dim3(1), dim3(64), 0, s, p, *in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_padded<R>, dim3(p.max_ell, in->batch), dim3(128), 0, s, p, *in, (R*)C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, true>), dim3(p.persist_blocks), dim3(NW * 64), lds, s,
-                       p, *in, (R*)W, (R*)C);
+    if constexpr (sizeof(R) == 4) {
+      if (split) {
+        hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, true, true>), dim3(p.persist_blocks),
+                           dim3(NW * 64), lds, s, p, *in, (R*)W, (R*)C);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, true, false>), dim3(p.persist_blocks), dim3(NW * 64),
+                       lds, s, p, *in, (R*)W, (R*)C);
     return hipGetLastError();
   }
-  auto kern = k_windows_cl<R, M, NW, TW, WRITE_W, DO_CL, false>;
   const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(groups * p.max_ell * SWIFTCL_NXCD)), dim3(NW * 64), lds, s, p, *in, (R*)W,
-                     (R*)C);
+  const dim3 grid((unsigned)(groups * p.max_ell * SWIFTCL_NXCD));
+  if constexpr (sizeof(R) == 4 && DO_CL) {
+    if (split) {
+      hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, WRITE_W, DO_CL, false, true>), grid, dim3(NW * 64), lds, s, p,
+                         *in, (R*)W, (R*)C);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, WRITE_W, DO_CL, false, false>), grid, dim3(NW * 64), lds, s, p, *in,
+                     (R*)W, (R*)C);
   return hipGetLastError();
 }
 
@@ -326,7 +593,11 @@ template <typename R, int M>
 static hipError_t launch_wcl_m(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (W) e = launch_wcl_t<R, M, true, false>(p, in, W, nullptr, s);
-  if (e == hipSuccess && C) e = launch_wcl_t<R, M, false, true>(p, in, nullptr, C, s);
+  if (e == hipSuccess && C) {
+    if (p.fused) e = launch_wcl_t<R, M, false, true>(p, in, nullptr, C, s);
+    else if constexpr (sizeof(R) == 4) e = launch_unfused<M>(p, in, C, s);
+    else e = hipErrorNotSupported;
+  }
   return e;
 }
 
@@ -343,11 +614,22 @@ hipError_t launch_windows_cl(const plan_dev& p, const swiftcl_inputs* in, void* 
 
 template <typename R, int M>
 static hipError_t prepare_fwd_t() {
-  constexpr int NW = wcl_shape<R>::NW;
-  constexpr bool TW = wcl_shape<R>::TW;
-  hipError_t e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, true, false, false>);
-  if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, false, true, false>);
-  if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, false, true, true>);
+  constexpr int NW = wcl_shape<R, M>::NW;
+  constexpr bool TW = wcl_shape<R, M>::TW;
+  const void* ks[] = {
+      (const void*)k_windows_cl<R, M, NW, TW, true, false, false, false>,
+      (const void*)k_windows_cl<R, M, NW, TW, false, true, false, false>,
+      (const void*)k_windows_cl<R, M, NW, TW, false, true, true, false>,
+  };
+  hipError_t e = hipSuccess;
+  for (const void* k : ks)
+    if (e == hipSuccess) e = lds_attr_once(k);
+  if constexpr (sizeof(R) == 4) {
+    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, false, true, false, true>);
+    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, false, true, true, true>);
+    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_v<M, 16, (M <= 512), true>);
+    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_v<M, 16, (M <= 512), false>);
+  }
   return e;
 }
 

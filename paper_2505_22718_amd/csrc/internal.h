@@ -69,6 +69,10 @@ struct plan_dev {
   int bwd_chunk_mul;  // multiplier of the backward multipole-chunk count (1, 2 or 4)
   int* sched;         // [8][sched_stride] + [8] totals: per-XCD work lists of the persistent launch
   int sched_stride;
+  // projection path: fused (windows in LDS, <= 16 tracers) or through the workspace below
+  int fused;
+  int vchunk;         // points per chunk of the unfused path
+  void* vbuf;         // [vchunk][max_ell][32][n_k] FP32, or bf16 hi then lo (unfused path only)
 };
 
 struct swiftcl_plan_s {
@@ -84,6 +88,8 @@ hipError_t prepare_assemble(const plan_dev& p);
 hipError_t prepare_backward(const plan_dev& p);
 size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k);
 size_t geometry_lds_bytes(const plan_dev& p);
+int windows_nw(int precision);
+bool windows_tw_lds(int precision, int M);
 size_t bwd_geometry_lds_bytes(const plan_dev& p);
 int backward_chunks(const plan_dev& p, int batch);
 swiftcl_status hip_check(hipError_t e, const char* what);

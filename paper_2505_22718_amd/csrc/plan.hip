@@ -216,7 +216,7 @@ static swiftcl_status validate_desc(const swiftcl_plan_desc* d) {
   const int m0 = d->edge_node > 0 ? d->edge_node : default_edge_node(d->n_chi, delta);
   if (m0 < 1 || m0 > d->n_chi - 2) { set_error("edge_node outside 1..n_chi-2"); return SWIFTCL_E_INVALID; }
   if (d->max_batch < 1 || d->max_tracers < 1 || d->max_ell < 1) { set_error("capacities must be >= 1"); return SWIFTCL_E_INVALID; }
-  if (d->max_tracers > 16) { set_error("max_tracers > 16 is not built"); return SWIFTCL_E_UNSUPPORTED; }
+  if (d->max_tracers > 32) { set_error("max_tracers > 32 is not built"); return SWIFTCL_E_UNSUPPORTED; }
   if (d->precision < 0 || d->precision > 2) { set_error("unknown precision"); return SWIFTCL_E_INVALID; }
   return SWIFTCL_OK;
 }
@@ -254,7 +254,7 @@ static void free_plan(swiftcl_plan_s* p) {
   if (!p) return;
   void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_suf, p->d.g,
-                  p->d.chat, p->d.sqrt_s, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched};
+                  p->d.chat, p->d.sqrt_s, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -271,12 +271,20 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   if ((st = hip_check(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, d->device),
                       "device attribute")) != SWIFTCL_OK)
     return st;
+  bool fused = false;
   {
     const bool dp = d->precision == SWIFTCL_FP64;
-    const size_t need = windows_cl_lds(d->n_chi / 2, dp ? 2 : 16, !dp, true, dp ? 8 : 4, d->n_k);
-    if (need > (size_t)lds_max) {
-      set_error("this n_chi / n_k / precision needs " + std::to_string(need) + " bytes of LDS per workgroup, the device has " +
-                std::to_string(lds_max));
+    const int M = d->n_chi / 2;
+    const size_t need = windows_cl_lds(M, windows_nw(d->precision), windows_tw_lds(d->precision, M), true,
+                                       dp ? 8 : 4, d->n_k);
+    fused = d->max_tracers <= 16 && need <= (size_t)lds_max;
+    if (!fused && dp) {
+      set_error("the FP64 path keeps the windows of <= 16 tracers in LDS; this n_chi / n_k / max_tracers needs " +
+                std::to_string(need) + " bytes per workgroup, the device has " + std::to_string(lds_max));
+      return SWIFTCL_E_UNSUPPORTED;
+    }
+    if (!fused && windows_cl_lds(M, 16, windows_tw_lds(d->precision, M), false, 4, d->n_k) > (size_t)lds_max) {
+      set_error("n_chi too large for the LDS of one workgroup");
       return SWIFTCL_E_UNSUPPORTED;
     }
   }
@@ -314,6 +322,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   p->d.k0 = d->k[0];
   p->d.taper_frac = d->taper_frac;
   p->d.m0 = d->edge_node > 0 ? d->edge_node : default_edge_node(d->n_chi, p->d.delta);
+  p->d.fused = fused ? 1 : 0;
   {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d->device) != hipSuccess || ncu < 8)
@@ -419,6 +428,16 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     probe.bwd_chunk_mul = 4;
     for (int bb = 1; bb <= B; ++bb) slots = std::max(slots, (long)bb * backward_chunks(probe, bb));
     p->d.bwd_slots = (int)slots;
+  }
+  if (!p->d.fused) {
+    // workspace of the unfused projection: V of up to 32 tracer slots, a chunk of points at a time
+    const size_t per_point = (size_t)p->d.max_ell * 32 * nk * 4;
+    const size_t budget = (size_t)512 << 20;
+    size_t chunk = budget / per_point;
+    if (chunk < 1) chunk = 1;
+    if (chunk > (size_t)B) chunk = B;
+    p->d.vchunk = (int)chunk;
+    ALLOC(vbuf, char, chunk * per_point);
   }
   p->d.sched_stride = B / SWIFTCL_NXCD + 2;
   ALLOC(sched, int, (size_t)(SWIFTCL_NXCD + 1) * p->d.sched_stride);
@@ -552,6 +571,10 @@ extern "C" swiftcl_status swiftcl_cl_backward(swiftcl_plan_t p, const swiftcl_in
   swiftcl_status st = check_inputs(p, in);
   if (st != SWIFTCL_OK) return st;
   if (!dC) { set_error("dC is NULL"); return SWIFTCL_E_INVALID; }
+  if (!p->d.fused || p->d.precision == SWIFTCL_SPLIT_BF16) {
+    set_error("the adjoint is built for plans whose windows fit in LDS (<= 16 tracers) in FP32 or FP64");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
   if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
@@ -567,6 +590,10 @@ extern "C" swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t p, const swif
   swiftcl_status st = check_inputs(p, in);
   if (st != SWIFTCL_OK) return st;
   if (!dC || !stage_ms) { set_error("dC or stage_ms is NULL"); return SWIFTCL_E_INVALID; }
+  if (!p->d.fused || p->d.precision == SWIFTCL_SPLIT_BF16) {
+    set_error("the adjoint is built for plans whose windows fit in LDS (<= 16 tracers) in FP32 or FP64");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
   if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
@@ -666,7 +693,7 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
     hipError_t e = launch_assemble(p->d, in, s);
     if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
     float tf[2] = {1e30f, 1e30f};
-    for (int m = 0; m < 2 && e == hipSuccess; ++m) {
+    for (int m = 0; m < (p->d.fused ? 2 : 1) && e == hipSuccess; ++m) {
       p->d.fwd_mode = m;
       tf[m] = time_ms(s, [&]() { return launch_windows_cl(p->d, in, nullptr, C, s); }, &e);
     }
@@ -674,7 +701,7 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
     p->d.fwd_mode = tf[1] < tf[0] ? 1 : 0;
     float tb[3] = {1e30f, 1e30f, 1e30f};
     const int muls[3] = {1, 2, 4};
-    if (dC) {
+    if (dC && p->d.fused && p->d.precision != SWIFTCL_SPLIT_BF16) {
       for (int i = 0; i < 3 && e == hipSuccess; ++i) {
         p->d.bwd_chunk_mul = muls[i];
         tb[i] = time_ms(s, [&]() { return launch_backward(p->d, in, dC, nullptr, nullptr, nullptr, nullptr, s); }, &e);

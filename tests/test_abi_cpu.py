@@ -75,7 +75,7 @@ def _desc(**over):
     (dict(fftlog_b00=1.2), -2),                              # b >= 1 outside eq. int_jl range
     (dict(n_bands=0), -1),
     (dict(taper_frac=1.0), -1),
-    (dict(max_tracers=17), -5),
+    (dict(max_tracers=33), -5),
     (dict(max_batch=0), -1),
     (dict(precision=7), -1),
     (dict(edge_node=600), -1),
