@@ -47,20 +47,28 @@ int backward_chunks(const plan_dev& p, int batch) {
 // Per multipole: recompute W (forward FFT), Y = G W on MFMA, dP partial, dx, r2c, accumulate dc.
 // Partial dc per (point, chunk, tracer, band) and partial sum_t W Y per (point, chunk, k) go to
 // the workspace; k_bwd_coeffs and k_bwd_geometry reduce them.
+// LDS: twiddles, then (FP32, COMPACT) WY[16][compact_vs] whose row t is also the FFT scratch of
+// wavefront t and the workgroup's dP partial dps[n_k] (~77 KiB for n_chi = n_k = 1024); or (FP64)
+// per-wave scratch [NW][FL] and WY[16][n_k + 2].  The dc accumulators held in registers across the
+// multipole loop need ~126 VGPRs, so one 1024-thread workgroup runs per CU (forcing two costs more
+// in spills than the occupancy gains).
 template <typename R, int M, int NW, bool TW_LDS>
 __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inputs in, const R* __restrict__ dC,
                                                          int nchunk) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr bool COMPACT = sizeof(R) == 4 && NW == 16;
   constexpr int RL = M / SWIFTCL_WAVE;
   constexpr int N = 2 * M;
-  constexpr int FL = fft_lds_size(M);
+  constexpr int FL = fft_lds_size(M, sizeof(R));
   constexpr int NTW = TW_LDS ? N : 0;
+  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
+  const int vs = COMPACT ? compact_vs(nk, M) : nk + 2;
   C2<R>* stw_l = (C2<R>*)smem;
-  C2<R>* fbuf = stw_l + NTW;                                           // [NW][FL]
-  R* WY = (R*)(smem + ((size_t)NTW + (size_t)NW * FL) * sizeof(C2<R>));  // [16][n_k + 2]
+  C2<R>* fbuf = stw_l + NTW;                                                              // [NW][FL]
+  R* WY = (R*)(smem + ((size_t)NTW + (COMPACT ? 0 : (size_t)NW * FL)) * sizeof(C2<R>));  // [16][vs]
+  R* dps = WY + (size_t)16 * vs;                                                          // [nk] (COMPACT)
   __shared__ R G[16][16];
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
-  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
   const int xcd = blockIdx.x % SWIFTCL_NXCD;
   const int rest = blockIdx.x / SWIFTCL_NXCD;
   const int chunk = rest % nchunk;
@@ -69,7 +77,6 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   const int Tb = clampb(in.n_tracers[b], 0, T);
   const int Lb = clampb(in.n_ell[b], 0, Lm);
   const int l0 = (int)(((long)chunk * Lb) / nchunk), l1 = (int)(((long)(chunk + 1) * Lb) / nchunk);
-  const int vs = nk + 2;
   const int npair = T * (T + 1) / 2;
   const C2<R>* stw = TW_LDS ? stw_l : (const C2<R>*)P.tw;
   if constexpr (TW_LDS) {
@@ -79,12 +86,14 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   const size_t slot = (size_t)b * nchunk + chunk;
   C2<R>* part = (C2<R>*)P.dchat_part + slot * T * nb * M;
   for (size_t i = threadIdx.x; i < (size_t)T * nb * M; i += NW * 64) part[i] = mk<R>(0, 0);
-  C2<R>* mine = fbuf + (size_t)wave * FL;
   const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
   const int ntiles = (nk + 15) / 16;
   // this workgroup's slice of the dP partials: column k is owned by one lane of one wavefront
   R* dpp = (R*)P.dpk_part + slot * nk;
-  for (int k = threadIdx.x; k < nk; k += NW * 64) dpp[k] = (R)0;
+  for (int k = threadIdx.x; k < nk; k += NW * 64) {
+    if (COMPACT) dps[k] = (R)0;
+    else dpp[k] = (R)0;
+  }
   C2<R> acc[RL];
 #pragma unroll
   for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
@@ -132,6 +141,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       const int kind = in.kind[(size_t)b * T + t] & 1;
       const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
       const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
+      C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)t * vs) : fbuf + (size_t)wave * FL;
       C2<R> v[RL];
       wave_sync();
 #pragma unroll
@@ -139,7 +149,10 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
         const int n = lane + SWIFTCL_WAVE * e;
         v[e] = cconj(cmul(ch[n], Ur[n]));
       }
-      wave_c2r<R, M>(v, mine, stw, lane);
+      int ln = lane;  // opaque copy: keeps the FFT's per-lane LDS addresses out of the multipole loop
+      asm volatile("" : "+v"(ln));
+      wave_c2r<R, M>(v, mine, stw, ln);
+      wave_sync();
       const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
       const R F = kind ? Fl : (R)1;
 #pragma unroll
@@ -171,7 +184,10 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       }
       s += __shfl_xor(s, 16);
       s += __shfl_xor(s, 32);
-      if (lane < 16 && col < nk) dpp[col] += s;
+      if (lane < 16 && col < nk) {
+        if (COMPACT) dps[col] += s;
+        else dpp[col] += s;
+      }
       wave_sync();
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -185,6 +201,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       const int kind = in.kind[(size_t)b * T + t] & 1;
       const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
       const R F = kind ? Fl : (R)1;
+      C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)t * vs) : fbuf + (size_t)wave * FL;
       C2<R> v[RL];
 #pragma unroll
       for (int e = 0; e < RL; ++e) {
@@ -199,7 +216,9 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
         }
       }
       wave_sync();
-      wave_r2c<R, M>(v, mine, stw, lane);
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
+      wave_r2c<R, M>(v, mine, stw, ln);
       const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
       if constexpr (NW >= 16) {
         // one tracer per wavefront: accumulate in registers, flushed when the band changes
@@ -229,13 +248,15 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]);
     }
   }
+  if (COMPACT)
+    for (int k = threadIdx.x; k < nk; k += NW * 64) dpp[k] = dps[k];  // the loop ended on a barrier
 }
 
 // Reduce dc over chunks and take it back through the forward real transform: dg per
 // (point, tracer, band), one wavefront per row.
 template <typename R, int M>
 __global__ __launch_bounds__(256) void k_bwd_coeffs(plan_dev P, swiftcl_inputs in, int nchunk) {
-  __shared__ C2<R> lds[4][fft_lds_size(M)];
+  __shared__ C2<R> lds[4][fft_lds_size(M, sizeof(R))];
   constexpr int RL = M / SWIFTCL_WAVE;
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, nb = P.n_bands, N = P.N;
@@ -501,7 +522,9 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   constexpr int NW = dp ? 2 : 16;
   constexpr bool TW = !dp;
   const int nchunk = backward_chunks(p, in->batch);
-  const size_t lds = windows_cl_lds(M, NW, TW, true, sizeof(R), p.n_k);
+  const size_t lds = dp ? windows_cl_lds(M, NW, TW, true, sizeof(R), p.n_k)
+                        : (TW ? 2 * (size_t)M * sizeof(C2<R>) : 0) +
+                              ((size_t)16 * compact_vs(p.n_k, M) + (size_t)p.n_k) * sizeof(R);
   auto k1 = k_bwd_windows<R, M, NW, TW>;
   hipError_t e;
   const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;

@@ -94,11 +94,27 @@ template <> struct fft_plan<512> { static constexpr int RL = 8, NP = 3; static c
 template <> struct fft_plan<1024> { static constexpr int RL = 16, NP = 3; static constexpr int rad[3] = {16, 8, 8}; };
 template <> struct fft_plan<2048> { static constexpr int RL = 32, NP = 3; static constexpr int rad[3] = {16, 16, 8}; };
 
-// LDS scratch layout of the wave FFT: one padding element every 8 complex values, so the
-// strided writes of the Stockham passes spread over all banks.  A wavefront's scratch holds
-// fft_lds_size(M) complex values.
-__host__ __device__ constexpr int fft_pad(int c) { return c + (c >> 3); }
-__host__ __device__ constexpr int fft_lds_size(int M) { return M + M / 8; }
+// LDS scratch layout of the wave FFT (64 banks of 4 bytes; a 64-bit access is served per half
+// wavefront, so 32 lanes must hit 32 distinct complex slots mod 32).
+//  * FP32, M = 512 (radix 8, 8, 8): an XOR swizzle of the complex index, no padding.  The low five
+//    bits are flipped by bits 5..7: the first pass writes 8 q + i (q = lane), the second
+//    64 (q / 8) + q % 8 + 8 i, every other access is 32 consecutive slots, and each of these
+//    lands on 32 distinct slots mod 32.
+//  * otherwise: one padding element every 8 complex values (the stride-8 writes of radix 8 and
+//    the quarter-wave 128-bit accesses of FP64 spread over all banks).
+// A wavefront's scratch holds fft_lds_size(M, sizeof(R)) complex values.
+__host__ __device__ constexpr bool fft_swizzled(int M, int rs) { return rs == 4 && M == 512; }
+__host__ __device__ constexpr int fft_lds_size(int M, int rs) { return fft_swizzled(M, rs) ? M : M + M / 8; }
+// Row stride (floats) of a [16][n_k] LDS tile whose row t doubles as the FFT scratch of the
+// wavefront that owns tracer t: room for both, and == 4 (mod 64) so that an MFMA operand read of
+// 16 rows x 4 consecutive k touches 64 distinct banks.
+__host__ __device__ constexpr int compact_vs(int n_k, int M) {
+  return (((n_k > 2 * fft_lds_size(M, 4) ? n_k : 2 * fft_lds_size(M, 4)) + 63) / 64) * 64 + 4;
+}
+template <typename R, int M> __device__ __forceinline__ int fft_at(int c) {
+  if constexpr (fft_swizzled(M, (int)sizeof(R))) return c ^ (((c >> 5) & 7) | (((c >> 6) & 3) << 3));
+  else return c + (c >> 3);
+}
 
 // One Stockham pass (self-sorting, natural-order output) of radix r on an M-point sequence.
 // Butterfly q (q = lane + 64 u) reads x[q + i M/r], applies twiddles e^{S 2 pi i i j / (Ls r)}
@@ -123,7 +139,7 @@ __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>*
     for (int u = 0; u < BPL; ++u) {
       const int q = lane + SWIFTCL_WAVE * u;
 #pragma unroll
-      for (int i = 0; i < r; ++i) b[u * r + i] = lds[fft_pad(q + i * (M / r))];
+      for (int i = 0; i < r; ++i) b[u * r + i] = lds[fft_at<R, M>(q + i * (M / r))];
     }
     wave_sync();
   }
@@ -153,14 +169,14 @@ __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>*
       const int j = q & (Ls - 1);
       const int base = (q / Ls) * L + j;
 #pragma unroll
-      for (int i = 0; i < r; ++i) lds[fft_pad(base + i * Ls)] = b[u * r + i];
+      for (int i = 0; i < r; ++i) lds[fft_at<R, M>(base + i * Ls)] = b[u * r + i];
     }
     wave_sync();
   }
 }
 
 // M-point complex FFT by one wavefront.  In and out: v[e] holds element lane + 64 e (natural
-// order).  lds: fft_lds_size(M) complex of scratch private to this wavefront.  S = -1 forward, +1 inverse
+// order).  lds: fft_lds_size(M, sizeof(R)) complex of scratch private to this wavefront.  S = -1 forward, +1 inverse
 // (unnormalised).  The twiddle table has N = 2M entries.
 template <typename R, int M, int S>
 __device__ __forceinline__ void wave_fft(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
@@ -198,7 +214,7 @@ __device__ __forceinline__ void wave_r2c(C2<R>* v, C2<R>* lds, const C2<R>* __re
   constexpr int RL = M / SWIFTCL_WAVE;
   wave_fft<R, M, -1>(v, lds, tw, lane);
 #pragma unroll
-  for (int e = 0; e < RL; ++e) lds[fft_pad(lane + SWIFTCL_WAVE * e)] = v[e];
+  for (int e = 0; e < RL; ++e) lds[fft_at<R, M>(lane + SWIFTCL_WAVE * e)] = v[e];
   wave_sync();
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
@@ -207,7 +223,7 @@ __device__ __forceinline__ void wave_r2c(C2<R>* v, C2<R>* lds, const C2<R>* __re
     if (n == 0) {
       v[e] = mk<R>(Zn.x + Zn.y, (R)0);
     } else {
-      const C2<R> Zm = cconj(lds[fft_pad(M - n)]);
+      const C2<R> Zm = cconj(lds[fft_at<R, M>(M - n)]);
       const C2<R> A = cscale(cadd(Zn, Zm), (R)0.5);
       const C2<R> Bd = cscale(csub(Zn, Zm), (R)0.5);
       const C2<R> t2 = cmul(tw[n], Bd);
@@ -224,7 +240,7 @@ template <typename R, int M>
 __device__ __forceinline__ void wave_c2r(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
   constexpr int RL = M / SWIFTCL_WAVE;
 #pragma unroll
-  for (int e = 0; e < RL; ++e) lds[fft_pad(lane + SWIFTCL_WAVE * e)] = v[e];
+  for (int e = 0; e < RL; ++e) lds[fft_at<R, M>(lane + SWIFTCL_WAVE * e)] = v[e];
   wave_sync();
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
@@ -232,7 +248,7 @@ __device__ __forceinline__ void wave_c2r(C2<R>* v, C2<R>* lds, const C2<R>* __re
     if (n == 0) {
       v[e] = mk<R>(v[e].x, v[e].x);  // X_0 (1 + i)
     } else {
-      const C2<R> Xm = cconj(lds[fft_pad(M - n)]);  // X_{n+M} = conj(X_{M-n})
+      const C2<R> Xm = cconj(lds[fft_at<R, M>(M - n)]);  // X_{n+M} = conj(X_{M-n})
       const C2<R> A = cadd(v[e], Xm);
       const C2<R> Bd = csub(v[e], Xm);
       const C2<R> t2 = cmul(cconj(tw[n]), Bd);

@@ -69,7 +69,7 @@ __global__ void k_sqrt_s(plan_dev P, swiftcl_inputs in) {
 // FFTLog coefficients: one wavefront per (point, tracer, band) row.
 template <typename R, int M>
 __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs in) {
-  __shared__ C2<R> lds[4][fft_lds_size(M)];
+  __shared__ C2<R> lds[4][fft_lds_size(M, sizeof(R))];
   constexpr int RL = M / SWIFTCL_WAVE;
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, nb = P.n_bands, N = P.N;
@@ -107,12 +107,15 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
 
 // Windows and / or C_l of one (point, multipole slot) by a workgroup of NW wavefronts (wave t
 // handles tracer t); stw: twiddles (LDS or global), fbuf: per-wave FFT scratch, V: sqrt(s) W.
-template <typename R, int M, int NW, bool WRITE_W, bool DO_CL, bool SPLIT>
+// COMPACT (FP32 projection): the FFT scratch of tracer t lives in V's row t (the wavefront writes
+// the row only after its transform): twiddles + 16 x compact_vs floats of LDS, which for
+// n_chi <= 1024 and n_k <= 1024 is 72 KiB, so two 1024-thread workgroups share a CU.
+template <typename R, int M, int NW, bool WRITE_W, bool DO_CL, bool SPLIT, bool COMPACT>
 __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl_inputs& in, R* __restrict__ Wout,
                                                 R* __restrict__ Cout, int b, int li, const C2<R>* stw, C2<R>* fbuf,
                                                 R* V) {
   constexpr int RL = M / SWIFTCL_WAVE;
-  constexpr int FL = fft_lds_size(M);
+  constexpr int FL = fft_lds_size(M, sizeof(R));
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
   const int Tb = clampi(in.n_tracers[b], 0, T);
@@ -134,11 +137,10 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
     if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
     ei = 0;
   }
-  const int vs = nk + 2;  // row stride of V: rows start on distinct banks
+  const int vs = COMPACT ? compact_vs(nk, M) : nk + 2;  // row stride of V: rows start on distinct banks
   const int band = P.ell_band[ei];
   const R Fl = (R)P.fell[ei];
   const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
-  C2<R>* mine = fbuf + (size_t)wave * FL;
   const int trows = DO_CL ? 16 : T;
   for (int t = wave; t < trows; t += NW) {
     if (t >= Tb) {
@@ -151,6 +153,7 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
     const int kind = in.kind[(size_t)b * T + t] & 1;
     const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
     const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
+    C2<R>* mine = COMPACT ? (C2<R>*)(V + (size_t)t * vs) : fbuf + (size_t)wave * FL;
     C2<R> v[RL];
     wave_sync();
 #pragma unroll
@@ -158,7 +161,10 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
       const int n = lane + SWIFTCL_WAVE * e;
       v[e] = cconj(cmul(ch[n], Ur[n]));  // X_n = conj(c_n U_l(n))
     }
-    wave_c2r<R, M>(v, mine, stw, lane);
+    int ln = lane;  // opaque copy: keeps the FFT's per-lane LDS addresses from being hoisted
+    asm volatile("" : "+v"(ln));
+    wave_c2r<R, M>(v, mine, stw, ln);
+    wave_sync();
     const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
     const R F = kind ? Fl : (R)1;
 #pragma unroll
@@ -210,7 +216,8 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
       acc = mfma_acc<R>::step(a, a, acc);
     }
   }
-  R* red = (R*)fbuf;  // the FFT scratch is free now: [NW][256]
+  R* red = COMPACT ? V : (R*)fbuf;  // [NW][256]: the FFT scratch, or V once every wave has read it
+  if (COMPACT) __syncthreads();
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[wave * 256 + mfma_acc<R>::row(lane, r) * 16 + (lane & 15)] = acc[r];
   __syncthreads();
@@ -234,15 +241,17 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
 // (point b = 8 i + x, multipole) items built by k_schedule (ragged multipole counts leave no idle
 // workgroup, and every block loads the twiddles once); padded slots are zeroed by k_zero_padded.
 template <typename R, int M, int NW, bool TW_LDS, bool WRITE_W, bool DO_CL, bool PERSIST, bool SPLIT>
-__global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inputs in, R* __restrict__ Wout,
-                                                        R* __restrict__ Cout) {
+__global__ __launch_bounds__(NW * 64)
+__attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && DO_CL && M <= 512) ? 8 : 1))) void k_windows_cl(
+    plan_dev P, swiftcl_inputs in, R* __restrict__ Wout, R* __restrict__ Cout) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr bool COMPACT = sizeof(R) == 4 && DO_CL;
   constexpr int N = 2 * M;
-  constexpr int FL = fft_lds_size(M);
+  constexpr int FL = fft_lds_size(M, sizeof(R));
   constexpr int NTW = TW_LDS ? N : 0;
-  C2<R>* stw_l = (C2<R>*)smem;                                        // [N] twiddles (TW_LDS)
-  C2<R>* fbuf = stw_l + NTW;                                          // [NW][FL]
-  R* V = (R*)(smem + ((size_t)NTW + (size_t)NW * FL) * sizeof(C2<R>));  // [16][n_k + 2]
+  C2<R>* stw_l = (C2<R>*)smem;  // [N] twiddles (TW_LDS)
+  C2<R>* fbuf = stw_l + NTW;    // [NW][FL] (not COMPACT)
+  R* V = (R*)(smem + ((size_t)NTW + (COMPACT ? 0 : (size_t)NW * FL)) * sizeof(C2<R>));  // [16][vs]
   const int xcd = blockIdx.x % SWIFTCL_NXCD;
   const int rest = blockIdx.x / SWIFTCL_NXCD;
   const C2<R>* stw = TW_LDS ? stw_l : (const C2<R>*)P.tw;
@@ -255,7 +264,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
       for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
       __syncthreads();
     }
-    windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT>(P, in, Wout, Cout, b, li, stw, fbuf, V);
+    windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT, COMPACT>(P, in, Wout, Cout, b, li, stw, fbuf, V);
   } else {
     if constexpr (TW_LDS) {
       const C2<R>* gtw = (const C2<R>*)P.tw;
@@ -274,7 +283,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_cl(plan_dev P, swiftcl_inpu
         if (offs[mid] <= k) lo = mid; else hi = mid;
       }
       const int b = lo * SWIFTCL_NXCD + xcd;
-      windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT>(P, in, Wout, Cout, b, k - offs[lo], stw, fbuf, V);
+      windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT, COMPACT>(P, in, Wout, Cout, b, k - offs[lo], stw, fbuf, V);
       __syncthreads();
     }
   }
@@ -328,7 +337,7 @@ hipError_t launch_forward_fft(const plan_dev& p, const swiftcl_inputs* in, hipSt
 
 // LDS bytes of the fused kernel (twiddles, per-wave FFT scratch, V)
 size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k) {
-  return ((tw_lds ? 2 * (size_t)M : 0) + (size_t)NW * fft_lds_size(M)) * 2 * rs +
+  return ((tw_lds ? 2 * (size_t)M : 0) + (size_t)NW * fft_lds_size(M, (int)rs)) * 2 * rs +
          (do_cl ? (size_t)16 * (n_k + 2) * rs : 0);
 }
 
@@ -359,7 +368,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
   typedef float R;
   constexpr int RL = M / SWIFTCL_WAVE;
   constexpr int N = 2 * M;
-  constexpr int FL = fft_lds_size(M);
+  constexpr int FL = fft_lds_size(M, sizeof(R));
   constexpr int NTW = TW_LDS ? N : 0;
   C2<R>* stw_l = (C2<R>*)smem;
   C2<R>* fbuf = stw_l + NTW;
@@ -556,7 +565,9 @@ template <typename R, int M, bool WRITE_W, bool DO_CL>
 static hipError_t launch_wcl_t(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s) {
   constexpr int NW = wcl_shape<R, M>::NW;
   constexpr bool TW = wcl_shape<R, M>::TW;
-  const size_t lds = windows_cl_lds(M, NW, TW, DO_CL, sizeof(R), p.n_k);
+  const size_t lds = (sizeof(R) == 4 && DO_CL)
+                         ? (TW ? 2 * (size_t)M * sizeof(C2<R>) : 0) + (size_t)16 * compact_vs(p.n_k, M) * sizeof(R)
+                         : windows_cl_lds(M, NW, TW, DO_CL, sizeof(R), p.n_k);
   const bool split = p.precision == SWIFTCL_SPLIT_BF16;
   if (DO_CL && !WRITE_W && p.fwd_mode == 1) {
     hipLaunchKernelGGL(k_schedule, dim3(1), dim3(64), 0, s, p, *in);
@@ -564,15 +575,17 @@ static hipError_t launch_wcl_t(const plan_dev& p, const swiftcl_inputs* in, void
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_padded<R>, dim3(p.max_ell, in->batch), dim3(128), 0, s, p, *in, (R*)C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the FP32 projection runs two workgroups per CU
+    const dim3 pgrid((unsigned)(p.persist_blocks * ((sizeof(R) == 4 && M <= 512) ? 2 : 1)));
     if constexpr (sizeof(R) == 4) {
       if (split) {
-        hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, true, true>), dim3(p.persist_blocks),
-                           dim3(NW * 64), lds, s, p, *in, (R*)W, (R*)C);
+        hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, true, true>), pgrid, dim3(NW * 64), lds, s, p,
+                           *in, (R*)W, (R*)C);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, true, false>), dim3(p.persist_blocks), dim3(NW * 64),
-                       lds, s, p, *in, (R*)W, (R*)C);
+    hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, true, false>), pgrid, dim3(NW * 64), lds, s, p, *in,
+                       (R*)W, (R*)C);
     return hipGetLastError();
   }
   const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
