@@ -100,27 +100,18 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   int cur_band = -1;
   __syncthreads();
 
-  for (int li = l0; li < l1; ++li) {
-    int ei = in.ell_idx[(size_t)b * Lm + li];
+  // multipole slot -> (union index, band, F(l)); a bad index is flagged and read as 0
+  auto ell_of = [&](int li, int& ei, int& band, R& Fl) {
+    ei = in.ell_idx[(size_t)b * Lm + li];
     if (ei < 0 || ei >= P.n_ell) {
       if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
       ei = 0;
     }
-    const int band = P.ell_band[ei];
-    const R Fl = (R)P.fell[ei];
-    if (NW >= 16 && band != cur_band) {
-      if (cur_band >= 0) {
-        for (int t = wave; t < Tb; t += NW) {
-          C2<R>* dst = part + ((size_t)t * nb + cur_band) * M;
-#pragma unroll
-          for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]);
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
-      cur_band = band;
-    }
-    // G of this multipole (symmetrised cotangent)
+    band = P.ell_band[ei];
+    Fl = (R)P.fell[ei];
+  };
+  // G of multipole slot li (symmetrised cotangent)
+  auto load_G = [&](int li) {
     for (int gi = threadIdx.x; gi < 256; gi += NW * 64) {
       const int i = gi / 16, j = gi % 16;
       R gv = (R)0;
@@ -132,7 +123,9 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       }
       G[i][j] = gv;
     }
-    // (1) W of every tracer into LDS
+  };
+  // (1) W of every tracer of multipole (ei, band, Fl) into its LDS row
+  auto windows = [&](int ei, int band, R Fl) {
     for (int t = wave; t < 16; t += NW) {
       if (t >= Tb) {
         for (int j = lane; j < nk; j += SWIFTCL_WAVE) WY[t * vs + j] = (R)0;
@@ -164,7 +157,20 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
         }
       }
     }
-    __syncthreads();
+  };
+
+  // Software pipeline over the multipoles of this chunk, two barriers per multipole: the adjoint
+  // transforms of slot li share a barrier interval with the windows of slot li + 1 (each wavefront
+  // only touches its own LDS rows there).
+  int ei = 0, band = 0;
+  R Fl = (R)0;
+  if (l0 < l1) {
+    ell_of(l0, ei, band, Fl);
+    load_G(l0);
+    windows(ei, band, Fl);
+  }
+  __syncthreads();
+  for (int li = l0; li < l1; ++li) {
     // (2) Y = G W on MFMA, tile by tile of 16 k (each tile owned by one wavefront, in place)
     using acc_t = typename bmfma<R>::type;
     for (int tile = wave; tile < ntiles; tile += NW) {
@@ -196,6 +202,18 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       }
     }
     __syncthreads();
+    if (NW >= 16 && band != cur_band) {
+      if (cur_band >= 0) {
+        for (int t = wave; t < Tb; t += NW) {
+          C2<R>* dst = part + ((size_t)t * nb + cur_band) * M;
+#pragma unroll
+          for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
+      cur_band = band;
+    }
     // (3) dx = 2 s F k^{-1-b} Y, r2c, dc += h_n conj(X_n) conj(U_l(n))
     for (int t = wave; t < Tb; t += NW) {
       const int kind = in.kind[(size_t)b * T + t] & 1;
@@ -238,6 +256,12 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
           dst[n] = cadd(dst[n], cscale(cmul(cconj(v[e]), cconj(Ur[n])), h));
         }
       }
+    }
+    // (1) for the next slot
+    if (li + 1 < l1) {
+      ell_of(li + 1, ei, band, Fl);
+      load_G(li + 1);
+      windows(ei, band, Fl);
     }
     __syncthreads();
   }
@@ -468,12 +492,14 @@ __global__ __launch_bounds__(512) void k_bwd_geometry(plan_dev P, swiftcl_inputs
         const double a = P.z_union[u], c = P.z_union[u + 1];
         const int ig = P.union_iv[u];
         const double w0 = seg0[u], w1 = seg1[u];
+        spline_adj_acc ac;
         for (int qn = 0; qn < 12; ++qn) {
           const double z = 0.5 * (c - a) * c_gl12_x[qn] + 0.5 * (a + c);
           const double w = 0.5 * (c - a) * c_gl12_w[qn];
           const double x = spline_at(zg, zgih, chi, mchi, ig, z, nullptr);
-          spline_value_adjoint(zs, zsih, iv, z, w * (w0 + w1 / x), dny, dnM);
+          ac.add(zs, zsih, iv, z, w * (w0 + w1 / x));
         }
+        ac.flush(zs, iv, dny, dnM);
       }
 #pragma unroll
       for (int k = 0; k < MAXN; ++k) {
@@ -484,12 +510,14 @@ __global__ __launch_bounds__(512) void k_bwd_geometry(plan_dev P, swiftcl_inputs
                   P.union_iv);
         if (s.uni < 0) continue;
         const double a = s.z, c = s.zc;
+        spline_adj_acc ac;
         for (int qn = 0; qn < 12; ++qn) {
           const double z = 0.5 * (c - a) * c_gl12_x[qn] + 0.5 * (a + c);
           const double w = 0.5 * (c - a) * c_gl12_w[qn];
           const double x = spline_at(zg, zgih, chi, mchi, s.ugi, z, nullptr);
-          spline_value_adjoint(zs, zsih, s.uni, z, w * (dI0[k] + dI1[k] / x), dny, dnM);
+          ac.add(zs, zsih, s.uni, z, w * (dI0[k] + dI1[k] / x));
         }
+        ac.flush(zs, s.uni, dny, dnM);
       }
     }
     // bias: block reduction

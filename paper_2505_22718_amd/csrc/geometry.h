@@ -215,6 +215,28 @@ __device__ __forceinline__ void spline_value_adjoint(const double* __restrict__ 
   unsafeAtomicAdd(&dM[i + 1], (B * B * B - B) * (h * h / 6.0) * dv);
 }
 
+// The same four cotangent weights summed in registers over points of one interval i (z, dv),
+// then added to LDS once: flush() after the last point.
+struct spline_adj_acc {
+  double y0 = 0.0, y1 = 0.0, m0 = 0.0, m1 = 0.0;
+  __device__ __forceinline__ void add(const double* __restrict__ x, const double* __restrict__ ih, int i, double z,
+                                      double dv) {
+    const double A = (x[i + 1] - z) * ih[i];
+    const double B = (z - x[i]) * ih[i];
+    y0 += A * dv;
+    y1 += B * dv;
+    m0 += (A * A * A - A) * dv;
+    m1 += (B * B * B - B) * dv;
+  }
+  __device__ __forceinline__ void flush(const double* __restrict__ x, int i, double* dy, double* dM) const {
+    const double h = x[i + 1] - x[i];
+    unsafeAtomicAdd(&dy[i], y0);
+    unsafeAtomicAdd(&dy[i + 1], y1);
+    unsafeAtomicAdd(&dM[i], m0 * (h * h / 6.0));
+    unsafeAtomicAdd(&dM[i + 1], m1 * (h * h / 6.0));
+  }
+};
+
 // In-place suffix sums x[u] <- sum_{v >= u} x[v] (prefix = false) or exclusive prefix sums
 // x[u] <- sum_{v < u} x[v] (prefix = true) over n values in LDS, by the whole block.
 // tmp: 2 * (blockDim / 64) doubles of LDS.
