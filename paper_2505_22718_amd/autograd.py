@@ -20,6 +20,9 @@ class ClFunction(torch.autograd.Function):
         C = plan.cl(t)
         ctx.plan = plan
         ctx.t = t
+        ctx.token = plan.state_token
+        # torch checks at backward time that none of these was modified in place since
+        ctx.save_for_backward(pk, bias, nz, D_z)
         return C
 
     @staticmethod
@@ -27,7 +30,10 @@ class ClFunction(torch.autograd.Function):
         want = [name for name, need in zip(("pk", "bias", "nz", "D"), ctx.needs_input_grad[2:]) if need]
         if not want:
             return None, None, None, None, None, None
-        g = ctx.plan.backward(ctx.t, dC.to(ctx.plan.out_dtype).contiguous(), want=tuple(want))
+        ctx.saved_tensors  # raises if an input was modified in place after the forward call
+        # no other forward on this plan since ours: its assembly and FFTLog state are still ours
+        reuse = ctx.plan.state_token is ctx.token
+        g = ctx.plan.backward(ctx.t, dC.to(ctx.plan.out_dtype).contiguous(), want=tuple(want), reuse_forward=reuse)
         return None, None, g.get("pk"), g.get("bias"), g.get("nz"), g.get("D")
 
 

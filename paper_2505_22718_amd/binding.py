@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_DOMAIN", -3: "E_NOMEM", -4: "E_
 
 SWIFTCL_CLUSTERING = 0
 SWIFTCL_LENSING = 1
+SWIFTCL_BWD_REUSE_FORWARD = 1
 SWIFTCL_FP64 = 0
 SWIFTCL_FP32 = 1
 SWIFTCL_SPLIT_BF16 = 2
@@ -95,13 +96,13 @@ def load(path: str = LIB_PATH):
     lib.swiftcl_windows.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
     lib.swiftcl_cl.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
     lib.swiftcl_cl_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, ctypes.POINTER(ctypes.c_float)]
-    lib.swiftcl_cl_backward.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, vp]
+    lib.swiftcl_cl_backward.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, ctypes.c_uint32, vp]
     lib.swiftcl_autotune.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, ctypes.c_char_p,
                                      ctypes.c_char_p, ctypes.c_int32]
     lib.swiftcl_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     lib.swiftcl_get_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
-    lib.swiftcl_cl_backward_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, vp,
-                                              ctypes.POINTER(ctypes.c_float)]
+    lib.swiftcl_cl_backward_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp,
+                                              ctypes.c_uint32, vp, ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTED:
         f = getattr(lib, name)
         if name != "swiftcl_last_error":
@@ -158,19 +159,19 @@ def swiftcl_cl_timed(plan, inputs: swiftcl_inputs, C: int, stream: int = 0):
 
 
 def swiftcl_cl_backward(plan, inputs: swiftcl_inputs, dC: int, dpk: int = 0, dbias: int = 0, dnz: int = 0,
-                        dD: int = 0, stream: int = 0):
+                        dD: int = 0, flags: int = 0, stream: int = 0):
     vp = ctypes.c_void_p
     _check(load().swiftcl_cl_backward(plan, ctypes.byref(inputs), vp(dC), vp(dpk or None), vp(dbias or None),
-                                      vp(dnz or None), vp(dD or None), vp(stream)))
+                                      vp(dnz or None), vp(dD or None), ctypes.c_uint32(flags), vp(stream)))
 
 
 def swiftcl_cl_backward_timed(plan, inputs: swiftcl_inputs, dC: int, dpk: int = 0, dbias: int = 0, dnz: int = 0,
-                              dD: int = 0, stream: int = 0):
+                              dD: int = 0, flags: int = 0, stream: int = 0):
     """Returns the device time (ms) of the five stages of a backward call."""
     vp = ctypes.c_void_p
     ms = (ctypes.c_float * 5)()
     _check(load().swiftcl_cl_backward_timed(plan, ctypes.byref(inputs), vp(dC), vp(dpk or None), vp(dbias or None),
-                                            vp(dnz or None), vp(dD or None), vp(stream), ms))
+                                            vp(dnz or None), vp(dD or None), ctypes.c_uint32(flags), vp(stream), ms))
     return [ms[i] for i in range(5)]
 
 

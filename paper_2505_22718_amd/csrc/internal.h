@@ -79,6 +79,9 @@ struct swiftcl_plan_s {
   plan_dev d{};
   std::vector<double> ell_host;
   size_t real_size = 4;  // sizeof(real) on the FFT path
+  // inputs whose assembly and FFTLog coefficients the last forward launch left in the workspace
+  bool fwd_valid = false;
+  swiftcl_inputs fwd_in{};
 };
 
 void set_error(const std::string& msg);

@@ -518,6 +518,19 @@ static swiftcl_status check_inputs(swiftcl_plan_t p, const swiftcl_inputs* in) {
   return SWIFTCL_OK;
 }
 
+// The workspace state (kernel samples, spline moments, lensing integrals, FFTLog coefficients)
+// now belongs to `in`; a backward call may skip recomputing it (SWIFTCL_BWD_REUSE_FORWARD).
+static void note_forward(swiftcl_plan_t p, const swiftcl_inputs* in) {
+  p->fwd_valid = true;
+  p->fwd_in = *in;
+}
+
+static bool same_inputs(const swiftcl_inputs& a, const swiftcl_inputs& b) {
+  return a.batch == b.batch && a.n_tracers == b.n_tracers && a.kind == b.kind && a.n_ell == b.n_ell &&
+         a.ell_idx == b.ell_idx && a.chi_z == b.chi_z && a.D_z == b.D_z && a.omega_m == b.omega_m && a.nz == b.nz &&
+         a.bias == b.bias && a.pk == b.pk;
+}
+
 static swiftcl_status run_forward(swiftcl_plan_t p, const swiftcl_inputs* in, void* W, void* C, void* stream) {
   swiftcl_status st = check_inputs(p, in);
   if (st != SWIFTCL_OK) return st;
@@ -525,8 +538,10 @@ static swiftcl_status run_forward(swiftcl_plan_t p, const swiftcl_inputs* in, vo
   if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
+  p->fwd_valid = false;
   hipError_t e = launch_assemble(p->d, in, s);
   if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+  if (e == hipSuccess) note_forward(p, in);
   if (e == hipSuccess) e = launch_windows_cl(p->d, in, W, C, s);
   return hip_check(e, "forward launch");
 }
@@ -552,10 +567,12 @@ extern "C" swiftcl_status swiftcl_cl_timed(swiftcl_plan_t p, const swiftcl_input
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipError_t e = hipSuccess;
   for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  p->fwd_valid = false;
   if (e == hipSuccess) e = hipEventRecord(ev[0], s);
   if (e == hipSuccess) e = launch_assemble(p->d, in, s);
   if (e == hipSuccess) e = hipEventRecord(ev[1], s);
   if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+  if (e == hipSuccess) note_forward(p, in);
   if (e == hipSuccess) e = hipEventRecord(ev[2], s);
   if (e == hipSuccess) e = launch_windows_cl(p->d, in, nullptr, C, s);
   if (e == hipSuccess) e = hipEventRecord(ev[3], s);
@@ -566,44 +583,66 @@ extern "C" swiftcl_status swiftcl_cl_timed(swiftcl_plan_t p, const swiftcl_input
   return hip_check(e, "timed forward");
 }
 
-extern "C" swiftcl_status swiftcl_cl_backward(swiftcl_plan_t p, const swiftcl_inputs* in, const void* dC,
-                                              double* dpk, double* dbias, double* dnz, double* dD, void* stream) {
+// Checks shared by the two backward entry points; `reuse` is set when the forward state is kept.
+static swiftcl_status backward_checks(swiftcl_plan_t p, const swiftcl_inputs* in, const void* dC, uint32_t flags,
+                                      bool* reuse) {
   swiftcl_status st = check_inputs(p, in);
   if (st != SWIFTCL_OK) return st;
   if (!dC) { set_error("dC is NULL"); return SWIFTCL_E_INVALID; }
+  if (flags & ~(uint32_t)SWIFTCL_BWD_REUSE_FORWARD) { set_error("unknown backward flag"); return SWIFTCL_E_INVALID; }
   if (!p->d.fused || p->d.precision == SWIFTCL_SPLIT_BF16) {
     set_error("the adjoint is built for plans whose windows fit in LDS (<= 16 tracers) in FP32 or FP64");
     return SWIFTCL_E_UNSUPPORTED;
   }
-  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  *reuse = (flags & SWIFTCL_BWD_REUSE_FORWARD) != 0;
+  if (*reuse && !(p->fwd_valid && same_inputs(p->fwd_in, *in))) {
+    set_error("SWIFTCL_BWD_REUSE_FORWARD: the plan's last forward call was made with other inputs");
+    return SWIFTCL_E_INVALID;
+  }
+  return hip_check(hipSetDevice(p->d.device), "hipSetDevice");
+}
+
+extern "C" swiftcl_status swiftcl_cl_backward(swiftcl_plan_t p, const swiftcl_inputs* in, const void* dC,
+                                              double* dpk, double* dbias, double* dnz, double* dD, uint32_t flags,
+                                              void* stream) {
+  bool reuse = false;
+  swiftcl_status st = backward_checks(p, in, dC, flags, &reuse);
+  if (st != SWIFTCL_OK) return st;
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_assemble(p->d, in, s);
-  if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+  hipError_t e = hipSuccess;
+  if (!reuse) {
+    p->fwd_valid = false;
+    e = launch_assemble(p->d, in, s);
+    if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+    if (e == hipSuccess) note_forward(p, in);
+  }
   if (e == hipSuccess) e = launch_backward(p->d, in, dC, dpk, dbias, dnz, dD, s);
   return hip_check(e, "backward launch");
 }
 
 extern "C" swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t p, const swiftcl_inputs* in, const void* dC,
-                                                    double* dpk, double* dbias, double* dnz, double* dD, void* stream,
-                                                    float* stage_ms) {
-  swiftcl_status st = check_inputs(p, in);
+                                                    double* dpk, double* dbias, double* dnz, double* dD,
+                                                    uint32_t flags, void* stream, float* stage_ms) {
+  if (!stage_ms) { set_error("stage_ms is NULL"); return SWIFTCL_E_INVALID; }
+  bool reuse = false;
+  swiftcl_status st = backward_checks(p, in, dC, flags, &reuse);
   if (st != SWIFTCL_OK) return st;
-  if (!dC || !stage_ms) { set_error("dC or stage_ms is NULL"); return SWIFTCL_E_INVALID; }
-  if (!p->d.fused || p->d.precision == SWIFTCL_SPLIT_BF16) {
-    set_error("the adjoint is built for plans whose windows fit in LDS (<= 16 tracers) in FP32 or FP64");
-    return SWIFTCL_E_UNSUPPORTED;
-  }
-  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   hipError_t e = hipSuccess;
   for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
   if (e == hipSuccess) e = hipEventRecord(ev[0], s);
-  if (e == hipSuccess) e = launch_assemble(p->d, in, s);
+  if (e == hipSuccess && !reuse) {
+    p->fwd_valid = false;
+    e = launch_assemble(p->d, in, s);
+  }
   if (e == hipSuccess) e = hipEventRecord(ev[1], s);
-  if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+  if (e == hipSuccess && !reuse) {
+    e = launch_forward_fft(p->d, in, s);
+    if (e == hipSuccess) note_forward(p, in);
+  }
   if (e == hipSuccess) e = hipEventRecord(ev[2], s);
   if (e == hipSuccess) e = launch_backward(p->d, in, dC, dpk, dbias, dnz, dD, s, &ev[3]);
   if (e == hipSuccess) e = hipEventRecord(ev[5], s);
@@ -690,8 +729,10 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
     p->d.bwd_chunk_mul = cm;
     rep = "cached " + key + ": fwd_mode=" + std::to_string(fm) + " bwd_chunk_mul=" + std::to_string(cm);
   } else {
+    p->fwd_valid = false;
     hipError_t e = launch_assemble(p->d, in, s);
     if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
+    if (e == hipSuccess) note_forward(p, in);
     float tf[2] = {1e30f, 1e30f};
     for (int m = 0; m < (p->d.fused ? 2 : 1) && e == hipSuccess; ++m) {
       p->d.fwd_mode = m;

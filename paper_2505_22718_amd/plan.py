@@ -60,6 +60,7 @@ class Plan:
         self.out_dtype = torch.float64 if precision == "fp64" else torch.float32
         with torch.cuda.device(self.device):
             self.handle = bd.swiftcl_plan(d, torch.cuda.current_stream(self.device).cuda_stream)
+        self.state_token = None
 
     @classmethod
     def for_workload(cls, wl, max_batch=None, precision=None, **kw):
@@ -93,15 +94,23 @@ class Plan:
             setattr(s, name, t[name].data_ptr())
         return s
 
+    # Every call that (re)computes the workspace's forward state sets a fresh token; autograd keeps
+    # the token of its forward call and reuses the state in backward if no other call came between.
+    def _new_state(self):
+        self.state_token = object()
+        return self.state_token
+
     def cl(self, t, out=None):
         B = t["n_tracers"].shape[0]
         if out is None:
             out = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
+        self._new_state()
         bd.swiftcl_cl(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
         return out
 
     def cl_timed(self, t, out):
         """Forward C_l with per-stage device times (ms): assembly, FFTLog coefficients, windows + C."""
+        self._new_state()
         return bd.swiftcl_cl_timed(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
 
     def windows(self, t, out=None):
@@ -109,10 +118,13 @@ class Plan:
         if out is None:
             out = torch.empty((B, self.max_ell, self.max_tracers, len(self.k)), dtype=self.out_dtype,
                               device=self.device)
+        self._new_state()
         bd.swiftcl_windows(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
         return out
 
-    def backward(self, t, dC, want=("pk", "bias", "nz", "D")):
+    def backward(self, t, dC, want=("pk", "bias", "nz", "D"), reuse_forward=False):
+        """Gradients of sum(dC * C).  reuse_forward: `t` is the input of the last forward call on
+        this plan (same tensors, unmodified), whose assembly and FFTLog state are kept."""
         B = t["n_tracers"].shape[0]
         f64 = dict(dtype=torch.float64, device=self.device)
         outs = {
@@ -122,25 +134,33 @@ class Plan:
             "D": torch.empty((B, len(self.z_geom)), **f64) if "D" in want else None,
         }
         ptr = {k: (v.data_ptr() if v is not None else 0) for k, v in outs.items()}
+        if not reuse_forward:
+            self._new_state()
         bd.swiftcl_cl_backward(self.handle, self.inputs_struct(t), dC.contiguous().data_ptr(), ptr["pk"],
-                               ptr["bias"], ptr["nz"], ptr["D"], self._stream())
+                               ptr["bias"], ptr["nz"], ptr["D"], _flags(reuse_forward), self._stream())
         return {k: v for k, v in outs.items() if v is not None}
 
-    def backward_timed(self, t, dC, outs):
+    def backward_timed(self, t, dC, outs, reuse_forward=False):
         """Backward with per-stage device times (ms); outs: dict of preallocated gradient tensors."""
         ptr = {k: (outs[k].data_ptr() if outs.get(k) is not None else 0) for k in ("pk", "bias", "nz", "D")}
+        if not reuse_forward:
+            self._new_state()
         return bd.swiftcl_cl_backward_timed(self.handle, self.inputs_struct(t), dC.data_ptr(), ptr["pk"],
-                                            ptr["bias"], ptr["nz"], ptr["D"], self._stream())
+                                            ptr["bias"], ptr["nz"], ptr["D"], _flags(reuse_forward),
+                                            self._stream())
 
-    def backward_into(self, t, dC, outs):
+    def backward_into(self, t, dC, outs, reuse_forward=False):
         """Backward into preallocated gradient tensors (no allocation)."""
         ptr = {k: (outs[k].data_ptr() if outs.get(k) is not None else 0) for k in ("pk", "bias", "nz", "D")}
+        if not reuse_forward:
+            self._new_state()
         bd.swiftcl_cl_backward(self.handle, self.inputs_struct(t), dC.data_ptr(), ptr["pk"], ptr["bias"],
-                               ptr["nz"], ptr["D"], self._stream())
+                               ptr["nz"], ptr["D"], _flags(reuse_forward), self._stream())
 
     def autotune(self, t, dC=None, cache_path=None):
         """Choose the launch shapes for inputs like `t` (see swiftcl_autotune); returns the report."""
         B = t["n_tracers"].shape[0]
+        self._new_state()
         C = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
         return bd.swiftcl_autotune(self.handle, self.inputs_struct(t), C.data_ptr(),
                                    dC.data_ptr() if dC is not None else 0, self._stream(), cache_path)
@@ -155,6 +175,10 @@ class Plan:
 
     def device_flags(self):
         return bd.swiftcl_device_flags(self.handle, self._stream())
+
+
+def _flags(reuse_forward):
+    return bd.SWIFTCL_BWD_REUSE_FORWARD if reuse_forward else 0
 
 
 def device_inputs(wl, device="cuda:0", points=None):

@@ -100,5 +100,7 @@ def test_null_arguments_rejected(lib):
     inp = bd.swiftcl_inputs()
     assert lib.swiftcl_cl(None, ctypes.byref(inp), None, None) == bd.SWIFTCL_E_INVALID
     assert lib.swiftcl_windows(None, ctypes.byref(inp), None, None) == bd.SWIFTCL_E_INVALID
-    assert lib.swiftcl_cl_backward(None, ctypes.byref(inp), None, None, None, None, None, None) == bd.SWIFTCL_E_INVALID
+    assert lib.swiftcl_cl_backward(None, ctypes.byref(inp), None, None, None, None, None, 0, None) == bd.SWIFTCL_E_INVALID
+    assert lib.swiftcl_cl_backward(None, ctypes.byref(inp), None, None, None, None, None,
+                                   bd.SWIFTCL_BWD_REUSE_FORWARD, None) == bd.SWIFTCL_E_INVALID
     assert lib.swiftcl_plan_destroy(None) == bd.SWIFTCL_E_INVALID

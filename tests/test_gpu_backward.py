@@ -112,3 +112,34 @@ def test_backward_ragged(dev):
         _check(wl, G, out, 1e-4, b=b, ndir=1)
         T = int(wl["n_tracers"][b])
         assert np.all(out["nz"][b, T:] == 0)
+
+
+def test_backward_reuse_forward(dev):
+    """SWIFTCL_BWD_REUSE_FORWARD keeps the forward's assembly and FFTLog state: the gradients equal
+    those of a recomputing call (to the FP64 atomics' summation order), and the call is refused
+    when the plan's last forward had other inputs or there was none."""
+    from paper_2505_22718_amd.binding import SwiftclError, SWIFTCL_E_INVALID
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    wl = synth.make_workload("cfg3", batch=4)
+    p = Plan.for_workload(wl, precision="fp32")
+    inp = device_inputs(wl, dev)
+    rng = np.random.default_rng(3)
+    dC = torch.as_tensor(rng.standard_normal((4, wl["ell_idx"].shape[1], p.n_pairs)), dtype=torch.float32,
+                         device=dev)
+    with pytest.raises(SwiftclError) as ei:
+        p.backward(inp, dC, reuse_forward=True)
+    assert ei.value.status == SWIFTCL_E_INVALID
+    ref = p.backward(inp, dC)
+    p.cl(inp)
+    got = p.backward(inp, dC, reuse_forward=True)
+    for k in ref:
+        scale = max(ref[k].abs().max().item(), 1e-300)
+        err = (got[k] - ref[k]).abs().max().item() / scale
+        _say(f"  {k}: reuse vs recompute {err:.2e}")
+        assert err < 1e-10
+    other = dict(inp)
+    other["pk"] = inp["pk"] * 1.01  # same shapes, another buffer
+    p.cl(other)
+    with pytest.raises(SwiftclError) as ei:
+        p.backward(inp, dC, reuse_forward=True)
+    assert ei.value.status == SWIFTCL_E_INVALID

@@ -73,8 +73,8 @@ def test_autotune_and_cache(dev, tmp_path):
     assert torch.equal(plan3.cl(t), C_tuned)
 
 
-@pytest.mark.parametrize("fwd_mode", [0, 1])
-def test_graph_capture_replay(dev, fwd_mode):
+@pytest.mark.parametrize("fwd_mode,reuse", [(0, False), (1, False), (1, True)])
+def test_graph_capture_replay(dev, fwd_mode, reuse):
     from paper_2505_22718_amd.plan import Plan, device_inputs
     B = 16
     wl = synth.make_workload("cfg3", batch=B)
@@ -95,13 +95,13 @@ def test_graph_capture_replay(dev, fwd_mode):
     with torch.cuda.stream(s):
         for _ in range(2):
             plan.cl(t, C)
-            plan.backward_into(t, dC, g)
+            plan.backward_into(t, dC, g, reuse_forward=reuse)
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         plan.cl(t, C)
-        plan.backward_into(t, dC, g)
+        plan.backward_into(t, dC, g, reuse_forward=reuse)
     for r in range(3):
         C.zero_()
         for v in g.values():
@@ -116,4 +116,4 @@ def test_graph_capture_replay(dev, fwd_mode):
         other = plan.cl(t)
         torch.cuda.synchronize()
         assert torch.equal(other, C_ref)
-    _say(f"  fwd_mode={fwd_mode}: 3 replays match")
+    _say(f"  fwd_mode={fwd_mode} reuse={reuse}: 3 replays match")
