@@ -67,7 +67,10 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   C2<R>* fbuf = stw_l + NTW;                                                              // [NW][FL]
   R* WY = (R*)(smem + ((size_t)NTW + (COMPACT ? 0 : (size_t)NW * FL)) * sizeof(C2<R>));  // [16][vs]
   R* dps = WY + (size_t)16 * vs;                                                          // [nk] (COMPACT)
-  __shared__ R G[16][16];
+  // G in MFMA operand order: Gp[s][l] = G[l % 16][4 (l / 16) + s] is what lane l feeds at
+  // reduction step s (the step covers tracers s, s + 4, s + 8, s + 12, so the W operand reads of
+  // 4 rows x 16 k touch distinct banks with the row stride == 4 mod 64)
+  __shared__ R Gp[4][64];
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
   const int xcd = blockIdx.x % SWIFTCL_NXCD;
   const int rest = blockIdx.x / SWIFTCL_NXCD;
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
         gv = dC[((size_t)b * Lm + li) * npair + p];
         if (i != j) gv *= (R)0.5;
       }
-      G[i][j] = gv;
+      Gp[j & 3][16 * (j >> 2) + i] = gv;
     }
   };
   // (1) W of every tracer of multipole (ei, band, Fl) into its LDS row
@@ -177,9 +180,9 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       const int col = tile * 16 + (lane & 15);
       acc_t y = {0, 0, 0, 0};
 #pragma unroll
-      for (int j0 = 0; j0 < 16; j0 += 4) {
-        const R a = G[lane & 15][j0 + lane / 16];
-        const R bo = col < nk ? WY[(j0 + lane / 16) * vs + col] : (R)0;
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const R a = Gp[s4][lane];
+        const R bo = col < nk ? WY[(4 * (lane / 16) + s4) * vs + col] : (R)0;
         y = bmfma<R>::step(a, bo, y);
       }
       R s = (R)0;

@@ -94,6 +94,21 @@ template <> struct fft_plan<512> { static constexpr int RL = 8, NP = 3; static c
 template <> struct fft_plan<1024> { static constexpr int RL = 16, NP = 3; static constexpr int rad[3] = {16, 8, 8}; };
 template <> struct fft_plan<2048> { static constexpr int RL = 32, NP = 3; static constexpr int rad[3] = {16, 16, 8}; };
 
+// The same schedule for host code: radix of pass p and number of passes of an M-point FFT.
+__host__ __device__ constexpr int fft_npass(int M) { return M == 128 ? 7 : (M == 256 ? 4 : 3); }
+__host__ __device__ constexpr int fft_radix(int M, int p) {
+  return M == 128 ? 2 : M == 256 ? 4 : M == 512 ? 8 : M == 1024 ? (p == 0 ? 16 : 8) : (p < 2 ? 16 : 8);
+}
+
+// Twiddle table of an M-point wave FFT inside a real transform of length N = 2M (2M - 1 complex
+// entries, built on the host):
+//   [0, M)                                  e^{-2 pi i n / N}      (real-transform post-processing)
+//   M + Ls - 1 + (i - 1) Ls + j, i = 1..r-1, j < Ls   e^{-2 pi i i j / (Ls r)}   for the pass of
+//                                           radix r and stride Ls (Ls = product of the earlier radices)
+// Each pass reads its twiddles at consecutive addresses (j = lane mod Ls), free of bank conflicts;
+// the pass blocks tile [M, 2M - 1) since sum over passes of (r - 1) Ls = M - 1.
+__host__ __device__ constexpr int fft_tw_index(int M, int Ls, int i, int j) { return M + Ls - 1 + (i - 1) * Ls + j; }
+
 // LDS scratch layout of the wave FFT (64 banks of 4 bytes; a 64-bit access is served per half
 // wavefront, so 32 lanes must hit 32 distinct complex slots mod 32).
 //  * FP32, M = 512 (radix 8, 8, 8): an XOR swizzle of the complex index, no padding.  The low five
@@ -119,14 +134,12 @@ template <typename R, int M> __device__ __forceinline__ int fft_at(int c) {
 // One Stockham pass (self-sorting, natural-order output) of radix r on an M-point sequence.
 // Butterfly q (q = lane + 64 u) reads x[q + i M/r], applies twiddles e^{S 2 pi i i j / (Ls r)}
 // with j = q mod Ls, runs dft<r> and writes Y_i to (q / Ls) Ls r + j + i Ls.
-// tw is the table e^{-2 pi i m / N}, m < N, N = 2M (global memory or LDS).
+// tw is the table described at fft_tw_index (global memory or LDS).
 template <typename R, int M, int r, int Ls, int S, bool FIRST, bool LAST>
 __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
   constexpr int RL = M / SWIFTCL_WAVE;
   constexpr int BPL = RL / r;
-  constexpr int N = 2 * M;
   constexpr int L = Ls * r;
-  constexpr int step = N / L;
   C2<R> b[RL];
   if constexpr (FIRST) {
     // registers hold x[lane + 64 e]; butterfly u input i is e = u + i * BPL
@@ -150,7 +163,7 @@ __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>*
       const int j = q & (Ls - 1);
 #pragma unroll
       for (int i = 1; i < r; ++i) {
-        C2<R> w = tw[(i * j * step) & (N - 1)];
+        C2<R> w = tw[fft_tw_index(M, Ls, i, j)];
         if (S > 0) w = cconj(w);
         b[u * r + i] = cmul(b[u * r + i], w);
       }
@@ -177,7 +190,7 @@ __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>*
 
 // M-point complex FFT by one wavefront.  In and out: v[e] holds element lane + 64 e (natural
 // order).  lds: fft_lds_size(M, sizeof(R)) complex of scratch private to this wavefront.  S = -1 forward, +1 inverse
-// (unnormalised).  The twiddle table has N = 2M entries.
+// (unnormalised).  tw: the table of fft_tw_index.
 template <typename R, int M, int S>
 __device__ __forceinline__ void wave_fft(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
   using P = fft_plan<M>;

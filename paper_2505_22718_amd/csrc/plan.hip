@@ -364,10 +364,22 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     const double w = (j == 0 || j == nk - 1) ? 0.5 * p->d.delta : p->d.delta;
     kw[j] = (2.0 / M_PI) * w * d->k[j] * d->k[j] * d->k[j];
   }
-  std::vector<double> twd(2 * (size_t)N);
-  for (int m = 0; m < N; ++m) {
-    twd[2 * m] = std::cos(2.0 * M_PI * m / N);
-    twd[2 * m + 1] = -std::sin(2.0 * M_PI * m / N);
+  // FFT twiddles in the layout of fft_tw_index (the last of the N slots is unused)
+  std::vector<double> twd(2 * (size_t)N, 0.0);
+  {
+    const int M = N / 2;
+    auto put = [&](int idx, double num, double den) {
+      twd[2 * (size_t)idx] = std::cos(2.0 * M_PI * num / den);
+      twd[2 * (size_t)idx + 1] = -std::sin(2.0 * M_PI * num / den);
+    };
+    for (int n = 0; n < M; ++n) put(n, n, N);
+    int Ls = 1;
+    for (int pass = 0; pass < fft_npass(M); ++pass) {
+      const int r = fft_radix(M, pass);
+      for (int i = 1; i < r; ++i)
+        for (int j = 0; j < Ls; ++j) put(fft_tw_index(M, Ls, i, j), (double)i * j, (double)Ls * r);
+      Ls *= r;
+    }
   }
   std::vector<double> lug, lun;
   spline_lu(d->z_geom, d->n_zg, lug);

@@ -24,6 +24,18 @@ def _f64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+# Plans dropped while a stream is being captured into a graph: freeing device memory then would
+# invalidate the capture, so their release waits for the next close() outside capture.
+_deferred_handles = []
+
+
+def _capturing():
+    try:
+        return torch.cuda.is_current_stream_capturing()
+    except Exception:
+        return False
+
+
 class Plan:
     """Owns one swiftcl plan on one device."""
 
@@ -69,9 +81,16 @@ class Plan:
                    precision=precision or ("fp32" if wl["precision"] == "split_bf16" else wl["precision"]), **kw)
 
     def close(self):
-        if getattr(self, "handle", None):
-            bd.swiftcl_plan_destroy(self.handle)
-            self.handle = None
+        h = getattr(self, "handle", None)
+        self.handle = None
+        if _capturing():
+            if h:
+                _deferred_handles.append(h)
+            return
+        while _deferred_handles:
+            bd.swiftcl_plan_destroy(_deferred_handles.pop())
+        if h:
+            bd.swiftcl_plan_destroy(h)
 
     def __del__(self):
         try:

@@ -7,6 +7,7 @@
   with eager work between the replays: every replay reproduces the eager forward bit for bit and
   the eager gradients to roundoff (the geometry adjoint sums with FP64 atomics).
 """
+import gc
 import os
 import sys
 
@@ -98,6 +99,7 @@ def test_graph_capture_replay(dev, fwd_mode, reuse):
             plan.backward_into(t, dC, g, reuse_forward=reuse)
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
+    gc.collect()  # no plan of an earlier test may be released (freed) during the capture
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         plan.cl(t, C)
