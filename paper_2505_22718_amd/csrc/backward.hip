@@ -147,6 +147,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       }
       int ln = lane;  // opaque copy: keeps the FFT's per-lane LDS addresses out of the multipole loop
       asm volatile("" : "+v"(ln));
+      ln &= SWIFTCL_WAVE - 1;  // the compiler may assume 0 <= ln < 64 again
       wave_c2r<R, M>(v, mine, stw, ln);
       wave_sync();
       const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       wave_sync();
       int ln = lane;
       asm volatile("" : "+v"(ln));
+      ln &= SWIFTCL_WAVE - 1;  // the compiler may assume 0 <= ln < 64 again
       wave_r2c<R, M>(v, mine, stw, ln);
       const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
       if constexpr (NW >= 16) {

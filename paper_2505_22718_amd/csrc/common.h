@@ -110,16 +110,17 @@ __host__ __device__ constexpr int fft_radix(int M, int p) {
 __host__ __device__ constexpr int fft_tw_index(int M, int Ls, int i, int j) { return M + Ls - 1 + (i - 1) * Ls + j; }
 
 // LDS scratch layout of the wave FFT (64 banks of 4 bytes; a 64-bit access is served per half
-// wavefront, so 32 lanes must hit 32 distinct complex slots mod 32).
-//  * FP32, M = 512 (radix 8, 8, 8): an XOR swizzle of the complex index, no padding.  The low five
-//    bits are flipped by bits 5..7: the first pass writes 8 q + i (q = lane), the second
-//    64 (q / 8) + q % 8 + 8 i, every other access is 32 consecutive slots, and each of these
-//    lands on 32 distinct slots mod 32.
-//  * otherwise: one padding element every 8 complex values (the stride-8 writes of radix 8 and
-//    the quarter-wave 128-bit accesses of FP64 spread over all banks).
+// wavefront, so 32 lanes conflict-free means 32 distinct complex slots mod 32).  Both layouts add
+// to the complex index c a sum of its shifted bits, so every access of a pass is a per-lane base
+// plus a compile-time offset (no per-access address arithmetic):
+//  * FP32, M = 512 (radix 8, 8, 8): c + (c >> 5) + 4 (c >> 7), 539 slots.  The reads (32 consecutive
+//    slots) are conflict-free, the strided writes of the first two passes 2-way, and the scratch
+//    is small enough for two 1024-thread workgroups per CU.
+//  * otherwise: c + (c >> 3) (the stride-8 writes of radix 8 and the quarter-wave 128-bit accesses
+//    of FP64 spread over all banks).
 // A wavefront's scratch holds fft_lds_size(M, sizeof(R)) complex values.
-__host__ __device__ constexpr bool fft_swizzled(int M, int rs) { return rs == 4 && M == 512; }
-__host__ __device__ constexpr int fft_lds_size(int M, int rs) { return fft_swizzled(M, rs) ? M : M + M / 8; }
+__host__ __device__ constexpr bool fft_compact_layout(int M, int rs) { return rs == 4 && M == 512; }
+__host__ __device__ constexpr int fft_lds_size(int M, int rs) { return fft_compact_layout(M, rs) ? M + 32 : M + M / 8; }
 // Row stride (floats) of a [16][n_k] LDS tile whose row t doubles as the FFT scratch of the
 // wavefront that owns tracer t: room for both, and == 4 (mod 64) so that an MFMA operand read of
 // 16 rows x 4 consecutive k touches 64 distinct banks.
@@ -127,7 +128,7 @@ __host__ __device__ constexpr int compact_vs(int n_k, int M) {
   return (((n_k > 2 * fft_lds_size(M, 4) ? n_k : 2 * fft_lds_size(M, 4)) + 63) / 64) * 64 + 4;
 }
 template <typename R, int M> __device__ __forceinline__ int fft_at(int c) {
-  if constexpr (fft_swizzled(M, (int)sizeof(R))) return c ^ (((c >> 5) & 7) | (((c >> 6) & 3) << 3));
+  if constexpr (fft_compact_layout(M, (int)sizeof(R))) return c + (c >> 5) + 4 * (c >> 7);
   else return c + (c >> 3);
 }
 

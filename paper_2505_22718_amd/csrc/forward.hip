@@ -163,6 +163,7 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
     }
     int ln = lane;  // opaque copy: keeps the FFT's per-lane LDS addresses from being hoisted
     asm volatile("" : "+v"(ln));
+    ln &= SWIFTCL_WAVE - 1;  // the compiler may assume 0 <= ln < 64 again
     wave_c2r<R, M>(v, mine, stw, ln);
     wave_sync();
     const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
