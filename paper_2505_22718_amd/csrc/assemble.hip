@@ -10,7 +10,7 @@
 // with w = 1/2 on the lower support edge (node m0), 1/2 + theta on the last node m1 and zero
 // outside [m0, m1]: the DFT of g is then the trapezoid rule of the cut kernel.
 //
-// One workgroup of 1024 threads owns one parameter point and keeps all of its samples in LDS:
+// One workgroup of GEOM_THREADS threads owns one parameter point and keeps all of its samples in LDS:
 // every spline is solved by one wavefront (the Thomas recurrences as parallel affine-map scans),
 // the lensing suffix integrals by a block scan, and one thread per chi node assembles g.
 #include "common.h"
@@ -19,6 +19,8 @@
 
 // tracers whose n(z) rows sit in LDS at once
 #define GEOM_GROUP 16
+// threads per point (with 512, 256 VGPRs per lane hold the per-node state without spilling)
+#define GEOM_THREADS 512
 
 size_t geometry_lds_bytes(const plan_dev& p) {
   const size_t tg = p.max_tracers < GEOM_GROUP ? p.max_tracers : GEOM_GROUP;
@@ -27,7 +29,7 @@ size_t geometry_lds_bytes(const plan_dev& p) {
 }
 
 template <typename R>
-__global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in) {
+__global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_inputs in) {
   extern __shared__ double sh[];
   const int b = blockIdx.x;
   if (b >= in.batch) return;
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
   }
 
   // node state: each thread owns nodes m = tid + k * nth
-  constexpr int MAXN = 2;  // n_chi <= 2048 (checked at plan time) with 1024 threads
+  constexpr int MAXN = 2048 / GEOM_THREADS;  // n_chi <= 2048 (checked at plan time)
   node_state ns[MAXN];
   R* g = (R*)P.g;
 #pragma unroll
@@ -126,6 +128,16 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
     ns[k].active = true;
     locate_node(ns[k], m, m0, m1, theta, chi0, P.delta, zg, zgih, chi, mchi, Dz, mD, nzg, zs, nzs, P.z_union, nu,
                 P.union_iv);
+    // the node geometry, for the adjoint
+    double* nf = P.node_f + (size_t)b * 4 * N + m;
+    int* ni = P.node_i + (size_t)b * 3 * N + m;
+    nf[0] = ns[k].z;
+    nf[N] = ns[k].chiz;
+    nf[2 * N] = ns[k].dchi;
+    nf[3 * N] = ns[k].D;
+    ni[0] = ns[k].ig;
+    ni[N] = ns[k].inz;
+    ni[2 * N] = ns[k].u;
   }
   const double pref = 1.5 * in.omega_m[b] * SWIFTCL_H0_OVER_C * SWIFTCL_H0_OVER_C;
   for (int g0 = 0; g0 < T; g0 += TG) {
@@ -156,7 +168,7 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
       }
       for (int bi = 0; bi < nb; ++bi)
         g[(((size_t)b * T + t) * nb + bi) * N + m] =
-            (R)(ns[k].w * f * exp(-P.fftlog_b[0][bi] * (double)m * P.delta));
+            (R)(ns[k].w * f * P.ebm[(size_t)bi * N + m]);
     }
   }
   // lensing tracers, one at a time: interval integrals, suffix scan, then q at every node
@@ -194,7 +206,7 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
       const double f = q * ns[k].D / (ns[k].chiz * ns[k].chiz);
       for (int bi = 0; bi < nb; ++bi)
         g[(((size_t)b * T + t) * nb + bi) * N + m] =
-            (R)(ns[k].w * f * exp(-P.fftlog_b[1][bi] * (double)m * P.delta));
+            (R)(ns[k].w * f * P.ebm[((size_t)nb + bi) * N + m]);
     }
     __syncthreads();
   }
@@ -205,9 +217,9 @@ __global__ __launch_bounds__(1024) void k_geometry(plan_dev P, swiftcl_inputs in
 hipError_t launch_assemble(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s) {
   const size_t lds = geometry_lds_bytes(p);
   if (p.precision == SWIFTCL_FP64)
-    hipLaunchKernelGGL(k_geometry<double>, dim3(in->batch), dim3(1024), lds, s, p, *in);
+    hipLaunchKernelGGL(k_geometry<double>, dim3(in->batch), dim3(GEOM_THREADS), lds, s, p, *in);
   else
-    hipLaunchKernelGGL(k_geometry<float>, dim3(in->batch), dim3(1024), lds, s, p, *in);
+    hipLaunchKernelGGL(k_geometry<float>, dim3(in->batch), dim3(GEOM_THREADS), lds, s, p, *in);
   return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ int backward_chunks(const plan_dev& p, int batch) {
 // (a5, a6) One workgroup per (point, chunk of multipole slots), NW wavefronts, wave t = tracer t.
 // Per multipole: recompute W (forward FFT), Y = G W on MFMA, dP partial, dx, r2c, accumulate dc.
 // Partial dc per (point, chunk, tracer, band) and partial sum_t W Y per (point, chunk, k) go to
-// the workspace; k_bwd_coeffs and k_bwd_geometry reduce them.
+// the workspace; k_bwd_coeffs and k_bwd_point reduce them.
 // LDS: twiddles, then (FP32, COMPACT) WY[16][compact_vs] whose row t is also the FFT scratch of
 // wavefront t and the workgroup's dP partial dps[n_k] (~77 KiB for n_chi = n_k = 1024); or (FP64)
 // per-wave scratch [NW][FL] and WY[16][n_k + 2].  The dc accumulators held in registers across the
@@ -329,22 +329,215 @@ __global__ __launch_bounds__(256) void k_bwd_coeffs(plan_dev P, swiftcl_inputs i
 }
 
 size_t bwd_geometry_lds_bytes(const plan_dev& p) {
-  return sizeof(double) * ((size_t)8 * p.n_zg + (size_t)6 * p.n_zs + (size_t)2 * p.n_union + 64);
+  return sizeof(double) * ((size_t)6 * p.n_zg + (size_t)6 * p.n_zs + (size_t)2 * p.n_union + 64);
 }
 
-// (a7) Chain rule through the kernel assembly, one workgroup of 512 threads per point (FP64).
+// (a7) Chain rule through the kernel assembly for one (point, tracer) per workgroup of 512
+// threads (FP64): dL/db_t, dL/dn_t (through the n(z) spline and, for lensing, the suffix integrals)
+// and this tracer's share of the cotangents of the D samples and of D'' (summed over tracers by
+// k_bwd_point).  The chi nodes' geometry (z, chi, dchi/dz, D and their intervals) comes from the
+// forward assembly; the chi spline (for the lensing quadrature) sits in LDS.
 template <typename R>
-__global__ __launch_bounds__(512) void k_bwd_geometry(plan_dev P, swiftcl_inputs in, int nchunk, double* dpk,
-                                                       double* dbias, double* dnz, double* dD) {
+__global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs in, double* dbias, double* dnz) {
+  extern __shared__ double sh[];
+  const int T = P.max_tracers;
+  const int b = blockIdx.x / T, t = blockIdx.x % T;
+  if (b >= in.batch) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int wave = tid / SWIFTCL_WAVE, lane = tid % SWIFTCL_WAVE;
+  const int nzg = P.n_zg, nzs = P.n_zs, nb = P.n_bands, N = P.N, nu = P.n_union;
+  const int Tb = clampb(in.n_tracers[b], 0, T);
+  if (t >= Tb) {
+    if (tid == 0 && dbias) dbias[(size_t)b * T + t] = 0.0;
+    if (dnz)
+      for (int i = tid; i < nzs; i += nth) dnz[((size_t)b * T + t) * nzs + i] = 0.0;
+    return;
+  }
+  double* zg = sh;                       // [nzg]
+  double* zgih = zg + nzg;               // [nzg] 1/h
+  double* chi = zgih + nzg;              // [nzg]
+  double* mchi = chi + nzg;              // [nzg]
+  double* dDy = mchi + nzg;              // [nzg] cotangent of D samples (value terms)
+  double* dDM = dDy + nzg;               // [nzg] cotangent of D'' (spline terms)
+  double* zs = dDM + nzg;                // [nzs]
+  double* zsih = zs + nzs;               // [nzs]
+  double* dny = zsih + nzs;              // [nzs] cotangent of this tracer's n samples
+  double* dnM = dny + nzs;               // [nzs]
+  double* nt = dnM + nzs;                // [nzs] this tracer's n samples
+  double* mt = nt + nzs;                 // [nzs] and their spline second derivatives
+  double* seg0 = mt + nzs;               // [nu]
+  double* seg1 = seg0 + nu;              // [nu]
+  double* tmp = seg1 + nu;               // [64]
+
+  const int kind = in.kind[(size_t)b * T + t] & 1;
+  for (int i = tid; i < nzg; i += nth) {
+    zg[i] = P.z_geom[i];
+    zgih[i] = P.lu_geom[3 * nzg + i];
+    chi[i] = in.chi_z[(size_t)b * nzg + i];
+    mchi[i] = P.m_chi[(size_t)b * nzg + i];
+    dDy[i] = 0.0;
+    dDM[i] = 0.0;
+  }
+  for (int i = tid; i < nzs; i += nth) {
+    zs[i] = P.z_nz[i];
+    zsih[i] = P.lu_nz[3 * nzs + i];
+    dny[i] = 0.0;
+    dnM[i] = 0.0;
+    nt[i] = in.nz[((size_t)b * T + t) * nzs + i];
+    mt[i] = P.m_n[((size_t)b * T + t) * nzs + i];
+  }
+  if (kind == SWIFTCL_LENSING) {
+    // the forward's suffix integrals of this tracer (q at every node)
+    const double* suf = P.lens_suf + ((size_t)b * T + t) * 2 * (nu + 1);
+    for (int u = tid; u < nu; u += nth) {
+      seg0[u] = suf[u];
+      seg1[u] = suf[(nu + 1) + u];
+    }
+  }
+  const double* pt = P.pt + (size_t)b * PT_STRIDE;
+  const double theta = pt[PT_THETA];
+  const int m0 = P.m0, m1 = (int)pt[PT_M1];
+  __syncthreads();
+
+  constexpr int MAXN = 4;  // n_chi <= 2048 with 512 threads
+  // dL/df at node m: sum over bands of dg w e^{-b m Delta}
+  auto df_at = [&](int m, double w) {
+    double s = 0.0;
+    for (int bi = 0; bi < nb; ++bi)
+      s += (double)((const R*)P.dg)[(((size_t)b * T + t) * nb + bi) * N + m] * P.ebm[((size_t)kind * nb + bi) * N + m];
+    return s * w;
+  };
+  auto fill = [&](node_state& s, int m) {
+    const double* nf = P.node_f + (size_t)b * 4 * N + m;
+    const int* ni = P.node_i + (size_t)b * 3 * N + m;
+    s.z = nf[0];
+    s.chiz = nf[N];
+    s.dchi = nf[2 * N];
+    s.D = nf[3 * N];
+    s.ig = ni[0];
+    s.inz = ni[N];
+    s.u = ni[2 * N];
+    s.w = (m == m0) ? 0.5 : (m == m1 ? 0.5 + theta : 1.0);
+    s.zc = P.z_union[s.u + 1];
+    s.ugi = P.union_iv[s.u];
+    s.uni = P.union_iv[nu + s.u];
+  };
+  const double pref = 1.5 * in.omega_m[b] * SWIFTCL_H0_OVER_C * SWIFTCL_H0_OVER_C;
+  double dbl = 0.0;
+  if (kind == SWIFTCL_CLUSTERING) {
+    const double bias = in.bias[(size_t)b * T + t];
+    for (int m = m0 + tid; m <= m1; m += nth) {
+      node_state s;
+      fill(s, m);
+      const double df = df_at(m, s.w);
+      const double n = s.inz < 0 ? 0.0 : spline_at(zs, zsih, nt, mt, s.inz, s.z, nullptr);
+      dbl += df * n * s.D / s.dchi;
+      if (s.inz >= 0) spline_value_adjoint(zs, zsih, s.inz, s.z, df * bias * s.D / s.dchi, dny, dnM);
+      spline_value_adjoint(zg, zgih, s.ig, s.z, df * bias * n / s.dchi, dDy, dDM);
+    }
+  } else {
+    double dI0[MAXN], dI1[MAXN];
+    int uu[MAXN];
+#pragma unroll
+    for (int k = 0; k < MAXN; ++k) {
+      dI0[k] = dI1[k] = 0.0;
+      uu[k] = -1;
+      const int m = m0 + tid + k * nth;
+      if (m > m1) continue;
+      node_state s;
+      fill(s, m);
+      uu[k] = s.u;
+      const double df = df_at(m, s.w);
+      double p0, p1;
+      lens_interval(s.z, s.zc, s.ugi, s.uni, zg, zgih, chi, mchi, zs, zsih, nt, mt, &p0, &p1);
+      const double I0 = p0 + (s.u + 1 < nu ? seg0[s.u + 1] : 0.0);
+      const double I1 = p1 + (s.u + 1 < nu ? seg1[s.u + 1] : 0.0);
+      const double x = s.chiz;
+      const double q = pref * x * (1.0 + s.z) * (I0 - x * I1);
+      spline_value_adjoint(zg, zgih, s.ig, s.z, df * q / (x * x), dDy, dDM);
+      const double dq = df * s.D / (x * x);
+      dI0[k] = dq * pref * x * (1.0 + s.z);
+      dI1[k] = -dq * pref * x * x * (1.0 + s.z);
+    }
+    __syncthreads();
+    // transpose of I(z_m) = partial(z_m) + suffix(u_m + 1): full intervals u get the sum of
+    // dI over nodes with u_m < u (an exclusive prefix over intervals)
+    for (int u = tid; u < nu; u += nth) { seg0[u] = 0.0; seg1[u] = 0.0; }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MAXN; ++k) {
+      if (uu[k] < 0) continue;
+      unsafeAtomicAdd(&seg0[uu[k]], dI0[k]);
+      unsafeAtomicAdd(&seg1[uu[k]], dI1[k]);
+    }
+    __syncthreads();
+    block_scan(seg0, nu, tmp, true);
+    block_scan(seg1, nu, tmp, true);
+    for (int u = tid; u < nu; u += nth) {
+      const int iv = P.union_iv[nu + u];
+      if (iv < 0) continue;
+      const double a = P.z_union[u], c = P.z_union[u + 1];
+      const int ig = P.union_iv[u];
+      const double w0 = seg0[u], w1 = seg1[u];
+      spline_adj_acc ac;
+      for (int qn = 0; qn < 12; ++qn) {
+        const double z = 0.5 * (c - a) * c_gl12_x[qn] + 0.5 * (a + c);
+        const double w = 0.5 * (c - a) * c_gl12_w[qn];
+        const double x = spline_at(zg, zgih, chi, mchi, ig, z, nullptr);
+        ac.add(zs, zsih, iv, z, w * (w0 + w1 / x));
+      }
+      ac.flush(zs, iv, dny, dnM);
+    }
+#pragma unroll
+    for (int k = 0; k < MAXN; ++k) {
+      if (uu[k] < 0) continue;
+      const int m = m0 + tid + k * nth;
+      node_state s;
+      fill(s, m);
+      if (s.uni < 0) continue;
+      const double a = s.z, c = s.zc;
+      spline_adj_acc ac;
+      for (int qn = 0; qn < 12; ++qn) {
+        const double z = 0.5 * (c - a) * c_gl12_x[qn] + 0.5 * (a + c);
+        const double w = 0.5 * (c - a) * c_gl12_w[qn];
+        const double x = spline_at(zg, zgih, chi, mchi, s.ugi, z, nullptr);
+        ac.add(zs, zsih, s.uni, z, w * (dI0[k] + dI1[k] / x));
+      }
+      ac.flush(zs, s.uni, dny, dnM);
+    }
+  }
+  // bias: block reduction
+  for (int off = 32; off >= 1; off >>= 1) dbl += __shfl_xor(dbl, off);
+  if (lane == 0) tmp[wave] = dbl;
+  __syncthreads();
+  if (tid == 0 && dbias) {
+    double s = 0.0;
+    for (int w = 0; w < nth / SWIFTCL_WAVE; ++w) s += tmp[w];
+    dbias[(size_t)b * T + t] = kind == SWIFTCL_CLUSTERING ? s : 0.0;
+  }
+  // n spline transpose
+  if (wave == 0) wave_spline_adjoint(dny, dnM, P.lu_nz, nzs, lane);
+  __syncthreads();
+  if (dnz)
+    for (int i = tid; i < nzs; i += nth) dnz[((size_t)b * T + t) * nzs + i] = dny[i];
+  double* part = P.ddD_part + ((size_t)b * T + t) * 2 * nzg;
+  for (int i = tid; i < nzg; i += nth) {
+    part[i] = dDy[i];
+    part[nzg + i] = dDM[i];
+  }
+}
+
+// Per point: dL/dP (the chunk partials times (2/pi) w k^3) and dL/dD (the tracers' shares summed
+// in tracer order, then the D spline transpose), one workgroup of 256 threads (FP64).
+template <typename R>
+__global__ __launch_bounds__(256) void k_bwd_point(plan_dev P, swiftcl_inputs in, int nchunk, double* dpk,
+                                                    double* dD) {
   extern __shared__ double sh[];
   const int b = blockIdx.x;
   if (b >= in.batch) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int wave = tid / SWIFTCL_WAVE, lane = tid % SWIFTCL_WAVE;
-  const int T = P.max_tracers, nzg = P.n_zg, nzs = P.n_zs, nb = P.n_bands, N = P.N, nu = P.n_union, nk = P.n_k;
-  const int Tb = clampb(in.n_tracers[b], 0, T);
-
-  // dP: reduce the chunk partials, times (2/pi) w k^3
+  const int T = P.max_tracers, nzg = P.n_zg, nk = P.n_k;
   if (dpk) {
     for (int k = tid; k < nk; k += nth) {
       double s = 0.0;
@@ -352,200 +545,24 @@ __global__ __launch_bounds__(512) void k_bwd_geometry(plan_dev P, swiftcl_inputs
       dpk[(size_t)b * nk + k] = P.kw[k] * s;
     }
   }
-  if (!dbias && !dnz && !dD) return;
-
-  double* zg = sh;                       // [nzg]
-  double* zgih = zg + nzg;               // [nzg]
-  double* chi = zgih + nzg;              // [nzg]
-  double* mchi = chi + nzg;              // [nzg]
-  double* Dz = mchi + nzg;               // [nzg]
-  double* mD = Dz + nzg;                 // [nzg]
-  double* dDy = mD + nzg;                // [nzg] cotangent of D samples (value terms)
-  double* dDM = dDy + nzg;               // [nzg] cotangent of D'' (spline terms)
-  double* zs = dDM + nzg;                // [nzs]
-  double* zsih = zs + nzs;               // [nzs]
-  double* dny = zsih + nzs;              // [nzs] cotangent of the current tracer's n samples
-  double* dnM = dny + nzs;               // [nzs]
-  double* nt = dnM + nzs;                // [nzs] the current tracer's n samples
-  double* mt = nt + nzs;                 // [nzs] and their spline second derivatives
-  double* seg0 = mt + nzs;               // [nu]
-  double* seg1 = seg0 + nu;              // [nu]
-  double* tmp = seg1 + nu;               // [64]
-
+  if (!dD) return;
+  const int Tb = clampb(in.n_tracers[b], 0, T);
+  double* dDy = sh;        // [nzg]
+  double* dDM = dDy + nzg; // [nzg]
   for (int i = tid; i < nzg; i += nth) {
-    zg[i] = P.z_geom[i];
-    zgih[i] = P.lu_geom[3 * nzg + i];
-    chi[i] = in.chi_z[(size_t)b * nzg + i];
-    mchi[i] = P.m_chi[(size_t)b * nzg + i];
-    Dz[i] = in.D_z[(size_t)b * nzg + i];
-    mD[i] = P.m_D[(size_t)b * nzg + i];
-    dDy[i] = 0.0;
-    dDM[i] = 0.0;
+    double sy = 0.0, sm = 0.0;
+    for (int t = 0; t < Tb; ++t) {
+      const double* part = P.ddD_part + ((size_t)b * T + t) * 2 * nzg;
+      sy += part[i];
+      sm += part[nzg + i];
+    }
+    dDy[i] = sy;
+    dDM[i] = sm;
   }
-  for (int i = tid; i < nzs; i += nth) {
-    zs[i] = P.z_nz[i];
-    zsih[i] = P.lu_nz[3 * nzs + i];
-  }
-  const double* pt = P.pt + (size_t)b * PT_STRIDE;
-  const double chi0 = pt[PT_CHI0], theta = pt[PT_THETA];
-  const int m0 = P.m0, m1 = (int)pt[PT_M1];
   __syncthreads();
-
-  // node positions: z (and its geometry interval) solved once, the rest re-derived where used
-  constexpr int MAXN = 4;  // n_chi <= 2048 with 512 threads
-  double nz_z[MAXN];
-  int nz_ig[MAXN];
-  bool act[MAXN];
-#pragma unroll
-  for (int k = 0; k < MAXN; ++k) {
-    const int m = tid + k * nth;
-    act[k] = m < N && m >= m0 && m <= m1;
-    nz_z[k] = 0.0;
-    nz_ig[k] = 0;
-    if (act[k]) nz_z[k] = node_z(m, m0, chi0, P.delta, zg, zgih, chi, mchi, nzg, &nz_ig[k]);
-  }
-  // df at node slot k of tracer t (kind): sum over bands of dg w e^{-b m Delta}
-  auto df_at = [&](int t, int kind, int k, double w) {
-    const int m = tid + k * nth;
-    double s = 0.0;
-    for (int bi = 0; bi < nb; ++bi)
-      s += (double)((const R*)P.dg)[(((size_t)b * T + t) * nb + bi) * N + m] *
-           exp(-P.fftlog_b[kind][bi] * (double)m * P.delta);
-    return s * w;
-  };
-  const double pref = 1.5 * in.omega_m[b] * SWIFTCL_H0_OVER_C * SWIFTCL_H0_OVER_C;
-  for (int t = 0; t < T; ++t) {
-    if (t >= Tb) {
-      if (tid == 0 && dbias) dbias[(size_t)b * T + t] = 0.0;
-      if (dnz)
-        for (int i = tid; i < nzs; i += nth) dnz[((size_t)b * T + t) * nzs + i] = 0.0;
-      continue;
-    }
-    const int kind = in.kind[(size_t)b * T + t] & 1;
-    for (int i = tid; i < nzs; i += nth) {
-      dny[i] = 0.0;
-      dnM[i] = 0.0;
-      nt[i] = in.nz[((size_t)b * T + t) * nzs + i];
-      mt[i] = P.m_n[((size_t)b * T + t) * nzs + i];
-    }
-    __syncthreads();
-    double dbl = 0.0;
-    if (kind == SWIFTCL_CLUSTERING) {
-      const double bias = in.bias[(size_t)b * T + t];
-#pragma unroll
-      for (int k = 0; k < MAXN; ++k) {
-        if (!act[k]) continue;
-        const int m = tid + k * nth;
-        node_state s;
-        node_fill(s, nz_z[k], nz_ig[k], m, m0, m1, theta, zg, zgih, chi, mchi, Dz, mD, zs, nzs, P.z_union, nu,
-                  P.union_iv);
-        const double df = df_at(t, 0, k, s.w);
-        const double n = s.inz < 0 ? 0.0 : spline_at(zs, zsih, nt, mt, s.inz, s.z, nullptr);
-        dbl += df * n * s.D / s.dchi;
-        if (s.inz >= 0) spline_value_adjoint(zs, zsih, s.inz, s.z, df * bias * s.D / s.dchi, dny, dnM);
-        spline_value_adjoint(zg, zgih, s.ig, s.z, df * bias * n / s.dchi, dDy, dDM);
-      }
-    } else {
-      // the forward's suffix integrals of this tracer (q at every node)
-      const double* suf = P.lens_suf + ((size_t)b * T + t) * 2 * (nu + 1);
-      for (int u = tid; u < nu; u += nth) {
-        seg0[u] = suf[u];
-        seg1[u] = suf[(nu + 1) + u];
-      }
-      __syncthreads();
-      double dI0[MAXN], dI1[MAXN];
-      int uu[MAXN];
-#pragma unroll
-      for (int k = 0; k < MAXN; ++k) {
-        dI0[k] = dI1[k] = 0.0;
-        uu[k] = 0;
-        if (!act[k]) continue;
-        const int m = tid + k * nth;
-        node_state s;
-        node_fill(s, nz_z[k], nz_ig[k], m, m0, m1, theta, zg, zgih, chi, mchi, Dz, mD, zs, nzs, P.z_union, nu,
-                  P.union_iv);
-        uu[k] = s.u;
-        const double df = df_at(t, 1, k, s.w);
-        double p0, p1;
-        lens_interval(s.z, s.zc, s.ugi, s.uni, zg, zgih, chi, mchi, zs, zsih, nt, mt, &p0, &p1);
-        const double I0 = p0 + (s.u + 1 < nu ? seg0[s.u + 1] : 0.0);
-        const double I1 = p1 + (s.u + 1 < nu ? seg1[s.u + 1] : 0.0);
-        const double x = s.chiz;
-        const double q = pref * x * (1.0 + s.z) * (I0 - x * I1);
-        spline_value_adjoint(zg, zgih, s.ig, s.z, df * q / (x * x), dDy, dDM);
-        const double dq = df * s.D / (x * x);
-        dI0[k] = dq * pref * x * (1.0 + s.z);
-        dI1[k] = -dq * pref * x * x * (1.0 + s.z);
-      }
-      __syncthreads();
-      // transpose of I(z_m) = partial(z_m) + suffix(u_m + 1): full intervals u get the sum of
-      // dI over nodes with u_m < u (an exclusive prefix over intervals)
-      for (int u = tid; u < nu; u += nth) { seg0[u] = 0.0; seg1[u] = 0.0; }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < MAXN; ++k) {
-        if (!act[k]) continue;
-        unsafeAtomicAdd(&seg0[uu[k]], dI0[k]);
-        unsafeAtomicAdd(&seg1[uu[k]], dI1[k]);
-      }
-      __syncthreads();
-      block_scan(seg0, nu, tmp, true);
-      block_scan(seg1, nu, tmp, true);
-      for (int u = tid; u < nu; u += nth) {
-        const int iv = P.union_iv[nu + u];
-        if (iv < 0) continue;
-        const double a = P.z_union[u], c = P.z_union[u + 1];
-        const int ig = P.union_iv[u];
-        const double w0 = seg0[u], w1 = seg1[u];
-        spline_adj_acc ac;
-        for (int qn = 0; qn < 12; ++qn) {
-          const double z = 0.5 * (c - a) * c_gl12_x[qn] + 0.5 * (a + c);
-          const double w = 0.5 * (c - a) * c_gl12_w[qn];
-          const double x = spline_at(zg, zgih, chi, mchi, ig, z, nullptr);
-          ac.add(zs, zsih, iv, z, w * (w0 + w1 / x));
-        }
-        ac.flush(zs, iv, dny, dnM);
-      }
-#pragma unroll
-      for (int k = 0; k < MAXN; ++k) {
-        if (!act[k]) continue;
-        const int m = tid + k * nth;
-        node_state s;
-        node_fill(s, nz_z[k], nz_ig[k], m, m0, m1, theta, zg, zgih, chi, mchi, Dz, mD, zs, nzs, P.z_union, nu,
-                  P.union_iv);
-        if (s.uni < 0) continue;
-        const double a = s.z, c = s.zc;
-        spline_adj_acc ac;
-        for (int qn = 0; qn < 12; ++qn) {
-          const double z = 0.5 * (c - a) * c_gl12_x[qn] + 0.5 * (a + c);
-          const double w = 0.5 * (c - a) * c_gl12_w[qn];
-          const double x = spline_at(zg, zgih, chi, mchi, s.ugi, z, nullptr);
-          ac.add(zs, zsih, s.uni, z, w * (dI0[k] + dI1[k] / x));
-        }
-        ac.flush(zs, s.uni, dny, dnM);
-      }
-    }
-    // bias: block reduction
-    for (int off = 32; off >= 1; off >>= 1) dbl += __shfl_xor(dbl, off);
-    if (lane == 0) tmp[wave] = dbl;
-    __syncthreads();
-    if (tid == 0 && dbias) {
-      double s = 0.0;
-      for (int w = 0; w < nth / SWIFTCL_WAVE; ++w) s += tmp[w];
-      dbias[(size_t)b * T + t] = kind == SWIFTCL_CLUSTERING ? s : 0.0;
-    }
-    // n spline transpose
-    if (wave == 0) wave_spline_adjoint(dny, dnM, P.lu_nz, nzs, lane);
-    __syncthreads();
-    if (dnz)
-      for (int i = tid; i < nzs; i += nth) dnz[((size_t)b * T + t) * nzs + i] = dny[i];
-    __syncthreads();
-  }
-  if (dD) {
-    if (wave == 0) wave_spline_adjoint(dDy, dDM, P.lu_geom, nzg, lane);
-    __syncthreads();
-    for (int i = tid; i < nzg; i += nth) dD[(size_t)b * nzg + i] = dDy[i];
-  }
+  if (wave == 0) wave_spline_adjoint(dDy, dDM, P.lu_geom, nzg, lane);
+  __syncthreads();
+  for (int i = tid; i < nzg; i += nth) dD[(size_t)b * nzg + i] = dDy[i];
 }
 
 template <typename R, int M>
@@ -569,8 +586,14 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   hipLaunchKernelGGL((k_bwd_coeffs<R, M>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in, nchunk);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-  const size_t lg = bwd_geometry_lds_bytes(p);
-  hipLaunchKernelGGL(k_bwd_geometry<R>, dim3(in->batch), dim3(512), lg, s, p, *in, nchunk, dpk, dbias, dnz, dD);
+  if (dbias || dnz || dD) {
+    const size_t lg = bwd_geometry_lds_bytes(p);
+    hipLaunchKernelGGL(k_bwd_tracer<R>, dim3((unsigned)((size_t)in->batch * p.max_tracers)), dim3(512), lg, s, p,
+                       *in, dbias, dnz);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_bwd_point<R>, dim3(in->batch), dim3(256), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
+                     nchunk, dpk, dD);
   return hipGetLastError();
 }
 
@@ -594,7 +617,8 @@ template <typename R, int M>
 static hipError_t prepare_bwd_t() {
   constexpr bool dp = sizeof(R) == 8;
   hipError_t e = lds_attr_once((const void*)k_bwd_windows<R, M, dp ? 2 : 16, !dp>);
-  if (e == hipSuccess) e = lds_attr_once((const void*)k_bwd_geometry<R>);
+  if (e == hipSuccess) e = lds_attr_once((const void*)k_bwd_tracer<R>);
+  if (e == hipSuccess) e = lds_attr_once((const void*)k_bwd_point<R>);
   return e;
 }
 

@@ -29,6 +29,23 @@ __device__ __forceinline__ double spline_at(const double* __restrict__ x, const 
   return v;
 }
 
+// Weights of the natural-spline value on interval i at z: value = wa y_i + wb y_{i+1} + wc M_i +
+// wd M_{i+1} (shared by every spline on the same knots).
+struct spline_w {
+  double wa, wb, wc, wd;
+  __device__ __forceinline__ spline_w(const double* __restrict__ x, const double* __restrict__ ih, int i, double z) {
+    const double h = x[i + 1] - x[i];
+    wa = (x[i + 1] - z) * ih[i];
+    wb = (z - x[i]) * ih[i];
+    const double h6 = h * h / 6.0;
+    wc = (wa * wa * wa - wa) * h6;
+    wd = (wb * wb * wb - wb) * h6;
+  }
+  __device__ __forceinline__ double at(const double* __restrict__ y, const double* __restrict__ Mv, int i) const {
+    return wa * y[i] + wb * y[i + 1] + wc * Mv[i] + wd * Mv[i + 1];
+  }
+};
+
 // largest i in [0, n-2] with x[i] <= v
 __device__ __forceinline__ int find_interval(const double* __restrict__ x, int n, double v) {
   int lo = 0, hi = n - 1;

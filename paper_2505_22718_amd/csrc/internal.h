@@ -41,6 +41,7 @@ struct plan_dev {
   double* fell;     // [n_ell] F(l) for lensing
   int* ell_band;    // [n_ell]
   double* kw;       // [n_k] (2/pi) w_j k_j^3
+  double* ebm;      // [2][n_bands][N] e^{-b m Delta}: the FFTLog bias factor of chi node m
   double* z_geom;   // [n_zg]
   double* z_nz;     // [n_zs]
   double* lu_geom;  // [4][n_zg] natural-spline Thomas factors (a, 1/pivot, c') and 1/h
@@ -54,6 +55,9 @@ struct plan_dev {
   double* m_D;      // [B][n_zg]
   double* m_n;      // [B][T][n_zs]
   double* lens_suf; // [B][T][2][n_union + 1]
+  double* node_f;   // [B][4][N] z, chi, dchi/dz, D at the active chi nodes (forward assembly)
+  int* node_i;      // [B][3][N] their geometry, n(z) and union intervals
+  double* ddD_part; // [B][T][2][n_zg] per-tracer cotangents of the D samples and of D'' (adjoint)
   void* g;          // [B][T][n_bands][N] real: tilted, edge-weighted kernel samples
   void* chat;       // [B][T][n_bands][M] complex real: FFTLog coefficients (phased)
   void* sqrt_s;     // [B][n_k] real: sqrt((2/pi) w k^3 P)

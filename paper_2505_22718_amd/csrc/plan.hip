@@ -252,8 +252,8 @@ template <typename T> static swiftcl_status dalloc(T** ptr, size_t count, const 
 
 static void free_plan(swiftcl_plan_s* p) {
   if (!p) return;
-  void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
-                  p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_suf, p->d.g,
+  void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
+                  p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_suf, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
                   p->d.chat, p->d.sqrt_s, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -364,6 +364,12 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     const double w = (j == 0 || j == nk - 1) ? 0.5 * p->d.delta : p->d.delta;
     kw[j] = (2.0 / M_PI) * w * d->k[j] * d->k[j] * d->k[j];
   }
+  // FFTLog bias factors e^{-b m Delta} per kind, band and chi node
+  std::vector<double> ebm((size_t)2 * nb * N);
+  for (int kind = 0; kind < 2; ++kind)
+    for (int bi = 0; bi < nb; ++bi)
+      for (int m = 0; m < N; ++m)
+        ebm[((size_t)kind * nb + bi) * N + m] = std::exp(-d->fftlog_b[kind][bi] * (double)m * p->d.delta);
   // FFT twiddles in the layout of fft_tw_index (the last of the N slots is unused)
   std::vector<double> twd(2 * (size_t)N, 0.0);
   {
@@ -417,6 +423,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(fell, double, p->d.n_ell);
   ALLOC(ell_band, int, p->d.n_ell);
   ALLOC(kw, double, nk);
+  ALLOC(ebm, double, (size_t)2 * nb * N);
   ALLOC(z_geom, double, p->d.n_zg);
   ALLOC(z_nz, double, p->d.n_zs);
   ALLOC(lu_geom, double, lug.size());
@@ -428,6 +435,9 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(m_D, double, (size_t)B * p->d.n_zg);
   ALLOC(m_n, double, (size_t)B * T * p->d.n_zs);
   ALLOC(lens_suf, double, (size_t)B * T * 2 * (p->d.n_union + 1));
+  ALLOC(node_f, double, (size_t)B * 4 * N);
+  ALLOC(node_i, int, (size_t)B * 3 * N);
+  if (fused && d->precision != SWIFTCL_SPLIT_BF16) ALLOC(ddD_part, double, (size_t)B * T * 2 * p->d.n_zg);
   ALLOC(g, char, (size_t)B * T * nb * N * rs);
   ALLOC(chat, char, (size_t)B * T * nb * M * 2 * rs);
   ALLOC(sqrt_s, char, (size_t)B * nk * rs);
@@ -475,6 +485,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
       {p->d.fell, fell.data(), fell.size() * sizeof(double)},
       {p->d.ell_band, band.data(), band.size() * sizeof(int)},
       {p->d.kw, kw.data(), kw.size() * sizeof(double)},
+      {p->d.ebm, ebm.data(), ebm.size() * sizeof(double)},
       {p->d.z_geom, d->z_geom, (size_t)p->d.n_zg * sizeof(double)},
       {p->d.z_nz, d->z_nz, (size_t)p->d.n_zs * sizeof(double)},
       {p->d.lu_geom, lug.data(), lug.size() * sizeof(double)},
