@@ -113,7 +113,7 @@ __host__ __device__ constexpr int fft_tw_index(int M, int Ls, int i, int j) { re
 // wavefront, so 32 lanes conflict-free means 32 distinct complex slots mod 32).  Both layouts add
 // to the complex index c a sum of its shifted bits, so every access of a pass is a per-lane base
 // plus a compile-time offset (no per-access address arithmetic):
-//  * FP32, M = 512 (radix 8, 8, 8): c + (c >> 5) + 4 (c >> 7), 539 slots.  The reads (32 consecutive
+//  * FP32, M = 512 (radix 8, 8, 8): c + (c >> 5) + 2 (c >> 6), 540 slots.  The reads (32 consecutive
 //    slots) are conflict-free, the strided writes of the first two passes 2-way, and the scratch
 //    is small enough for two 1024-thread workgroups per CU.
 //  * otherwise: c + (c >> 3) (the stride-8 writes of radix 8 and the quarter-wave 128-bit accesses
@@ -127,8 +127,13 @@ __host__ __device__ constexpr int fft_lds_size(int M, int rs) { return fft_compa
 __host__ __device__ constexpr int compact_vs(int n_k, int M) {
   return (((n_k > 2 * fft_lds_size(M, 4) ? n_k : 2 * fft_lds_size(M, 4)) + 63) / 64) * 64 + 4;
 }
+// Both layouts are sums of right shifts of c, so fft_at(x + K) = fft_at(x) + fft_at(K) whenever x
+// and K have no bit in common, and fft_at is linear on multiples of 64.  The passes split every
+// index into a per-lane part (lane < 64) and a compile-time part that way, so that the compiler
+// folds the latter into the LDS instruction's offset; the mirrored read of the real transforms,
+// M - n = (64 - lane) + 64 (RL - 1 - e), uses the linearity for lane 0.
 template <typename R, int M> __device__ __forceinline__ int fft_at(int c) {
-  if constexpr (fft_compact_layout(M, (int)sizeof(R))) return c + (c >> 5) + 4 * (c >> 7);
+  if constexpr (fft_compact_layout(M, (int)sizeof(R))) return c + (c >> 5) + 2 * (c >> 6);
   else return c + (c >> 3);
 }
 
@@ -151,9 +156,8 @@ __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>*
   } else {
 #pragma unroll
     for (int u = 0; u < BPL; ++u) {
-      const int q = lane + SWIFTCL_WAVE * u;
 #pragma unroll
-      for (int i = 0; i < r; ++i) b[u * r + i] = lds[fft_at<R, M>(q + i * (M / r))];
+      for (int i = 0; i < r; ++i) b[u * r + i] = lds[fft_at<R, M>(lane) + fft_at<R, M>(SWIFTCL_WAVE * u + i * (M / r))];
     }
     wave_sync();
   }
@@ -183,7 +187,7 @@ __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>*
       const int j = q & (Ls - 1);
       const int base = (q / Ls) * L + j;
 #pragma unroll
-      for (int i = 0; i < r; ++i) lds[fft_at<R, M>(base + i * Ls)] = b[u * r + i];
+      for (int i = 0; i < r; ++i) lds[fft_at<R, M>(base) + fft_at<R, M>(i * Ls)] = b[u * r + i];
     }
     wave_sync();
   }
@@ -228,7 +232,7 @@ __device__ __forceinline__ void wave_r2c(C2<R>* v, C2<R>* lds, const C2<R>* __re
   constexpr int RL = M / SWIFTCL_WAVE;
   wave_fft<R, M, -1>(v, lds, tw, lane);
 #pragma unroll
-  for (int e = 0; e < RL; ++e) lds[fft_at<R, M>(lane + SWIFTCL_WAVE * e)] = v[e];
+  for (int e = 0; e < RL; ++e) lds[fft_at<R, M>(lane) + fft_at<R, M>(SWIFTCL_WAVE * e)] = v[e];
   wave_sync();
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
@@ -237,7 +241,7 @@ __device__ __forceinline__ void wave_r2c(C2<R>* v, C2<R>* lds, const C2<R>* __re
     if (n == 0) {
       v[e] = mk<R>(Zn.x + Zn.y, (R)0);
     } else {
-      const C2<R> Zm = cconj(lds[fft_at<R, M>(M - n)]);
+      const C2<R> Zm = cconj(lds[fft_at<R, M>(SWIFTCL_WAVE - lane) + fft_at<R, M>(SWIFTCL_WAVE * (RL - 1 - e))]);
       const C2<R> A = cscale(cadd(Zn, Zm), (R)0.5);
       const C2<R> Bd = cscale(csub(Zn, Zm), (R)0.5);
       const C2<R> t2 = cmul(tw[n], Bd);
@@ -254,7 +258,7 @@ template <typename R, int M>
 __device__ __forceinline__ void wave_c2r(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
   constexpr int RL = M / SWIFTCL_WAVE;
 #pragma unroll
-  for (int e = 0; e < RL; ++e) lds[fft_at<R, M>(lane + SWIFTCL_WAVE * e)] = v[e];
+  for (int e = 0; e < RL; ++e) lds[fft_at<R, M>(lane) + fft_at<R, M>(SWIFTCL_WAVE * e)] = v[e];
   wave_sync();
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
@@ -262,7 +266,7 @@ __device__ __forceinline__ void wave_c2r(C2<R>* v, C2<R>* lds, const C2<R>* __re
     if (n == 0) {
       v[e] = mk<R>(v[e].x, v[e].x);  // X_0 (1 + i)
     } else {
-      const C2<R> Xm = cconj(lds[fft_at<R, M>(M - n)]);  // X_{n+M} = conj(X_{M-n})
+      const C2<R> Xm = cconj(lds[fft_at<R, M>(SWIFTCL_WAVE - lane) + fft_at<R, M>(SWIFTCL_WAVE * (RL - 1 - e))]);  // X_{n+M} = conj(X_{M-n})
       const C2<R> A = cadd(v[e], Xm);
       const C2<R> Bd = csub(v[e], Xm);
       const C2<R> t2 = cmul(cconj(tw[n]), Bd);
