@@ -181,6 +181,9 @@ def main():
              "nz": torch.empty((B, plan.max_tracers, len(wl["z_nz"])), **f64),
              "D": torch.empty((B, len(wl["z_geom"])), **f64)}
 
+    # launch shapes picked by the library's autotuner on this batch (outside the timed region)
+    tune_report = plan.autotune(inp, dC)
+
     def step():
         plan.cl(inp, out)
         # the backward keeps the forward's assembly and FFTLog state (same inputs)
@@ -242,6 +245,7 @@ def main():
                      "bwd_fftlog_coeffs": float(bstages[1]), "bwd_windows": float(bstages[2]),
                      "bwd_coeffs": float(bstages[3]), "bwd_geometry": float(bstages[4])},
         "device_flags": flags,
+        "launch": dict(plan.launch_config(), autotune=tune_report),
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

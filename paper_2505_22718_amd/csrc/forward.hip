@@ -238,9 +238,10 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
 
 // Launch modes.  PERSIST = false: one workgroup per (point, multipole slot), blocks mapped so that
 // all multipoles of one point run on one XCD (block = ((b / 8) * Lm + l) * 8 + b % 8); padded
-// slots write zeros.  PERSIST = true: a grid sized to the chip; XCD x walks the compact list of
-// (point b = 8 i + x, multipole) items built by k_schedule (ragged multipole counts leave no idle
-// workgroup, and every block loads the twiddles once); padded slots are zeroed by k_zero_padded.
+// slots write zeros.  PERSIST = true: a grid sized to the chip; the blocks of XCD x walk the
+// compact list of (point b = 8 i + x, multipole) items built by k_schedule with the grid stride
+// (ragged multipole counts leave no idle workgroup, and every block loads the twiddles once);
+// padded slots are zeroed by k_zero_padded.
 template <typename R, int M, int NW, bool TW_LDS, bool WRITE_W, bool DO_CL, bool PERSIST, bool SPLIT>
 __global__ __launch_bounds__(NW * 64)
 __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && DO_CL && M <= 512) ? 8 : 1))) void k_windows_cl(
@@ -277,15 +278,19 @@ __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && DO_CL && M <= 512) ? 8 : 1
     const int total = P.sched[SWIFTCL_NXCD * stride + xcd];
     const int nx = (in.batch - xcd + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
     const int g8 = gridDim.x / SWIFTCL_NXCD;
+    // items rest, rest + g8, ...: the blocks of an XCD work on neighbouring items at any time, so
+    // the coefficients of the few points in flight stay in that XCD's L2
+    if (rest >= total) return;
+    int i = 0, hi = nx;  // largest i with offs[i] <= rest
+    while (hi - i > 1) {
+      const int mid = (i + hi) >> 1;
+      if (offs[mid] <= rest) i = mid; else hi = mid;
+    }
     for (int k = rest; k < total; k += g8) {
-      int lo = 0, hi = nx;  // largest i with offs[i] <= k
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (offs[mid] <= k) lo = mid; else hi = mid;
-      }
-      const int b = lo * SWIFTCL_NXCD + xcd;
-      windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT, COMPACT>(P, in, Wout, Cout, b, k - offs[lo], stw, fbuf, V);
+      windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT, COMPACT>(P, in, Wout, Cout, i * SWIFTCL_NXCD + xcd,
+                                                                k - offs[i], stw, fbuf, V);
       __syncthreads();
+      while (i + 1 < nx && offs[i + 1] <= k + g8) ++i;  // the point holding item k + g8
     }
   }
 }
