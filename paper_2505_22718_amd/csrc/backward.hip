@@ -67,6 +67,8 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   C2<R>* fbuf = stw_l + NTW;                                                              // [NW][FL]
   R* WY = (R*)(smem + ((size_t)NTW + (COMPACT ? 0 : (size_t)NW * FL)) * sizeof(C2<R>));  // [16][vs]
   R* dps = WY + (size_t)16 * vs;                                                          // [nk] (COMPACT)
+  R* kss = dps + nk;            // [2][nb][nk] k scale tables (COMPACT)
+  R* sql = kss + 2 * nb * nk;   // [nk] sqrt(s) of this point (COMPACT)
   // G in MFMA operand order: Gp[s][l] = G[l % 16][4 (l / 16) + s] is what lane l feeds at
   // reduction step s (the step covers tracers s, s + 4, s + 8, s + 12, so the W operand reads of
   // 4 rows x 16 k touch distinct banks with the row stride == 4 mod 64)
@@ -88,8 +90,15 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   }
   const size_t slot = (size_t)b * nchunk + chunk;
   C2<R>* part = (C2<R>*)P.dchat_part + slot * T * nb * M;
-  for (size_t i = threadIdx.x; i < (size_t)T * nb * M; i += NW * 64) part[i] = mk<R>(0, 0);
+  if (!COMPACT)  // (COMPACT: every (tracer, band) row of the slot is stored once, below)
+    for (size_t i = threadIdx.x; i < (size_t)T * nb * M; i += NW * 64) part[i] = mk<R>(0, 0);
   const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
+  if (COMPACT) {
+    for (int i = threadIdx.x; i < 2 * nb * nk; i += NW * 64) kss[i] = ((const R*)P.kscale)[i];
+    for (int i = threadIdx.x; i < nk; i += NW * 64) sql[i] = sq[i];
+    sq = sql;
+  }
+  const R* kscale = COMPACT ? (const R*)kss : (const R*)P.kscale;
   const int ntiles = (nk + 15) / 16;
   // this workgroup's slice of the dP partials: column k is owned by one lane of one wavefront
   R* dpp = (R*)P.dpk_part + slot * nk;
@@ -101,6 +110,18 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
 #pragma unroll
   for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
   int cur_band = -1;
+  unsigned flushed = 0;  // bands whose partial rows this workgroup has written
+  // add the accumulators of band cur_band to the partial rows (store on the first visit)
+  auto flush = [&]() {
+    const bool again = (flushed >> cur_band) & 1u;
+    for (int t = wave; t < Tb; t += NW) {
+      C2<R>* dst = part + ((size_t)t * nb + cur_band) * M;
+#pragma unroll
+      for (int e = 0; e < RL; ++e)
+        dst[lane + SWIFTCL_WAVE * e] = again ? cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]) : acc[e];
+    }
+    flushed |= 1u << cur_band;
+  };
   __syncthreads();
 
   // multipole slot -> (union index, band, F(l)); a bad index is flagged and read as 0
@@ -150,7 +171,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       ln &= SWIFTCL_WAVE - 1;  // the compiler may assume 0 <= ln < 64 again
       wave_c2r<R, M>(v, mine, stw, ln);
       wave_sync();
-      const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
+      const R* ks = kscale + ((size_t)kind * nb + band) * nk;
       const R F = kind ? Fl : (R)1;
 #pragma unroll
       for (int e = 0; e < RL; ++e) {
@@ -207,13 +228,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
     }
     __syncthreads();
     if (NW >= 16 && band != cur_band) {
-      if (cur_band >= 0) {
-        for (int t = wave; t < Tb; t += NW) {
-          C2<R>* dst = part + ((size_t)t * nb + cur_band) * M;
-#pragma unroll
-          for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]);
-        }
-      }
+      if (cur_band >= 0) flush();
 #pragma unroll
       for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
       cur_band = band;
@@ -221,7 +236,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
     // (3) dx = 2 s F k^{-1-b} Y, r2c, dc += h_n conj(X_n) conj(U_l(n))
     for (int t = wave; t < Tb; t += NW) {
       const int kind = in.kind[(size_t)b * T + t] & 1;
-      const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
+      const R* ks = kscale + ((size_t)kind * nb + band) * nk;
       const R F = kind ? Fl : (R)1;
       C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)t * vs) : fbuf + (size_t)wave * FL;
       C2<R> v[RL];
@@ -237,19 +252,25 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
           v[e] = mk<R>(0, 0);
         }
       }
+      const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
+      C2<R> ur[NW >= 16 ? RL : 1];
+      if constexpr (NW >= 16) {
+        // issued before the transform, used after it
+#pragma unroll
+        for (int e = 0; e < RL; ++e) ur[e] = Ur[lane + SWIFTCL_WAVE * e];
+      }
       wave_sync();
       int ln = lane;
       asm volatile("" : "+v"(ln));
       ln &= SWIFTCL_WAVE - 1;  // the compiler may assume 0 <= ln < 64 again
       wave_r2c<R, M>(v, mine, stw, ln);
-      const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
       if constexpr (NW >= 16) {
         // one tracer per wavefront: accumulate in registers, flushed when the band changes
 #pragma unroll
         for (int e = 0; e < RL; ++e) {
           const int n = lane + SWIFTCL_WAVE * e;
           const R h = n == 0 ? (R)1 : (R)2;
-          acc[e] = cadd(acc[e], cscale(cmul(cconj(v[e]), cconj(Ur[n])), h));
+          acc[e] = cadd(acc[e], cscale(cmul(cconj(v[e]), cconj(ur[e])), h));
         }
       } else {
         // a wavefront serves several tracers: add into this workgroup's partial slot directly
@@ -270,11 +291,16 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
     }
     __syncthreads();
   }
-  if (NW >= 16 && cur_band >= 0) {
-    for (int t = wave; t < Tb; t += NW) {
-      C2<R>* dst = part + ((size_t)t * nb + cur_band) * M;
+  if (NW >= 16) {
+    if (cur_band >= 0) flush();
+    // bands this chunk never reached: zero rows (the reduction sums every chunk's row)
+    for (int bi = 0; bi < nb; ++bi) {
+      if ((flushed >> bi) & 1u) continue;
+      for (int t = wave; t < Tb; t += NW) {
+        C2<R>* dst = part + ((size_t)t * nb + bi) * M;
 #pragma unroll
-      for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]);
+        for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = mk<R>(0, 0);
+      }
     }
   }
   if (COMPACT)
@@ -574,7 +600,7 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   const int nchunk = backward_chunks(p, in->batch);
   const size_t lds = dp ? windows_cl_lds(M, NW, TW, true, sizeof(R), p.n_k)
                         : (TW ? 2 * (size_t)M * sizeof(C2<R>) : 0) +
-                              ((size_t)16 * compact_vs(p.n_k, M) + (size_t)p.n_k) * sizeof(R);
+                              ((size_t)16 * compact_vs(p.n_k, M) + (size_t)(2 + 2 * p.n_bands) * p.n_k) * sizeof(R);
   auto k1 = k_bwd_windows<R, M, NW, TW>;
   hipError_t e;
   const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
