@@ -160,7 +160,8 @@ swiftcl_status swiftcl_cl_backward(swiftcl_plan_t plan, const swiftcl_inputs* in
  * multipole counts).  Times, on the caller's inputs, the forward projection launched as one
  * workgroup per (point, multipole slot) or as a persistent grid walking per-XCD compact work
  * lists, and (if dC is not NULL) the adjoint with 1, 2 or 4 times its base number of multipole
- * chunks; keeps the fastest in the plan.  With cache_path (may be NULL) the choice is read from,
+ * chunks; keeps the fastest in the plan (a variant other than the default, fwd_mode 0 and
+ * bwd_chunk_mul 1, must be at least 2% faster).  With cache_path (may be NULL) the choice is read from,
  * or appended to, a file with one JSON object per line keyed by architecture and shape.  `C`
  * (output-shaped scratch, overwritten) and `dC` are device buffers laid out as for swiftcl_cl /
  * swiftcl_cl_backward.  `report` (may be NULL) receives a one-line summary.  Synchronises `stream`;
