@@ -99,6 +99,16 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
     theta = 0.0;
   }
   const int m0 = P.m0, m1 = (int)m1d;
+  {
+    // FFTLog phase of every coefficient, shared by all tracers and bands of the point
+    const double dphi = -2.0 * M_PI * (log(P.k0) + lchi0) / ((double)N * P.delta);
+    double2* ph = (double2*)P.phase + (size_t)b * (N / 2);
+    for (int n = tid; n < N / 2; n += nth) {
+      double sn, cs;
+      sincos(dphi * (double)n, &sn, &cs);
+      ph[n] = make_double2(cs, sn);
+    }
+  }
   if (tid == 0) {
     if (flag) atomicOr(P.flags, flag);
     double* pt = P.pt + (size_t)b * PT_STRIDE;

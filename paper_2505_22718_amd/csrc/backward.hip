@@ -312,6 +312,14 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
 template <typename R, int M>
 __global__ __launch_bounds__(256) void k_bwd_coeffs(plan_dev P, swiftcl_inputs in, int nchunk) {
   __shared__ C2<R> lds[4][fft_lds_size(M, sizeof(R))];
+  // FP32: the twiddle table staged in LDS by the block (FP64 reads it through the cache)
+  constexpr bool TWS = sizeof(R) == 4;
+  __shared__ C2<R> stw_s[TWS ? 2 * M : 1];
+  if constexpr (TWS) {
+    for (int i = threadIdx.x; i < 2 * M; i += blockDim.x) stw_s[i] = ((const C2<R>*)P.tw)[i];
+    __syncthreads();
+  }
+  const C2<R>* twp = TWS ? (const C2<R>*)stw_s : (const C2<R>*)P.tw;
   constexpr int RL = M / SWIFTCL_WAVE;
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, nb = P.n_bands, N = P.N;
@@ -339,17 +347,16 @@ __global__ __launch_bounds__(256) void k_bwd_coeffs(plan_dev P, swiftcl_inputs i
   const double* pt = P.pt + (size_t)b * PT_STRIDE;
   const int kind = in.kind[(size_t)b * T + t] & 1;
   const double scale = pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] / (double)N;
-  const double dphi = -2.0 * M_PI * pt[PT_LNK0CHI0] / ((double)N * P.delta);
+  const double2* ph = (const double2*)P.phase + (size_t)b * M;
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
     const int n = lane + SWIFTCL_WAVE * e;
-    double sn, cs;
-    sincos(dphi * (double)n, &sn, &cs);
+    const double cs = ph[n].x, sn = ph[n].y;
     // e_n = dc_n conj(alpha_n); the c2r doubles n > 0, so pass e_n / 2 there
     C2<R> en = cmul(v[e], mk<R>((R)(cs * scale), (R)(-sn * scale)));
     v[e] = n == 0 ? en : cscale(en, (R)0.5);
   }
-  wave_c2r<R, M>(v, lds[wave], (const C2<R>*)P.tw, lane);
+  wave_c2r<R, M>(v, lds[wave], twp, lane);
 #pragma unroll
   for (int e = 0; e < RL; ++e) out[lane + SWIFTCL_WAVE * e] = v[e];
 }

@@ -70,6 +70,14 @@ __global__ void k_sqrt_s(plan_dev P, swiftcl_inputs in) {
 template <typename R, int M>
 __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs in) {
   __shared__ C2<R> lds[4][fft_lds_size(M, sizeof(R))];
+  // FP32: the twiddle table staged in LDS by the block (FP64 reads it through the cache)
+  constexpr bool TWS = sizeof(R) == 4;
+  __shared__ C2<R> stw_s[TWS ? 2 * M : 1];
+  if constexpr (TWS) {
+    for (int i = threadIdx.x; i < 2 * M; i += blockDim.x) stw_s[i] = ((const C2<R>*)P.tw)[i];
+    __syncthreads();
+  }
+  const C2<R>* twp = TWS ? (const C2<R>*)stw_s : (const C2<R>*)P.tw;
   constexpr int RL = M / SWIFTCL_WAVE;
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, nb = P.n_bands, N = P.N;
@@ -87,7 +95,7 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
     return;
   }
   const C2<R>* g2 = (const C2<R>*)((const R*)P.g + row * N);
-  const C2<R>* tw = (const C2<R>*)P.tw;
+  const C2<R>* tw = twp;
   C2<R> v[RL];
 #pragma unroll
   for (int e = 0; e < RL; ++e) v[e] = g2[lane + SWIFTCL_WAVE * e];
@@ -95,13 +103,12 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
   const double* pt = P.pt + (size_t)b * PT_STRIDE;
   const int kind = in.kind[(size_t)b * T + t] & 1;
   const double scale = pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] / (double)N;
-  const double dphi = -2.0 * M_PI * pt[PT_LNK0CHI0] / ((double)N * P.delta);
+  const double2* ph = (const double2*)P.phase + (size_t)b * M;
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
     const int n = lane + SWIFTCL_WAVE * e;
-    double sn, cs;
-    sincos(dphi * (double)n, &sn, &cs);
-    out[n] = cmul(v[e], mk<R>((R)(cs * scale), (R)(sn * scale)));
+    const double2 a = ph[n];
+    out[n] = cmul(v[e], mk<R>((R)(a.x * scale), (R)(a.y * scale)));
   }
 }
 

@@ -55,6 +55,8 @@ struct plan_dev {
   double* m_D;      // [B][n_zg]
   double* m_n;      // [B][T][n_zs]
   double* lens_suf; // [B][T][2][n_union + 1]
+  double* phase;    // [B][N/2] complex e^{-2 pi i n ln(k_0 chi_0) / (N Delta)}: the FFTLog phase
+                    // of coefficient n (forward assembly)
   double* node_f;   // [B][4][N] z, chi, dchi/dz, D at the active chi nodes (forward assembly)
   int* node_i;      // [B][3][N] their geometry, n(z) and union intervals
   double* ddD_part; // [B][T][2][n_zg] per-tracer cotangents of the D samples and of D'' (adjoint)
