@@ -196,14 +196,6 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
     __syncthreads();
     block_scan(seg0, nu, tmp, false);
     block_scan(seg1, nu, tmp, false);
-    {
-      // keep the suffix integrals for the adjoint
-      double* suf = P.lens_suf + ((size_t)b * T + t) * 2 * (nu + 1);
-      for (int u = tid; u < nu; u += nth) {
-        suf[u] = seg0[u];
-        suf[(nu + 1) + u] = seg1[u];
-      }
-    }
 #pragma unroll
     for (int k = 0; k < MAXN; ++k) {
       if (!ns[k].active) continue;
@@ -213,6 +205,7 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
       const double I0 = p0 + (ns[k].u + 1 < nu ? seg0[ns[k].u + 1] : 0.0);
       const double I1 = p1 + (ns[k].u + 1 < nu ? seg1[ns[k].u + 1] : 0.0);
       const double q = pref * ns[k].chiz * (1.0 + ns[k].z) * (I0 - ns[k].chiz * I1);
+      P.lens_q[((size_t)b * T + t) * N + m] = q;  // for the adjoint
       const double f = q * ns[k].D / (ns[k].chiz * ns[k].chiz);
       for (int bi = 0; bi < nb; ++bi)
         g[(((size_t)b * T + t) * nb + bi) * N + m] =

@@ -419,14 +419,6 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
     nt[i] = in.nz[((size_t)b * T + t) * nzs + i];
     mt[i] = P.m_n[((size_t)b * T + t) * nzs + i];
   }
-  if (kind == SWIFTCL_LENSING) {
-    // the forward's suffix integrals of this tracer (q at every node)
-    const double* suf = P.lens_suf + ((size_t)b * T + t) * 2 * (nu + 1);
-    for (int u = tid; u < nu; u += nth) {
-      seg0[u] = suf[u];
-      seg1[u] = suf[(nu + 1) + u];
-    }
-  }
   const double* pt = P.pt + (size_t)b * PT_STRIDE;
   const double theta = pt[PT_THETA];
   const int m0 = P.m0, m1 = (int)pt[PT_M1];
@@ -481,12 +473,8 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
       fill(s, m);
       uu[k] = s.u;
       const double df = df_at(m, s.w);
-      double p0, p1;
-      lens_interval(s.z, s.zc, s.ugi, s.uni, zg, zgih, chi, mchi, zs, zsih, nt, mt, &p0, &p1);
-      const double I0 = p0 + (s.u + 1 < nu ? seg0[s.u + 1] : 0.0);
-      const double I1 = p1 + (s.u + 1 < nu ? seg1[s.u + 1] : 0.0);
       const double x = s.chiz;
-      const double q = pref * x * (1.0 + s.z) * (I0 - x * I1);
+      const double q = P.lens_q[((size_t)b * T + t) * N + m];  // the forward's q at this node
       spline_value_adjoint(zg, zgih, s.ig, s.z, df * q / (x * x), dDy, dDM);
       const double dq = df * s.D / (x * x);
       dI0[k] = dq * pref * x * (1.0 + s.z);

@@ -54,7 +54,7 @@ struct plan_dev {
   double* m_chi;    // [B][n_zg] spline second derivatives
   double* m_D;      // [B][n_zg]
   double* m_n;      // [B][T][n_zs]
-  double* lens_suf; // [B][T][2][n_union + 1]
+  double* lens_q;   // [B][T][N] lensing efficiency q at the active chi nodes (forward assembly)
   double* phase;    // [B][N/2] complex e^{-2 pi i n ln(k_0 chi_0) / (N Delta)}: the FFTLog phase
                     // of coefficient n (forward assembly)
   double* node_f;   // [B][4][N] z, chi, dchi/dz, D at the active chi nodes (forward assembly)

@@ -253,7 +253,7 @@ template <typename T> static swiftcl_status dalloc(T** ptr, size_t count, const 
 static void free_plan(swiftcl_plan_s* p) {
   if (!p) return;
   void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
-                  p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_suf, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
+                  p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
                   p->d.chat, p->d.sqrt_s, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -434,7 +434,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(m_chi, double, (size_t)B * p->d.n_zg);
   ALLOC(m_D, double, (size_t)B * p->d.n_zg);
   ALLOC(m_n, double, (size_t)B * T * p->d.n_zs);
-  ALLOC(lens_suf, double, (size_t)B * T * 2 * (p->d.n_union + 1));
+  ALLOC(lens_q, double, (size_t)B * T * N);
   ALLOC(phase, double, (size_t)B * N);
   ALLOC(node_f, double, (size_t)B * 4 * N);
   ALLOC(node_i, int, (size_t)B * 3 * N);
