@@ -63,7 +63,11 @@ __global__ void k_sqrt_s(plan_dev P, swiftcl_inputs in) {
   if (b >= in.batch || j >= P.n_k) return;
   const double v = P.kw[j] * in.pk[(size_t)b * P.n_k + j];
   if (!(v >= 0.0) || !isfinite(v)) atomicOr(P.flags, FLAG_NONFINITE);
-  ((R*)P.sqrt_s)[(size_t)b * P.n_k + j] = (R)sqrt(fmax(v, 0.0));
+  const R sq = (R)sqrt(fmax(v, 0.0));
+  ((R*)P.sqrt_s)[(size_t)b * P.n_k + j] = sq;
+  // kscale * sqrt(s) for every kind and band: the projection scales its windows once
+  for (int kb = 0; kb < 2 * P.n_bands; ++kb)
+    ((R*)P.kss)[((size_t)b * 2 * P.n_bands + kb) * P.n_k + j] = ((const R*)P.kscale)[(size_t)kb * P.n_k + j] * sq;
 }
 
 // FFTLog coefficients: one wavefront per (point, tracer, band) row.
@@ -147,7 +151,6 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
   const int vs = COMPACT ? compact_vs(nk, M) : nk + 2;  // row stride of V: rows start on distinct banks
   const int band = P.ell_band[ei];
   const R Fl = (R)P.fell[ei];
-  const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
   const int trows = DO_CL ? 16 : T;
   for (int t = wave; t < trows; t += NW) {
     if (t >= Tb) {
@@ -174,22 +177,21 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
     wave_c2r<R, M>(v, mine, stw, ln);
     wave_sync();
     const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
+    const R* kq = (const R*)P.kss + (((size_t)b * 2 + kind) * nb + band) * nk;
     const R F = kind ? Fl : (R)1;
 #pragma unroll
     for (int e = 0; e < RL; ++e) {
       const int j = lane + SWIFTCL_WAVE * e;
       const int k0 = 2 * j;
       if (k0 < nk) {
-        const C2<R> kk = *(const C2<R>*)(ks + k0);
-        const R w0 = F * kk.x * v[e].x;
-        const R w1 = F * kk.y * v[e].y;
         if (WRITE_W) {
+          const C2<R> kk = *(const C2<R>*)(ks + k0);
           C2<R>* dst = (C2<R>*)(Wout + (((size_t)b * Lm + li) * T + t) * nk + k0);
-          *dst = mk<R>(w0, w1);
+          *dst = mk<R>(F * kk.x * v[e].x, F * kk.y * v[e].y);
         }
-        if (DO_CL) {
-          const C2<R> s2 = *(const C2<R>*)(sq + k0);
-          *(C2<R>*)(V + t * vs + k0) = mk<R>(w0 * s2.x, w1 * s2.y);
+        if (DO_CL) {  // V = sqrt(s) W
+          const C2<R> kk = *(const C2<R>*)(kq + k0);
+          *(C2<R>*)(V + t * vs + k0) = mk<R>(F * kk.x * v[e].x, F * kk.y * v[e].y);
         }
       }
     }

@@ -63,6 +63,7 @@ struct plan_dev {
   void* g;          // [B][T][n_bands][N] real: tilted, edge-weighted kernel samples
   void* chat;       // [B][T][n_bands][M] complex real: FFTLog coefficients (phased)
   void* sqrt_s;     // [B][n_k] real: sqrt((2/pi) w k^3 P)
+  void* kss;        // [B][2][n_bands][n_k] real: kscale * sqrt_s, the window-to-V factor
   int* flags;       // [1]
   // backward workspace
   void* dchat_part; // [bwd_slots][T][n_bands][M] complex real: dc partials per (point, chunk)

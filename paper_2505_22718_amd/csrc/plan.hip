@@ -254,7 +254,7 @@ static void free_plan(swiftcl_plan_s* p) {
   if (!p) return;
   void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
-                  p->d.chat, p->d.sqrt_s, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf};
+                  p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -442,6 +442,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(g, char, (size_t)B * T * nb * N * rs);
   ALLOC(chat, char, (size_t)B * T * nb * M * 2 * rs);
   ALLOC(sqrt_s, char, (size_t)B * nk * rs);
+  ALLOC(kss, char, (size_t)B * 2 * nb * nk * rs);
   ALLOC(flags, int, 1);
   {
     // (point, chunk) slots of the backward partials: the most any batch size and chunk
