@@ -68,7 +68,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   R* WY = (R*)(smem + ((size_t)NTW + (COMPACT ? 0 : (size_t)NW * FL)) * sizeof(C2<R>));  // [16][vs]
   R* dps = WY + (size_t)16 * vs;                                                          // [nk] (COMPACT)
   R* kss = dps + nk;            // [2][nb][nk] k scale tables (COMPACT)
-  R* sql = kss + 2 * nb * nk;   // [nk] sqrt(s) of this point (COMPACT)
+  R* kdx = kss + 2 * nb * nk;   // [2][nb][nk] 2 s kscale of this point: the cotangent scale (COMPACT)
   // G in MFMA operand order: Gp[s][l] = G[l % 16][4 (l / 16) + s] is what lane l feeds at
   // reduction step s (the step covers tracers s, s + 4, s + 8, s + 12, so the W operand reads of
   // 4 rows x 16 k touch distinct banks with the row stride == 4 mod 64)
@@ -94,9 +94,12 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
     for (size_t i = threadIdx.x; i < (size_t)T * nb * M; i += NW * 64) part[i] = mk<R>(0, 0);
   const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
   if (COMPACT) {
-    for (int i = threadIdx.x; i < 2 * nb * nk; i += NW * 64) kss[i] = ((const R*)P.kscale)[i];
-    for (int i = threadIdx.x; i < nk; i += NW * 64) sql[i] = sq[i];
-    sq = sql;
+    for (int i = threadIdx.x; i < 2 * nb * nk; i += NW * 64) {
+      const R ks = ((const R*)P.kscale)[i];
+      const R s = sq[i % nk];
+      kss[i] = ks;
+      kdx[i] = (R)2 * s * s * ks;
+    }
   }
   const R* kscale = COMPACT ? (const R*)kss : (const R*)P.kscale;
   const int ntiles = (nk + 15) / 16;
@@ -245,9 +248,14 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
         const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
         if (k0 < nk) {
           const C2<R> y2 = *(const C2<R>*)(WY + t * vs + k0);
-          const C2<R> kk = *(const C2<R>*)(ks + k0);
-          const C2<R> s2 = *(const C2<R>*)(sq + k0);
-          v[e] = mk<R>((R)2 * s2.x * s2.x * F * kk.x * y2.x, (R)2 * s2.y * s2.y * F * kk.y * y2.y);
+          if constexpr (COMPACT) {
+            const C2<R> kx = *(const C2<R>*)(kdx + ((size_t)kind * nb + band) * nk + k0);
+            v[e] = mk<R>(F * kx.x * y2.x, F * kx.y * y2.y);
+          } else {
+            const C2<R> kk = *(const C2<R>*)(ks + k0);
+            const C2<R> s2 = *(const C2<R>*)(sq + k0);
+            v[e] = mk<R>((R)2 * s2.x * s2.x * F * kk.x * y2.x, (R)2 * s2.y * s2.y * F * kk.y * y2.y);
+          }
         } else {
           v[e] = mk<R>(0, 0);
         }
@@ -586,6 +594,12 @@ __global__ __launch_bounds__(256) void k_bwd_point(plan_dev P, swiftcl_inputs in
   for (int i = tid; i < nzg; i += nth) dD[(size_t)b * nzg + i] = dDy[i];
 }
 
+size_t bwd_windows_lds(const plan_dev& p) {
+  if (p.precision == SWIFTCL_FP64) return windows_cl_lds(p.M, 2, false, true, 8, p.n_k);
+  const size_t tw = 2 * (size_t)p.M * 2 * sizeof(float);  // FP32 stages the twiddles (TW = !dp)
+  return tw + ((size_t)16 * compact_vs(p.n_k, p.M) + (size_t)(1 + 4 * p.n_bands) * p.n_k) * sizeof(float);
+}
+
 template <typename R, int M>
 static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,
                                double* dbias, double* dnz, double* dD, hipStream_t s, hipEvent_t* ev) {
@@ -593,9 +607,7 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   constexpr int NW = dp ? 2 : 16;
   constexpr bool TW = !dp;
   const int nchunk = backward_chunks(p, in->batch);
-  const size_t lds = dp ? windows_cl_lds(M, NW, TW, true, sizeof(R), p.n_k)
-                        : (TW ? 2 * (size_t)M * sizeof(C2<R>) : 0) +
-                              ((size_t)16 * compact_vs(p.n_k, M) + (size_t)(2 + 2 * p.n_bands) * p.n_k) * sizeof(R);
+  const size_t lds = bwd_windows_lds(p);
   auto k1 = k_bwd_windows<R, M, NW, TW>;
   hipError_t e;
   const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;

@@ -78,6 +78,7 @@ struct plan_dev {
   int sched_stride;
   // projection path: fused (windows in LDS, <= 16 tracers) or through the workspace below
   int fused;
+  int adjoint;        // swiftcl_cl_backward available (fused, FP32/FP64, its LDS fits the device)
   int vchunk;         // points per chunk of the unfused path
   void* vbuf;         // [vchunk][max_ell][32][n_k] FP32, or bf16 hi then lo (unfused path only)
 };
@@ -96,6 +97,7 @@ hipError_t lds_attr_once(const void* kern);
 hipError_t prepare_forward(const plan_dev& p);
 hipError_t prepare_assemble(const plan_dev& p);
 hipError_t prepare_backward(const plan_dev& p);
+size_t bwd_windows_lds(const plan_dev& p);  // dynamic LDS of the adjoint windows kernel
 size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k);
 size_t geometry_lds_bytes(const plan_dev& p);
 int windows_nw(int precision);

@@ -323,6 +323,9 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   p->d.taper_frac = d->taper_frac;
   p->d.m0 = d->edge_node > 0 ? d->edge_node : default_edge_node(d->n_chi, p->d.delta);
   p->d.fused = fused ? 1 : 0;
+  p->d.adjoint = (fused && d->precision != SWIFTCL_SPLIT_BF16 &&
+                  bwd_windows_lds(p->d) + 4096 <= (size_t)lds_max)  // + the kernel's static LDS
+                     ? 1 : 0;
   {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d->device) != hipSuccess || ncu < 8)
@@ -615,7 +618,7 @@ static swiftcl_status backward_checks(swiftcl_plan_t p, const swiftcl_inputs* in
   if (st != SWIFTCL_OK) return st;
   if (!dC) { set_error("dC is NULL"); return SWIFTCL_E_INVALID; }
   if (flags & ~(uint32_t)SWIFTCL_BWD_REUSE_FORWARD) { set_error("unknown backward flag"); return SWIFTCL_E_INVALID; }
-  if (!p->d.fused || p->d.precision == SWIFTCL_SPLIT_BF16) {
+  if (!p->d.adjoint) {
     set_error("the adjoint is built for plans whose windows fit in LDS (<= 16 tracers) in FP32 or FP64");
     return SWIFTCL_E_UNSUPPORTED;
   }
