@@ -509,9 +509,9 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
       const int ig = P.union_iv[u];
       const double w0 = seg0[u], w1 = seg1[u];
       spline_adj_acc ac;
-      for (int qn = 0; qn < 12; ++qn) {
-        const double z = 0.5 * (c - a) * c_gl12_x[qn] + 0.5 * (a + c);
-        const double w = 0.5 * (c - a) * c_gl12_w[qn];
+      for (int qn = 0; qn < SWIFTCL_NGL; ++qn) {
+        const double z = 0.5 * (c - a) * c_gl_x[qn] + 0.5 * (a + c);
+        const double w = 0.5 * (c - a) * c_gl_w[qn];
         const double x = spline_at(zg, zgih, chi, mchi, ig, z, nullptr);
         ac.add(zs, zsih, iv, z, w * (w0 + w1 / x));
       }
@@ -526,9 +526,9 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
       if (s.uni < 0) continue;
       const double a = s.z, c = s.zc;
       spline_adj_acc ac;
-      for (int qn = 0; qn < 12; ++qn) {
-        const double z = 0.5 * (c - a) * c_gl12_x[qn] + 0.5 * (a + c);
-        const double w = 0.5 * (c - a) * c_gl12_w[qn];
+      for (int qn = 0; qn < SWIFTCL_NGL; ++qn) {
+        const double z = 0.5 * (c - a) * c_gl_x[qn] + 0.5 * (a + c);
+        const double w = 0.5 * (c - a) * c_gl_w[qn];
         const double x = spline_at(zg, zgih, chi, mchi, s.ugi, z, nullptr);
         ac.add(zs, zsih, s.uni, z, w * (dI0[k] + dI1[k] / x));
       }
