@@ -108,6 +108,67 @@ def profile_pass(B):
     print("profile pass done: 2 steps, then a 268435456-byte copy", flush=True)
 
 
+def time_ms(fn, steps, stream):
+    """Average device time of fn() over `steps` calls (HIP events on `stream`), after one warm-up."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def extra_configs(steps):
+    """The other measured shapes: one point (latency), the ragged batch (256 points of 6, 10 or 15
+    tracers and 50..103 multipoles) and the 30-tracer split-precision batch (64 points, 465
+    spectra x 200 l, N_k = N_chi = 2048; forward only: the adjoint is built for <= 16 tracers)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    out = {}
+    stream = torch.cuda.current_stream()
+    f64 = dict(dtype=torch.float64, device="cuda:0")
+
+    def fwd_bwd(wl, precision=None, backward=True, tune=False):
+        plan = Plan.for_workload(wl, precision=precision)
+        inp = device_inputs(wl, "cuda:0")
+        B = int(wl["batch"])
+        C = torch.empty((B, plan.max_ell, plan.n_pairs), dtype=plan.out_dtype, device="cuda:0")
+        dC = torch.as_tensor(np.random.default_rng(0).standard_normal(tuple(C.shape)), dtype=plan.out_dtype,
+                             device="cuda:0")
+        if tune:
+            plan.autotune(inp, dC if backward else None)
+        r = {"forward_ms": time_ms(lambda: plan.cl(inp, C), steps, stream)}
+        if backward:
+            g = {"pk": torch.empty((B, len(wl["k"])), **f64), "bias": torch.empty((B, plan.max_tracers), **f64),
+                 "nz": torch.empty((B, plan.max_tracers, len(wl["z_nz"])), **f64),
+                 "D": torch.empty((B, len(wl["z_geom"])), **f64)}
+
+            def step():
+                plan.cl(inp, C)
+                plan.backward_into(inp, dC, g, reuse_forward=True)
+            r["fwd_bwd_ms"] = time_ms(step, steps, stream)
+        return r, B
+
+    r, B = fwd_bwd(synth.make_workload("cfg1"))
+    out["one_point_latency"] = dict(r, workload="1 point, 15 tracers x 103 l, N_k = N_chi = 1024, FP32")
+    r, B = fwd_bwd(synth.make_workload("cfg3"), tune=True)
+    out["ragged_batch"] = dict(r, points_per_s_fwd_bwd=B / (r["fwd_bwd_ms"] * 1e-3),
+                               points_per_s_forward=B / (r["forward_ms"] * 1e-3),
+                               workload="256 points of 6/10/15 tracers and 50..103 l, FP32, autotuned launch")
+    r, B = fwd_bwd(synth.make_workload("cfg4"), precision="split_bf16", backward=False)
+    out["split_bf16_30_tracers"] = dict(r, points_per_s_forward=B / (r["forward_ms"] * 1e-3),
+                                        workload="64 points x 30 tracers (465 spectra) x 200 l, N_k = N_chi = 2048, "
+                                                 "BF16 hi+lo projection")
+    return out
+
+
 def cpu_baseline(wl, seconds, plan_out):
     """Time the FP64 oracle on as many points as fit in `seconds` (at least one)."""
     import numpy as np
@@ -147,6 +208,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the one-point, ragged and split-precision lines")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run two steps and a 256 MiB copy for rocprofv3 counters; no JSON line")
     args = ap.parse_args()
@@ -248,6 +310,8 @@ def main():
         "launch": dict(plan.launch_config(), autotune=tune_report),
         "roofline": roofline,
     }
+    if not args.no_extras:
+        result["other_shapes"] = extra_configs(max(3, args.steps // 4))
     if not args.no_cpu_baseline:
         gpu_out = out.cpu().numpy().astype(np.float64)
         cb, err = cpu_baseline(wl, args.cpu_seconds, gpu_out)
