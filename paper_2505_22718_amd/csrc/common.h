@@ -116,11 +116,14 @@ __host__ __device__ constexpr int fft_tw_index(int M, int Ls, int i, int j) { re
 //  * FP32, M = 512 (radix 8, 8, 8): c + (c >> 5) + 2 (c >> 6), 540 slots.  The reads (32 consecutive
 //    slots) are conflict-free, the strided writes of the first two passes 2-way, and the scratch
 //    is small enough for two 1024-thread workgroups per CU.
+//  * FP32, M = 1024 (radix 16, 8, 8): c + (c >> 5), 1055 slots: reads and the first pass's writes
+//    conflict-free, the second pass's writes 2-way; 16 wavefronts' scratch and the twiddles fit
+//    one workgroup's LDS.
 //  * otherwise: c + (c >> 3) (the stride-8 writes of radix 8 and the quarter-wave 128-bit accesses
 //    of FP64 spread over all banks).
 // A wavefront's scratch holds fft_lds_size(M, sizeof(R)) complex values.
-__host__ __device__ constexpr bool fft_compact_layout(int M, int rs) { return rs == 4 && M == 512; }
-__host__ __device__ constexpr int fft_lds_size(int M, int rs) { return fft_compact_layout(M, rs) ? M + 32 : M + M / 8; }
+__host__ __device__ constexpr bool fft_compact_layout(int M, int rs) { return rs == 4 && (M == 512 || M == 1024); }
+__host__ __device__ constexpr int fft_lds_size(int M, int rs) { return fft_compact_layout(M, rs) ? (M == 512 ? M + 32 : M + M / 32) : M + M / 8; }
 // Row stride (floats) of a [16][n_k] LDS tile whose row t doubles as the FFT scratch of the
 // wavefront that owns tracer t: room for both, and == 4 (mod 64) so that an MFMA operand read of
 // 16 rows x 4 consecutive k touches 64 distinct banks.
@@ -133,7 +136,8 @@ __host__ __device__ constexpr int compact_vs(int n_k, int M) {
 // folds the latter into the LDS instruction's offset; the mirrored read of the real transforms,
 // M - n = (64 - lane) + 64 (RL - 1 - e), uses the linearity for lane 0.
 template <typename R, int M> __device__ __forceinline__ int fft_at(int c) {
-  if constexpr (fft_compact_layout(M, (int)sizeof(R))) return c + (c >> 5) + 2 * (c >> 6);
+  if constexpr (fft_compact_layout(M, (int)sizeof(R)) && M == 512) return c + (c >> 5) + 2 * (c >> 6);
+  else if constexpr (fft_compact_layout(M, (int)sizeof(R))) return c + (c >> 5);
   else return c + (c >> 3);
 }
 

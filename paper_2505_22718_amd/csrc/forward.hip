@@ -370,6 +370,9 @@ template <int M> struct wcl_shape<double, M> {
 
 int windows_nw(int precision) { return precision == SWIFTCL_FP64 ? 2 : 16; }
 bool windows_tw_lds(int precision, int M) { return precision != SWIFTCL_FP64 && M <= 512; }
+// the unfused FP32 windows kernel (no V rows in LDS) stages the twiddles up to n_chi = 2048
+constexpr bool unfused_tw(int M) { return M <= 1024; }
+bool unfused_tw_lds(int M) { return unfused_tw(M); }
 
 // ---------------------------------------------------------------------------------------------
 // Unfused projection for more than 16 tracers or windows too large for LDS (FP32 / split):
@@ -421,7 +424,6 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
   }
   const int band = P.ell_band[ei];
   const R Fl = (R)P.fell[ei];
-  const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
   C2<R>* mine = fbuf + (size_t)wave * FL;
   for (int t = wave; t < 32; t += NW) {
     const size_t rb = (row0 + t) * nk;
@@ -442,16 +444,18 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
       const int n = lane + SWIFTCL_WAVE * e;
       v[e] = cconj(cmul(ch[n], Ur[n]));
     }
-    wave_c2r<R, M>(v, mine, stw, lane);
-    const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
+    int ln = lane;  // opaque copy: keeps the FFT's per-lane LDS addresses out of the tracer loop
+    asm volatile("" : "+v"(ln));
+    ln &= SWIFTCL_WAVE - 1;
+    wave_c2r<R, M>(v, mine, stw, ln);
+    const R* kq = (const R*)P.kss + (((size_t)b * 2 + kind) * nb + band) * nk;  // kscale * sqrt(s)
     const R F = kind ? Fl : (R)1;
 #pragma unroll
     for (int e = 0; e < RL; ++e) {
       const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
       if (k0 < nk) {
-        const C2<R> kk = *(const C2<R>*)(ks + k0);
-        const C2<R> s2 = *(const C2<R>*)(sq + k0);
-        const float x0 = F * kk.x * v[e].x * s2.x, x1 = F * kk.y * v[e].y * s2.y;
+        const C2<R> kk = *(const C2<R>*)(kq + k0);
+        const float x0 = F * kk.x * v[e].x, x1 = F * kk.y * v[e].y;
         if (SPLIT) {
           unsigned short h0, l0, h1, l1;
           split_bf16(x0, &h0, &l0);
@@ -557,7 +561,7 @@ __global__ __launch_bounds__(256) void k_contract(plan_dev P, swiftcl_inputs in,
 template <int M>
 static hipError_t launch_unfused(const plan_dev& p, const swiftcl_inputs* in, void* C, hipStream_t s) {
   constexpr int NW = 16;
-  constexpr bool TW = M <= 512;
+  constexpr bool TW = unfused_tw(M);
   const bool split = p.precision == SWIFTCL_SPLIT_BF16;
   const size_t lds = windows_cl_lds(M, NW, TW, false, sizeof(float), p.n_k);
   for (int b0 = 0; b0 < in->batch; b0 += p.vchunk) {
@@ -655,8 +659,8 @@ static hipError_t prepare_fwd_t() {
   if constexpr (sizeof(R) == 4) {
     if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, false, true, false, true>);
     if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, false, true, true, true>);
-    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_v<M, 16, (M <= 512), true>);
-    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_v<M, 16, (M <= 512), false>);
+    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_v<M, 16, unfused_tw(M), true>);
+    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_v<M, 16, unfused_tw(M), false>);
   }
   return e;
 }

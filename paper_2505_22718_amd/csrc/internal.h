@@ -99,6 +99,7 @@ hipError_t prepare_assemble(const plan_dev& p);
 hipError_t prepare_backward(const plan_dev& p);
 size_t bwd_windows_lds(const plan_dev& p);  // dynamic LDS of the adjoint windows kernel
 size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k);
+bool unfused_tw_lds(int M);
 size_t geometry_lds_bytes(const plan_dev& p);
 int windows_nw(int precision);
 bool windows_tw_lds(int precision, int M);

@@ -283,7 +283,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
                 std::to_string(need) + " bytes per workgroup, the device has " + std::to_string(lds_max));
       return SWIFTCL_E_UNSUPPORTED;
     }
-    if (!fused && windows_cl_lds(M, 16, windows_tw_lds(d->precision, M), false, 4, d->n_k) > (size_t)lds_max) {
+    if (!fused && windows_cl_lds(M, 16, unfused_tw_lds(M), false, 4, d->n_k) > (size_t)lds_max) {
       set_error("n_chi too large for the LDS of one workgroup");
       return SWIFTCL_E_UNSUPPORTED;
     }
