@@ -12,7 +12,8 @@
 //
 // One workgroup of GEOM_THREADS threads owns one parameter point and keeps all of its samples in LDS:
 // every spline is solved by one wavefront (the Thomas recurrences as parallel affine-map scans),
-// the lensing suffix integrals by a block scan, and one thread per chi node assembles g.
+// and the threads assemble g of the clustering tracers node by node; the lensing tracers follow
+// in k_geom_lens (one workgroup each: interval integrals, suffix scans, q at every node).
 #include "common.h"
 #include "geometry.h"
 #include "internal.h"
@@ -24,8 +25,7 @@
 
 size_t geometry_lds_bytes(const plan_dev& p) {
   const size_t tg = p.max_tracers < GEOM_GROUP ? p.max_tracers : GEOM_GROUP;
-  return sizeof(double) * ((size_t)6 * p.n_zg + (size_t)3 * p.n_zs + (size_t)2 * tg * p.n_zs +
-                           (size_t)2 * p.n_union + 64);
+  return sizeof(double) * ((size_t)6 * p.n_zg + (size_t)3 * p.n_zs + (size_t)2 * tg * p.n_zs);
 }
 
 template <typename R>
@@ -54,9 +54,6 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
   double* nzr = zsih + 2 * (size_t)nzs; // [TG][nzs] n(z) rows of the current tracer group (one spare row of
                                         // nzs before it keeps the layout simple)
   double* mn = nzr + (size_t)TG * nzs;  // [TG][nzs]
-  double* seg0 = mn + (size_t)TG * nzs; // [nu]
-  double* seg1 = seg0 + nu;             // [nu]
-  double* tmp = seg1 + nu;              // [64]
 
   const double* chig = in.chi_z + (size_t)b * nzg;
   const double* Dg = in.D_z + (size_t)b * nzg;
@@ -149,7 +146,6 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
     ni[N] = ns[k].inz;
     ni[2 * N] = ns[k].u;
   }
-  const double pref = 1.5 * in.omega_m[b] * SWIFTCL_H0_OVER_C * SWIFTCL_H0_OVER_C;
   for (int g0 = 0; g0 < T; g0 += TG) {
   const int g1 = min(g0 + TG, T);
   // n(z) rows and their splines for tracers [g0, g1) of this point
@@ -181,52 +177,105 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
             (R)(ns[k].w * f * P.ebm[(size_t)bi * N + m]);
     }
   }
-  // lensing tracers, one at a time: interval integrals, suffix scan, then q at every node
-  for (int t = g0; t < min(g1, Tb); ++t) {
-    if (in.kind[(size_t)b * T + t] != SWIFTCL_LENSING) continue;
-    const double* nt = nzr + (size_t)(t - g0) * nzs;
-    const double* mt = mn + (size_t)(t - g0) * nzs;
-    for (int u = tid; u < nu; u += nth) {
-      double s0, s1;
-      lens_interval(P.z_union[u], P.z_union[u + 1], P.union_iv[u], P.union_iv[nu + u], zg, zgih, chi, mchi, zs, zsih,
-                    nt, mt, &s0, &s1);
-      seg0[u] = s0;
-      seg1[u] = s1;
-    }
-    __syncthreads();
-    block_scan(seg0, nu, tmp, false);
-    block_scan(seg1, nu, tmp, false);
-#pragma unroll
-    for (int k = 0; k < MAXN; ++k) {
-      if (!ns[k].active) continue;
-      const int m = tid + k * nth;
-      double p0, p1;
-      lens_interval(ns[k].z, ns[k].zc, ns[k].ugi, ns[k].uni, zg, zgih, chi, mchi, zs, zsih, nt, mt, &p0, &p1);
-      const double I0 = p0 + (ns[k].u + 1 < nu ? seg0[ns[k].u + 1] : 0.0);
-      const double I1 = p1 + (ns[k].u + 1 < nu ? seg1[ns[k].u + 1] : 0.0);
-      const double q = pref * ns[k].chiz * (1.0 + ns[k].z) * (I0 - ns[k].chiz * I1);
-      P.lens_q[((size_t)b * T + t) * N + m] = q;  // for the adjoint
-      const double f = q * ns[k].D / (ns[k].chiz * ns[k].chiz);
-      for (int bi = 0; bi < nb; ++bi)
-        g[(((size_t)b * T + t) * nb + bi) * N + m] =
-            (R)(ns[k].w * f * P.ebm[((size_t)nb + bi) * N + m]);
-    }
-    __syncthreads();
-  }
+  // (lensing tracers: k_geom_lens, one workgroup per (point, tracer))
   __syncthreads();
   }  // tracer groups
 }
 
+size_t lens_lds_bytes(const plan_dev& p) {
+  return sizeof(double) * ((size_t)4 * p.n_zg + (size_t)4 * p.n_zs + (size_t)2 * p.n_union + 64);
+}
+
+// Lensing tracers (Sec. 2.3, eq. tomographic lens efficiency): one workgroup of 512 threads per
+// (point, tracer), idle for clustering and padded slots.  The interval integrals of n and n/chi
+// over the union of the z grids, their suffix sums (block scans), then q and g at every active
+// node; the node geometry and the n(z) spline moments come from k_geometry.
+template <typename R>
+__global__ __launch_bounds__(512) void k_geom_lens(plan_dev P, swiftcl_inputs in) {
+  extern __shared__ double sh[];
+  const int T = P.max_tracers;
+  const int b = blockIdx.x / T, t = blockIdx.x % T;
+  if (b >= in.batch) return;
+  const int Tb = in.n_tracers[b] < T ? in.n_tracers[b] : T;
+  if (t >= Tb || in.kind[(size_t)b * T + t] != SWIFTCL_LENSING) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int nzg = P.n_zg, nzs = P.n_zs, nb = P.n_bands, N = P.N, nu = P.n_union;
+  double* zg = sh;              // [nzg]
+  double* zgih = zg + nzg;      // [nzg]
+  double* chi = zgih + nzg;     // [nzg]
+  double* mchi = chi + nzg;     // [nzg]
+  double* zs = mchi + nzg;      // [nzs]
+  double* zsih = zs + nzs;      // [nzs]
+  double* nt = zsih + nzs;      // [nzs] this tracer's n samples
+  double* mt = nt + nzs;        // [nzs] and their spline moments
+  double* seg0 = mt + nzs;      // [nu]
+  double* seg1 = seg0 + nu;     // [nu]
+  double* tmp = seg1 + nu;      // [64]
+  for (int i = tid; i < nzg; i += nth) {
+    zg[i] = P.z_geom[i];
+    zgih[i] = P.lu_geom[3 * nzg + i];
+    chi[i] = in.chi_z[(size_t)b * nzg + i];
+    mchi[i] = P.m_chi[(size_t)b * nzg + i];
+  }
+  for (int i = tid; i < nzs; i += nth) {
+    zs[i] = P.z_nz[i];
+    zsih[i] = P.lu_nz[3 * nzs + i];
+    nt[i] = in.nz[((size_t)b * T + t) * nzs + i];
+    mt[i] = P.m_n[((size_t)b * T + t) * nzs + i];
+  }
+  __syncthreads();
+  for (int u = tid; u < nu; u += nth) {
+    double s0, s1;
+    lens_interval(P.z_union[u], P.z_union[u + 1], P.union_iv[u], P.union_iv[nu + u], zg, zgih, chi, mchi, zs, zsih,
+                  nt, mt, &s0, &s1);
+    seg0[u] = s0;
+    seg1[u] = s1;
+  }
+  __syncthreads();
+  block_scan(seg0, nu, tmp, false);
+  block_scan(seg1, nu, tmp, false);
+  const double* pt = P.pt + (size_t)b * PT_STRIDE;
+  const double theta = pt[PT_THETA];
+  const int m0 = P.m0, m1 = (int)pt[PT_M1];
+  const double pref = 1.5 * in.omega_m[b] * SWIFTCL_H0_OVER_C * SWIFTCL_H0_OVER_C;
+  R* g = (R*)P.g;
+  for (int m = m0 + tid; m <= m1; m += nth) {
+    const double* nf = P.node_f + (size_t)b * 4 * N + m;
+    const int* ni = P.node_i + (size_t)b * 3 * N + m;
+    const double z = nf[0], x = nf[N], D = nf[3 * N];
+    const int u = ni[2 * N];
+    const double w = (m == m0) ? 0.5 : (m == m1 ? 0.5 + theta : 1.0);
+    double p0, p1;
+    lens_interval(z, P.z_union[u + 1], P.union_iv[u], P.union_iv[nu + u], zg, zgih, chi, mchi, zs, zsih, nt, mt, &p0,
+                  &p1);
+    const double I0 = p0 + (u + 1 < nu ? seg0[u + 1] : 0.0);
+    const double I1 = p1 + (u + 1 < nu ? seg1[u + 1] : 0.0);
+    const double q = pref * x * (1.0 + z) * (I0 - x * I1);
+    P.lens_q[((size_t)b * T + t) * N + m] = q;  // for the adjoint
+    const double fv = q * D / (x * x);
+    for (int bi = 0; bi < nb; ++bi)
+      g[(((size_t)b * T + t) * nb + bi) * N + m] = (R)(w * fv * P.ebm[((size_t)nb + bi) * N + m]);
+  }
+}
+
 hipError_t launch_assemble(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s) {
-  const size_t lds = geometry_lds_bytes(p);
-  if (p.precision == SWIFTCL_FP64)
+  const size_t lds = geometry_lds_bytes(p), ll = lens_lds_bytes(p);
+  const dim3 gl((unsigned)((size_t)in->batch * p.max_tracers));
+  if (p.precision == SWIFTCL_FP64) {
     hipLaunchKernelGGL(k_geometry<double>, dim3(in->batch), dim3(GEOM_THREADS), lds, s, p, *in);
-  else
+    hipLaunchKernelGGL(k_geom_lens<double>, gl, dim3(512), ll, s, p, *in);
+  } else {
     hipLaunchKernelGGL(k_geometry<float>, dim3(in->batch), dim3(GEOM_THREADS), lds, s, p, *in);
+    hipLaunchKernelGGL(k_geom_lens<float>, gl, dim3(512), ll, s, p, *in);
+  }
   return hipGetLastError();
 }
 
 hipError_t prepare_assemble(const plan_dev& p) {
-  return p.precision == SWIFTCL_FP64 ? lds_attr_once((const void*)k_geometry<double>)
-                                     : lds_attr_once((const void*)k_geometry<float>);
+  hipError_t e = p.precision == SWIFTCL_FP64 ? lds_attr_once((const void*)k_geometry<double>)
+                                             : lds_attr_once((const void*)k_geometry<float>);
+  if (e == hipSuccess)
+    e = p.precision == SWIFTCL_FP64 ? lds_attr_once((const void*)k_geom_lens<double>)
+                                    : lds_attr_once((const void*)k_geom_lens<float>);
+  return e;
 }
