@@ -14,6 +14,8 @@ Modules
               j_l(k chi), used to pin the FFTLog oracle (method-error floor)
   limber      the Limber limit (eq. Limber), a high-l check of the quadrature
   gradients   exact / directional derivatives of C_l for the adjoint tests
+  kgrowth     scale-dependent growth D(k, z) (Sec. 3.2): coefficients at N_interp
+              k nodes, continued along ln k by a natural cubic spline
 
 Readings of the paper that the oracle fixes are listed in each function's
 docstring; every one is shared, by statement and not by code, with the HIP

@@ -16,6 +16,8 @@ only; its benchmark files are not used):
   cfg2  cfg1 with biases scaled by U(0.9, 1.1)
   cfg3  256 points, per-point cosmology, ragged tracer / multipole counts
   cfg4  20 clustering + 10 lensing bins, 2048 k, N_chi 2048, 200 l in [2, 3000]
+
+scale_dependent_growth() adds growth samples D(k, z) at interpolation nodes in k to any of them.
 """
 from __future__ import annotations
 
@@ -79,6 +81,29 @@ def growth_factor(z, om, refine=8):
     i_at[order] = cum[1:-1]
     i_one = cum[-1]
     return (e_of_z(z, om) * i_at) / (e_of_z(0.0, om) * i_one)
+
+
+def interpolation_nodes(k, n_interp):
+    """The k nodes of scale-dependent growth: n_interp points uniform in ln k from k[0] to k[-1]."""
+    k = np.asarray(k, float)
+    return np.exp(np.linspace(np.log(k[0]), np.log(k[-1]), int(n_interp)))
+
+
+def scale_dependent_growth(wl, n_interp, f_nu=0.05, k_fs=0.1):
+    """Add D(k, z) samples of a massive-neutrino-like growth suppression to workload wl.
+
+    Below the free-streaming scale k_fs growth is the scale-free D(z); far above it the growth
+    exponent is lowered by 3 f_nu / 5, so D(k, z) = D(z)^(1 - 3 f_nu / 5 * k^2 / (k^2 + k_fs^2)),
+    which keeps D(k, 0) = 1.  Adds k_nodes[n_interp] and D_kz[B, n_interp, nzg] (samples on the
+    geometry z grid at each node); returns wl.
+    """
+    kn = interpolation_nodes(wl["k"], n_interp)
+    supp = 0.6 * f_nu * kn ** 2 / (kn ** 2 + k_fs ** 2)
+    D = np.asarray(wl["D_z"], float)
+    wl["n_interp"] = int(n_interp)
+    wl["k_nodes"] = kn
+    wl["D_kz"] = np.ascontiguousarray(D[:, None, :] ** (1.0 - supp[None, :, None]))
+    return wl
 
 
 def bbks_transfer(q):
