@@ -81,6 +81,8 @@ typedef struct {
   int32_t max_ell;      /* capacity: multipoles per point (row stride of ell_idx and outputs)   */
   int32_t precision;    /* swiftcl_precision                                                     */
   int32_t device;       /* HIP device ordinal the plan lives on                                  */
+  int32_t n_interp;     /* scale-dependent growth (Sec. 3.2, swiftcl_cl_kgrowth): number of k nodes
+                           N_interp, 0 = none, else 2..n_k; FP32 and split-precision plans only   */
 } swiftcl_plan_desc;
 
 /* Per-call inputs.  Device pointers owned by the caller, row-major, never written. */
@@ -185,6 +187,23 @@ swiftcl_status swiftcl_get_launch(swiftcl_plan_t plan, int32_t* fwd_mode, int32_
 swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t plan, const swiftcl_inputs* in, const void* dC,
                                          double* dpk, double* dbias, double* dnz, double* dD, uint32_t flags,
                                          void* stream, float* stage_ms);
+
+/* Angular power spectra with scale-dependent growth D(k, z) (Sec. 3.2: P(k, chi, chi') =
+ * P(k, z_fid) D(k, z(chi)) D(k, z(chi')), FFTLog coefficients c_n(k) of f(chi) D(k, chi)).  The
+ * coefficients are computed at the plan's n_interp nodes kappa_a = k_0 (k_max / k_0)^{a / (n_interp-1)}
+ * (uniform in ln k, both ends included) and continued to every k node by the natural cubic spline in
+ * ln k through the node values; the window at k_j uses c_n(k_j), so the inverse transform becomes a
+ * dense sum over n per k (run as a GEMM on MFMA).  Growth at a node is continued in z by the natural
+ * cubic spline, like D(z).
+ *   D_kz  device, double, [B][n_interp][n_zg]: D(kappa_a, z_geom) of every point; it replaces
+ *         in->D_z, which is not read.
+ *   C     as for swiftcl_cl (float).
+ * Needs a plan with n_interp >= 2 (else SWIFTCL_E_INVALID); FP32 or split precision.  Non-finite
+ * D_kz samples raise the device flag of non-finite inputs.  Overwrites the plan's forward state (a
+ * backward call after it cannot use SWIFTCL_BWD_REUSE_FORWARD).  No allocation and no
+ * synchronisation: safe inside hipGraph capture. */
+swiftcl_status swiftcl_cl_kgrowth(swiftcl_plan_t plan, const swiftcl_inputs* in, const double* D_kz, void* C,
+                                  void* stream);
 
 #ifdef __cplusplus
 }

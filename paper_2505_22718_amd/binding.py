@@ -53,6 +53,7 @@ class swiftcl_plan_desc(ctypes.Structure):
         ("max_ell", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("device", ctypes.c_int32),
+        ("n_interp", ctypes.c_int32),
     ]
 
 
@@ -74,7 +75,8 @@ class swiftcl_inputs(ctypes.Structure):
 
 EXPORTED = ["swiftcl_plan", "swiftcl_plan_destroy", "swiftcl_last_error", "swiftcl_device_flags",
             "swiftcl_windows", "swiftcl_cl", "swiftcl_cl_timed", "swiftcl_cl_backward",
-            "swiftcl_cl_backward_timed", "swiftcl_autotune", "swiftcl_set_launch", "swiftcl_get_launch"]
+            "swiftcl_cl_backward_timed", "swiftcl_autotune", "swiftcl_set_launch", "swiftcl_get_launch",
+            "swiftcl_cl_kgrowth"]
 
 _lib = None
 
@@ -96,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.swiftcl_windows.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
     lib.swiftcl_cl.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
     lib.swiftcl_cl_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, ctypes.POINTER(ctypes.c_float)]
+    lib.swiftcl_cl_kgrowth.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp]
     lib.swiftcl_cl_backward.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, ctypes.c_uint32, vp]
     lib.swiftcl_autotune.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, ctypes.c_char_p,
                                      ctypes.c_char_p, ctypes.c_int32]
@@ -149,6 +152,11 @@ def swiftcl_windows(plan, inputs: swiftcl_inputs, W: int, stream: int = 0):
 
 def swiftcl_cl(plan, inputs: swiftcl_inputs, C: int, stream: int = 0):
     _check(load().swiftcl_cl(plan, ctypes.byref(inputs), ctypes.c_void_p(C), ctypes.c_void_p(stream)))
+
+
+def swiftcl_cl_kgrowth(plan, inputs: swiftcl_inputs, D_kz: int, C: int, stream: int = 0):
+    _check(load().swiftcl_cl_kgrowth(plan, ctypes.byref(inputs), ctypes.c_void_p(D_kz), ctypes.c_void_p(C),
+                                     ctypes.c_void_p(stream)))
 
 
 def swiftcl_cl_timed(plan, inputs: swiftcl_inputs, C: int, stream: int = 0):

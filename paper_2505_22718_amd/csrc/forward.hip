@@ -558,6 +558,21 @@ __global__ __launch_bounds__(256) void k_contract(plan_dev P, swiftcl_inputs in,
   }
 }
 
+hipError_t launch_contract(const plan_dev& p, const swiftcl_inputs* in, void* C, int b0, int nbp, hipStream_t s) {
+  const dim3 g2((unsigned)((size_t)nbp * p.max_ell));
+  if (p.precision == SWIFTCL_SPLIT_BF16) hipLaunchKernelGGL(k_contract<true>, g2, dim3(256), 0, s, p, *in, (float*)C, b0, nbp);
+  else hipLaunchKernelGGL(k_contract<false>, g2, dim3(256), 0, s, p, *in, (float*)C, b0, nbp);
+  return hipGetLastError();
+}
+
+hipError_t launch_sqrt_s(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s) {
+  if (p.precision == SWIFTCL_FP64)
+    hipLaunchKernelGGL(k_sqrt_s<double>, dim3((p.n_k + 255) / 256, in->batch), dim3(256), 0, s, p, *in);
+  else
+    hipLaunchKernelGGL(k_sqrt_s<float>, dim3((p.n_k + 255) / 256, in->batch), dim3(256), 0, s, p, *in);
+  return hipGetLastError();
+}
+
 template <int M>
 static hipError_t launch_unfused(const plan_dev& p, const swiftcl_inputs* in, void* C, hipStream_t s) {
   constexpr int NW = 16;

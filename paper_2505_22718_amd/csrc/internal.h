@@ -80,7 +80,18 @@ struct plan_dev {
   int fused;
   int adjoint;        // swiftcl_cl_backward available (fused, FP32/FP64, its LDS fits the device)
   int vchunk;         // points per chunk of the unfused path
-  void* vbuf;         // [vchunk][max_ell][32][n_k] FP32, or bf16 hi then lo (unfused path only)
+  void* vbuf;         // [vchunk][max_ell][32][n_k] FP32, or bf16 hi then lo (unfused and kgrowth paths)
+  // scale-dependent growth (swiftcl_cl_kgrowth); points run in chunks of vchunk
+  int n_interp;       // k nodes (0 = not built)
+  int kg_ntile;       // slot tiles per (point, tracer): ceil(max_ell / 64) + n_bands
+  double* kg_ones;    // [max_batch][n_zg] ones: the assembly's D(z) while growth sits at the nodes
+  int* kg_ia;         // [n_k] node interval a_j of k_j
+  float* kg_w;        // [n_k][4] spline weights of c_a, c_{a+1}, M_a, M_{a+1} at k_j
+  float* kg_ip;       // [n_interp] 1 / pivot of the node spline's tridiagonal system
+  void* kg_c;         // [vchunk][T][n_bands][n_interp][M] complex float: node coefficients
+  void* kg_m;         // same layout: their second derivatives along ln k
+  int* kg_perm;       // [vchunk][max_ell] multipole slots grouped by band
+  int* kg_tile;       // [vchunk][kg_ntile][4] band, first entry of kg_perm, count, 0
 };
 
 struct swiftcl_plan_s {
@@ -112,6 +123,11 @@ hipError_t launch_u_table(const plan_dev& p, const double* d_ell, hipStream_t s)
 hipError_t launch_assemble(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s);
 hipError_t launch_forward_fft(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s);
 hipError_t launch_windows_cl(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s);
+hipError_t launch_sqrt_s(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s);
+// C of points [b0, b0 + nbp) from the V rows in the workspace (vbuf)
+hipError_t launch_contract(const plan_dev& p, const swiftcl_inputs* in, void* C, int b0, int nbp, hipStream_t s);
+hipError_t launch_kgrowth(const plan_dev& p, const swiftcl_inputs* in, const double* D_kz, void* C, hipStream_t s);
+size_t kgrowth_fft_lds(int M, int n_zg);  // dynamic LDS of the node-coefficient kernel
 // ev (optional): two events recorded after the first and second backward kernels
 hipError_t launch_backward(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,
                            double* dbias, double* dnz, double* dD, hipStream_t s, hipEvent_t* ev = nullptr);

@@ -218,6 +218,13 @@ static swiftcl_status validate_desc(const swiftcl_plan_desc* d) {
   if (d->max_batch < 1 || d->max_tracers < 1 || d->max_ell < 1) { set_error("capacities must be >= 1"); return SWIFTCL_E_INVALID; }
   if (d->max_tracers > 32) { set_error("max_tracers > 32 is not built"); return SWIFTCL_E_UNSUPPORTED; }
   if (d->precision < 0 || d->precision > 2) { set_error("unknown precision"); return SWIFTCL_E_INVALID; }
+  if (d->n_interp != 0) {
+    if (d->n_interp < 2 || d->n_interp > d->n_k) { set_error("n_interp must be 0 or in 2..n_k"); return SWIFTCL_E_INVALID; }
+    if (d->precision == SWIFTCL_FP64) {
+      set_error("scale-dependent growth (n_interp > 0) is built for FP32 and split precision");
+      return SWIFTCL_E_UNSUPPORTED;
+    }
+  }
   return SWIFTCL_OK;
 }
 
@@ -254,7 +261,8 @@ static void free_plan(swiftcl_plan_s* p) {
   if (!p) return;
   void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
-                  p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf};
+                  p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf,
+                  p->d.kg_ones, p->d.kg_ia, p->d.kg_w, p->d.kg_ip, p->d.kg_c, p->d.kg_m, p->d.kg_perm, p->d.kg_tile};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -297,7 +305,8 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     probe.n_zs = d->n_zs;
     probe.max_tracers = d->max_tracers;
     probe.n_union = (int)us.size() - 1;
-    if (geometry_lds_bytes(probe) > (size_t)lds_max || bwd_geometry_lds_bytes(probe) > (size_t)lds_max) {
+    if (geometry_lds_bytes(probe) > (size_t)lds_max || bwd_geometry_lds_bytes(probe) > (size_t)lds_max ||
+        (d->n_interp > 0 && kgrowth_fft_lds(d->n_chi / 2, d->n_zg) > (size_t)lds_max)) {
       set_error("geometry samples exceed the LDS of one workgroup (n_zg, n_zs, max_tracers too large)");
       return SWIFTCL_E_UNSUPPORTED;
     }
@@ -456,15 +465,58 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     for (int bb = 1; bb <= B; ++bb) slots = std::max(slots, (long)bb * backward_chunks(probe, bb));
     p->d.bwd_slots = (int)slots;
   }
-  if (!p->d.fused) {
-    // workspace of the unfused projection: V of up to 32 tracer slots, a chunk of points at a time
+  p->d.n_interp = d->n_interp;
+  if (!p->d.fused || p->d.n_interp > 0) {
+    // workspace of the unfused projection (V of up to 32 tracer slots) and of scale-dependent
+    // growth (node coefficients and their spline moments), a chunk of points at a time
     const size_t per_point = (size_t)p->d.max_ell * 32 * nk * 4;
-    const size_t budget = (size_t)512 << 20;
-    size_t chunk = budget / per_point;
+    size_t chunk = ((size_t)512 << 20) / per_point;
+    if (p->d.n_interp > 0) {
+      const size_t per_kg = per_point + (size_t)2 * T * nb * p->d.n_interp * M * 8;
+      chunk = ((size_t)4 << 30) / per_kg;
+    }
     if (chunk < 1) chunk = 1;
     if (chunk > (size_t)B) chunk = B;
     p->d.vchunk = (int)chunk;
     ALLOC(vbuf, char, chunk * per_point);
+  }
+  std::vector<int> kg_ia;
+  std::vector<float> kg_w, kg_ip;
+  std::vector<double> kg_ones;
+  if (p->d.n_interp > 0) {
+    const int A = p->d.n_interp;
+    const size_t chunk = p->d.vchunk;
+    p->d.kg_ntile = (p->d.max_ell + 63) / 64 + nb;
+    ALLOC(kg_ones, double, (size_t)B * p->d.n_zg);
+    ALLOC(kg_ia, int, nk);
+    ALLOC(kg_w, float, (size_t)4 * nk);
+    ALLOC(kg_ip, float, A);
+    ALLOC(kg_c, char, chunk * T * nb * A * M * 8);
+    ALLOC(kg_m, char, chunk * T * nb * A * M * 8);
+    ALLOC(kg_perm, int, chunk * p->d.max_ell);
+    ALLOC(kg_tile, int, chunk * p->d.kg_ntile * 4);
+    // natural spline through the nodes, uniform in ln k: interval, offset and weights of every k node
+    const double lk0 = std::log(d->k[0]);
+    const double h = (std::log(d->k[nk - 1]) - lk0) / (A - 1);
+    kg_ia.resize(nk);
+    kg_w.resize((size_t)4 * nk);
+    for (int j = 0; j < nk; ++j) {
+      const double u = (std::log(d->k[j]) - lk0) / h;
+      const int a = std::min(std::max((int)std::floor(u), 0), A - 2);
+      const double tt = u - a, ut = 1.0 - tt;
+      kg_ia[j] = a;
+      kg_w[4 * (size_t)j] = (float)ut;
+      kg_w[4 * (size_t)j + 1] = (float)tt;
+      kg_w[4 * (size_t)j + 2] = (float)(h * h / 6.0 * (ut * ut * ut - ut));
+      kg_w[4 * (size_t)j + 3] = (float)(h * h / 6.0 * (tt * tt * tt - tt));
+    }
+    kg_ip.assign(A, 0.f);
+    double ip = 0.0;
+    for (int a = 1; a + 1 < A; ++a) {
+      ip = 1.0 / (4.0 - ip);
+      kg_ip[a] = (float)ip;
+    }
+    kg_ones.assign((size_t)B * p->d.n_zg, 1.0);
   }
   p->d.sched_stride = B / SWIFTCL_NXCD + 2;
   ALLOC(sched, int, (size_t)(SWIFTCL_NXCD + 1) * p->d.sched_stride);
@@ -502,6 +554,16 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   for (auto& u : ups) {
     e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) break;
+  }
+  if (e == hipSuccess && p->d.n_interp > 0) {
+    const Up kg[] = {{p->d.kg_ones, kg_ones.data(), kg_ones.size() * sizeof(double)},
+                     {p->d.kg_ia, kg_ia.data(), kg_ia.size() * sizeof(int)},
+                     {p->d.kg_w, kg_w.data(), kg_w.size() * sizeof(float)},
+                     {p->d.kg_ip, kg_ip.data(), kg_ip.size() * sizeof(float)}};
+    for (auto& u : kg) {
+      e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) break;
+    }
   }
   if (e == hipSuccess) e = hipMemsetAsync(p->d.flags, 0, sizeof(int), s);
   if (e == hipSuccess) e = launch_u_table(p->d, d_ell, s);
@@ -609,6 +671,30 @@ extern "C" swiftcl_status swiftcl_cl_timed(swiftcl_plan_t p, const swiftcl_input
   for (int i = 0; i < 4; ++i)
     if (ev[i]) (void)hipEventDestroy(ev[i]);
   return hip_check(e, "timed forward");
+}
+
+extern "C" swiftcl_status swiftcl_cl_kgrowth(swiftcl_plan_t p, const swiftcl_inputs* in, const double* D_kz, void* C,
+                                             void* stream) {
+  if (!p) { set_error("plan is NULL"); return SWIFTCL_E_INVALID; }
+  if (!in) { set_error("inputs is NULL"); return SWIFTCL_E_INVALID; }
+  if (!D_kz || !C) { set_error("D_kz or C is NULL"); return SWIFTCL_E_INVALID; }
+  if (p->d.n_interp < 2) {
+    set_error("the plan has no interpolation nodes in k (n_interp = 0)");
+    return SWIFTCL_E_INVALID;
+  }
+  // the kernels are assembled without growth (D = 1); growth enters per node
+  swiftcl_inputs in1 = *in;
+  in1.D_z = p->d.kg_ones;
+  swiftcl_status st = check_inputs(p, &in1);
+  if (st != SWIFTCL_OK) return st;
+  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  p->fwd_valid = false;
+  hipError_t e = launch_assemble(p->d, &in1, s);
+  if (e == hipSuccess) e = launch_sqrt_s(p->d, &in1, s);
+  if (e == hipSuccess) e = launch_kgrowth(p->d, &in1, D_kz, C, s);
+  return hip_check(e, "scale-dependent growth launch");
 }
 
 // Checks shared by the two backward entry points; `reuse` is set when the forward state is kept.

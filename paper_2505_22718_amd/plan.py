@@ -41,7 +41,7 @@ class Plan:
 
     def __init__(self, k, ell, z_geom, z_nz, n_chi, max_batch, max_tracers, max_ell, precision="fp32",
                  band_ell_lo=DEFAULT_BAND_ELL_LO, fftlog_b=DEFAULT_FFTLOG_B, taper_frac=0.0, edge_node=0,
-                 device=0):
+                 device=0, n_interp=0):
         self.k = _f64(k)
         self.ell = _f64(ell)
         self.z_geom = _f64(z_geom)
@@ -68,6 +68,8 @@ class Plan:
         d.max_batch, d.max_tracers, d.max_ell = self.max_batch, self.max_tracers, self.max_ell
         d.precision = PRECISIONS[precision]
         d.device = self.device.index or 0
+        d.n_interp = int(n_interp)
+        self.n_interp = int(n_interp)
         self.desc = d
         self.out_dtype = torch.float64 if precision == "fp64" else torch.float32
         with torch.cuda.device(self.device):
@@ -125,6 +127,15 @@ class Plan:
             out = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
         self._new_state()
         bd.swiftcl_cl(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
+        return out
+
+    def cl_kgrowth(self, t, D_kz, out=None):
+        """C_l with scale-dependent growth: D_kz [B][n_interp][n_zg] float64 on the plan's device."""
+        B = t["n_tracers"].shape[0]
+        if out is None:
+            out = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
+        self._new_state()
+        bd.swiftcl_cl_kgrowth(self.handle, self.inputs_struct(t), D_kz.data_ptr(), out.data_ptr(), self._stream())
         return out
 
     def cl_timed(self, t, out):

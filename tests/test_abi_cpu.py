@@ -81,6 +81,9 @@ def _desc(**over):
     (dict(edge_node=600), -1),
     (dict(z_nz=np.linspace(0.0, 3, 200)), -1),               # n(z) grid outside the geometry range
     (dict(k=np.array([1e-4] + [np.nan] * 255)), -1),
+    (dict(n_interp=1), -1),                                  # one node cannot be interpolated
+    (dict(n_interp=257), -1),                                # more nodes than k nodes
+    (dict(n_interp=16), -5),                                 # scale-dependent growth in FP64
 ])
 def test_plan_rejects_bad_descriptor(lib, over, code):
     d, keep = _desc(**over)
@@ -103,4 +106,5 @@ def test_null_arguments_rejected(lib):
     assert lib.swiftcl_cl_backward(None, ctypes.byref(inp), None, None, None, None, None, 0, None) == bd.SWIFTCL_E_INVALID
     assert lib.swiftcl_cl_backward(None, ctypes.byref(inp), None, None, None, None, None,
                                    bd.SWIFTCL_BWD_REUSE_FORWARD, None) == bd.SWIFTCL_E_INVALID
+    assert lib.swiftcl_cl_kgrowth(None, ctypes.byref(inp), None, None, None) == bd.SWIFTCL_E_INVALID
     assert lib.swiftcl_plan_destroy(None) == bd.SWIFTCL_E_INVALID
