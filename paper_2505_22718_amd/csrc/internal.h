@@ -88,6 +88,7 @@ struct plan_dev {
   int* kg_ia;         // [n_k] node interval a_j of k_j
   float* kg_w;        // [n_k][4] spline weights of c_a, c_{a+1}, M_a, M_{a+1} at k_j
   float* kg_ip;       // [n_interp] 1 / pivot of the node spline's tridiagonal system
+  float* kg_uh;       // [2][n_ell][M / 16][4][8] U in the GEMM's A-operand order (h_n and signs folded)
   void* kg_c;         // [vchunk][T][n_bands][n_interp][M] complex float: node coefficients
   void* kg_m;         // same layout: their second derivatives along ln k
   int* kg_perm;       // [vchunk][max_ell] multipole slots grouped by band
@@ -128,6 +129,7 @@ hipError_t launch_sqrt_s(const plan_dev& p, const swiftcl_inputs* in, hipStream_
 hipError_t launch_contract(const plan_dev& p, const swiftcl_inputs* in, void* C, int b0, int nbp, hipStream_t s);
 hipError_t launch_kgrowth(const plan_dev& p, const swiftcl_inputs* in, const double* D_kz, void* C, hipStream_t s);
 size_t kgrowth_fft_lds(int M, int n_zg);  // dynamic LDS of the node-coefficient kernel
+hipError_t launch_kgrowth_tables(const plan_dev& p, hipStream_t s);  // plan time, after the U table
 // ev (optional): two events recorded after the first and second backward kernels
 hipError_t launch_backward(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,
                            double* dbias, double* dnz, double* dD, hipStream_t s, hipEvent_t* ev = nullptr);

@@ -17,6 +17,8 @@
 //   k_kg_cspline  per (point, tracer, band, n): the node spline along ln k (Thomas, FP32)
 //   k_kg_windows  the GEMM above, one workgroup per (point, tracer, slot tile, 64 k nodes)
 //   k_contract    C = V V^T per (point, multipole) from the workspace (forward.hip)
+#include <type_traits>
+
 #include "common.h"
 #include "geometry.h"
 #include "internal.h"
@@ -29,8 +31,6 @@ __device__ __forceinline__ int clamp_i(int v, int lo, int hi) { return v < lo ? 
 
 constexpr int KG_TILE = 64;   // slots and k nodes per GEMM workgroup
 constexpr int KG_KC = 16;     // coefficients n per K chunk (32 real K rows)
-constexpr int KG_AS = 2 * KG_KC + 1;  // padded row of the U tile
-constexpr int KG_BS = KG_TILE + 4;    // padded row of the X tile
 
 // One thread per point: slot permutation (stable, grouped by band) and the tile list.
 __global__ void k_kg_slots(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
@@ -187,18 +187,39 @@ __device__ __forceinline__ unsigned short bf16_rne_kg(float x) {
   return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-// W tile [<= 64 slots of one band] x [64 k nodes] of one (point, tracer) by 4 wavefronts: wave w
-// owns k nodes 16w..16w+15 and every 16-row tile of slots.  Per K chunk the block writes U (A
-// operand, [slot][2n + {0,1}] = h_n (Re U, -Im U)) and X (B operand, [2n + {0,1}][k] = (Re X, Im X))
-// to LDS, then each wave runs 8 k-steps of 16x16x4 f32 MFMAs.  Blocks of one (point, tracer) share
+// U in the A-operand order of the GEMM: for every (kind, multipole) and chunk c of 16 coefficients,
+// 4 groups k of 8 consecutive K steps; entry [k][s] is h_n Re U(n) (k even) or -h_n Im U(n) (k odd)
+// with n = 16 c + 8 (k / 2) + s.  Lane (row, k) of a 16x16x4 MFMA then loads its A values for the
+// chunk's 8 K steps as 8 consecutive floats.  Built once per plan.
+__global__ void k_kg_utab(plan_dev P) {
+  const int M = P.M;
+  const size_t total = (size_t)2 * P.n_ell * 2 * M;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int s = (int)(i & 7), k = (int)((i >> 3) & 3);
+    const size_t row_c = i >> 5;  // (kind, multipole, chunk)
+    const int c = (int)(row_c % (M / KG_KC));
+    const size_t row = row_c / (M / KG_KC);
+    const int n = KG_KC * c + 8 * (k >> 1) + s;
+    const float2 u = ((const float2*)P.U)[row * M + n];
+    const float h = n == 0 ? 1.f : 2.f;
+    P.kg_uh[i] = (k & 1) ? -h * u.y : h * u.x;
+  }
+}
+
+// W tile [<= 64 slots of one band] x [64 k nodes] of one (point, tracer) by 4 wavefronts.  Wave w
+// owns k nodes 16w..16w+15 and runs the whole K loop on its own: its U fragments come from the
+// operand-ordered table (two 16-byte loads per row tile and chunk), and it builds its 16 columns of
+// X, 16 coefficients at a time, in a private LDS strip laid out so that each lane then reads its 8
+// B values as two 16-byte loads.  No block barrier in the loop.  Blocks of one (point, tracer) share
 // an XCD, so its node coefficients are read into one L2.
+constexpr int KG_XP = 36;  // floats per k-node row of the X strip: [4 groups][8 steps] + 4 (banks)
+
+constexpr int KG_UP = 36;  // floats per slot row of the U tile: [4 groups][8 steps] + 4 (banks)
+
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
-  __shared__ float As[KG_TILE][KG_AS];
-  __shared__ float Bs[2 * KG_KC][KG_BS];
-  __shared__ float2 stw[1024];
-  __shared__ float4 wts[KG_TILE];
-  __shared__ int ias[KG_TILE];
+  __shared__ __align__(16) float Xs[4][16][KG_XP];
+  __shared__ __align__(16) float Us[2][KG_TILE][KG_UP];
   __shared__ int eis[KG_TILE];
   __shared__ int lis[KG_TILE];
   const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands, M = P.M, A = P.n_interp;
@@ -217,101 +238,121 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
   if (cnt <= 0) return;
   const int kind = in.kind[(size_t)b * T + t] & 1;
   const int tid = threadIdx.x, wave = tid / SWIFTCL_WAVE, lane = tid % SWIFTCL_WAVE;
-  const int j0 = jt * KG_TILE;
-  for (int i = tid; i < M; i += 256) stw[i] = ((const float2*)P.tw)[i];
   if (tid < KG_TILE) {
-    const int r = tid;
     int li = -1, ei = 0;
-    if (r < cnt) {
-      li = P.kg_perm[(size_t)bl * Lm + s0 + r];
+    if (tid < cnt) {
+      li = P.kg_perm[(size_t)bl * Lm + s0 + tid];
       ei = in.ell_idx[(size_t)b * Lm + li];
       if (ei < 0 || ei >= P.n_ell) ei = 0;  // flagged by k_kg_slots
     }
-    lis[r] = li;
-    eis[r] = ei;
-    const int j = j0 + r;
-    ias[r] = j < nk ? P.kg_ia[j] : 0;
-    wts[r] = j < nk ? ((const float4*)P.kg_w)[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    lis[tid] = li;
+    eis[tid] = ei;
   }
   __syncthreads();
-  const float2* U = (const float2*)P.U + (size_t)kind * P.n_ell * M;
-  const size_t cbase = (((size_t)bl * T + t) * nb + band) * A;
-  const float2* kc = (const float2*)P.kg_c + cbase * M;
-  const float2* km = (const float2*)P.kg_m + cbase * M;
   const int nrt = (cnt + 15) / 16;
   const int Nmask = 2 * M - 1;
+  const float2* tw = (const float2*)P.tw;
+  auto twid = [&](int v) {
+    const int qq = v & Nmask;
+    float2 e = tw[qq & (M - 1)];
+    if (qq >= M) { e.x = -e.x; e.y = -e.y; }
+    return e;
+  };
+  const int jl = lane & 15, kq = lane >> 4;
+  const int j = KG_TILE * jt + 16 * wave + jl;  // this lane's k node
+  const bool jok = j < nk;
+  // A: the block stages the operand-ordered U rows of its slots, one chunk ahead, in LDS; thread
+  // tid copies 16 bytes (4 k steps) of slots tid / 8 and tid / 8 + 32
+  const float* uh = P.kg_uh + (size_t)kind * P.n_ell * 2 * M;
+  const int ur = tid >> 3, uc = 4 * (tid & 7);
+  const int uoff0 = eis[ur] * 2 * M + uc, uoff1 = eis[ur + 32] * 2 * M + uc;
+  const bool ul1 = ur + 32 < cnt;
+  // B generation: coefficients nl = kq + 4 q of k node j from its node interval
+  const int jc = jok ? j : nk - 1;
+  const int ia = P.kg_ia[jc];
+  const float4 wb = ((const float4*)P.kg_w)[jc];
+  const size_t cbase = (((size_t)bl * T + t) * nb + band) * A;
+  const float2* kc = (const float2*)P.kg_c + (cbase + ia) * M + kq;
+  const float2* km = (const float2*)P.kg_m + (cbase + ia) * M + kq;
+  float2 eq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) eq[q] = twid((kq + 4 * q) * j);
+  float* xs = &Xs[wave][0][0];
   v4f acc[4];
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) acc[rt] = (v4f){0.f, 0.f, 0.f, 0.f};
-  for (int n0 = 0; n0 < M; n0 += KG_KC) {
-    // A operand: 64 slots x 16 coefficients; lanes run along n (coalesced rows of U)
+  // the K loop, instantiated for the number of 16-slot row tiles so that no MFMA sits behind a branch
+  auto kloop = [&](auto nrt_c) {
+    constexpr int NRT = decltype(nrt_c)::value;
     {
-      const int nl = tid & (KG_KC - 1);
-      const int n = n0 + nl;
-      const float h = n == 0 ? 1.f : 2.f;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = (tid >> 4) + 16 * q;
-        float2 u = make_float2(0.f, 0.f);
-        if (r < cnt) u = U[(size_t)eis[r] * M + n];
-        As[r][2 * nl] = h * u.x;
-        As[r][2 * nl + 1] = -h * u.y;
-      }
-    }
-    // B operand: 16 coefficients x 64 k nodes; lanes run along k
-    {
-      const int jj = tid & (KG_TILE - 1);
-      const int j = j0 + jj;
-      const int a = ias[jj];
-      const float4 w = wts[jj];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int nl = (tid >> 6) + 4 * q;
-        const int n = n0 + nl;
-        float2 x = make_float2(0.f, 0.f);
-        if (j < nk) {
-          const float2 ca = kc[(size_t)a * M + n], cb = kc[(size_t)(a + 1) * M + n];
-          const float2 ma = km[(size_t)a * M + n], mb = km[(size_t)(a + 1) * M + n];
-          float2 c;
-          c.x = w.x * ca.x + w.y * cb.x + w.z * ma.x + w.w * mb.x;
-          c.y = w.x * ca.y + w.y * cb.y + w.z * ma.y + w.w * mb.y;
-          const int qq = (n * j) & Nmask;
-          float2 e = stw[qq & (M - 1)];
-          if (qq >= M) { e.x = -e.x; e.y = -e.y; }
-          x = cmul(c, e);
-        }
-        Bs[2 * nl][jj] = x.x;
-        Bs[2 * nl + 1][jj] = x.y;
-      }
+      *(float4*)&Us[0][ur][uc] = *(const float4*)(uh + uoff0);
+      if (NRT > 2) *(float4*)&Us[0][ur + 32][uc] = ul1 ? *(const float4*)(uh + uoff1) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __syncthreads();
+    int buf = 0;
+    for (int n0 = 0; n0 < M; n0 += KG_KC) {
+      // next chunk's U rows, in flight during this chunk
+      float4 un0 = make_float4(0.f, 0.f, 0.f, 0.f), un1 = un0;
+      const bool more = n0 + KG_KC < M;
+      if (more) {
+        un0 = *(const float4*)(uh + uoff0 + 2 * (n0 + KG_KC));
+        if (NRT > 2 && ul1) un1 = *(const float4*)(uh + uoff1 + 2 * (n0 + KG_KC));
+      }
+      const float2 e0 = twid(n0 * j);
 #pragma unroll
-    for (int ks = 0; ks < 2 * KG_KC / 4; ++ks) {
-      const float bv = Bs[4 * ks + (lane >> 4)][16 * wave + (lane & 15)];
+      for (int q = 0; q < 4; ++q) {
+        const int nl = kq + 4 * q;
+        const float2 ca = kc[n0 + 4 * q], cb = kc[M + n0 + 4 * q];
+        const float2 ma = km[n0 + 4 * q], mb = km[M + n0 + 4 * q];
+        float2 c;
+        c.x = wb.x * ca.x + wb.y * cb.x + wb.z * ma.x + wb.w * mb.x;
+        c.y = wb.x * ca.y + wb.y * cb.y + wb.z * ma.y + wb.w * mb.y;
+        const float2 x = cmul(c, cmul(e0, eq[q]));
+        // K order of the chunk: group 2 (nl / 8) + {0: Re, 1: Im}, step nl % 8
+        xs[jl * KG_XP + 16 * (nl >> 3) + (nl & 7)] = jok ? x.x : 0.f;
+        xs[jl * KG_XP + 16 * (nl >> 3) + 8 + (nl & 7)] = jok ? x.y : 0.f;
+      }
+      wave_sync();
+      const float4 b0v = *(const float4*)(xs + jl * KG_XP + 8 * kq);
+      const float4 b1v = *(const float4*)(xs + jl * KG_XP + 8 * kq + 4);
+      wave_sync();
+      const float bf[8] = {b0v.x, b0v.y, b0v.z, b0v.w, b1v.x, b1v.y, b1v.z, b1v.w};
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-        if (rt < nrt) {
-          const float av = As[16 * rt + (lane & 15)][4 * ks + (lane >> 4)];
-          acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rt], 0, 0, 0);
-        }
+      for (int rt = 0; rt < NRT; ++rt) {
+        const float4 a0 = *(const float4*)&Us[buf][16 * rt + jl][8 * kq];
+        const float4 a1 = *(const float4*)&Us[buf][16 * rt + jl][8 * kq + 4];
+        const float af[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s], bf[s], acc[rt], 0, 0, 0);
+      }
+      if (more) {
+        *(float4*)&Us[buf ^ 1][ur][uc] = un0;
+        if (NRT > 2) *(float4*)&Us[buf ^ 1][ur + 32][uc] = un1;
+      }
+      __syncthreads();
+      buf ^= 1;
     }
-    __syncthreads();
+  };
+  switch (nrt) {
+    case 1: kloop(std::integral_constant<int, 1>{}); break;
+    case 2: kloop(std::integral_constant<int, 2>{}); break;
+    case 3: kloop(std::integral_constant<int, 3>{}); break;
+    default: kloop(std::integral_constant<int, 4>{}); break;
   }
   // V = F(l) kscale sqrt(s) W into the workspace rows (point, slot, tracer)
-  const int j = j0 + 16 * wave + (lane & 15);
-  if (j >= nk) return;
-  const float kq = ((const float*)P.kss)[(((size_t)b * 2 + kind) * nb + band) * nk + j];
+  if (!jok) return;
+  const float kqv = ((const float*)P.kss)[(((size_t)b * 2 + kind) * nb + band) * nk + j];
   const size_t lo_off = (size_t)P.vchunk * Lm * 32 * nk;
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) {
     if (rt >= nrt) continue;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int r = 16 * rt + 4 * (lane >> 4) + q;
+      const int r = 16 * rt + 4 * kq + q;
       if (r >= cnt) continue;
       const int li = lis[r];
       const float F = kind ? (float)P.fell[eis[r]] : 1.f;
-      const float x = F * kq * acc[rt][q];
+      const float x = F * kqv * acc[rt][q];
       const size_t o = (((size_t)bl * Lm + li) * 32 + t) * nk + j;
       if (SPLIT) {
         const unsigned short hi = bf16_rne_kg(x);
@@ -370,6 +411,11 @@ size_t kgrowth_fft_lds(int M, int n_zg) {
     case 1024: return kg_fft_lds<1024>(n_zg);
   }
   return 0;
+}
+
+hipError_t launch_kgrowth_tables(const plan_dev& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_kg_utab, dim3(256), dim3(256), 0, s, p);
+  return hipGetLastError();
 }
 
 hipError_t launch_kgrowth(const plan_dev& p, const swiftcl_inputs* in, const double* D_kz, void* C, hipStream_t s) {

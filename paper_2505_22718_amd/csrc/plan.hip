@@ -262,7 +262,8 @@ static void free_plan(swiftcl_plan_s* p) {
   void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
                   p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf,
-                  p->d.kg_ones, p->d.kg_ia, p->d.kg_w, p->d.kg_ip, p->d.kg_c, p->d.kg_m, p->d.kg_perm, p->d.kg_tile};
+                  p->d.kg_ones, p->d.kg_ia, p->d.kg_w, p->d.kg_ip, p->d.kg_uh, p->d.kg_c, p->d.kg_m, p->d.kg_perm,
+                  p->d.kg_tile};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -491,6 +492,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     ALLOC(kg_ia, int, nk);
     ALLOC(kg_w, float, (size_t)4 * nk);
     ALLOC(kg_ip, float, A);
+    ALLOC(kg_uh, float, (size_t)2 * p->d.n_ell * 2 * M);
     ALLOC(kg_c, char, chunk * T * nb * A * M * 8);
     ALLOC(kg_m, char, chunk * T * nb * A * M * 8);
     ALLOC(kg_perm, int, chunk * p->d.max_ell);
@@ -567,6 +569,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   }
   if (e == hipSuccess) e = hipMemsetAsync(p->d.flags, 0, sizeof(int), s);
   if (e == hipSuccess) e = launch_u_table(p->d, d_ell, s);
+  if (e == hipSuccess && p->d.n_interp > 0) e = launch_kgrowth_tables(p->d, s);
   // the host vectors above die at return: finish the copies before handing the plan out
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(d_ell);
