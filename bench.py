@@ -108,6 +108,22 @@ def profile_pass(B):
     print("profile pass done: 2 steps, then a 268435456-byte copy", flush=True)
 
 
+def profile_kgrowth_pass(B):
+    """Two calls of scale-dependent growth on the benchmark batch (D(k, z) at 200 k nodes); run
+    under rocprofv3."""
+    import torch
+    import synth
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    wl = synth.scale_dependent_growth(synth.make_workload("cfg1_batch", batch=B), 200)
+    plan = Plan.for_workload(wl, n_interp=200)
+    inp = device_inputs(wl, "cuda:0")
+    D = torch.as_tensor(wl["D_kz"], dtype=torch.float64, device="cuda:0")
+    for _ in range(2):
+        plan.cl_kgrowth(inp, D)
+    torch.cuda.synchronize()
+    print("kgrowth profile pass done: 2 calls", flush=True)
+
+
 def time_ms(fn, steps, stream):
     """Average device time of fn() over `steps` calls (HIP events on `stream`), after one warm-up."""
     import torch
@@ -125,8 +141,9 @@ def time_ms(fn, steps, stream):
 
 def extra_configs(steps):
     """The other measured shapes: one point (latency), the ragged batch (256 points of 6, 10 or 15
-    tracers and 50..103 multipoles) and the 30-tracer split-precision batch (64 points, 465
-    spectra x 200 l, N_k = N_chi = 2048; forward only: the adjoint is built for <= 16 tracers)."""
+    tracers and 50..103 multipoles), the 30-tracer split-precision batch (64 points, 465
+    spectra x 200 l, N_k = N_chi = 2048; forward only: the adjoint is built for <= 16 tracers) and
+    scale-dependent growth (the benchmark batch with D(k, z) at 200 k nodes, forward only)."""
     import numpy as np
     import torch
     import synth
@@ -166,6 +183,20 @@ def extra_configs(steps):
     out["split_bf16_30_tracers"] = dict(r, points_per_s_forward=B / (r["forward_ms"] * 1e-3),
                                         workload="64 points x 30 tracers (465 spectra) x 200 l, N_k = N_chi = 2048, "
                                                  "BF16 hi+lo projection")
+    # scale-dependent growth D(k, z) at the paper's default of 200 k nodes (swiftcl_cl_kgrowth)
+    wl = synth.scale_dependent_growth(synth.make_workload("cfg1_batch", batch=256), 200)
+    plan = Plan.for_workload(wl, n_interp=200)
+    inp = device_inputs(wl, "cuda:0")
+    D = torch.as_tensor(wl["D_kz"], **f64)
+    C = torch.empty((256, plan.max_ell, plan.n_pairs), dtype=plan.out_dtype, device="cuda:0")
+    ms = time_ms(lambda: plan.cl_kgrowth(inp, D, C), steps, stream)
+    # the windows GEMM: [103 l] x [N_chi real K] x [N_k] per tracer
+    gemm_flop = 2.0 * 103 * wl["n_chi"] * len(wl["k"]) * 15 * 256
+    out["scale_dependent_growth"] = dict(
+        forward_ms=ms, points_per_s_forward=256 / (ms * 1e-3), windows_gemm_tflop=gemm_flop / 1e12,
+        whole_call_tflops=gemm_flop / (ms * 1e-3) / 1e12, device_flags=plan.device_flags(),
+        workload="256 points x 15 tracers x 103 l, N_k = N_chi = 1024, D(k, z) at 200 k nodes, FP32")
+    del plan, D, C
     return out
 
 
@@ -211,6 +242,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the one-point, ragged and split-precision lines")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run two steps and a 256 MiB copy for rocprofv3 counters; no JSON line")
+    ap.add_argument("--profile-kgrowth", action="store_true",
+                    help="run two scale-dependent-growth calls of the batch for rocprofv3; no JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -220,6 +253,9 @@ def main():
 
     if args.profile_pass:
         profile_pass(args.batch)
+        return
+    if args.profile_kgrowth:
+        profile_kgrowth_pass(args.batch)
         return
 
     import numpy as np
