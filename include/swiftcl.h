@@ -205,6 +205,15 @@ swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t plan, const swiftcl_inpu
 swiftcl_status swiftcl_cl_kgrowth(swiftcl_plan_t plan, const swiftcl_inputs* in, const double* D_kz, void* C,
                                   void* stream);
 
+/* The Limber limit (Sec. 2.6, eq. Limber): j_l(k chi) taken as a delta function at k = (l + 1/2)/chi,
+ *   C_l^{ij} = int dchi / chi^2 g_i g_j P((l + 1/2)/chi),  g = f (clustering), F(l) f / k^2 (lensing),
+ * integrated on the plan's log-chi nodes with the FFTLog path's edge weights (dchi = chi dln chi),
+ * P continued by the natural cubic spline of ln P in ln k and zero outside the k nodes.  Its error
+ * is O(1/l): a cheap path for high multipoles and a check of the windows there.  Same inputs and
+ * output layout as swiftcl_cl, every precision.  Overwrites the plan's forward state.  No allocation
+ * and no synchronisation: safe inside hipGraph capture. */
+swiftcl_status swiftcl_cl_limber(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

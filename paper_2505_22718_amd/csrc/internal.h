@@ -41,6 +41,9 @@ struct plan_dev {
   double* fell;     // [n_ell] F(l) for lensing
   int* ell_band;    // [n_ell]
   double* kw;       // [n_k] (2/pi) w_j k_j^3
+  double* ell_v;    // [n_ell] the multipoles
+  double* lnk;      // [n_k] ln k_j
+  double* lu_k;     // [4][n_k] natural-spline Thomas factors of the ln k grid and 1/h (Limber P)
   double* ebm;      // [2][n_bands][N] e^{-b m Delta}: the FFTLog bias factor of chi node m
   double* z_geom;   // [n_zg]
   double* z_nz;     // [n_zs]
@@ -55,6 +58,7 @@ struct plan_dev {
   double* m_D;      // [B][n_zg]
   double* m_n;      // [B][T][n_zs]
   double* lens_q;   // [B][T][N] lensing efficiency q at the active chi nodes (forward assembly)
+  double* lnp;      // [B][2][n_k] ln P and its spline moments in ln k (Limber)
   double* phase;    // [B][N/2] complex e^{-2 pi i n ln(k_0 chi_0) / (N Delta)}: the FFTLog phase
                     // of coefficient n (forward assembly)
   double* node_f;   // [B][4][N] z, chi, dchi/dz, D at the active chi nodes (forward assembly)
@@ -129,6 +133,7 @@ hipError_t launch_sqrt_s(const plan_dev& p, const swiftcl_inputs* in, hipStream_
 hipError_t launch_contract(const plan_dev& p, const swiftcl_inputs* in, void* C, int b0, int nbp, hipStream_t s);
 hipError_t launch_kgrowth(const plan_dev& p, const swiftcl_inputs* in, const double* D_kz, void* C, hipStream_t s);
 size_t kgrowth_fft_lds(int M, int n_zg);  // dynamic LDS of the node-coefficient kernel
+hipError_t launch_limber(const plan_dev& p, const swiftcl_inputs* in, void* C, hipStream_t s);
 hipError_t launch_kgrowth_tables(const plan_dev& p, hipStream_t s);  // plan time, after the U table
 // ev (optional): two events recorded after the first and second backward kernels
 hipError_t launch_backward(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,

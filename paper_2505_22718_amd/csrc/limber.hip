@@ -1,0 +1,168 @@
+// The Limber limit (paper Sec. 2.6, eq. Limber): j_l(k chi) acts as a delta function at
+// k = (l + 1/2) / chi, so for every multipole
+//   C_l^{ij} = int dchi / chi^2 g_i(chi) g_j(chi) P((l + 1/2) / chi),   g = c(l, k) f,
+// with c = 1 for clustering and F(l) / k^2 = F(l) chi^2 / (l + 1/2)^2 for lensing.  The integral
+// runs on the log-chi nodes of the FFTLog path (dchi = chi dln chi), with the same edge weights:
+//   C_l^{ij} = Delta sum_m w_m g_i(chi_m) g_j(chi_m) P((l + 1/2) / chi_m) / chi_m,
+// P by the natural cubic spline of ln P in ln k (zero outside the k nodes).  The kernels come from
+// the assembly (band 0 samples, untilted), so this is a cheap branch for high multipoles and a
+// check of the FFTLog windows where the Limber error O(1/l) is small.
+#include "common.h"
+#include "geometry.h"
+#include "internal.h"
+
+namespace {
+
+__device__ __forceinline__ int clamp_l(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+constexpr int LB_CH = 128;  // chi nodes per LDS chunk
+
+// ln P and its natural-spline moments in ln k, one wavefront per point.
+__global__ __launch_bounds__(64) void k_limber_pk(plan_dev P, swiftcl_inputs in) {
+  extern __shared__ double sh[];
+  const int b = blockIdx.x, lane = threadIdx.x, nk = P.n_k;
+  double* y = sh;
+  double* Mo = sh + nk;
+  bool bad = false;
+  for (int j = lane; j < nk; j += SWIFTCL_WAVE) {
+    const double v = in.pk[(size_t)b * nk + j];
+    bad |= !(v > 0.0) || !isfinite(v);
+    y[j] = log(fmax(v, 1e-300));
+  }
+  if (bad) atomicOr(P.flags, FLAG_NONFINITE);
+  wave_sync();
+  wave_spline(y, P.lu_k, nk, Mo, lane);
+  for (int j = lane; j < nk; j += SWIFTCL_WAVE) {
+    P.lnp[((size_t)b * 2) * nk + j] = y[j];
+    P.lnp[((size_t)b * 2 + 1) * nk + j] = Mo[j];
+  }
+}
+
+// One block per (point, multipole slot).  Per chunk of chi nodes: the weights
+// s_m = Delta P(nu / chi_m) / (chi_m w_m) and H_t(m) = w_m f_t(chi_m) [chi_m^2 for lensing] in LDS
+// (w_m f_t is the band-0 kernel sample without its tilt), then every thread sums its tracer pairs;
+// the lensing factor (F(l) / nu^2) per lensing tracer of the pair is applied at the end.
+template <typename R>
+__global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R* __restrict__ Cout) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = P.max_tracers, Lm = P.max_ell, N = P.N, nb = P.n_bands, nk = P.n_k;
+  R* H = (R*)smem;             // [T][LB_CH]
+  R* s = H + (size_t)T * LB_CH;  // [LB_CH]
+  int* lens = (int*)(s + LB_CH);  // [T]
+  const int b = blockIdx.x / Lm, li = blockIdx.x % Lm;
+  if (b >= in.batch) return;
+  const int npair = T * (T + 1) / 2;
+  R* c = Cout + ((size_t)b * Lm + li) * npair;
+  const int Tb = clamp_l(in.n_tracers[b], 0, T);
+  const int Lb = clamp_l(in.n_ell[b], 0, Lm);
+  if (li >= Lb) {
+    for (int p = threadIdx.x; p < npair; p += blockDim.x) c[p] = (R)0;
+    return;
+  }
+  int ei = in.ell_idx[(size_t)b * Lm + li];
+  if (ei < 0 || ei >= P.n_ell) {
+    if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+    ei = 0;
+  }
+  for (int t = threadIdx.x; t < T; t += blockDim.x) lens[t] = t < Tb ? (in.kind[(size_t)b * T + t] & 1) : 0;
+  __syncthreads();
+  const double nu = P.ell_v[ei] + 0.5;
+  const double lnu = log(nu);
+  const double* pt = P.pt + (size_t)b * PT_STRIDE;
+  const double chi0 = pt[PT_CHI0], lchi0 = log(chi0), theta = pt[PT_THETA];
+  const int m0 = P.m0, m1 = (int)pt[PT_M1];
+  const double* lnp = P.lnp + (size_t)b * 2 * nk;
+  const double* lnk = P.lnk;
+  const double* lkih = P.lu_k + 3 * (size_t)nk;
+  // this thread's tracer pairs (row-major upper triangle)
+  constexpr int MAXP = (32 * 33 / 2 + 255) / 256;
+  int pi[MAXP], pj[MAXP];
+  R acc[MAXP];
+#pragma unroll
+  for (int q = 0; q < MAXP; ++q) {
+    const int p = threadIdx.x + 256 * q;
+    int i = 0, rem = p;
+    while (i < T && rem >= T - i) { rem -= T - i; ++i; }
+    pi[q] = p < npair ? i : 0;
+    pj[q] = p < npair ? i + rem : 0;
+    acc[q] = (R)0;
+  }
+  for (int mc = m0; mc <= m1; mc += LB_CH) {
+    __syncthreads();  // the previous chunk's readers are done
+    for (int idx = threadIdx.x; idx < LB_CH; idx += blockDim.x) {
+      const int m = mc + idx;
+      double sv = 0.0;
+      if (m <= m1) {
+        const double lchi = lchi0 + (double)m * P.delta;
+        const double w = m == m0 ? 0.5 : (m == m1 ? 0.5 + theta : 1.0);
+        const double x = lnu - lchi;  // ln k of the Limber node
+        if (x >= lnk[0] && x <= lnk[nk - 1]) {
+          const int iv = clamp_l((int)floor((x - lnk[0]) / P.delta), 0, nk - 2);
+          const double lv = spline_at(lnk, lkih, lnp, lnp + nk, iv, x, nullptr);
+          sv = P.delta * exp(lv - lchi) / w;
+        }
+      }
+      s[idx] = (R)sv;
+    }
+    for (int e = threadIdx.x; e < T * LB_CH; e += blockDim.x) {
+      const int t = e / LB_CH, idx = e % LB_CH;
+      const int m = mc + idx;
+      double h = 0.0;
+      if (t < Tb && m <= m1) {
+        const int kind = in.kind[(size_t)b * T + t] & 1;
+        const double gv = (double)((const R*)P.g)[(((size_t)b * T + t) * nb) * N + m];
+        h = gv / P.ebm[((size_t)kind * nb) * N + m];
+        if (kind) {
+          const double chi = exp(lchi0 + (double)m * P.delta);
+          h *= chi * chi;
+        }
+      }
+      H[(size_t)t * LB_CH + idx] = (R)h;
+    }
+    __syncthreads();
+    const int cnt = m1 - mc + 1 < LB_CH ? m1 - mc + 1 : LB_CH;
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+      if (threadIdx.x + 256 * q >= npair) continue;
+      const R* hi = H + (size_t)pi[q] * LB_CH;
+      const R* hj = H + (size_t)pj[q] * LB_CH;
+      R a = acc[q];
+      for (int idx = 0; idx < cnt; ++idx) a += hi[idx] * hj[idx] * s[idx];
+      acc[q] = a;
+    }
+  }
+  const double al = P.fell[ei] / (nu * nu);
+#pragma unroll
+  for (int q = 0; q < MAXP; ++q) {
+    const int p = threadIdx.x + 256 * q;
+    if (p >= npair) continue;
+    const int i = pi[q], j = pj[q];
+    R v = (R)0;
+    if (i < Tb && j < Tb) {
+      double f = (double)acc[q];
+      if (lens[i]) f *= al;
+      if (lens[j]) f *= al;
+      v = (R)f;
+    }
+    c[p] = v;
+  }
+}
+
+}  // namespace
+
+size_t limber_lds_bytes(const plan_dev& p) {
+  const size_t rs = p.precision == SWIFTCL_FP64 ? 8 : 4;
+  return rs * ((size_t)p.max_tracers * LB_CH + LB_CH) + sizeof(int) * (size_t)p.max_tracers;
+}
+
+hipError_t launch_limber(const plan_dev& p, const swiftcl_inputs* in, void* C, hipStream_t s) {
+  hipLaunchKernelGGL(k_limber_pk, dim3(in->batch), dim3(64), sizeof(double) * 2 * (size_t)p.n_k, s, p, *in);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)((size_t)in->batch * p.max_ell));
+  if (p.precision == SWIFTCL_FP64)
+    hipLaunchKernelGGL(k_limber<double>, grid, dim3(256), limber_lds_bytes(p), s, p, *in, (double*)C);
+  else
+    hipLaunchKernelGGL(k_limber<float>, grid, dim3(256), limber_lds_bytes(p), s, p, *in, (float*)C);
+  return hipGetLastError();
+}

@@ -259,7 +259,8 @@ template <typename T> static swiftcl_status dalloc(T** ptr, size_t count, const 
 
 static void free_plan(swiftcl_plan_s* p) {
   if (!p) return;
-  void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
+  void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.ell_v, p->d.lnk, p->d.lu_k,
+                  p->d.lnp, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
                   p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf,
                   p->d.kg_ones, p->d.kg_ia, p->d.kg_w, p->d.kg_ip, p->d.kg_uh, p->d.kg_c, p->d.kg_m, p->d.kg_perm,
@@ -400,9 +401,11 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
       Ls *= r;
     }
   }
-  std::vector<double> lug, lun;
+  std::vector<double> lug, lun, luk, lnk(nk);
   spline_lu(d->z_geom, d->n_zg, lug);
   spline_lu(d->z_nz, d->n_zs, lun);
+  for (int j = 0; j < nk; ++j) lnk[j] = std::log(d->k[j]);
+  spline_lu(lnk.data(), nk, luk);
   // knots of the lensing quadrature: union of both grids inside the geometry range
   std::set<double> us(d->z_geom, d->z_geom + d->n_zg);
   for (int i = 0; i < d->n_zs; ++i) us.insert(d->z_nz[i]);
@@ -436,6 +439,10 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(fell, double, p->d.n_ell);
   ALLOC(ell_band, int, p->d.n_ell);
   ALLOC(kw, double, nk);
+  ALLOC(ell_v, double, p->d.n_ell);
+  ALLOC(lnk, double, nk);
+  ALLOC(lu_k, double, luk.size());
+  ALLOC(lnp, double, (size_t)B * 2 * nk);
   ALLOC(ebm, double, (size_t)2 * nb * N);
   ALLOC(z_geom, double, p->d.n_zg);
   ALLOC(z_nz, double, p->d.n_zs);
@@ -544,6 +551,9 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
       {p->d.fell, fell.data(), fell.size() * sizeof(double)},
       {p->d.ell_band, band.data(), band.size() * sizeof(int)},
       {p->d.kw, kw.data(), kw.size() * sizeof(double)},
+      {p->d.ell_v, d->ell, (size_t)p->d.n_ell * sizeof(double)},
+      {p->d.lnk, lnk.data(), lnk.size() * sizeof(double)},
+      {p->d.lu_k, luk.data(), luk.size() * sizeof(double)},
       {p->d.ebm, ebm.data(), ebm.size() * sizeof(double)},
       {p->d.z_geom, d->z_geom, (size_t)p->d.n_zg * sizeof(double)},
       {p->d.z_nz, d->z_nz, (size_t)p->d.n_zs * sizeof(double)},
@@ -698,6 +708,19 @@ extern "C" swiftcl_status swiftcl_cl_kgrowth(swiftcl_plan_t p, const swiftcl_inp
   if (e == hipSuccess) e = launch_sqrt_s(p->d, &in1, s);
   if (e == hipSuccess) e = launch_kgrowth(p->d, &in1, D_kz, C, s);
   return hip_check(e, "scale-dependent growth launch");
+}
+
+extern "C" swiftcl_status swiftcl_cl_limber(swiftcl_plan_t p, const swiftcl_inputs* in, void* C, void* stream) {
+  swiftcl_status st = check_inputs(p, in);
+  if (st != SWIFTCL_OK) return st;
+  if (!C) { set_error("C is NULL"); return SWIFTCL_E_INVALID; }
+  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  p->fwd_valid = false;  // the FFTLog coefficients are not computed
+  hipError_t e = launch_assemble(p->d, in, s);
+  if (e == hipSuccess) e = launch_limber(p->d, in, C, s);
+  return hip_check(e, "Limber launch");
 }
 
 // Checks shared by the two backward entry points; `reuse` is set when the forward state is kept.

@@ -138,6 +138,15 @@ class Plan:
         bd.swiftcl_cl_kgrowth(self.handle, self.inputs_struct(t), D_kz.data_ptr(), out.data_ptr(), self._stream())
         return out
 
+    def cl_limber(self, t, out=None):
+        """C_l in the Limber limit on the plan's chi nodes (same layout as cl)."""
+        B = t["n_tracers"].shape[0]
+        if out is None:
+            out = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
+        self._new_state()
+        bd.swiftcl_cl_limber(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
+        return out
+
     def cl_timed(self, t, out):
         """Forward C_l with per-stage device times (ms): assembly, FFTLog coefficients, windows + C."""
         self._new_state()

@@ -107,4 +107,5 @@ def test_null_arguments_rejected(lib):
     assert lib.swiftcl_cl_backward(None, ctypes.byref(inp), None, None, None, None, None,
                                    bd.SWIFTCL_BWD_REUSE_FORWARD, None) == bd.SWIFTCL_E_INVALID
     assert lib.swiftcl_cl_kgrowth(None, ctypes.byref(inp), None, None, None) == bd.SWIFTCL_E_INVALID
+    assert lib.swiftcl_cl_limber(None, ctypes.byref(inp), None, None) == bd.SWIFTCL_E_INVALID
     assert lib.swiftcl_plan_destroy(None) == bd.SWIFTCL_E_INVALID
