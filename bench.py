@@ -143,7 +143,8 @@ def extra_configs(steps):
     """The other measured shapes: one point (latency), the ragged batch (256 points of 6, 10 or 15
     tracers and 50..103 multipoles), the 30-tracer split-precision batch (64 points, 465
     spectra x 200 l, N_k = N_chi = 2048; forward only: the adjoint is built for <= 16 tracers) and
-    scale-dependent growth (the benchmark batch with D(k, z) at 200 k nodes, forward only)."""
+    scale-dependent growth (the benchmark batch with D(k, z) at 200 k nodes, forward only) and the
+    Limber limit of the benchmark batch."""
     import numpy as np
     import torch
     import synth
@@ -197,6 +198,14 @@ def extra_configs(steps):
         whole_call_tflops=gemm_flop / (ms * 1e-3) / 1e12, device_flags=plan.device_flags(),
         workload="256 points x 15 tracers x 103 l, N_k = N_chi = 1024, D(k, z) at 200 k nodes, FP32")
     del plan, D, C
+    # the Limber limit of the benchmark batch on the same chi nodes (swiftcl_cl_limber)
+    wl = synth.make_workload("cfg1_batch", batch=256)
+    plan = Plan.for_workload(wl)
+    inp = device_inputs(wl, "cuda:0")
+    C = torch.empty((256, plan.max_ell, plan.n_pairs), dtype=plan.out_dtype, device="cuda:0")
+    ms = time_ms(lambda: plan.cl_limber(inp, C), steps, stream)
+    out["limber"] = dict(forward_ms=ms, points_per_s_forward=256 / (ms * 1e-3),
+                         workload="256 points x 15 tracers x 103 l, Limber on the N_chi = 1024 nodes, FP32")
     return out
 
 
