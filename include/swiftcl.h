@@ -98,6 +98,10 @@ typedef struct {
   const double* nz;          /* [B][max_tracers][n_zs] n(z) samples per unit z                  */
   const double* bias;        /* [B][max_tracers] linear bias b_1 (clustering only)              */
   const double* pk;          /* [B][n_k] P(k, z_fid) on the plan's k nodes, (Mpc/h)^3, > 0      */
+  const double* ia;          /* [B][n_zg] NLA amplitude A_IA(z_geom) of the lensing tracers, or NULL
+                                (no intrinsic alignment; Sec. 2.3: their kernel becomes
+                                (q + A_IA n dz/dchi) D / chi^2); the backward calls carry it into
+                                dL/dn and dL/dD but do not differentiate A_IA itself                 */
 } swiftcl_inputs;
 
 /* Build a plan: validates the descriptor, builds the log-chi grid, the FP64 table of Bessel

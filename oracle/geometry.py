@@ -29,11 +29,13 @@ _GL = np.polynomial.legendre.leggauss(12)
 class PointGeometry:
     """Continuous geometry, growth and redshift distributions of one parameter point."""
 
-    def __init__(self, z_geom, chi_z, D_z, omega_m, z_nz, nz, kinds, bias):
+    def __init__(self, z_geom, chi_z, D_z, omega_m, z_nz, nz, kinds, bias, ia=None):
         self.z_geom = np.asarray(z_geom, float)
         self.z_nz = np.asarray(z_nz, float)
         self.chi_spl = CubicSpline(self.z_geom, chi_z, bc_type="natural")
         self.D_spl = CubicSpline(self.z_geom, D_z, bc_type="natural")
+        # NLA amplitude A_IA(z) of the lensing tracers (Sec. 2.3), None = no intrinsic alignment
+        self.ia_spl = None if ia is None else CubicSpline(self.z_geom, ia, bc_type="natural")
         self.nz = np.asarray(nz, float)
         self.n_spl = [CubicSpline(self.z_nz, n_t, bc_type="natural") for n_t in self.nz]
         self.omega_m = float(omega_m)
@@ -100,16 +102,26 @@ class PointGeometry:
         I0, I1 = self.lensing_integrals(t, z)
         return 1.5 * self.omega_m * H0_OVER_C ** 2 * chi * (1.0 + z) * (I0 - chi * I1)
 
+    def ia_of_z(self, z):
+        """A_IA(z), 0 without intrinsic alignment."""
+        z = np.atleast_1d(np.asarray(z, float))
+        return np.zeros_like(z) if self.ia_spl is None else self.ia_spl(z)
+
     # --- radial kernels ------------------------------------------------------------------
     def f_of_z(self, t, z):
-        """Radial kernel per unit chi, f_t, evaluated at redshift z (inside the support)."""
+        """Radial kernel per unit chi, f_t, evaluated at redshift z (inside the support).
+
+        Lensing tracers carry the NLA term of Sec. 2.3: the window of intrinsic alignment has the
+        lensing prefactor and 1/chi^2 with n(chi) A_IA(z) in place of the lens efficiency, so
+        f = (q + A_IA n dz/dchi) D / chi^2.
+        """
         z = np.atleast_1d(np.asarray(z, float))
         D = self.D_spl(z)
+        dzdchi = 1.0 / self.chi_spl(z, 1)
         if self.kinds[t] == 0:
-            dzdchi = 1.0 / self.chi_spl(z, 1)
             return self.bias[t] * self.n_of_z(t, z) * dzdchi * D
         chi = self.chi_spl(z)
-        return self.lensing_q(t, z) * D / chi ** 2
+        return (self.lensing_q(t, z) + self.ia_of_z(z) * self.n_of_z(t, z) * dzdchi) * D / chi ** 2
 
     def f_of_chi(self, t, chi):
         """f_t(chi), zero outside [chi(z_min), chi(z_max)]."""
@@ -125,8 +137,10 @@ class PointGeometry:
 def point_geometry(wl, b):
     """PointGeometry of parameter point b of a synthetic workload dict."""
     T = int(wl["n_tracers"][b])
+    ia = wl.get("ia")
     return PointGeometry(wl["z_geom"], wl["chi_z"][b], wl["D_z"][b], wl["omega_m"][b], wl["z_nz"],
-                         wl["nz"][b, :T], wl["kind"][b, :T], wl["bias"][b, :T])
+                         wl["nz"][b, :T], wl["kind"][b, :T], wl["bias"][b, :T],
+                         ia=None if ia is None else ia[b])
 
 
 def ell_prefactor(kind, ell, k):

@@ -52,15 +52,17 @@ def _dL(G, W, dW, pk, method):
 
 
 def directional_nz(wl, b, G, t, v, method=None):
-    """d/deps L(n_t + eps v) for tracer t of point b; v sampled on z_nz."""
+    """d/deps L(n_t + eps v) for tracer t of point b; v sampled on z_nz.  The windows are linear in
+    n (through the lens efficiency and the intrinsic-alignment term alike), so dW is the window of v."""
     method = method or fftlog.method_for(wl)
     geo = point_geometry(wl, b)
     ells = fftlog.point_ells(wl, b)
     W = fftlog.windows_point(geo, ells, method)
     nz_v = np.zeros_like(geo.nz)
     nz_v[t] = v
+    ia = wl.get("ia")
     gv = PointGeometry(geo.z_geom, wl["chi_z"][b], wl["D_z"][b], geo.omega_m, geo.z_nz, nz_v,
-                       geo.kinds, geo.bias)
+                       geo.kinds, geo.bias, ia=None if ia is None else ia[b])
     dW = fftlog.windows_point(gv, ells, method)
     mask = np.zeros(len(geo.kinds), bool)
     mask[t] = True
@@ -75,7 +77,8 @@ def directional_D(wl, b, G, v, method=None):
     ells = fftlog.point_ells(wl, b)
     W = fftlog.windows_point(geo, ells, method)
     T = len(geo.kinds)
+    ia = wl.get("ia")
     gv = PointGeometry(geo.z_geom, wl["chi_z"][b], v, geo.omega_m, geo.z_nz, wl["nz"][b, :T],
-                       geo.kinds, geo.bias)
+                       geo.kinds, geo.bias, ia=None if ia is None else ia[b])
     dW = fftlog.windows_point(gv, ells, method)
     return _dL(G, W, dW, wl["pk"][b], method)

@@ -45,8 +45,9 @@ def ln_nodes(method: fftlog.Method, n_interp):
 def node_geometries(wl, b):
     """One PointGeometry per node: the point's geometry with D(z) replaced by D(kappa_a, z)."""
     T = int(wl["n_tracers"][b])
+    ia = wl.get("ia")
     geos = [PointGeometry(wl["z_geom"], wl["chi_z"][b], wl["D_kz"][b, a], wl["omega_m"][b], wl["z_nz"],
-                          wl["nz"][b, :T], wl["kind"][b, :T], wl["bias"][b, :T])
+                          wl["nz"][b, :T], wl["kind"][b, :T], wl["bias"][b, :T], ia=None if ia is None else ia[b])
             for a in range(wl["D_kz"].shape[1])]
     # every node has the point's chi(z): solve z(chi) once and share the roots
     solve = geos[0].z_of_chi

@@ -48,7 +48,7 @@ def cl_limber(geo: PointGeometry, ells, k, pk, n_panels=4000):
         if geo.kinds[t] == 0:
             f[t] = geo.bias[t] * geo.n_of_z(t, z) * D / dchi
         else:
-            f[t] = lens(t, z) * D / chi ** 2
+            f[t] = (lens(t, z) + geo.ia_of_z(z) * geo.n_of_z(t, z) / dchi) * D / chi ** 2
     out = np.zeros((len(ells), T, T))
     for li, ell in enumerate(ells):
         nu = ell + 0.5

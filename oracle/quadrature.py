@@ -77,7 +77,7 @@ def windows_quadrature(geo: PointGeometry, ells, k, lens_table=None):
             if geo.kinds[t] == 0:
                 h[t] = geo.bias[t] * geo.n_of_z(t, z) * D
             else:
-                h[t] = lens_table(t, z) * D * geo.chi_spl(z, 1) / chi ** 2
+                h[t] = (lens_table(t, z) * geo.chi_spl(z, 1) + geo.ia_of_z(z) * geo.n_of_z(t, z)) * D / chi ** 2
         hw = h * wz[None, :]
         for li, ell in enumerate(ells):
             jl = spherical_jn_real(ell, kk * chi)

@@ -70,6 +70,7 @@ class swiftcl_inputs(ctypes.Structure):
         ("nz", ctypes.c_void_p),
         ("bias", ctypes.c_void_p),
         ("pk", ctypes.c_void_p),
+        ("ia", ctypes.c_void_p),
     ]
 
 

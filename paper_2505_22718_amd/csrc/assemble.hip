@@ -25,7 +25,7 @@
 
 size_t geometry_lds_bytes(const plan_dev& p) {
   const size_t tg = p.max_tracers < GEOM_GROUP ? p.max_tracers : GEOM_GROUP;
-  return sizeof(double) * ((size_t)6 * p.n_zg + (size_t)3 * p.n_zs + (size_t)2 * tg * p.n_zs);
+  return sizeof(double) * ((size_t)7 * p.n_zg + (size_t)3 * p.n_zs + (size_t)2 * tg * p.n_zs);
 }
 
 template <typename R>
@@ -54,6 +54,7 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
   double* nzr = zsih + 2 * (size_t)nzs; // [TG][nzs] n(z) rows of the current tracer group (one spare row of
                                         // nzs before it keeps the layout simple)
   double* mn = nzr + (size_t)TG * nzs;  // [TG][nzs]
+  double* mia = mn + (size_t)TG * nzs;  // [nzg] spline moments of A_IA(z), if given
 
   const double* chig = in.chi_z + (size_t)b * nzg;
   const double* Dg = in.D_z + (size_t)b * nzg;
@@ -69,14 +70,22 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
   }
   __syncthreads();
 
-  // splines of chi(z) and D(z), one wavefront each
+  // splines of chi(z), D(z) and A_IA(z), one wavefront each
+  const double* iag = in.ia ? in.ia + (size_t)b * nzg : nullptr;
   if (wave == 0) wave_spline(chi, P.lu_geom, nzg, mchi, lane);
   else if (wave == 1) wave_spline(Dz, P.lu_geom, nzg, mD, lane);
+  else if (wave == 2 && iag) {
+    bool bad = false;
+    for (int i = lane; i < nzg; i += SWIFTCL_WAVE) bad |= !isfinite(iag[i]);
+    if (bad) atomicOr(P.flags, FLAG_NONFINITE);
+    wave_spline(iag, P.lu_geom, nzg, mia, lane);
+  }
   __syncthreads();
-  // keep the spline coefficients for the adjoint
+  // keep the spline coefficients for the lensing kernels and the adjoint
   for (int i = tid; i < nzg; i += nth) {
     P.m_chi[(size_t)b * nzg + i] = mchi[i];
     P.m_D[(size_t)b * nzg + i] = mD[i];
+    if (iag) P.m_ia[(size_t)b * nzg + i] = mia[i];
   }
 
   // per-point scalars
@@ -252,7 +261,15 @@ __global__ __launch_bounds__(512) void k_geom_lens(plan_dev P, swiftcl_inputs in
     const double I1 = p1 + (u + 1 < nu ? seg1[u + 1] : 0.0);
     const double q = pref * x * (1.0 + z) * (I0 - x * I1);
     P.lens_q[((size_t)b * T + t) * N + m] = q;  // for the adjoint
-    const double fv = q * D / (x * x);
+    double fq = q;
+    if (in.ia) {
+      // intrinsic alignment (NLA): n(chi) A_IA(z) joins the lens efficiency
+      const int ig = ni[0], inz = ni[N];
+      const double a = spline_at(zg, zgih, in.ia + (size_t)b * nzg, P.m_ia + (size_t)b * nzg, ig, z, nullptr);
+      const double n = inz < 0 ? 0.0 : spline_at(zs, zsih, nt, mt, inz, z, nullptr);
+      fq += a * n / nf[2 * N];
+    }
+    const double fv = fq * D / (x * x);
     for (int bi = 0; bi < nb; ++bi)
       g[(((size_t)b * T + t) * nb + bi) * N + m] = (R)(w * fv * P.ebm[((size_t)nb + bi) * N + m]);
   }
@@ -269,13 +286,4 @@ hipError_t launch_assemble(const plan_dev& p, const swiftcl_inputs* in, hipStrea
     hipLaunchKernelGGL(k_geom_lens<float>, gl, dim3(512), ll, s, p, *in);
   }
   return hipGetLastError();
-}
-
-hipError_t prepare_assemble(const plan_dev& p) {
-  hipError_t e = p.precision == SWIFTCL_FP64 ? lds_attr_once((const void*)k_geometry<double>)
-                                             : lds_attr_once((const void*)k_geometry<float>);
-  if (e == hipSuccess)
-    e = p.precision == SWIFTCL_FP64 ? lds_attr_once((const void*)k_geom_lens<double>)
-                                    : lds_attr_once((const void*)k_geom_lens<float>);
-  return e;
 }

@@ -483,7 +483,15 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
       const double df = df_at(m, s.w);
       const double x = s.chiz;
       const double q = P.lens_q[((size_t)b * T + t) * N + m];  // the forward's q at this node
-      spline_value_adjoint(zg, zgih, s.ig, s.z, df * q / (x * x), dDy, dDM);
+      double fq = q;
+      if (in.ia) {
+        // intrinsic alignment: f = (q + A_IA n dz/dchi) D / chi^2 is also local in n
+        const double a = spline_at(zg, zgih, in.ia + (size_t)b * nzg, P.m_ia + (size_t)b * nzg, s.ig, s.z, nullptr);
+        const double n = s.inz < 0 ? 0.0 : spline_at(zs, zsih, nt, mt, s.inz, s.z, nullptr);
+        fq += a * n / s.dchi;
+        if (s.inz >= 0) spline_value_adjoint(zs, zsih, s.inz, s.z, df * a * s.D / (s.dchi * x * x), dny, dnM);
+      }
+      spline_value_adjoint(zg, zgih, s.ig, s.z, df * fq / (x * x), dDy, dDM);
       const double dq = df * s.D / (x * x);
       dI0[k] = dq * pref * x * (1.0 + s.z);
       dI1[k] = -dq * pref * x * x * (1.0 + s.z);
@@ -646,22 +654,3 @@ hipError_t launch_backward(const plan_dev& p, const swiftcl_inputs* in, const vo
   return hipErrorInvalidValue;
 }
 
-template <typename R, int M>
-static hipError_t prepare_bwd_t() {
-  constexpr bool dp = sizeof(R) == 8;
-  hipError_t e = lds_attr_once((const void*)k_bwd_windows<R, M, dp ? 2 : 16, !dp>);
-  if (e == hipSuccess) e = lds_attr_once((const void*)k_bwd_tracer<R>);
-  if (e == hipSuccess) e = lds_attr_once((const void*)k_bwd_point<R>);
-  return e;
-}
-
-hipError_t prepare_backward(const plan_dev& p) {
-  const bool dp = p.precision == SWIFTCL_FP64;
-  switch (p.M) {
-    case 128: return dp ? prepare_bwd_t<double, 128>() : prepare_bwd_t<float, 128>();
-    case 256: return dp ? prepare_bwd_t<double, 256>() : prepare_bwd_t<float, 256>();
-    case 512: return dp ? prepare_bwd_t<double, 512>() : prepare_bwd_t<float, 512>();
-    case 1024: return dp ? prepare_bwd_t<double, 1024>() : prepare_bwd_t<float, 1024>();
-  }
-  return hipErrorInvalidValue;
-}

@@ -659,34 +659,3 @@ hipError_t launch_windows_cl(const plan_dev& p, const swiftcl_inputs* in, void* 
   return hipErrorInvalidValue;
 }
 
-template <typename R, int M>
-static hipError_t prepare_fwd_t() {
-  constexpr int NW = wcl_shape<R, M>::NW;
-  constexpr bool TW = wcl_shape<R, M>::TW;
-  const void* ks[] = {
-      (const void*)k_windows_cl<R, M, NW, TW, true, false, false, false>,
-      (const void*)k_windows_cl<R, M, NW, TW, false, true, false, false>,
-      (const void*)k_windows_cl<R, M, NW, TW, false, true, true, false>,
-  };
-  hipError_t e = hipSuccess;
-  for (const void* k : ks)
-    if (e == hipSuccess) e = lds_attr_once(k);
-  if constexpr (sizeof(R) == 4) {
-    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, false, true, false, true>);
-    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_cl<R, M, NW, TW, false, true, true, true>);
-    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_v<M, 16, unfused_tw(M), true>);
-    if (e == hipSuccess) e = lds_attr_once((const void*)k_windows_v<M, 16, unfused_tw(M), false>);
-  }
-  return e;
-}
-
-hipError_t prepare_forward(const plan_dev& p) {
-  const bool dp = p.precision == SWIFTCL_FP64;
-  switch (p.M) {
-    case 128: return dp ? prepare_fwd_t<double, 128>() : prepare_fwd_t<float, 128>();
-    case 256: return dp ? prepare_fwd_t<double, 256>() : prepare_fwd_t<float, 256>();
-    case 512: return dp ? prepare_fwd_t<double, 512>() : prepare_fwd_t<float, 512>();
-    case 1024: return dp ? prepare_fwd_t<double, 1024>() : prepare_fwd_t<float, 1024>();
-  }
-  return hipErrorInvalidValue;
-}

@@ -56,6 +56,7 @@ struct plan_dev {
   double* pt;       // [B][PT_STRIDE]
   double* m_chi;    // [B][n_zg] spline second derivatives
   double* m_D;      // [B][n_zg]
+  double* m_ia;     // [B][n_zg] spline moments of A_IA(z) (intrinsic alignment inputs only)
   double* m_n;      // [B][T][n_zs]
   double* lens_q;   // [B][T][N] lensing efficiency q at the active chi nodes (forward assembly)
   double* lnp;      // [B][2][n_k] ln P and its spline moments in ln k (Limber)
@@ -109,10 +110,6 @@ struct swiftcl_plan_s {
 };
 
 void set_error(const std::string& msg);
-hipError_t lds_attr_once(const void* kern);
-hipError_t prepare_forward(const plan_dev& p);
-hipError_t prepare_assemble(const plan_dev& p);
-hipError_t prepare_backward(const plan_dev& p);
 size_t bwd_windows_lds(const plan_dev& p);  // dynamic LDS of the adjoint windows kernel
 size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k);
 bool unfused_tw_lds(int M);

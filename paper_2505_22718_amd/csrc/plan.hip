@@ -13,7 +13,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
-#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -33,22 +32,6 @@ swiftcl_status hip_check(hipError_t e, const char* what) {
 }
 
 extern "C" const char* swiftcl_last_error(void) { return g_last_error.c_str(); }
-
-// Raise a kernel's dynamic-LDS limit to the device maximum, once per kernel and process.  The
-// plan calls it for every kernel it will launch, so the launches themselves make no attribute
-// calls (they can run under hipGraph capture).
-hipError_t lds_attr_once(const void* kern) {
-  static std::mutex mu;
-  static std::set<const void*> done;
-  std::lock_guard<std::mutex> lock(mu);
-  if (done.count(kern)) return hipSuccess;
-  int dev = 0, lds = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  if (e == hipSuccess) e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess) done.insert(kern);
-  return e;
-}
 
 // ---------------------------------------------------------------------------------------------
 // Complex log-gamma in FP64 (Stirling's series with Bernoulli-number coefficients after an
@@ -261,7 +244,7 @@ static void free_plan(swiftcl_plan_s* p) {
   if (!p) return;
   void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.ell_v, p->d.lnk, p->d.lu_k,
                   p->d.lnp, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
-                  p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
+                  p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_ia, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
                   p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf,
                   p->d.kg_ones, p->d.kg_ia, p->d.kg_w, p->d.kg_ip, p->d.kg_uh, p->d.kg_c, p->d.kg_m, p->d.kg_perm,
                   p->d.kg_tile};
@@ -453,6 +436,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(pt, double, (size_t)B * PT_STRIDE);
   ALLOC(m_chi, double, (size_t)B * p->d.n_zg);
   ALLOC(m_D, double, (size_t)B * p->d.n_zg);
+  ALLOC(m_ia, double, (size_t)B * p->d.n_zg);
   ALLOC(m_n, double, (size_t)B * T * p->d.n_zs);
   ALLOC(lens_q, double, (size_t)B * T * N);
   ALLOC(phase, double, (size_t)B * N);
@@ -631,7 +615,7 @@ static void note_forward(swiftcl_plan_t p, const swiftcl_inputs* in) {
 static bool same_inputs(const swiftcl_inputs& a, const swiftcl_inputs& b) {
   return a.batch == b.batch && a.n_tracers == b.n_tracers && a.kind == b.kind && a.n_ell == b.n_ell &&
          a.ell_idx == b.ell_idx && a.chi_z == b.chi_z && a.D_z == b.D_z && a.omega_m == b.omega_m && a.nz == b.nz &&
-         a.bias == b.bias && a.pk == b.pk;
+         a.bias == b.bias && a.pk == b.pk && a.ia == b.ia;
 }
 
 static swiftcl_status run_forward(swiftcl_plan_t p, const swiftcl_inputs* in, void* W, void* C, void* stream) {

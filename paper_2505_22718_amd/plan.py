@@ -113,6 +113,8 @@ class Plan:
         s.batch = int(t["n_tracers"].shape[0])
         for name in ("n_tracers", "kind", "n_ell", "ell_idx", "chi_z", "D_z", "omega_m", "nz", "bias", "pk"):
             setattr(s, name, t[name].data_ptr())
+        ia = t.get("ia")  # NLA amplitude A_IA(z) of the lensing tracers, optional
+        s.ia = ia.data_ptr() if ia is not None else None
         return s
 
     # Every call that (re)computes the workspace's forward state sets a fresh token; autograd keeps
@@ -228,7 +230,7 @@ def device_inputs(wl, device="cuda:0", points=None):
     def f(x, dt):
         return torch.as_tensor(np.ascontiguousarray(np.asarray(x)[sel]), dtype=dt).to(dev)
 
-    return {
+    out = {
         "n_tracers": f(wl["n_tracers"], torch.int32),
         "kind": f(wl["kind"], torch.int32),
         "n_ell": f(wl["n_ell"], torch.int32),
@@ -240,3 +242,6 @@ def device_inputs(wl, device="cuda:0", points=None):
         "bias": f(wl["bias"], torch.float64),
         "pk": f(wl["pk"], torch.float64),
     }
+    if wl.get("ia") is not None:
+        out["ia"] = f(wl["ia"], torch.float64)
+    return out

@@ -17,7 +17,8 @@ only; its benchmark files are not used):
   cfg3  256 points, per-point cosmology, ragged tracer / multipole counts
   cfg4  20 clustering + 10 lensing bins, 2048 k, N_chi 2048, 200 l in [2, 3000]
 
-scale_dependent_growth() adds growth samples D(k, z) at interpolation nodes in k to any of them.
+scale_dependent_growth() adds growth samples D(k, z) at interpolation nodes in k to any of them,
+intrinsic_alignment() an NLA amplitude A_IA(z) for the lensing tracers.
 """
 from __future__ import annotations
 
@@ -103,6 +104,15 @@ def scale_dependent_growth(wl, n_interp, f_nu=0.05, k_fs=0.1):
     wl["n_interp"] = int(n_interp)
     wl["k_nodes"] = kn
     wl["D_kz"] = np.ascontiguousarray(D[:, None, :] ** (1.0 - supp[None, :, None]))
+    return wl
+
+
+def intrinsic_alignment(wl, a1=0.5):
+    """Add the NLA amplitude of the lensing tracers, A_IA(z) = -a1 C1 rho_crit Omega_m / D(z) with
+    C1 rho_crit = 0.0134 (the usual normalisation of the non-linear alignment model), sampled on the
+    geometry z grid: wl["ia"] [B, nzg].  Returns wl."""
+    om = np.asarray(wl["omega_m"], float)
+    wl["ia"] = np.ascontiguousarray(-a1 * 0.0134 * om[:, None] / np.asarray(wl["D_z"], float))
     return wl
 
 

@@ -96,6 +96,16 @@ def test_backward_cfg2_fp32(dev):
     _check(wl, G, out, 1e-4)
 
 
+def test_backward_intrinsic_alignment(dev):
+    """NLA intrinsic alignment in the lensing kernels: the adjoint's dL/dn of a lensing tracer
+    picks up the local n term, dL/dD the IA share of the kernel (directions checked for one
+    clustering and one lensing tracer)."""
+    wl = synth.intrinsic_alignment(synth.make_workload("cfg2"))
+    _say("backward cfg2 fp64 with intrinsic alignment")
+    G, out = _run(wl, dev, "fp64")
+    _check(wl, G, out, 1e-9, ndir=2)
+
+
 def test_backward_cfg2_fp64(dev):
     wl = synth.make_workload("cfg2")
     _say("backward cfg2 fp64")

@@ -119,3 +119,42 @@ def test_graph_capture_replay(dev, fwd_mode, reuse):
         torch.cuda.synchronize()
         assert torch.equal(other, C_ref)
     _say(f"  fwd_mode={fwd_mode} reuse={reuse}: 3 replays match")
+
+
+def test_graph_capture_kgrowth_and_limber(dev):
+    """swiftcl_cl_kgrowth (chunked launches) and swiftcl_cl_limber captured in one hipGraph: every
+    replay, with eager work between them, reproduces the eager C_l bit for bit."""
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    B = 16
+    wl = synth.scale_dependent_growth(synth.make_workload("cfg3", batch=B), 10)
+    plan = Plan.for_workload(wl, n_interp=10)
+    t = device_inputs(wl, dev)
+    D = torch.as_tensor(wl["D_kz"], dtype=torch.float64, device=dev)
+    Ck_ref = plan.cl_kgrowth(t, D).clone()
+    Cl_ref = plan.cl_limber(t).clone()
+    torch.cuda.synchronize()
+    Ck, Cl = torch.zeros_like(Ck_ref), torch.zeros_like(Cl_ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            plan.cl_kgrowth(t, D, Ck)
+            plan.cl_limber(t, Cl)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    gc.collect()  # no plan of an earlier test may be released (freed) during the capture
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.cl_kgrowth(t, D, Ck)
+        plan.cl_limber(t, Cl)
+    for r in range(3):
+        Ck.zero_()
+        Cl.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Ck, Ck_ref), f"kgrowth replay {r}"
+        assert torch.equal(Cl, Cl_ref), f"limber replay {r}"
+        other = plan.cl_kgrowth(t, D)
+        torch.cuda.synchronize()
+        assert torch.equal(other, Ck_ref)
+    _say("  kgrowth + limber: 3 replays match")
