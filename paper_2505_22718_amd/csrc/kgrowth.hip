@@ -207,13 +207,13 @@ __global__ void k_kg_utab(plan_dev P) {
 }
 
 // W tile [<= 64 slots of one band] x [64 k nodes] of one (point, tracer) by 4 wavefronts.  Wave w
-// owns k nodes 16w..16w+15 and runs the whole K loop on its own: its U fragments come from the
-// operand-ordered table (two 16-byte loads per row tile and chunk), and it builds its 16 columns of
-// X, 16 coefficients at a time, in a private LDS strip laid out so that each lane then reads its 8
-// B values as two 16-byte loads.  No block barrier in the loop.  Blocks of one (point, tracer) share
-// an XCD, so its node coefficients are read into one L2.
+// owns k nodes 16w..16w+15.  Per chunk of 16 coefficients the block copies the slots' rows of the
+// operand-ordered U table into a double-buffered LDS tile (the next chunk's rows are loaded during
+// this chunk's MFMAs; one block barrier per chunk), and each wave builds its own 16 columns of X in a
+// private LDS strip laid out so that each lane then reads its 8 B values (and, per row tile, its 8
+// A values) as two 16-byte loads.  Blocks of one (point, tracer) share an XCD, so its node
+// coefficients are read into one L2.
 constexpr int KG_XP = 36;  // floats per k-node row of the X strip: [4 groups][8 steps] + 4 (banks)
-
 constexpr int KG_UP = 36;  // floats per slot row of the U tile: [4 groups][8 steps] + 4 (banks)
 
 template <bool SPLIT>
