@@ -83,6 +83,12 @@ typedef struct {
   int32_t device;       /* HIP device ordinal the plan lives on                                  */
   int32_t n_interp;     /* scale-dependent growth (Sec. 3.2, swiftcl_cl_kgrowth): number of k nodes
                            N_interp, 0 = none, else 2..n_k; FP32 and split-precision plans only   */
+  int32_t rsd;          /* 1: redshift-space distortions of the clustering tracers (eq. RSD),
+                           -int dchi f(z) n dz/dchi D j_l''(k chi) added to their windows, with
+                           f = dln D/dln a from the D(z) spline; 0: none.  FP32 and split plans;
+                           the projection runs through the workspace; swiftcl_windows,
+                           swiftcl_cl_backward, swiftcl_cl_kgrowth and swiftcl_cl_limber refuse
+                           such plans                                                              */
 } swiftcl_plan_desc;
 
 /* Per-call inputs.  Device pointers owned by the caller, row-major, never written. */

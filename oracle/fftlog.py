@@ -75,8 +75,9 @@ def chi_grid(geo: PointGeometry, method: Method):
     return chi0, chi0 * np.exp(np.arange(method.n_chi) * method.delta)
 
 
-def sampled_kernels(geo: PointGeometry, method: Method):
-    """Step 1: w_m f_t(chi_m) on the grid, with the edge weights of reading R5.
+def sampled_kernels(geo: PointGeometry, method: Method, rsd=False):
+    """Step 1: w_m f_t(chi_m) on the grid, with the edge weights of reading R5 (with rsd=True the
+    RSD kernels of eq. RSD instead).
 
     Returns (chi0, chi_m, F) with F of shape [T, N].
     """
@@ -97,7 +98,7 @@ def sampled_kernels(geo: PointGeometry, method: Method):
     w[0] = 0.5
     w[-1] = 0.5 + theta if m1 > m0 else w[-1]
     for t in range(T):
-        F[t, nodes] = w * geo.f_of_z(t, z)
+        F[t, nodes] = w * (geo.f_rsd_of_z(t, z) if rsd else geo.f_of_z(t, z))
     return chi0, chi, F
 
 
@@ -136,9 +137,21 @@ def bessel_power_integral(ell, p, k):
     return np.sqrt(np.pi) * np.exp(log_val)
 
 
-def windows_point(geo: PointGeometry, ells, method: Method):
-    """Step 4: W[l, t, j] = Delta_l^t(k_j) for one parameter point."""
+def jl2_coefficients(ell):
+    """j_l'' = a j_{l-2} + b j_l + c j_{l+2}: from j_l' = (l j_{l-1} - (l+1) j_{l+1}) / (2l+1)
+    applied twice (valid for real l)."""
+    a = ell * (ell - 1.0) / ((2.0 * ell - 1.0) * (2.0 * ell + 1.0))
+    b = -(2.0 * ell * ell + 2.0 * ell - 1.0) / ((2.0 * ell - 1.0) * (2.0 * ell + 3.0))
+    c = (ell + 1.0) * (ell + 2.0) / ((2.0 * ell + 1.0) * (2.0 * ell + 3.0))
+    return a, b, c
+
+
+def windows_point(geo: PointGeometry, ells, method: Method, rsd=False):
+    """Step 4: W[l, t, j] = Delta_l^t(k_j) for one parameter point.  rsd=True adds the RSD term of
+    the clustering tracers (eq. RSD): the same steps for the RSD kernels with the integral of
+    chi^p j_l'' (three terms of eq. int_jl) in place of that of chi^p j_l."""
     chi0, chi, F = sampled_kernels(geo, method)
+    FR = sampled_kernels(geo, method, rsd=True)[2] if rsd else None
     T = len(geo.kinds)
     W = np.zeros((len(ells), T, method.n_k))
     coeff = {}
@@ -158,6 +171,14 @@ def windows_point(geo: PointGeometry, ells, method: Method):
             p = b + 1j * 2.0 * np.pi * n / (N * method.delta)
             M = bessel_power_integral(ell, p[None, :], k[:, None])  # [Nk, N-1]
             delta_lk = M @ c.T  # [Nk, T_kind], imaginary part is rounding only
+            if rsd and kind == 0:
+                if ("rsd", b) not in coeff:
+                    coeff[("rsd", b)] = fftlog_coefficients(FR[ts], chi, chi0, b, method)
+                cr = coeff[("rsd", b)][1]
+                a2, a0, a4 = jl2_coefficients(ell)
+                MR = sum(ai * bessel_power_integral(s, p[None, :], k[:, None])
+                         for ai, s in ((a2, ell - 2.0), (a0, ell), (a4, ell + 2.0)))
+                delta_lk = delta_lk + MR @ cr.T
             W[li, ts, :] = (delta_lk.real * ell_prefactor(kind, ell, k)[:, None]).T
     return W
 
@@ -194,7 +215,7 @@ def point_ells(wl, b):
 
 def windows(wl, b, method=None):
     method = method or method_for(wl)
-    return windows_point(point_geometry(wl, b), point_ells(wl, b), method)
+    return windows_point(point_geometry(wl, b), point_ells(wl, b), method, rsd=bool(wl.get("rsd", False)))
 
 
 def cl(wl, b, method=None, return_windows=False):

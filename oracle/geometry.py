@@ -102,6 +102,19 @@ class PointGeometry:
         I0, I1 = self.lensing_integrals(t, z)
         return 1.5 * self.omega_m * H0_OVER_C ** 2 * chi * (1.0 + z) * (I0 - chi * I1)
 
+    def growth_rate(self, z):
+        """f(z) = dln D / dln a = -(1+z) D'(z) / D(z), from the D(z) spline."""
+        z = np.atleast_1d(np.asarray(z, float))
+        return -(1.0 + z) * self.D_spl(z, 1) / self.D_spl(z)
+
+    def f_rsd_of_z(self, t, z):
+        """Radial kernel of the RSD term of clustering tracer t (eq. RSD), per unit chi:
+        -f(z) n(z) dz/dchi D(z); it multiplies j_l'' instead of j_l.  Zero for lensing tracers."""
+        z = np.atleast_1d(np.asarray(z, float))
+        if self.kinds[t] != 0:
+            return np.zeros_like(z)
+        return -self.growth_rate(z) * self.n_of_z(t, z) * self.D_spl(z) / self.chi_spl(z, 1)
+
     def ia_of_z(self, z):
         """A_IA(z), 0 without intrinsic alignment."""
         z = np.atleast_1d(np.asarray(z, float))

@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import numpy as np
 from scipy.interpolate import CubicSpline
-from scipy.special import jv
+from scipy.special import jv, jvp
 
 from .geometry import PointGeometry, ell_prefactor
 
@@ -56,8 +56,20 @@ def _panels(geo: PointGeometry, k):
     return np.concatenate(edges)
 
 
-def windows_quadrature(geo: PointGeometry, ells, k, lens_table=None):
-    """W[l, t, j] = c_t(l, k_j) int dz (dchi/dz) f_t j_l(k_j chi(z)) for the given ells and k."""
+def spherical_jn2_real(ell, x):
+    """j_l''(x) from the spherical Bessel equation: j'' = -(2/x) j' - (1 - l(l+1)/x^2) j, with
+    j' from J_nu' (scipy jvp), real order."""
+    x = np.asarray(x, float)
+    nu = ell + 0.5
+    s = np.sqrt(np.pi / (2.0 * x))
+    j = s * jv(nu, x)
+    jp = s * (jvp(nu, x) - jv(nu, x) / (2.0 * x))
+    return -(2.0 / x) * jp - (1.0 - ell * (ell + 1.0) / x ** 2) * j
+
+
+def windows_quadrature(geo: PointGeometry, ells, k, lens_table=None, rsd=False):
+    """W[l, t, j] = c_t(l, k_j) int dz (dchi/dz) f_t j_l(k_j chi(z)) for the given ells and k; with
+    rsd=True the clustering tracers add int dz (dchi/dz) f_rsd j_l''(k_j chi(z)) (eq. RSD)."""
     k = np.atleast_1d(np.asarray(k, float))
     T = len(geo.kinds)
     if lens_table is None and np.any(geo.kinds == 1):
@@ -79,9 +91,13 @@ def windows_quadrature(geo: PointGeometry, ells, k, lens_table=None):
             else:
                 h[t] = (lens_table(t, z) * geo.chi_spl(z, 1) + geo.ia_of_z(z) * geo.n_of_z(t, z)) * D / chi ** 2
         hw = h * wz[None, :]
+        if rsd:
+            hr = np.array([geo.f_rsd_of_z(t, z) * geo.chi_spl(z, 1) for t in range(T)]) * wz[None, :]
         for li, ell in enumerate(ells):
             jl = spherical_jn_real(ell, kk * chi)
             integral = hw @ jl
+            if rsd:
+                integral = integral + hr @ spherical_jn2_real(ell, kk * chi)
             for t in range(T):
                 W[li, t, j] = integral[t] * ell_prefactor(geo.kinds[t], ell, kk)
     return W

@@ -54,6 +54,7 @@ class swiftcl_plan_desc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("device", ctypes.c_int32),
         ("n_interp", ctypes.c_int32),
+        ("rsd", ctypes.c_int32),
     ]
 
 

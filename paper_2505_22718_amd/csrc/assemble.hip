@@ -138,7 +138,10 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
     if (m >= N) continue;
     if (m < m0 || m > m1) {
       for (int t = 0; t < T; ++t)
-        for (int bi = 0; bi < nb; ++bi) g[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
+        for (int bi = 0; bi < nb; ++bi) {
+          g[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
+          if (P.rsd) ((R*)P.g_r)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
+        }
       continue;
     }
     ns[k].active = true;
@@ -172,18 +175,30 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
   for (int k = 0; k < MAXN; ++k) {
     if (!ns[k].active) continue;
     const int m = tid + k * nth;
+    // RSD (eq. RSD): -f(z) n dz/dchi D with f = dln D/dln a = -(1+z) D'/D, i.e. (1+z) D' n / (dchi/dz)
+    double dD = 0.0;
+    if (P.rsd) (void)spline_at(zg, zgih, Dz, mD, ns[k].ig, ns[k].z, &dD);
     for (int t = g0; t < g1; ++t) {
-      if (t < Tb && in.kind[(size_t)b * T + t] != SWIFTCL_CLUSTERING) continue;
-      double f = 0.0;
+      const bool clus = t < Tb && in.kind[(size_t)b * T + t] == SWIFTCL_CLUSTERING;
+      if (t < Tb && !clus) {
+        if (P.rsd)
+          for (int bi = 0; bi < nb; ++bi) ((R*)P.g_r)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
+        continue;
+      }
+      double f = 0.0, fr = 0.0;
       if (t < Tb) {
         const double n = ns[k].inz < 0 ? 0.0
                          : spline_at(zs, zsih, nzr + (size_t)(t - g0) * nzs, mn + (size_t)(t - g0) * nzs, ns[k].inz,
                                      ns[k].z, nullptr);
         f = in.bias[(size_t)b * T + t] * n * ns[k].D / ns[k].dchi;
+        fr = (1.0 + ns[k].z) * dD * n / ns[k].dchi;
       }
-      for (int bi = 0; bi < nb; ++bi)
+      for (int bi = 0; bi < nb; ++bi) {
         g[(((size_t)b * T + t) * nb + bi) * N + m] =
             (R)(ns[k].w * f * P.ebm[(size_t)bi * N + m]);
+        if (P.rsd)
+          ((R*)P.g_r)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)(ns[k].w * fr * P.ebm[(size_t)bi * N + m]);
+      }
     }
   }
   // (lensing tracers: k_geom_lens, one workgroup per (point, tracer))

@@ -70,8 +70,8 @@ __global__ void k_sqrt_s(plan_dev P, swiftcl_inputs in) {
     ((R*)P.kss)[((size_t)b * 2 * P.n_bands + kb) * P.n_k + j] = ((const R*)P.kscale)[(size_t)kb * P.n_k + j] * sq;
 }
 
-// FFTLog coefficients: one wavefront per (point, tracer, band) row.
-template <typename R, int M>
+// FFTLog coefficients: one wavefront per (point, tracer, band) row (RSD: of the RSD kernels).
+template <typename R, int M, bool RSD = false>
 __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs in) {
   __shared__ C2<R> lds[4][fft_lds_size(M, sizeof(R))];
   // FP32: the twiddle table staged in LDS by the block (FP64 reads it through the cache)
@@ -91,14 +91,14 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
   const int bi = (int)(row % nb);
   const int t = (int)((row / nb) % T);
   const int b = (int)(row / ((long)nb * T));
-  C2<R>* out = (C2<R>*)P.chat + row * M;
+  C2<R>* out = (C2<R>*)(RSD ? P.chat_r : P.chat) + row * M;
   const int Tb = clampi(in.n_tracers[b], 0, T);
   if (t >= Tb) {
 #pragma unroll
     for (int e = 0; e < RL; ++e) out[lane + SWIFTCL_WAVE * e] = mk<R>(0, 0);
     return;
   }
-  const C2<R>* g2 = (const C2<R>*)((const R*)P.g + row * N);
+  const C2<R>* g2 = (const C2<R>*)((const R*)(RSD ? P.g_r : P.g) + row * N);
   const C2<R>* tw = twp;
   C2<R> v[RL];
 #pragma unroll
@@ -336,6 +336,7 @@ static hipError_t launch_fwd_t(const plan_dev& p, const swiftcl_inputs* in, hipS
   if (e != hipSuccess) return e;
   const long rows = (long)in->batch * p.max_tracers * p.n_bands;
   hipLaunchKernelGGL((k_forward_fft<R, M>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in);
+  if (p.rsd) hipLaunchKernelGGL((k_forward_fft<R, M, true>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in);
   return hipGetLastError();
 }
 
@@ -380,7 +381,7 @@ bool unfused_tw_lds(int M) { return unfused_tw(M); }
 // workspace, k_contract forms the 32 x 32 Gram matrix from three 16 x 16 MFMA tile pairs
 // (0,0), (0,1), (1,1).  Points are processed in chunks of P.vchunk.
 // ---------------------------------------------------------------------------------------------
-template <int M, int NW, bool TW_LDS, bool SPLIT>
+template <int M, int NW, bool TW_LDS, bool SPLIT, bool RSD>
 __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
   extern __shared__ __align__(16) unsigned char smem[];
   typedef float R;
@@ -443,6 +444,16 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
     for (int e = 0; e < RL; ++e) {
       const int n = lane + SWIFTCL_WAVE * e;
       v[e] = cconj(cmul(ch[n], Ur[n]));
+    }
+    if (RSD && kind == SWIFTCL_CLUSTERING) {
+      // the RSD window of a clustering tracer shares its prefactor and k scale: add its term
+      const C2<R>* chr = (const C2<R>*)P.chat_r + (((size_t)b * T + t) * nb + band) * M;
+      const C2<R>* URr = (const C2<R>*)P.UR + (size_t)ei * M;
+#pragma unroll
+      for (int e = 0; e < RL; ++e) {
+        const int n = lane + SWIFTCL_WAVE * e;
+        v[e] = cadd(v[e], cconj(cmul(chr[n], URr[n])));
+      }
     }
     int ln = lane;  // opaque copy: keeps the FFT's per-lane LDS addresses out of the tracer loop
     asm volatile("" : "+v"(ln));
@@ -583,8 +594,13 @@ static hipError_t launch_unfused(const plan_dev& p, const swiftcl_inputs* in, vo
     const int nbp = in->batch - b0 < p.vchunk ? in->batch - b0 : p.vchunk;
     const size_t groups = (size_t)(nbp + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
     const dim3 g1((unsigned)(groups * p.max_ell * SWIFTCL_NXCD));
-    if (split) hipLaunchKernelGGL((k_windows_v<M, NW, TW, true>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
-    else hipLaunchKernelGGL((k_windows_v<M, NW, TW, false>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
+    if (p.rsd) {
+      if (split) hipLaunchKernelGGL((k_windows_v<M, NW, TW, true, true>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
+      else hipLaunchKernelGGL((k_windows_v<M, NW, TW, false, true>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
+    } else {
+      if (split) hipLaunchKernelGGL((k_windows_v<M, NW, TW, true, false>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
+      else hipLaunchKernelGGL((k_windows_v<M, NW, TW, false, false>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 g2((unsigned)((size_t)nbp * p.max_ell));

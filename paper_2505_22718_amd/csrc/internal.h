@@ -88,6 +88,12 @@ struct plan_dev {
   void* vbuf;         // [vchunk][max_ell][32][n_k] FP32, or bf16 hi then lo (unfused and kgrowth paths)
   // scale-dependent growth (swiftcl_cl_kgrowth); points run in chunks of vchunk
   int n_interp;       // k nodes (0 = not built)
+  // redshift-space distortions (eq. RSD) of the clustering tracers: a second coefficient set per
+  // (tracer, band) times the table of the integral of chi^p j_l''
+  int rsd;
+  void* UR;           // [n_ell][M] complex: sum_s a_s(l) U_s(n) over s = l-2, l, l+2 (clustering bias)
+  void* g_r;          // [B][T][n_bands][N] real: tilted, edge-weighted RSD kernel samples
+  void* chat_r;       // [B][T][n_bands][M] complex: their FFTLog coefficients
   int kg_ntile;       // slot tiles per (point, tracer): ceil(max_ell / 64) + n_bands
   double* kg_ones;    // [max_batch][n_zg] ones: the assembly's D(z) while growth sits at the nodes
   int* kg_ia;         // [n_k] node interval a_j of k_j

@@ -115,6 +115,49 @@ __global__ void k_u_table(C2<R>* __restrict__ U, const double* __restrict__ ell,
   }
 }
 
+// The RSD table (eq. RSD): the integral of chi^p j_l'' is that of chi^p times
+// a j_{l-2} + b j_l + c j_{l+2} (j_l' = (l j_{l-1} - (l+1) j_{l+1}) / (2l+1) applied twice), i.e. the
+// same combination of three U values of eq. int_jl at the clustering bias of l's band.
+__device__ inline zd u_value(double l, double b, double eta) {
+  zd pa = {0.5 * (1.0 + l + b), 0.5 * eta};
+  zd pb = {0.5 * (2.0 + l - b), -0.5 * eta};
+  zd lg = zsub(zlgamma(pa), zlgamma(pb));
+  lg.x += (b - 1.0) * 0.69314718055994530942;
+  lg.y += eta * 0.69314718055994530942;
+  const double mag = 1.7724538509055160273 * exp(lg.x);
+  double sn, cs;
+  sincos(lg.y, &sn, &cs);
+  return {mag * cs, mag * sn};
+}
+
+template <typename R>
+__global__ void k_u_rsd(C2<R>* __restrict__ UR, const double* __restrict__ ell, const int* __restrict__ band,
+                        double b0, double b1, double b2, double b3, int n_ell, int M, double delta, double taper_frac) {
+  const int li = blockIdx.x;
+  const int n = blockIdx.y * blockDim.x + threadIdx.x;
+  if (li >= n_ell || n >= M) return;
+  const double l = ell[li];
+  const double bclus[4] = {b0, b1, b2, b3};
+  const double b = bclus[band[li]];
+  const double eta = 2.0 * M_PI * (double)n / (2.0 * M * delta);
+  double tap = 1.0;
+  if (taper_frac > 0.0) {
+    double x = (double)n / (double)M, x0 = 1.0 - taper_frac;
+    if (x > x0) tap = 0.5 * (1.0 + cos(M_PI * fmin((x - x0) / taper_frac, 1.0)));
+  }
+  const double am = l * (l - 1.0) / ((2.0 * l - 1.0) * (2.0 * l + 1.0));
+  const double a0 = -(2.0 * l * l + 2.0 * l - 1.0) / ((2.0 * l - 1.0) * (2.0 * l + 3.0));
+  const double ap = (l + 1.0) * (l + 2.0) / ((2.0 * l + 1.0) * (2.0 * l + 3.0));
+  const zd um = u_value(l - 2.0, b, eta), u0 = u_value(l, b, eta), up = u_value(l + 2.0, b, eta);
+  double vx = (am * um.x + a0 * u0.x + ap * up.x) * tap;
+  double vy = (am * um.y + a0 * u0.y + ap * up.y) * tap;
+  if (n == 0) vy = 0.0;
+  C2<R> v;
+  v.x = (R)vx;
+  v.y = (R)vy;
+  UR[(size_t)li * M + n] = v;
+}
+
 hipError_t launch_u_table(const plan_dev& pd, const double* d_ell, hipStream_t s) {
   const plan_dev* p = &pd;
   dim3 grid(p->n_ell, (p->M + 127) / 128);
@@ -126,6 +169,9 @@ hipError_t launch_u_table(const plan_dev& pd, const double* d_ell, hipStream_t s
   else
     hipLaunchKernelGGL(k_u_table<float>, grid, dim3(128), 0, s, (float2*)p->U, d_ell, p->ell_band, b[0], b[1],
                        b[2], b[3], c[0], c[1], c[2], c[3], p->n_ell, p->M, p->delta, p->taper_frac);
+  if (p->rsd)  // RSD plans are FP32 / split
+    hipLaunchKernelGGL(k_u_rsd<float>, grid, dim3(128), 0, s, (float2*)p->UR, d_ell, p->ell_band, b[0], b[1], b[2],
+                       b[3], p->n_ell, p->M, p->delta, p->taper_frac);
   return hipGetLastError();
 }
 
@@ -201,6 +247,11 @@ static swiftcl_status validate_desc(const swiftcl_plan_desc* d) {
   if (d->max_batch < 1 || d->max_tracers < 1 || d->max_ell < 1) { set_error("capacities must be >= 1"); return SWIFTCL_E_INVALID; }
   if (d->max_tracers > 32) { set_error("max_tracers > 32 is not built"); return SWIFTCL_E_UNSUPPORTED; }
   if (d->precision < 0 || d->precision > 2) { set_error("unknown precision"); return SWIFTCL_E_INVALID; }
+  if (d->rsd != 0 && d->rsd != 1) { set_error("rsd must be 0 or 1"); return SWIFTCL_E_INVALID; }
+  if (d->rsd && d->precision == SWIFTCL_FP64) {
+    set_error("redshift-space distortions are built for FP32 and split precision");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
   if (d->n_interp != 0) {
     if (d->n_interp < 2 || d->n_interp > d->n_k) { set_error("n_interp must be 0 or in 2..n_k"); return SWIFTCL_E_INVALID; }
     if (d->precision == SWIFTCL_FP64) {
@@ -247,7 +298,7 @@ static void free_plan(swiftcl_plan_s* p) {
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_ia, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
                   p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf,
                   p->d.kg_ones, p->d.kg_ia, p->d.kg_w, p->d.kg_ip, p->d.kg_uh, p->d.kg_c, p->d.kg_m, p->d.kg_perm,
-                  p->d.kg_tile};
+                  p->d.kg_tile, p->d.UR, p->d.g_r, p->d.chat_r};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -270,7 +321,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     const int M = d->n_chi / 2;
     const size_t need = windows_cl_lds(M, windows_nw(d->precision), windows_tw_lds(d->precision, M), true,
                                        dp ? 8 : 4, d->n_k);
-    fused = d->max_tracers <= 16 && need <= (size_t)lds_max;
+    fused = d->max_tracers <= 16 && need <= (size_t)lds_max && !d->rsd;
     if (!fused && dp) {
       set_error("the FP64 path keeps the windows of <= 16 tracers in LDS; this n_chi / n_k / max_tracers needs " +
                 std::to_string(need) + " bytes per workgroup, the device has " + std::to_string(lds_max));
@@ -317,6 +368,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   p->d.taper_frac = d->taper_frac;
   p->d.m0 = d->edge_node > 0 ? d->edge_node : default_edge_node(d->n_chi, p->d.delta);
   p->d.fused = fused ? 1 : 0;
+  p->d.rsd = d->rsd;
   p->d.adjoint = (fused && d->precision != SWIFTCL_SPLIT_BF16 &&
                   bwd_windows_lds(p->d) + 4096 <= (size_t)lds_max)  // + the kernel's static LDS
                      ? 1 : 0;
@@ -445,6 +497,11 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   if (fused && d->precision != SWIFTCL_SPLIT_BF16) ALLOC(ddD_part, double, (size_t)B * T * 2 * p->d.n_zg);
   ALLOC(g, char, (size_t)B * T * nb * N * rs);
   ALLOC(chat, char, (size_t)B * T * nb * M * 2 * rs);
+  if (p->d.rsd) {
+    ALLOC(UR, char, (size_t)p->d.n_ell * M * 2 * rs);
+    ALLOC(g_r, char, (size_t)B * T * nb * N * rs);
+    ALLOC(chat_r, char, (size_t)B * T * nb * M * 2 * rs);
+  }
   ALLOC(sqrt_s, char, (size_t)B * nk * rs);
   ALLOC(kss, char, (size_t)B * 2 * nb * nk * rs);
   ALLOC(flags, int, 1);
@@ -635,6 +692,10 @@ static swiftcl_status run_forward(swiftcl_plan_t p, const swiftcl_inputs* in, vo
 
 extern "C" swiftcl_status swiftcl_windows(swiftcl_plan_t p, const swiftcl_inputs* in, void* W, void* stream) {
   if (!W) { set_error("W is NULL"); return SWIFTCL_E_INVALID; }
+  if (p && p->d.rsd) {
+    set_error("windows output is not built with redshift-space distortions (C_l is)");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
   return run_forward(p, in, W, nullptr, stream);
 }
 
@@ -679,6 +740,10 @@ extern "C" swiftcl_status swiftcl_cl_kgrowth(swiftcl_plan_t p, const swiftcl_inp
     set_error("the plan has no interpolation nodes in k (n_interp = 0)");
     return SWIFTCL_E_INVALID;
   }
+  if (p->d.rsd) {
+    set_error("scale-dependent growth is not built with redshift-space distortions");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
   // the kernels are assembled without growth (D = 1); growth enters per node
   swiftcl_inputs in1 = *in;
   in1.D_z = p->d.kg_ones;
@@ -698,6 +763,10 @@ extern "C" swiftcl_status swiftcl_cl_limber(swiftcl_plan_t p, const swiftcl_inpu
   swiftcl_status st = check_inputs(p, in);
   if (st != SWIFTCL_OK) return st;
   if (!C) { set_error("C is NULL"); return SWIFTCL_E_INVALID; }
+  if (p->d.rsd) {
+    set_error("the Limber path does not include redshift-space distortions");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
   if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
@@ -715,7 +784,8 @@ static swiftcl_status backward_checks(swiftcl_plan_t p, const swiftcl_inputs* in
   if (!dC) { set_error("dC is NULL"); return SWIFTCL_E_INVALID; }
   if (flags & ~(uint32_t)SWIFTCL_BWD_REUSE_FORWARD) { set_error("unknown backward flag"); return SWIFTCL_E_INVALID; }
   if (!p->d.adjoint) {
-    set_error("the adjoint is built for plans whose windows fit in LDS (<= 16 tracers) in FP32 or FP64");
+    set_error("the adjoint is built for plans whose windows fit in LDS (<= 16 tracers) in FP32 or FP64, "
+              "without redshift-space distortions");
     return SWIFTCL_E_UNSUPPORTED;
   }
   *reuse = (flags & SWIFTCL_BWD_REUSE_FORWARD) != 0;

@@ -41,7 +41,7 @@ class Plan:
 
     def __init__(self, k, ell, z_geom, z_nz, n_chi, max_batch, max_tracers, max_ell, precision="fp32",
                  band_ell_lo=DEFAULT_BAND_ELL_LO, fftlog_b=DEFAULT_FFTLOG_B, taper_frac=0.0, edge_node=0,
-                 device=0, n_interp=0):
+                 device=0, n_interp=0, rsd=False):
         self.k = _f64(k)
         self.ell = _f64(ell)
         self.z_geom = _f64(z_geom)
@@ -70,6 +70,8 @@ class Plan:
         d.device = self.device.index or 0
         d.n_interp = int(n_interp)
         self.n_interp = int(n_interp)
+        d.rsd = 1 if rsd else 0
+        self.rsd = bool(rsd)
         self.desc = d
         self.out_dtype = torch.float64 if precision == "fp64" else torch.float32
         with torch.cuda.device(self.device):

@@ -84,6 +84,8 @@ def _desc(**over):
     (dict(n_interp=1), -1),                                  # one node cannot be interpolated
     (dict(n_interp=257), -1),                                # more nodes than k nodes
     (dict(n_interp=16), -5),                                 # scale-dependent growth in FP64
+    (dict(rsd=1), -5),                                       # RSD in FP64
+    (dict(rsd=2), -1),
 ])
 def test_plan_rejects_bad_descriptor(lib, over, code):
     d, keep = _desc(**over)
