@@ -89,6 +89,9 @@ typedef struct {
                            the projection runs through the workspace; swiftcl_windows,
                            swiftcl_cl_backward, swiftcl_cl_kgrowth and swiftcl_cl_limber refuse
                            such plans                                                              */
+  int32_t magnification; /* 1: the plan can carry magnification bias of the clustering tracers
+                           (eq. magnification bias; inputs `mag`), with the same restrictions as
+                           rsd; 0: none                                                            */
 } swiftcl_plan_desc;
 
 /* Per-call inputs.  Device pointers owned by the caller, row-major, never written. */
@@ -108,6 +111,10 @@ typedef struct {
                                 (no intrinsic alignment; Sec. 2.3: their kernel becomes
                                 (q + A_IA n dz/dchi) D / chi^2); the backward calls carry it into
                                 dL/dn and dL/dD but do not differentiate A_IA itself                 */
+  const double* mag;         /* [B][max_tracers] lensing-bias coefficients C_g of the clustering
+                                tracers (eq. magnification bias: l(l+1)/k^2 C_g int dchi / chi^2
+                                q_g D j_l joins their window, q_g the lens efficiency of their own
+                                n(z)), or NULL; needs a plan built with magnification = 1            */
 } swiftcl_inputs;
 
 /* Build a plan: validates the descriptor, builds the log-chi grid, the FP64 table of Bessel

@@ -75,7 +75,7 @@ def chi_grid(geo: PointGeometry, method: Method):
     return chi0, chi0 * np.exp(np.arange(method.n_chi) * method.delta)
 
 
-def sampled_kernels(geo: PointGeometry, method: Method, rsd=False):
+def sampled_kernels(geo: PointGeometry, method: Method, rsd=False, mag=False):
     """Step 1: w_m f_t(chi_m) on the grid, with the edge weights of reading R5 (with rsd=True the
     RSD kernels of eq. RSD instead).
 
@@ -98,7 +98,7 @@ def sampled_kernels(geo: PointGeometry, method: Method, rsd=False):
     w[0] = 0.5
     w[-1] = 0.5 + theta if m1 > m0 else w[-1]
     for t in range(T):
-        F[t, nodes] = w * (geo.f_rsd_of_z(t, z) if rsd else geo.f_of_z(t, z))
+        F[t, nodes] = w * (geo.f_rsd_of_z(t, z) if rsd else (geo.f_mag_of_z(t, z) if mag else geo.f_of_z(t, z)))
     return chi0, chi, F
 
 
@@ -149,9 +149,12 @@ def jl2_coefficients(ell):
 def windows_point(geo: PointGeometry, ells, method: Method, rsd=False):
     """Step 4: W[l, t, j] = Delta_l^t(k_j) for one parameter point.  rsd=True adds the RSD term of
     the clustering tracers (eq. RSD): the same steps for the RSD kernels with the integral of
-    chi^p j_l'' (three terms of eq. int_jl) in place of that of chi^p j_l."""
+    chi^p j_l'' (three terms of eq. int_jl) in place of that of chi^p j_l.  A geometry with
+    lensing-bias coefficients adds the magnification term (eq. magnification bias)."""
     chi0, chi, F = sampled_kernels(geo, method)
     FR = sampled_kernels(geo, method, rsd=True)[2] if rsd else None
+    mag = geo.mag is not None
+    FM = sampled_kernels(geo, method, mag=True)[2] if mag else None
     T = len(geo.kinds)
     W = np.zeros((len(ells), T, method.n_k))
     coeff = {}
@@ -180,6 +183,16 @@ def windows_point(geo: PointGeometry, ells, method: Method, rsd=False):
                          for ai, s in ((a2, ell - 2.0), (a0, ell), (a4, ell + 2.0)))
                 delta_lk = delta_lk + MR @ cr.T
             W[li, ts, :] = (delta_lk.real * ell_prefactor(kind, ell, k)[:, None]).T
+            if mag and kind == 0:
+                # magnification: a lensing-type kernel with prefactor l(l+1)/k^2, decomposed with the
+                # bias b - 2 (reading R20)
+                bm = b - 2.0
+                if ("mag", bm) not in coeff:
+                    coeff[("mag", bm)] = fftlog_coefficients(FM[ts], chi, chi0, bm, method)
+                cm = coeff[("mag", bm)][1]
+                pm = bm + 1j * 2.0 * np.pi * n / (N * method.delta)
+                dm = bessel_power_integral(ell, pm[None, :], k[:, None]) @ cm.T
+                W[li, ts, :] += (dm.real * (ell * (ell + 1.0) / k ** 2)[:, None]).T
     return W
 
 

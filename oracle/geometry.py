@@ -29,13 +29,15 @@ _GL = np.polynomial.legendre.leggauss(12)
 class PointGeometry:
     """Continuous geometry, growth and redshift distributions of one parameter point."""
 
-    def __init__(self, z_geom, chi_z, D_z, omega_m, z_nz, nz, kinds, bias, ia=None):
+    def __init__(self, z_geom, chi_z, D_z, omega_m, z_nz, nz, kinds, bias, ia=None, mag=None):
         self.z_geom = np.asarray(z_geom, float)
         self.z_nz = np.asarray(z_nz, float)
         self.chi_spl = CubicSpline(self.z_geom, chi_z, bc_type="natural")
         self.D_spl = CubicSpline(self.z_geom, D_z, bc_type="natural")
         # NLA amplitude A_IA(z) of the lensing tracers (Sec. 2.3), None = no intrinsic alignment
         self.ia_spl = None if ia is None else CubicSpline(self.z_geom, ia, bc_type="natural")
+        # lensing-bias coefficients C_g of the clustering tracers (eq. magnification bias), or None
+        self.mag = None if mag is None else np.asarray(mag, float)
         self.nz = np.asarray(nz, float)
         self.n_spl = [CubicSpline(self.z_nz, n_t, bc_type="natural") for n_t in self.nz]
         self.omega_m = float(omega_m)
@@ -115,6 +117,15 @@ class PointGeometry:
             return np.zeros_like(z)
         return -self.growth_rate(z) * self.n_of_z(t, z) * self.D_spl(z) / self.chi_spl(z, 1)
 
+    def f_mag_of_z(self, t, z):
+        """Radial kernel of the magnification term of clustering tracer t (eq. magnification bias),
+        per unit chi: C_g q_t(z) D / chi^2 with q_t the lens efficiency of the tracer's own n(z); its
+        prefactor is l(l+1)/k^2.  Zero for lensing tracers or without magnification."""
+        z = np.atleast_1d(np.asarray(z, float))
+        if self.mag is None or self.kinds[t] != 0:
+            return np.zeros_like(z)
+        return self.mag[t] * self.lensing_q(t, z) * self.D_spl(z) / self.chi_spl(z) ** 2
+
     def ia_of_z(self, z):
         """A_IA(z), 0 without intrinsic alignment."""
         z = np.atleast_1d(np.asarray(z, float))
@@ -150,10 +161,10 @@ class PointGeometry:
 def point_geometry(wl, b):
     """PointGeometry of parameter point b of a synthetic workload dict."""
     T = int(wl["n_tracers"][b])
-    ia = wl.get("ia")
+    ia, mag = wl.get("ia"), wl.get("mag")
     return PointGeometry(wl["z_geom"], wl["chi_z"][b], wl["D_z"][b], wl["omega_m"][b], wl["z_nz"],
                          wl["nz"][b, :T], wl["kind"][b, :T], wl["bias"][b, :T],
-                         ia=None if ia is None else ia[b])
+                         ia=None if ia is None else ia[b], mag=None if mag is None else mag[b, :T])
 
 
 def ell_prefactor(kind, ell, k):

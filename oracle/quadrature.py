@@ -38,7 +38,8 @@ class LensingTable:
         zt = np.concatenate([np.linspace(knots[i], knots[i + 1], refine + 1)[:-1]
                              for i in range(len(knots) - 1)] + [[knots[-1]]])
         self.spl = {}
-        for t in np.nonzero(geo.kinds == 1)[0]:
+        # lensing tracers, and clustering tracers too when they carry magnification
+        for t in np.nonzero((geo.kinds == 1) | (geo.mag is not None))[0]:
             self.spl[int(t)] = CubicSpline(zt, geo.lensing_q(int(t), zt))
 
     def __call__(self, t, z):
@@ -72,7 +73,7 @@ def windows_quadrature(geo: PointGeometry, ells, k, lens_table=None, rsd=False):
     rsd=True the clustering tracers add int dz (dchi/dz) f_rsd j_l''(k_j chi(z)) (eq. RSD)."""
     k = np.atleast_1d(np.asarray(k, float))
     T = len(geo.kinds)
-    if lens_table is None and np.any(geo.kinds == 1):
+    if lens_table is None and (np.any(geo.kinds == 1) or geo.mag is not None):
         lens_table = LensingTable(geo)
     x, w = _GL16
     W = np.zeros((len(ells), T, len(k)))
@@ -93,6 +94,10 @@ def windows_quadrature(geo: PointGeometry, ells, k, lens_table=None, rsd=False):
         hw = h * wz[None, :]
         if rsd:
             hr = np.array([geo.f_rsd_of_z(t, z) * geo.chi_spl(z, 1) for t in range(T)]) * wz[None, :]
+        if geo.mag is not None:
+            # magnification (eq. magnification bias): C_g q D / chi^2 with prefactor l(l+1)/k^2
+            hm = np.array([geo.mag[t] * lens_table(t, z) * D * geo.chi_spl(z, 1) / chi ** 2 if geo.kinds[t] == 0
+                           else np.zeros_like(z) for t in range(T)]) * wz[None, :]
         for li, ell in enumerate(ells):
             jl = spherical_jn_real(ell, kk * chi)
             integral = hw @ jl
@@ -100,4 +105,6 @@ def windows_quadrature(geo: PointGeometry, ells, k, lens_table=None, rsd=False):
                 integral = integral + hr @ spherical_jn2_real(ell, kk * chi)
             for t in range(T):
                 W[li, t, j] = integral[t] * ell_prefactor(geo.kinds[t], ell, kk)
+            if geo.mag is not None:
+                W[li, :, j] += (hm @ jl) * ell * (ell + 1.0) / kk ** 2
     return W

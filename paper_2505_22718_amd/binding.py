@@ -55,6 +55,7 @@ class swiftcl_plan_desc(ctypes.Structure):
         ("device", ctypes.c_int32),
         ("n_interp", ctypes.c_int32),
         ("rsd", ctypes.c_int32),
+        ("magnification", ctypes.c_int32),
     ]
 
 
@@ -72,6 +73,7 @@ class swiftcl_inputs(ctypes.Structure):
         ("bias", ctypes.c_void_p),
         ("pk", ctypes.c_void_p),
         ("ia", ctypes.c_void_p),
+        ("mag", ctypes.c_void_p),
     ]
 
 

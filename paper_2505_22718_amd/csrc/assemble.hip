@@ -141,6 +141,7 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
         for (int bi = 0; bi < nb; ++bi) {
           g[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
           if (P.rsd) ((R*)P.g_r)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
+          if (P.mag) ((R*)P.g_mu)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
         }
       continue;
     }
@@ -181,10 +182,15 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
     for (int t = g0; t < g1; ++t) {
       const bool clus = t < Tb && in.kind[(size_t)b * T + t] == SWIFTCL_CLUSTERING;
       if (t < Tb && !clus) {
-        if (P.rsd)
-          for (int bi = 0; bi < nb; ++bi) ((R*)P.g_r)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
+        for (int bi = 0; bi < nb; ++bi) {
+          if (P.rsd) ((R*)P.g_r)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
+          if (P.mag) ((R*)P.g_mu)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
+        }
         continue;
       }
+      // (the magnification samples of clustering tracers come from k_geom_lens)
+      if (t >= Tb && P.mag)
+        for (int bi = 0; bi < nb; ++bi) ((R*)P.g_mu)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
       double f = 0.0, fr = 0.0;
       if (t < Tb) {
         const double n = ns[k].inz < 0 ? 0.0
@@ -221,7 +227,10 @@ __global__ __launch_bounds__(512) void k_geom_lens(plan_dev P, swiftcl_inputs in
   const int b = blockIdx.x / T, t = blockIdx.x % T;
   if (b >= in.batch) return;
   const int Tb = in.n_tracers[b] < T ? in.n_tracers[b] : T;
-  if (t >= Tb || in.kind[(size_t)b * T + t] != SWIFTCL_LENSING) return;
+  if (t >= Tb) return;
+  // lensing tracers, and clustering tracers whose magnification needs their own lens efficiency
+  const bool lensing = in.kind[(size_t)b * T + t] == SWIFTCL_LENSING;
+  if (!lensing && !(P.mag && in.mag)) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int nzg = P.n_zg, nzs = P.n_zs, nb = P.n_bands, N = P.N, nu = P.n_union;
   double* zg = sh;              // [nzg]
@@ -275,6 +284,14 @@ __global__ __launch_bounds__(512) void k_geom_lens(plan_dev P, swiftcl_inputs in
     const double I0 = p0 + (u + 1 < nu ? seg0[u + 1] : 0.0);
     const double I1 = p1 + (u + 1 < nu ? seg1[u + 1] : 0.0);
     const double q = pref * x * (1.0 + z) * (I0 - x * I1);
+    if (!lensing) {
+      // magnification (eq. magnification bias): C_g q D / chi^2, tilted with the bias b - 2
+      const double fm = in.mag[(size_t)b * T + t] * q * D / (x * x);
+      const double e2 = exp(2.0 * (double)m * P.delta);
+      for (int bi = 0; bi < nb; ++bi)
+        ((R*)P.g_mu)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)(w * fm * P.ebm[(size_t)bi * N + m] * e2);
+      continue;
+    }
     P.lens_q[((size_t)b * T + t) * N + m] = q;  // for the adjoint
     double fq = q;
     if (in.ia) {

@@ -70,8 +70,9 @@ __global__ void k_sqrt_s(plan_dev P, swiftcl_inputs in) {
     ((R*)P.kss)[((size_t)b * 2 * P.n_bands + kb) * P.n_k + j] = ((const R*)P.kscale)[(size_t)kb * P.n_k + j] * sq;
 }
 
-// FFTLog coefficients: one wavefront per (point, tracer, band) row (RSD: of the RSD kernels).
-template <typename R, int M, bool RSD = false>
+// FFTLog coefficients: one wavefront per (point, tracer, band) row.  SET 0: the kernels; 1: the RSD
+// kernels; 2: the magnification kernels (tilted with the bias b - 2, hence the extra chi_0^2).
+template <typename R, int M, int SET = 0>
 __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs in) {
   __shared__ C2<R> lds[4][fft_lds_size(M, sizeof(R))];
   // FP32: the twiddle table staged in LDS by the block (FP64 reads it through the cache)
@@ -91,14 +92,14 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
   const int bi = (int)(row % nb);
   const int t = (int)((row / nb) % T);
   const int b = (int)(row / ((long)nb * T));
-  C2<R>* out = (C2<R>*)(RSD ? P.chat_r : P.chat) + row * M;
+  C2<R>* out = (C2<R>*)(SET == 1 ? P.chat_r : (SET == 2 ? P.chat_mu : P.chat)) + row * M;
   const int Tb = clampi(in.n_tracers[b], 0, T);
   if (t >= Tb) {
 #pragma unroll
     for (int e = 0; e < RL; ++e) out[lane + SWIFTCL_WAVE * e] = mk<R>(0, 0);
     return;
   }
-  const C2<R>* g2 = (const C2<R>*)((const R*)(RSD ? P.g_r : P.g) + row * N);
+  const C2<R>* g2 = (const C2<R>*)((const R*)(SET == 1 ? P.g_r : (SET == 2 ? P.g_mu : P.g)) + row * N);
   const C2<R>* tw = twp;
   C2<R> v[RL];
 #pragma unroll
@@ -106,7 +107,8 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
   wave_r2c<R, M>(v, lds[wave], tw, lane);
   const double* pt = P.pt + (size_t)b * PT_STRIDE;
   const int kind = in.kind[(size_t)b * T + t] & 1;
-  const double scale = pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] / (double)N;
+  double scale = pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] / (double)N;
+  if (SET == 2) scale *= pt[PT_CHI0] * pt[PT_CHI0];
   const double2* ph = (const double2*)P.phase + (size_t)b * M;
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
@@ -336,7 +338,9 @@ static hipError_t launch_fwd_t(const plan_dev& p, const swiftcl_inputs* in, hipS
   if (e != hipSuccess) return e;
   const long rows = (long)in->batch * p.max_tracers * p.n_bands;
   hipLaunchKernelGGL((k_forward_fft<R, M>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in);
-  if (p.rsd) hipLaunchKernelGGL((k_forward_fft<R, M, true>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in);
+  if (p.rsd) hipLaunchKernelGGL((k_forward_fft<R, M, 1>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in);
+  if (p.mag && in->mag)
+    hipLaunchKernelGGL((k_forward_fft<R, M, 2>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in);
   return hipGetLastError();
 }
 
@@ -381,7 +385,8 @@ bool unfused_tw_lds(int M) { return unfused_tw(M); }
 // workspace, k_contract forms the 32 x 32 Gram matrix from three 16 x 16 MFMA tile pairs
 // (0,0), (0,1), (1,1).  Points are processed in chunks of P.vchunk.
 // ---------------------------------------------------------------------------------------------
-template <int M, int NW, bool TW_LDS, bool SPLIT, bool RSD>
+// EXTRA bit 1: the plan carries RSD, bit 2: magnification (used when the inputs give C_g)
+template <int M, int NW, bool TW_LDS, bool SPLIT, int EXTRA>
 __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
   extern __shared__ __align__(16) unsigned char smem[];
   typedef float R;
@@ -445,7 +450,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
       const int n = lane + SWIFTCL_WAVE * e;
       v[e] = cconj(cmul(ch[n], Ur[n]));
     }
-    if (RSD && kind == SWIFTCL_CLUSTERING) {
+    if ((EXTRA & 1) && kind == SWIFTCL_CLUSTERING) {
       // the RSD window of a clustering tracer shares its prefactor and k scale: add its term
       const C2<R>* chr = (const C2<R>*)P.chat_r + (((size_t)b * T + t) * nb + band) * M;
       const C2<R>* URr = (const C2<R>*)P.UR + (size_t)ei * M;
@@ -453,6 +458,16 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
       for (int e = 0; e < RL; ++e) {
         const int n = lane + SWIFTCL_WAVE * e;
         v[e] = cadd(v[e], cconj(cmul(chr[n], URr[n])));
+      }
+    }
+    if ((EXTRA & 2) && in.mag && kind == SWIFTCL_CLUSTERING) {
+      // magnification: l(l+1) U at the bias b - 2 shares the density window's k scale
+      const C2<R>* chm = (const C2<R>*)P.chat_mu + (((size_t)b * T + t) * nb + band) * M;
+      const C2<R>* Umr = (const C2<R>*)P.Umu + (size_t)ei * M;
+#pragma unroll
+      for (int e = 0; e < RL; ++e) {
+        const int n = lane + SWIFTCL_WAVE * e;
+        v[e] = cadd(v[e], cconj(cmul(chm[n], Umr[n])));
       }
     }
     int ln = lane;  // opaque copy: keeps the FFT's per-lane LDS addresses out of the tracer loop
@@ -594,13 +609,14 @@ static hipError_t launch_unfused(const plan_dev& p, const swiftcl_inputs* in, vo
     const int nbp = in->batch - b0 < p.vchunk ? in->batch - b0 : p.vchunk;
     const size_t groups = (size_t)(nbp + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
     const dim3 g1((unsigned)(groups * p.max_ell * SWIFTCL_NXCD));
-    if (p.rsd) {
-      if (split) hipLaunchKernelGGL((k_windows_v<M, NW, TW, true, true>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
-      else hipLaunchKernelGGL((k_windows_v<M, NW, TW, false, true>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
-    } else {
-      if (split) hipLaunchKernelGGL((k_windows_v<M, NW, TW, true, false>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
-      else hipLaunchKernelGGL((k_windows_v<M, NW, TW, false, false>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp);
+#define SWIFTCL_WV(SP, EX) hipLaunchKernelGGL((k_windows_v<M, NW, TW, SP, EX>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp)
+    switch ((p.rsd ? 1 : 0) | (p.mag ? 2 : 0)) {
+      case 0: if (split) SWIFTCL_WV(true, 0); else SWIFTCL_WV(false, 0); break;
+      case 1: if (split) SWIFTCL_WV(true, 1); else SWIFTCL_WV(false, 1); break;
+      case 2: if (split) SWIFTCL_WV(true, 2); else SWIFTCL_WV(false, 2); break;
+      default: if (split) SWIFTCL_WV(true, 3); else SWIFTCL_WV(false, 3); break;
     }
+#undef SWIFTCL_WV
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 g2((unsigned)((size_t)nbp * p.max_ell));

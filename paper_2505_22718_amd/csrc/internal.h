@@ -94,6 +94,12 @@ struct plan_dev {
   void* UR;           // [n_ell][M] complex: sum_s a_s(l) U_s(n) over s = l-2, l, l+2 (clustering bias)
   void* g_r;          // [B][T][n_bands][N] real: tilted, edge-weighted RSD kernel samples
   void* chat_r;       // [B][T][n_bands][M] complex: their FFTLog coefficients
+  // magnification bias of the clustering tracers: a lensing-type kernel decomposed with the bias
+  // b - 2, so that its l(l+1)/k^2 window shares the density window's k scale
+  int mag;
+  void* Umu;          // [n_ell][M] complex: l(l+1) U_l(n) at the bias b - 2 of the clustering band
+  void* g_mu;         // [B][T][n_bands][N] real: tilted, edge-weighted C_g q D / chi^2 samples
+  void* chat_mu;      // [B][T][n_bands][M] complex: their FFTLog coefficients
   int kg_ntile;       // slot tiles per (point, tracer): ceil(max_ell / 64) + n_bands
   double* kg_ones;    // [max_batch][n_zg] ones: the assembly's D(z) while growth sits at the nodes
   int* kg_ia;         // [n_k] node interval a_j of k_j

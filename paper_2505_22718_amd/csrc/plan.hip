@@ -158,6 +158,31 @@ __global__ void k_u_rsd(C2<R>* __restrict__ UR, const double* __restrict__ ell, 
   UR[(size_t)li * M + n] = v;
 }
 
+// Magnification (eq. magnification bias): l(l+1) U_l(n) at the bias b - 2 of the clustering band, so
+// that with the clustering k scale k^{-1-b} the window carries l(l+1) k^{-2} k^{-1-(b-2)-i eta}.
+template <typename R>
+__global__ void k_u_mag(C2<R>* __restrict__ Um, const double* __restrict__ ell, const int* __restrict__ band,
+                        double b0, double b1, double b2, double b3, int n_ell, int M, double delta, double taper_frac) {
+  const int li = blockIdx.x;
+  const int n = blockIdx.y * blockDim.x + threadIdx.x;
+  if (li >= n_ell || n >= M) return;
+  const double l = ell[li];
+  const double bclus[4] = {b0, b1, b2, b3};
+  const double b = bclus[band[li]] - 2.0;
+  const double eta = 2.0 * M_PI * (double)n / (2.0 * M * delta);
+  double tap = 1.0;
+  if (taper_frac > 0.0) {
+    double x = (double)n / (double)M, x0 = 1.0 - taper_frac;
+    if (x > x0) tap = 0.5 * (1.0 + cos(M_PI * fmin((x - x0) / taper_frac, 1.0)));
+  }
+  const zd u = u_value(l, b, eta);
+  const double f = l * (l + 1.0) * tap;
+  C2<R> v;
+  v.x = (R)(f * u.x);
+  v.y = (R)(n == 0 ? 0.0 : f * u.y);
+  Um[(size_t)li * M + n] = v;
+}
+
 hipError_t launch_u_table(const plan_dev& pd, const double* d_ell, hipStream_t s) {
   const plan_dev* p = &pd;
   dim3 grid(p->n_ell, (p->M + 127) / 128);
@@ -169,8 +194,11 @@ hipError_t launch_u_table(const plan_dev& pd, const double* d_ell, hipStream_t s
   else
     hipLaunchKernelGGL(k_u_table<float>, grid, dim3(128), 0, s, (float2*)p->U, d_ell, p->ell_band, b[0], b[1],
                        b[2], b[3], c[0], c[1], c[2], c[3], p->n_ell, p->M, p->delta, p->taper_frac);
-  if (p->rsd)  // RSD plans are FP32 / split
+  if (p->rsd)  // RSD and magnification plans are FP32 / split
     hipLaunchKernelGGL(k_u_rsd<float>, grid, dim3(128), 0, s, (float2*)p->UR, d_ell, p->ell_band, b[0], b[1], b[2],
+                       b[3], p->n_ell, p->M, p->delta, p->taper_frac);
+  if (p->mag)
+    hipLaunchKernelGGL(k_u_mag<float>, grid, dim3(128), 0, s, (float2*)p->Umu, d_ell, p->ell_band, b[0], b[1], b[2],
                        b[3], p->n_ell, p->M, p->delta, p->taper_frac);
   return hipGetLastError();
 }
@@ -248,6 +276,11 @@ static swiftcl_status validate_desc(const swiftcl_plan_desc* d) {
   if (d->max_tracers > 32) { set_error("max_tracers > 32 is not built"); return SWIFTCL_E_UNSUPPORTED; }
   if (d->precision < 0 || d->precision > 2) { set_error("unknown precision"); return SWIFTCL_E_INVALID; }
   if (d->rsd != 0 && d->rsd != 1) { set_error("rsd must be 0 or 1"); return SWIFTCL_E_INVALID; }
+  if (d->magnification != 0 && d->magnification != 1) { set_error("magnification must be 0 or 1"); return SWIFTCL_E_INVALID; }
+  if (d->magnification && d->precision == SWIFTCL_FP64) {
+    set_error("magnification bias is built for FP32 and split precision");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
   if (d->rsd && d->precision == SWIFTCL_FP64) {
     set_error("redshift-space distortions are built for FP32 and split precision");
     return SWIFTCL_E_UNSUPPORTED;
@@ -298,7 +331,7 @@ static void free_plan(swiftcl_plan_s* p) {
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_ia, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
                   p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf,
                   p->d.kg_ones, p->d.kg_ia, p->d.kg_w, p->d.kg_ip, p->d.kg_uh, p->d.kg_c, p->d.kg_m, p->d.kg_perm,
-                  p->d.kg_tile, p->d.UR, p->d.g_r, p->d.chat_r};
+                  p->d.kg_tile, p->d.UR, p->d.g_r, p->d.chat_r, p->d.Umu, p->d.g_mu, p->d.chat_mu};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -321,7 +354,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     const int M = d->n_chi / 2;
     const size_t need = windows_cl_lds(M, windows_nw(d->precision), windows_tw_lds(d->precision, M), true,
                                        dp ? 8 : 4, d->n_k);
-    fused = d->max_tracers <= 16 && need <= (size_t)lds_max && !d->rsd;
+    fused = d->max_tracers <= 16 && need <= (size_t)lds_max && !d->rsd && !d->magnification;
     if (!fused && dp) {
       set_error("the FP64 path keeps the windows of <= 16 tracers in LDS; this n_chi / n_k / max_tracers needs " +
                 std::to_string(need) + " bytes per workgroup, the device has " + std::to_string(lds_max));
@@ -369,6 +402,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   p->d.m0 = d->edge_node > 0 ? d->edge_node : default_edge_node(d->n_chi, p->d.delta);
   p->d.fused = fused ? 1 : 0;
   p->d.rsd = d->rsd;
+  p->d.mag = d->magnification;
   p->d.adjoint = (fused && d->precision != SWIFTCL_SPLIT_BF16 &&
                   bwd_windows_lds(p->d) + 4096 <= (size_t)lds_max)  // + the kernel's static LDS
                      ? 1 : 0;
@@ -497,6 +531,11 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   if (fused && d->precision != SWIFTCL_SPLIT_BF16) ALLOC(ddD_part, double, (size_t)B * T * 2 * p->d.n_zg);
   ALLOC(g, char, (size_t)B * T * nb * N * rs);
   ALLOC(chat, char, (size_t)B * T * nb * M * 2 * rs);
+  if (p->d.mag) {
+    ALLOC(Umu, char, (size_t)p->d.n_ell * M * 2 * rs);
+    ALLOC(g_mu, char, (size_t)B * T * nb * N * rs);
+    ALLOC(chat_mu, char, (size_t)B * T * nb * M * 2 * rs);
+  }
   if (p->d.rsd) {
     ALLOC(UR, char, (size_t)p->d.n_ell * M * 2 * rs);
     ALLOC(g_r, char, (size_t)B * T * nb * N * rs);
@@ -654,6 +693,7 @@ extern "C" swiftcl_status swiftcl_device_flags(swiftcl_plan_t p, void* stream, i
 static swiftcl_status check_inputs(swiftcl_plan_t p, const swiftcl_inputs* in) {
   if (!p) { set_error("plan is NULL"); return SWIFTCL_E_INVALID; }
   if (!in) { set_error("inputs is NULL"); return SWIFTCL_E_INVALID; }
+  if (in->mag && !p->d.mag) { set_error("inputs carry magnification; build the plan with magnification = 1"); return SWIFTCL_E_INVALID; }
   if (in->batch < 1 || in->batch > p->d.max_batch) { set_error("batch outside 1..max_batch"); return SWIFTCL_E_INVALID; }
   const void* req[] = {in->n_tracers, in->kind, in->n_ell, in->ell_idx, in->chi_z, in->D_z,
                        in->omega_m, in->nz, in->bias, in->pk};
@@ -672,7 +712,7 @@ static void note_forward(swiftcl_plan_t p, const swiftcl_inputs* in) {
 static bool same_inputs(const swiftcl_inputs& a, const swiftcl_inputs& b) {
   return a.batch == b.batch && a.n_tracers == b.n_tracers && a.kind == b.kind && a.n_ell == b.n_ell &&
          a.ell_idx == b.ell_idx && a.chi_z == b.chi_z && a.D_z == b.D_z && a.omega_m == b.omega_m && a.nz == b.nz &&
-         a.bias == b.bias && a.pk == b.pk && a.ia == b.ia;
+         a.bias == b.bias && a.pk == b.pk && a.ia == b.ia && a.mag == b.mag;
 }
 
 static swiftcl_status run_forward(swiftcl_plan_t p, const swiftcl_inputs* in, void* W, void* C, void* stream) {
@@ -692,8 +732,8 @@ static swiftcl_status run_forward(swiftcl_plan_t p, const swiftcl_inputs* in, vo
 
 extern "C" swiftcl_status swiftcl_windows(swiftcl_plan_t p, const swiftcl_inputs* in, void* W, void* stream) {
   if (!W) { set_error("W is NULL"); return SWIFTCL_E_INVALID; }
-  if (p && p->d.rsd) {
-    set_error("windows output is not built with redshift-space distortions (C_l is)");
+  if (p && (p->d.rsd || p->d.mag)) {
+    set_error("windows output is not built with redshift-space distortions or magnification (C_l is)");
     return SWIFTCL_E_UNSUPPORTED;
   }
   return run_forward(p, in, W, nullptr, stream);
@@ -740,8 +780,8 @@ extern "C" swiftcl_status swiftcl_cl_kgrowth(swiftcl_plan_t p, const swiftcl_inp
     set_error("the plan has no interpolation nodes in k (n_interp = 0)");
     return SWIFTCL_E_INVALID;
   }
-  if (p->d.rsd) {
-    set_error("scale-dependent growth is not built with redshift-space distortions");
+  if (p->d.rsd || p->d.mag) {
+    set_error("scale-dependent growth is not built with redshift-space distortions or magnification");
     return SWIFTCL_E_UNSUPPORTED;
   }
   // the kernels are assembled without growth (D = 1); growth enters per node
@@ -763,8 +803,8 @@ extern "C" swiftcl_status swiftcl_cl_limber(swiftcl_plan_t p, const swiftcl_inpu
   swiftcl_status st = check_inputs(p, in);
   if (st != SWIFTCL_OK) return st;
   if (!C) { set_error("C is NULL"); return SWIFTCL_E_INVALID; }
-  if (p->d.rsd) {
-    set_error("the Limber path does not include redshift-space distortions");
+  if (p->d.rsd || p->d.mag) {
+    set_error("the Limber path does not include redshift-space distortions or magnification");
     return SWIFTCL_E_UNSUPPORTED;
   }
   if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
@@ -785,7 +825,7 @@ static swiftcl_status backward_checks(swiftcl_plan_t p, const swiftcl_inputs* in
   if (flags & ~(uint32_t)SWIFTCL_BWD_REUSE_FORWARD) { set_error("unknown backward flag"); return SWIFTCL_E_INVALID; }
   if (!p->d.adjoint) {
     set_error("the adjoint is built for plans whose windows fit in LDS (<= 16 tracers) in FP32 or FP64, "
-              "without redshift-space distortions");
+              "without redshift-space distortions or magnification");
     return SWIFTCL_E_UNSUPPORTED;
   }
   *reuse = (flags & SWIFTCL_BWD_REUSE_FORWARD) != 0;

@@ -41,7 +41,7 @@ class Plan:
 
     def __init__(self, k, ell, z_geom, z_nz, n_chi, max_batch, max_tracers, max_ell, precision="fp32",
                  band_ell_lo=DEFAULT_BAND_ELL_LO, fftlog_b=DEFAULT_FFTLOG_B, taper_frac=0.0, edge_node=0,
-                 device=0, n_interp=0, rsd=False):
+                 device=0, n_interp=0, rsd=False, magnification=False):
         self.k = _f64(k)
         self.ell = _f64(ell)
         self.z_geom = _f64(z_geom)
@@ -72,6 +72,8 @@ class Plan:
         self.n_interp = int(n_interp)
         d.rsd = 1 if rsd else 0
         self.rsd = bool(rsd)
+        d.magnification = 1 if magnification else 0
+        self.magnification = bool(magnification)
         self.desc = d
         self.out_dtype = torch.float64 if precision == "fp64" else torch.float32
         with torch.cuda.device(self.device):
@@ -117,6 +119,8 @@ class Plan:
             setattr(s, name, t[name].data_ptr())
         ia = t.get("ia")  # NLA amplitude A_IA(z) of the lensing tracers, optional
         s.ia = ia.data_ptr() if ia is not None else None
+        mag = t.get("mag")  # lensing-bias coefficients C_g of the clustering tracers, optional
+        s.mag = mag.data_ptr() if mag is not None else None
         return s
 
     # Every call that (re)computes the workspace's forward state sets a fresh token; autograd keeps
@@ -246,4 +250,6 @@ def device_inputs(wl, device="cuda:0", points=None):
     }
     if wl.get("ia") is not None:
         out["ia"] = f(wl["ia"], torch.float64)
+    if wl.get("mag") is not None:
+        out["mag"] = f(wl["mag"], torch.float64)
     return out

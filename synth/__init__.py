@@ -116,6 +116,20 @@ def intrinsic_alignment(wl, a1=0.5):
     return wl
 
 
+def magnification_bias(wl):
+    """Add the lensing-bias coefficient C_g = 5 s - 2 of the clustering tracers (eq. magnification
+    bias), with a number-count slope s rising from 0.2 to 0.6 over the bins in order: wl["mag"]
+    [B, T], zero for lensing tracers.  Returns wl."""
+    kinds = np.asarray(wl["kind"])
+    mag = np.zeros(kinds.shape)
+    for b in range(kinds.shape[0]):
+        cl = np.nonzero(kinds[b] == KIND_CLUSTERING)[0]
+        s = np.linspace(0.2, 0.6, max(len(cl), 1))[:len(cl)]
+        mag[b, cl] = 5.0 * s - 2.0
+    wl["mag"] = mag
+    return wl
+
+
 def bbks_transfer(q):
     """BBKS fitting form (Bardeen, Bond, Kaiser & Szalay 1986, eq. G3), q = k / Gamma."""
     q = np.asarray(q, float)

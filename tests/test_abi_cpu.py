@@ -86,6 +86,7 @@ def _desc(**over):
     (dict(n_interp=16), -5),                                 # scale-dependent growth in FP64
     (dict(rsd=1), -5),                                       # RSD in FP64
     (dict(rsd=2), -1),
+    (dict(magnification=1), -5),                             # magnification in FP64
 ])
 def test_plan_rejects_bad_descriptor(lib, over, code):
     d, keep = _desc(**over)

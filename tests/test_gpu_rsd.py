@@ -83,3 +83,42 @@ def test_rsd_refused_where_not_built(dev):
         with pytest.raises(bd.SwiftclError) as ei:
             call()
         assert ei.value.status == bd.SWIFTCL_E_UNSUPPORTED
+
+
+# --- magnification bias (eq. magnification bias) -----------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol,rsd", [("fp32", 1e-4, False), ("split_bf16", 1e-3, False),
+                                               ("fp32", 1e-4, True)])
+def test_magnification_parity(dev, precision, tol, rsd):
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    wl = synth.magnification_bias(_wl())
+    wl["rsd"] = rsd
+    _say(f"magnification cfg1 {precision}, rsd={rsd}")
+    p = Plan.for_workload(wl, precision=precision, rsd=rsd, magnification=True)
+    C = p.cl(device_inputs(wl, dev)).cpu().numpy()[0].astype(np.float64)
+    assert p.device_flags() == 0
+    e = eps_metric(full_from_packed(C, 15), full_from_packed(fftlog.cl(wl, 0), 15))
+    _say(f"  max eps {e.max():.3e}")
+    assert e.max() < tol
+    # the term is on: clustering x lensing spectra move away from the magnification-free oracle
+    C0 = fftlog.cl(dict(wl, mag=None), 0)
+    assert np.max(np.abs(C[0] - C0[0]) / np.max(np.abs(C0[0]))) > 1e-3
+
+
+def test_magnification_plan_without_inputs_and_inputs_without_plan(dev):
+    from paper_2505_22718_amd import binding as bd
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    wl = synth.magnification_bias(_wl())
+    wl["rsd"] = False
+    t = device_inputs(wl, dev)
+    # a magnification plan called without C_g: no magnification term
+    p = Plan.for_workload(wl, magnification=True)
+    t0 = {k: v for k, v in t.items() if k != "mag"}
+    C = p.cl(t0).cpu().numpy()[0].astype(np.float64)
+    e = eps_metric(full_from_packed(C, 15), full_from_packed(fftlog.cl(dict(wl, mag=None), 0), 15))
+    assert e.max() < 1e-4
+    # C_g given to a plan built without magnification
+    q = Plan.for_workload(wl)
+    with pytest.raises(bd.SwiftclError) as ei:
+        q.cl(t)
+    assert ei.value.status == bd.SWIFTCL_E_INVALID
