@@ -16,6 +16,9 @@ Modules
   gradients   exact / directional derivatives of C_l for the adjoint tests
   kgrowth     scale-dependent growth D(k, z) (Sec. 3.2): coefficients at N_interp
               k nodes, continued along ln k by a natural cubic spline
+The optional terms of Sec. 2.2-2.3 (intrinsic alignment, RSD, magnification bias) live in
+geometry (their radial kernels), fftlog (their FFTLog windows) and quadrature (the same windows
+by direct integration, j_l'' from the Bessel equation).
 
 Readings of the paper that the oracle fixes are listed in each function's
 docstring; every one is shared, by statement and not by code, with the HIP
