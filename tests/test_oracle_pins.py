@@ -147,6 +147,41 @@ def test_method_floor_cfg1_magnification():
     assert eps.max() < 6e-5
 
 
+def test_growth_rate_matches_closed_form(wl1):
+    """f = dln D/dln a from the D(z) spline (the RSD kernel's growth rate) against the closed form of
+    the LCDM growth integral D ~ E(a) int_0^a da' / (a' E)^3:  f = -3/2 Omega_m(a) + 1 / (a^2 E^3 I(a))."""
+    geo = geometry.point_geometry(wl1, 0)
+    om = float(wl1["omega_m"][0])
+    z = np.array([0.1, 0.5, 1.0, 2.0, 2.9])
+    a = 1.0 / (1.0 + z)
+    E = synth.e_of_z(z, om)
+    I = np.array([integrate.quad(lambda x: 1.0 / (x * synth.e_of_z(1.0 / x - 1.0, om)) ** 3, 1e-8, ai,
+                                 epsabs=0, epsrel=1e-12)[0] for ai in a])
+    f_exact = -1.5 * om * (1.0 + z) ** 3 / E ** 2 + 1.0 / (a ** 2 * E ** 3 * I)
+    assert np.max(np.abs(geo.growth_rate(z) / f_exact - 1.0)) < 1e-6
+
+
+def test_magnification_window_is_the_scaled_lensing_window(wl1):
+    """A clustering tracer with C_g = 1 gains l(l+1)/k^2 int q D / chi^2 j_l: the lensing window of
+    the same n(z) times l(l+1)/F(l).  Where b - 2 equals the lensing bias (band 2) the two are the
+    same numbers; in bands 0 and 1 they differ by the method error of the two biases."""
+    m = fftlog.method_for(wl1)
+    nz = wl1["nz"][0, [3, 3]]
+    args = (wl1["z_geom"], wl1["chi_z"][0], wl1["D_z"][0], wl1["omega_m"][0], wl1["z_nz"], nz,
+            np.array([0, 1]), np.array([1.0, 1.0]))
+    with_mag = geometry.PointGeometry(*args, mag=np.array([1.0, 0.0]))
+    plain = geometry.PointGeometry(*args)
+    ells = fftlog.point_ells(wl1, 0)[[0, 5, 9, 20, 50, 102]]
+    W1 = fftlog.windows_point(with_mag, ells, m)
+    W0 = fftlog.windows_point(plain, ells, m)
+    F = np.sqrt((ells + 2) * (ells + 1) * ells * (ells - 1))
+    ref = (ells * (ells + 1) / F)[:, None] * W0[:, 1]
+    rel = np.max(np.abs((W1[:, 0] - W0[:, 0]) - ref), axis=1) / np.max(np.abs(ref), axis=1)
+    band2 = np.array([m.band(l) == 2 for l in ells])
+    assert rel[band2].max() < 1e-12
+    assert rel[~band2].max() < 5e-5
+
+
 def test_planted_edge_weight_mistake_is_caught(wl1, monkeypatch):
     """Dropping the half weight of the lower support edge must break the floor pin."""
     real = fftlog.sampled_kernels
