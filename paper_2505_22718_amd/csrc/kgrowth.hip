@@ -66,9 +66,9 @@ __global__ void k_kg_slots(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
   for (; nt < P.kg_ntile; ++nt) tile[nt] = make_int4(0, 0, 0, 0);
 }
 
-// One workgroup (4 wavefronts) per (point, node).  Dynamic LDS: twiddles [2M], FFT scratch
-// [4][fft_lds_size], growth on the chi nodes [2M] float, D(kappa_a, z) samples and their spline
-// moments [2][n_zg] double.
+// One workgroup (4 wavefronts) per (point, node).  Dynamic LDS: twiddles [2M], growth on the chi
+// nodes [2M] float, then the D(kappa_a, z) samples and their spline moments [2][n_zg] double, which
+// are dead once the growth is sampled and share their space with the FFT scratch [4][fft_lds_size].
 template <int M>
 __global__ __launch_bounds__(256) void k_kg_fft(plan_dev P, swiftcl_inputs in, const double* __restrict__ Dkz,
                                                 int b0, int nbp) {
@@ -78,9 +78,9 @@ __global__ __launch_bounds__(256) void k_kg_fft(plan_dev P, swiftcl_inputs in, c
   constexpr int RL = M / SWIFTCL_WAVE;
   constexpr int FL = fft_lds_size(M, sizeof(R));
   C2<R>* stw = (C2<R>*)smem;
-  C2<R>* fbuf = stw + N;
-  float* Dk = (float*)(fbuf + 4 * FL);
-  double* y = (double*)(Dk + N);
+  float* Dk = (float*)(stw + N);
+  C2<R>* fbuf = (C2<R>*)(Dk + N);
+  double* y = (double*)(Dk + N);  // same space as fbuf
   const int nzg = P.n_zg;
   double* Mo = y + nzg;
   const int A = P.n_interp;
@@ -162,23 +162,41 @@ __global__ __launch_bounds__(256) void k_kg_cspline(plan_dev P, swiftcl_inputs i
   float2* m = (float2*)P.kg_m + (size_t)row * A * M + n;
   m[0] = make_float2(0.f, 0.f);
   m[(size_t)(A - 1) * M] = make_float2(0.f, 0.f);
+  // each recurrence step waits on one load: the loads of KG_PF steps are issued together
+  constexpr int KG_PF = 8;
   float2 cm = c[0], c0 = c[(size_t)M];
   float2 d = make_float2(0.f, 0.f);
-  for (int a = 1; a + 1 < A; ++a) {
-    const float2 cp = c[(size_t)(a + 1) * M];
-    const float ip = P.kg_ip[a];
-    d.x = (s6 * (cp.x - 2.f * c0.x + cm.x) - d.x) * ip;
-    d.y = (s6 * (cp.y - 2.f * c0.y + cm.y) - d.y) * ip;
-    m[(size_t)a * M] = d;
-    cm = c0;
-    c0 = cp;
+  for (int a0 = 1; a0 + 1 < A; a0 += KG_PF) {
+    float2 cps[KG_PF];
+#pragma unroll
+    for (int i = 0; i < KG_PF; ++i)
+      cps[i] = a0 + i + 1 < A ? c[(size_t)(a0 + i + 1) * M] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < KG_PF; ++i) {
+      const int a = a0 + i;
+      if (a + 1 >= A) break;
+      const float2 cp = cps[i];
+      const float ip = P.kg_ip[a];
+      d.x = (s6 * (cp.x - 2.f * c0.x + cm.x) - d.x) * ip;
+      d.y = (s6 * (cp.y - 2.f * c0.y + cm.y) - d.y) * ip;
+      m[(size_t)a * M] = d;
+      cm = c0;
+      c0 = cp;
+    }
   }
   float2 mn = make_float2(0.f, 0.f);
-  for (int a = A - 2; a >= 1; --a) {
-    const float2 da = m[(size_t)a * M];
-    const float ip = P.kg_ip[a];
-    mn = make_float2(da.x - ip * mn.x, da.y - ip * mn.y);
-    m[(size_t)a * M] = mn;
+  for (int a0 = A - 2; a0 >= 1; a0 -= KG_PF) {
+    float2 ds[KG_PF];
+#pragma unroll
+    for (int i = 0; i < KG_PF; ++i) ds[i] = a0 - i >= 1 ? m[(size_t)(a0 - i) * M] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < KG_PF; ++i) {
+      const int a = a0 - i;
+      if (a < 1) break;
+      const float ip = P.kg_ip[a];
+      mn = make_float2(ds[i].x - ip * mn.x, ds[i].y - ip * mn.y);
+      m[(size_t)a * M] = mn;
+    }
   }
 }
 
@@ -368,8 +386,9 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
 
 template <int M>
 size_t kg_fft_lds(int n_zg) {
-  return sizeof(float2) * (size_t)(2 * M + 4 * fft_lds_size(M, sizeof(float))) + sizeof(float) * 2 * M +
-         sizeof(double) * 2 * (size_t)n_zg;
+  const size_t fft = sizeof(float2) * 4 * (size_t)fft_lds_size(M, sizeof(float));
+  const size_t spl = sizeof(double) * 2 * (size_t)n_zg;
+  return sizeof(float2) * 2 * (size_t)M + sizeof(float) * 2 * M + (fft > spl ? fft : spl);
 }
 
 template <int M>
