@@ -1,0 +1,29 @@
+"""Host-side contract of bench.py (no GPU): one GPU only, and the HBM-traffic record of the dominant
+kernel is reported only while its sources are the ones the counters were taken on."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_traffic_record_matches_the_committed_sources():
+    got = bench.traffic_bytes()
+    assert got is not None and got > 0
+    # the algorithmic traffic of one launch is ~157 MB; the record must be of that order
+    assert 1.0e8 < got < 3.0e8
+
+
+def test_traffic_record_is_dropped_when_the_sources_change(monkeypatch):
+    monkeypatch.setattr(bench, "sources_digest", lambda: "0" * 64)
+    assert bench.traffic_bytes() is None
