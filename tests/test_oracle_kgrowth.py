@@ -43,6 +43,14 @@ def test_scale_free_growth_is_fftlog(wl1s):
     assert _eps(kgrowth.cl(wl, 0, m), fftlog.cl(wl, 0, m)) < 1e-12
 
 
+def test_scale_free_growth_is_fftlog_with_intrinsic_alignment(wl1s):
+    """The node geometries carry the NLA term of the lensing tracers like the scale-free one."""
+    wl = synth.intrinsic_alignment(dict(wl1s))
+    wl["D_kz"] = np.repeat(wl["D_z"][:, None, :], 4, 1)
+    m = fftlog.method_for(wl)
+    assert _eps(kgrowth.cl(wl, 0, m), fftlog.cl(wl, 0, m)) < 1e-12
+
+
 def test_growth_linear_in_ln_k_rescales_pk(wl1s):
     wl = dict(wl1s)
     m = fftlog.method_for(wl)
