@@ -140,6 +140,10 @@ class Plan:
     def cl_kgrowth(self, t, D_kz, out=None):
         """C_l with scale-dependent growth: D_kz [B][n_interp][n_zg] float64 on the plan's device."""
         B = t["n_tracers"].shape[0]
+        want = (B, self.n_interp, len(self.z_geom))
+        if (tuple(D_kz.shape) != want or D_kz.dtype != torch.float64 or not D_kz.is_contiguous()
+                or D_kz.device != self.device):
+            raise ValueError(f"D_kz must be a contiguous float64 tensor of shape {want} on {self.device}")
         if out is None:
             out = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
         self._new_state()
