@@ -112,3 +112,47 @@ def test_null_arguments_rejected(lib):
     assert lib.swiftcl_cl_kgrowth(None, ctypes.byref(inp), None, None, None) == bd.SWIFTCL_E_INVALID
     assert lib.swiftcl_cl_limber(None, ctypes.byref(inp), None, None) == bd.SWIFTCL_E_INVALID
     assert lib.swiftcl_plan_destroy(None) == bd.SWIFTCL_E_INVALID
+
+
+def _header_fields(struct):
+    """Field names of a typedef'd struct in include/swiftcl.h, in order (array fields by name)."""
+    text = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                             "include", "swiftcl.h")).read()
+    text = re.sub(r"//[^\n]*", "", re.sub(r"/\*.*?\*/", "", text, flags=re.S))
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + struct + r"\s*;", text).group(1)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            names.append(re.match(r".*?(\w+)\s*(\[[^\]]*\])*\s*$", decl, flags=re.S).group(1))
+    return names
+
+
+@pytest.mark.parametrize("struct", ["swiftcl_plan_desc", "swiftcl_inputs"])
+def test_binding_structs_match_the_header(struct):
+    from paper_2505_22718_amd import binding as bd
+    got = [name for name, _ in getattr(bd, struct)._fields_]
+    assert got == _header_fields(struct)
+
+
+@pytest.mark.parametrize("struct", ["swiftcl_plan_desc", "swiftcl_inputs"])
+def test_binding_struct_offsets_match_a_c_compiler(struct, tmp_path):
+    """sizeof and every field's offsetof as gcc lays the header's struct out, against ctypes."""
+    import shutil
+    import subprocess
+    from paper_2505_22718_amd import binding as bd
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    cls = getattr(bd, struct)
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ['#include "swiftcl.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {name}));' for name, _ in cls._fields_]
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(cls)] + [getattr(cls, name).offset for name, _ in cls._fields_]
+    assert got == want
