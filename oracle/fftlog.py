@@ -37,10 +37,11 @@ from scipy.special import loggamma
 from .geometry import PointGeometry, ell_prefactor, point_geometry
 
 # Default FFTLog bias bands: band boundaries in l and, per tracer kind, the b of
-# each band (kind 0 clustering, kind 1 lensing).  Chosen by measuring the
-# method error against direct quadrature on the 15-tracer workload.
+# each band (kind 0 clustering, kind 1 lensing, kind 2 CMB lensing).  Chosen by
+# measuring the method error against direct quadrature on the 15-tracer workload
+# (and that workload with a CMB-lensing tracer for the third row).
 DEFAULT_BAND_ELL_LO = (0.0, 3.0, 6.0)
-DEFAULT_FFTLOG_B = ((0.1, -0.2, -0.5), (-1.5, -2.0, -2.5))
+DEFAULT_FFTLOG_B = ((0.1, -0.2, -0.5), (-1.5, -2.0, -2.5), (-1.0, -1.0, -2.0))
 
 
 class Method:
@@ -61,7 +62,10 @@ class Method:
         return int(np.searchsorted(self.band_ell_lo, ell, side="right") - 1)
 
     def b_of(self, kind, ell):
-        return self.fftlog_b[kind][self.band(ell)]
+        """Bias b of a tracer kind at multipole l.  A table with two rows gives CMB lensing (kind 2) the
+        lensing row: its kernel has the lensing 1/chi behaviour at small chi."""
+        row = self.fftlog_b[kind] if kind < len(self.fftlog_b) else self.fftlog_b[1]
+        return row[self.band(ell)]
 
 
 def default_edge_node(n_chi, delta, support_efolds=5.0):
@@ -161,7 +165,7 @@ def windows_point(geo: PointGeometry, ells, method: Method, rsd=False):
     k = method.k
     N = method.n_chi
     for li, ell in enumerate(ells):
-        for kind in (0, 1):
+        for kind in (0, 1, 2):
             ts = np.nonzero(geo.kinds == kind)[0]
             if len(ts) == 0:
                 continue

@@ -9,13 +9,19 @@ Paper, Sec. 2.2 (galaxy clustering) and Sec. 2.3 (weak lensing):
                (eq. tomographic lens efficiency).  Written in z:
                q(chi) = 1.5 Om (H0/c)^2 chi (1+z) int_z^{z_max} dz' n(z') (1 - chi/chi(z')).
                The radial kernel is f = q D / chi^2 and c(l, k) = F(l) / k^2.
+  CMB lensing  (Sec. 2.4) Delta_l^{CMB,kappa}(k) = l(l+1) (3 Om H0^2 / 2 c^2 k^2)
+               int_0^{chi_*} dchi a^-1 (chi_* - chi) / (chi chi_*) D j_l(k chi): the lensing kernel
+               of one source plane at chi_*, f = 1.5 Om (H0/c)^2 (1+z) (chi_* - chi) / (chi chi_*) D,
+               with the convergence prefactor c(l, k) = l(l+1) / k^2 in place of F(l) / k^2.
 
 Readings (the paper does not fix them):
   * every sampled input is continued by a natural cubic spline; n(z) is zero
     outside its sample range;
   * z(chi) is the inverse of the chi(z) spline, dz/dchi = 1 / (chi spline)';
   * the kernels are supported on [chi(z_min), chi(z_max)] of the geometry grid;
-  * D(k, z) = D(z), z_fid = 0 (linear growth).
+  * D(k, z) = D(z), z_fid = 0 (linear growth);
+  * the last-scattering surface z_* of a CMB-lensing tracer is given with the geometry, by default
+    the top of its grid; the kernel is zero above it.
 """
 from __future__ import annotations
 
@@ -23,13 +29,14 @@ import numpy as np
 from scipy.interpolate import CubicSpline
 
 H0_OVER_C = 1.0 / 2997.92458  # h/Mpc
+KIND_CLUSTERING, KIND_LENSING, KIND_CMB_LENSING = 0, 1, 2
 _GL = np.polynomial.legendre.leggauss(12)
 
 
 class PointGeometry:
     """Continuous geometry, growth and redshift distributions of one parameter point."""
 
-    def __init__(self, z_geom, chi_z, D_z, omega_m, z_nz, nz, kinds, bias, ia=None, mag=None):
+    def __init__(self, z_geom, chi_z, D_z, omega_m, z_nz, nz, kinds, bias, ia=None, mag=None, z_star=None):
         self.z_geom = np.asarray(z_geom, float)
         self.z_nz = np.asarray(z_nz, float)
         self.chi_spl = CubicSpline(self.z_geom, chi_z, bc_type="natural")
@@ -46,6 +53,11 @@ class PointGeometry:
         self.z_min, self.z_max = self.z_geom[0], self.z_geom[-1]
         self.chi_min = float(self.chi_spl(self.z_min))
         self.chi_max = float(self.chi_spl(self.z_max))
+        # source plane of the CMB-lensing tracers (Sec. 2.4)
+        self.z_star = self.z_max if z_star is None else float(z_star)
+        if not self.z_min < self.z_star <= self.z_max:
+            raise ValueError("z_star must lie inside the geometry grid")
+        self.chi_star = float(self.chi_spl(self.z_star))
         self._lens_tables = {}
 
     # --- elementary continuous functions -------------------------------------------------
@@ -126,6 +138,14 @@ class PointGeometry:
             return np.zeros_like(z)
         return self.mag[t] * self.lensing_q(t, z) * self.D_spl(z) / self.chi_spl(z) ** 2
 
+    def cmb_kernel(self, z):
+        """CMB-lensing kernel per unit chi (Sec. 2.4, without l(l+1)/k^2):
+        1.5 Om (H0/c)^2 (1+z) (chi_* - chi) / (chi chi_*) D(z), zero above z_*."""
+        z = np.atleast_1d(np.asarray(z, float))
+        chi = self.chi_spl(z)
+        f = 1.5 * self.omega_m * H0_OVER_C ** 2 * (1.0 + z) * (self.chi_star - chi) / (chi * self.chi_star)
+        return np.where(z <= self.z_star, f * self.D_spl(z), 0.0)
+
     def ia_of_z(self, z):
         """A_IA(z), 0 without intrinsic alignment."""
         z = np.atleast_1d(np.asarray(z, float))
@@ -142,8 +162,10 @@ class PointGeometry:
         z = np.atleast_1d(np.asarray(z, float))
         D = self.D_spl(z)
         dzdchi = 1.0 / self.chi_spl(z, 1)
-        if self.kinds[t] == 0:
+        if self.kinds[t] == KIND_CLUSTERING:
             return self.bias[t] * self.n_of_z(t, z) * dzdchi * D
+        if self.kinds[t] == KIND_CMB_LENSING:
+            return self.cmb_kernel(z)
         chi = self.chi_spl(z)
         return (self.lensing_q(t, z) + self.ia_of_z(z) * self.n_of_z(t, z) * dzdchi) * D / chi ** 2
 
@@ -164,12 +186,16 @@ def point_geometry(wl, b):
     ia, mag = wl.get("ia"), wl.get("mag")
     return PointGeometry(wl["z_geom"], wl["chi_z"][b], wl["D_z"][b], wl["omega_m"][b], wl["z_nz"],
                          wl["nz"][b, :T], wl["kind"][b, :T], wl["bias"][b, :T],
-                         ia=None if ia is None else ia[b], mag=None if mag is None else mag[b, :T])
+                         ia=None if ia is None else ia[b], mag=None if mag is None else mag[b, :T],
+                         z_star=wl.get("z_star"))
 
 
 def ell_prefactor(kind, ell, k):
-    """c(l, k): 1 for clustering, sqrt((l+2)!/(l-2)!) / k^2 for lensing (real l)."""
-    if kind == 0:
+    """c(l, k): 1 for clustering, sqrt((l+2)!/(l-2)!) / k^2 for lensing, l(l+1) / k^2 for CMB
+    lensing (real l)."""
+    if kind == KIND_CLUSTERING:
         return np.ones_like(np.asarray(k, float))
+    if kind == KIND_CMB_LENSING:
+        return ell * (ell + 1.0) / np.asarray(k, float) ** 2
     F = np.sqrt((ell + 2.0) * (ell + 1.0) * ell * (ell - 1.0))
     return F / np.asarray(k, float) ** 2

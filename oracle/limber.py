@@ -3,8 +3,8 @@
 With j_l(x) ~ sqrt(pi/(2l+1)) delta(l + 1/2 - x) every window collapses onto
 chi = (l+1/2)/k and
   C_l^{ij} ~ int dchi / chi^2 c_i c_j f_i(chi) f_j(chi) P((l+1/2)/chi),
-where c = 1 for clustering and c = F(l) chi^2 / (l+1/2)^2 for lensing
-(F(l)/k^2 evaluated at the Limber k).  Its error is O(1/l).
+where c = 1 for clustering, c = F(l) chi^2 / (l+1/2)^2 for lensing (F(l)/k^2 evaluated at the
+Limber k) and c = l(l+1) chi^2 / (l+1/2)^2 for CMB lensing.  Its error is O(1/l).
 
 P is the user's samples, interpolated by a cubic spline in (ln k, ln P) and
 set to zero outside [k_min, k_max] so that the comparison sees the same
@@ -30,6 +30,14 @@ from .quadrature import LensingTable
 _GL16 = np.polynomial.legendre.leggauss(16)
 
 
+def _limber_prefactor(kinds, ell, chi):
+    """c_t(l) at the Limber k = (l+1/2)/chi: [T, len(chi)]."""
+    nu = ell + 0.5
+    F = np.sqrt((ell + 2.0) * (ell + 1.0) * ell * (ell - 1.0))
+    scale = np.select([kinds == 1, kinds == 2], [F, ell * (ell + 1.0)], 0.0)
+    return np.where(kinds[:, None] == 0, 1.0, scale[:, None] * chi[None, :] ** 2 / nu ** 2)
+
+
 def cl_limber(geo: PointGeometry, ells, k, pk, n_panels=4000):
     k = np.asarray(k, float)
     lp = CubicSpline(np.log(k), np.log(pk))
@@ -47,6 +55,8 @@ def cl_limber(geo: PointGeometry, ells, k, pk, n_panels=4000):
     for t in range(T):
         if geo.kinds[t] == 0:
             f[t] = geo.bias[t] * geo.n_of_z(t, z) * D / dchi
+        elif geo.kinds[t] == 2:
+            f[t] = geo.cmb_kernel(z)
         else:
             f[t] = (lens(t, z) + geo.ia_of_z(z) * geo.n_of_z(t, z) / dchi) * D / chi ** 2
     out = np.zeros((len(ells), T, T))
@@ -55,8 +65,7 @@ def cl_limber(geo: PointGeometry, ells, k, pk, n_panels=4000):
         kl = nu / chi
         inside = (kl >= k[0]) & (kl <= k[-1])
         P = np.where(inside, np.exp(lp(np.log(np.clip(kl, k[0], k[-1])))), 0.0)
-        F = np.sqrt((ell + 2.0) * (ell + 1.0) * ell * (ell - 1.0))
-        c = np.where(geo.kinds[:, None] == 1, F * chi[None, :] ** 2 / nu ** 2, 1.0)
+        c = _limber_prefactor(geo.kinds, ell, chi)
         g = f * c
         out[li] = (g * (wz * dchi * P / chi ** 2)[None, :]) @ g.T
     return out
@@ -85,8 +94,7 @@ def cl_limber_grid(geo: PointGeometry, ells, method, pk):
         kl = nu / x
         inside = (kl >= k[0]) & (kl <= k[-1])
         P = np.where(inside, np.exp(lp(np.log(np.clip(kl, k[0], k[-1])))), 0.0)
-        Fl = np.sqrt((ell + 2.0) * (ell + 1.0) * ell * (ell - 1.0))
-        c = np.where(geo.kinds[:, None] == 1, Fl * x[None, :] ** 2 / nu ** 2, 1.0)
+        c = _limber_prefactor(geo.kinds, ell, x)
         g = f * c
         out[li] = (g * (d * w * P / x)[None, :]) @ g.T
     return out

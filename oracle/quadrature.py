@@ -1,7 +1,7 @@
 """The plain definition of the k-windows, by direct quadrature (oracle; FP64).
 
 Paper, Sec. 2.1: Delta_l^i(k) = c(l) int_0^inf dchi W^i(chi) j_l(k chi), with the
-kernels of Sec. 2.2 / 2.3 (see geometry.py).  Here the chi integral is written
+kernels of Sec. 2.2 - 2.4 (see geometry.py).  Here the chi integral is written
 in z on the kernel support and integrated by composite 16-point
 Gauss-Legendre: panels break at every knot of the geometry and n(z) grids and
 are at most pi/k wide in chi (half an oscillation of j_l).
@@ -89,6 +89,8 @@ def windows_quadrature(geo: PointGeometry, ells, k, lens_table=None, rsd=False):
         for t in range(T):
             if geo.kinds[t] == 0:
                 h[t] = geo.bias[t] * geo.n_of_z(t, z) * D
+            elif geo.kinds[t] == 2:
+                h[t] = geo.cmb_kernel(z) * geo.chi_spl(z, 1)
             else:
                 h[t] = (lens_table(t, z) * geo.chi_spl(z, 1) + geo.ia_of_z(z) * geo.n_of_z(t, z)) * D / chi ** 2
         hw = h * wz[None, :]

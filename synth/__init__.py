@@ -18,7 +18,8 @@ only; its benchmark files are not used):
   cfg4  20 clustering + 10 lensing bins, 2048 k, N_chi 2048, 200 l in [2, 3000]
 
 scale_dependent_growth() adds growth samples D(k, z) at interpolation nodes in k to any of them,
-intrinsic_alignment() an NLA amplitude A_IA(z) for the lensing tracers.
+intrinsic_alignment() an NLA amplitude A_IA(z) for the lensing tracers, cmb_lensing() a CMB-lensing
+tracer with the geometry continued to the last-scattering surface.
 """
 from __future__ import annotations
 
@@ -31,6 +32,7 @@ N_ZGEOM = 1024
 N_ZNZ = 200
 KIND_CLUSTERING = 0
 KIND_LENSING = 1
+KIND_CMB_LENSING = 2
 
 _GL8 = np.polynomial.legendre.leggauss(8)
 
@@ -127,6 +129,47 @@ def magnification_bias(wl):
         s = np.linspace(0.2, 0.6, max(len(cl), 1))[:len(cl)]
         mag[b, cl] = 5.0 * s - 2.0
     wl["mag"] = mag
+    return wl
+
+
+def cmb_lensing(wl, z_star=1090.0, n_high=256):
+    """Add a CMB-lensing tracer (kind 2) to every point of workload wl, after its last tracer.
+
+    The geometry grid is continued from its top to the last-scattering redshift z_star by n_high
+    points uniform in ln(1 + z), and chi(z), D(z) are recomputed on it for each point's Omega_m
+    (flat LCDM without radiation, as everywhere here); the tracer's n(z) row is zero and its bias 1.
+    Adds z_star; returns wl.  Apply it before the modifiers that add per-grid or per-tracer samples.
+    """
+    for key in ("ia", "mag", "D_kz"):
+        if key in wl:
+            raise ValueError(f"cmb_lensing() must run before the workload gets {key!r}")
+    z_lo = np.asarray(wl["z_geom"], float)
+    if not z_star > z_lo[-1]:
+        raise ValueError("z_star must lie above the geometry grid")
+    z_hi = np.expm1(np.linspace(np.log1p(z_lo[-1]), np.log1p(z_star), n_high + 1))[1:]
+    z_hi[-1] = z_star
+    z_geom = np.concatenate([z_lo, z_hi])
+    om = np.asarray(wl["omega_m"], float)
+    B, T = np.asarray(wl["kind"]).shape
+    ntr = np.asarray(wl["n_tracers"], np.int32)
+    nz = np.zeros((B, T + 1, np.asarray(wl["nz"]).shape[2]))
+    kinds = np.zeros((B, T + 1), np.int32)
+    bias = np.ones((B, T + 1))
+    nz[:, :T] = wl["nz"]
+    kinds[:, :T] = wl["kind"]
+    bias[:, :T] = wl["bias"]
+    for b in range(B):
+        t = int(ntr[b])
+        nz[b, t:] = 0.0
+        kinds[b, t:] = 0
+        bias[b, t:] = 1.0
+        nz[b, t + 1:T + 1] = np.asarray(wl["nz"])[b, t:T]
+        kinds[b, t + 1:T + 1] = np.asarray(wl["kind"])[b, t:T]
+        bias[b, t + 1:T + 1] = np.asarray(wl["bias"])[b, t:T]
+        kinds[b, t] = KIND_CMB_LENSING
+    wl.update(z_geom=z_geom, chi_z=np.array([comoving_distance(z_geom, o) for o in om]),
+              D_z=np.array([growth_factor(z_geom, o) for o in om]), nz=nz, kind=kinds, bias=bias,
+              n_tracers=ntr + 1, z_star=float(z_star))
     return wl
 
 
