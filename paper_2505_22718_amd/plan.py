@@ -1,7 +1,9 @@
 """Torch-facing plan: device buffers and streams around the C entry points.
 
-Every computation happens in libswiftcl.so; this module only builds the descriptor, hands
-over device pointers and the current HIP stream, and allocates outputs.
+Every computation happens in libswiftcl.so; this module only builds the descriptor, checks that
+every tensor it hands over has the layout the library reads (shape in the plan's sizes, type,
+contiguity, the plan's device: a kernel would index any other tensor out of bounds), hands over
+device pointers and the current HIP stream, and allocates outputs.
 """
 from __future__ import annotations
 
@@ -22,6 +24,73 @@ PRECISIONS = {"fp64": bd.SWIFTCL_FP64, "fp32": bd.SWIFTCL_FP32, "split_bf16": bd
 
 def _f64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# The per-call input tensors in the layout the library reads (swiftcl_inputs in include/swiftcl.h),
+# each dimension named after a plan size; B is the batch.
+INPUT_LAYOUT = (
+    ("n_tracers", torch.int32, ("B",)),
+    ("kind", torch.int32, ("B", "max_tracers")),
+    ("n_ell", torch.int32, ("B",)),
+    ("ell_idx", torch.int32, ("B", "max_ell")),
+    ("chi_z", torch.float64, ("B", "n_zg")),
+    ("D_z", torch.float64, ("B", "n_zg")),
+    ("omega_m", torch.float64, ("B",)),
+    ("nz", torch.float64, ("B", "max_tracers", "n_zs")),
+    ("bias", torch.float64, ("B", "max_tracers")),
+    ("pk", torch.float64, ("B", "n_k")),
+)
+OPTIONAL_INPUT_LAYOUT = (
+    ("ia", torch.float64, ("B", "n_zg")),
+    ("mag", torch.float64, ("B", "max_tracers")),
+)
+# gradient outputs of the backward calls
+GRAD_LAYOUT = (
+    ("pk", ("B", "n_k")),
+    ("bias", ("B", "max_tracers")),
+    ("nz", ("B", "max_tracers", "n_zs")),
+    ("D", ("B", "n_zg")),
+)
+
+
+def check_tensor(name, x, shape, dtype, device):
+    """Raise ValueError unless x is a contiguous `dtype` tensor of exactly `shape` on `device`.  The
+    kernels index every buffer with the plan's sizes, so any other tensor would be read or written
+    out of bounds; the check reads metadata only (no synchronisation, fine under graph capture)."""
+    shape = tuple(int(v) for v in shape)
+    if (isinstance(x, torch.Tensor) and tuple(x.shape) == shape and x.dtype == dtype and x.device == device
+            and x.is_contiguous()):
+        return
+    if isinstance(x, torch.Tensor):
+        got = f"{tuple(x.shape)} {x.dtype} on {x.device}" + ("" if x.is_contiguous() else ", not contiguous")
+    else:
+        got = type(x).__name__
+    raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {shape} on {device}; got {got}")
+
+
+def check_inputs(t, dims, device):
+    """Check a dict of per-call input tensors against INPUT_LAYOUT before its pointers are handed
+    over.  dims: the plan's max_tracers, max_ell, n_zg, n_zs and n_k.  Returns the batch B."""
+    n = t.get("n_tracers")
+    if not isinstance(n, torch.Tensor) or n.dim() != 1:
+        raise ValueError("inputs need n_tracers, a 1-d tensor of the batch's tracer counts")
+    size = dict(dims, B=int(n.shape[0]))
+    for name, dtype, layout in INPUT_LAYOUT:
+        if name not in t:
+            raise ValueError(f"inputs lack {name!r}")
+        check_tensor(name, t[name], [size[d] for d in layout], dtype, device)
+    for name, dtype, layout in OPTIONAL_INPUT_LAYOUT:
+        if t.get(name) is not None:
+            check_tensor(name, t[name], [size[d] for d in layout], dtype, device)
+    return size["B"]
+
+
+def check_grads(outs, B, dims, device):
+    """Check preallocated gradient tensors (any subset of pk, bias, nz, D; float64)."""
+    size = dict(dims, B=B)
+    for name, layout in GRAD_LAYOUT:
+        if outs.get(name) is not None:
+            check_tensor(f"gradient {name}", outs[name], [size[d] for d in layout], torch.float64, device)
 
 
 # Plans dropped while a stream is being captured into a graph: freeing device memory then would
@@ -50,6 +119,8 @@ class Plan:
         self.max_batch, self.max_tracers, self.max_ell = int(max_batch), int(max_tracers), int(max_ell)
         self.precision = precision
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, 0)
         d = bd.swiftcl_plan_desc()
         d.n_chi = self.n_chi
         d.edge_node = int(edge_node)
@@ -67,7 +138,7 @@ class Plan:
         d.n_zs, d.z_nz = len(self.z_nz), self.z_nz.ctypes.data_as(dp)
         d.max_batch, d.max_tracers, d.max_ell = self.max_batch, self.max_tracers, self.max_ell
         d.precision = PRECISIONS[precision]
-        d.device = self.device.index or 0
+        d.device = self.device.index
         d.n_interp = int(n_interp)
         self.n_interp = int(n_interp)
         d.rsd = 1 if rsd else 0
@@ -111,10 +182,24 @@ class Plan:
     def _stream(self):
         return torch.cuda.current_stream(self.device).cuda_stream
 
-    @staticmethod
-    def inputs_struct(t):
+    @property
+    def dims(self):
+        """The plan sizes that the input, output and gradient layouts are written in."""
+        return dict(max_tracers=self.max_tracers, max_ell=self.max_ell, n_zg=len(self.z_geom),
+                    n_zs=len(self.z_nz), n_k=len(self.k))
+
+    def _cl_buffer(self, name, x, B):
+        """A [B][max_ell][n_pairs] buffer of the output type: checked if given, else allocated."""
+        shape = (B, self.max_ell, self.n_pairs)
+        if x is None:
+            return torch.empty(shape, dtype=self.out_dtype, device=self.device)
+        check_tensor(name, x, shape, self.out_dtype, self.device)
+        return x
+
+    def inputs_struct(self, t):
+        """The swiftcl_inputs of a dict of device tensors, after check_inputs."""
         s = bd.swiftcl_inputs()
-        s.batch = int(t["n_tracers"].shape[0])
+        s.batch = check_inputs(t, self.dims, self.device)
         for name in ("n_tracers", "kind", "n_ell", "ell_idx", "chi_z", "D_z", "omega_m", "nz", "bias", "pk"):
             setattr(s, name, t[name].data_ptr())
         ia = t.get("ia")  # NLA amplitude A_IA(z) of the lensing tracers, optional
@@ -130,53 +215,53 @@ class Plan:
         return self.state_token
 
     def cl(self, t, out=None):
-        B = t["n_tracers"].shape[0]
-        if out is None:
-            out = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
+        s = self.inputs_struct(t)
+        out = self._cl_buffer("out", out, s.batch)
         self._new_state()
-        bd.swiftcl_cl(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
+        bd.swiftcl_cl(self.handle, s, out.data_ptr(), self._stream())
         return out
 
     def cl_kgrowth(self, t, D_kz, out=None):
         """C_l with scale-dependent growth: D_kz [B][n_interp][n_zg] float64 on the plan's device."""
-        B = t["n_tracers"].shape[0]
-        want = (B, self.n_interp, len(self.z_geom))
-        if (tuple(D_kz.shape) != want or D_kz.dtype != torch.float64 or not D_kz.is_contiguous()
-                or D_kz.device != self.device):
-            raise ValueError(f"D_kz must be a contiguous float64 tensor of shape {want} on {self.device}")
-        if out is None:
-            out = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
+        s = self.inputs_struct(t)
+        check_tensor("D_kz", D_kz, (s.batch, self.n_interp, len(self.z_geom)), torch.float64, self.device)
+        out = self._cl_buffer("out", out, s.batch)
         self._new_state()
-        bd.swiftcl_cl_kgrowth(self.handle, self.inputs_struct(t), D_kz.data_ptr(), out.data_ptr(), self._stream())
+        bd.swiftcl_cl_kgrowth(self.handle, s, D_kz.data_ptr(), out.data_ptr(), self._stream())
         return out
 
     def cl_limber(self, t, out=None):
         """C_l in the Limber limit on the plan's chi nodes (same layout as cl)."""
-        B = t["n_tracers"].shape[0]
-        if out is None:
-            out = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
+        s = self.inputs_struct(t)
+        out = self._cl_buffer("out", out, s.batch)
         self._new_state()
-        bd.swiftcl_cl_limber(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
+        bd.swiftcl_cl_limber(self.handle, s, out.data_ptr(), self._stream())
         return out
 
     def cl_timed(self, t, out):
         """Forward C_l with per-stage device times (ms): assembly, FFTLog coefficients, windows + C."""
+        s = self.inputs_struct(t)
+        out = self._cl_buffer("out", out, s.batch)
         self._new_state()
-        return bd.swiftcl_cl_timed(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
+        return bd.swiftcl_cl_timed(self.handle, s, out.data_ptr(), self._stream())
 
     def windows(self, t, out=None):
-        B = t["n_tracers"].shape[0]
+        s = self.inputs_struct(t)
+        shape = (s.batch, self.max_ell, self.max_tracers, len(self.k))
         if out is None:
-            out = torch.empty((B, self.max_ell, self.max_tracers, len(self.k)), dtype=self.out_dtype,
-                              device=self.device)
+            out = torch.empty(shape, dtype=self.out_dtype, device=self.device)
+        else:
+            check_tensor("out", out, shape, self.out_dtype, self.device)
         self._new_state()
-        bd.swiftcl_windows(self.handle, self.inputs_struct(t), out.data_ptr(), self._stream())
+        bd.swiftcl_windows(self.handle, s, out.data_ptr(), self._stream())
         return out
 
     def backward(self, t, dC, want=("pk", "bias", "nz", "D"), reuse_forward=False):
         """Gradients of sum(dC * C).  reuse_forward: `t` is the input of the last forward call on
         this plan (same tensors, unmodified), whose assembly and FFTLog state are kept."""
-        B = t["n_tracers"].shape[0]
+        s = self.inputs_struct(t)
+        B = s.batch
+        dC = self._cl_buffer("dC", dC.contiguous(), B)
         f64 = dict(dtype=torch.float64, device=self.device)
         outs = {
             "pk": torch.empty((B, len(self.k)), **f64) if "pk" in want else None,
@@ -187,34 +272,43 @@ class Plan:
         ptr = {k: (v.data_ptr() if v is not None else 0) for k, v in outs.items()}
         if not reuse_forward:
             self._new_state()
-        bd.swiftcl_cl_backward(self.handle, self.inputs_struct(t), dC.contiguous().data_ptr(), ptr["pk"],
-                               ptr["bias"], ptr["nz"], ptr["D"], _flags(reuse_forward), self._stream())
+        bd.swiftcl_cl_backward(self.handle, s, dC.data_ptr(), ptr["pk"], ptr["bias"], ptr["nz"], ptr["D"],
+                               _flags(reuse_forward), self._stream())
         return {k: v for k, v in outs.items() if v is not None}
 
     def backward_timed(self, t, dC, outs, reuse_forward=False):
         """Backward with per-stage device times (ms); outs: dict of preallocated gradient tensors."""
-        ptr = {k: (outs[k].data_ptr() if outs.get(k) is not None else 0) for k in ("pk", "bias", "nz", "D")}
+        s, ptr = self._backward_args(t, dC, outs)
         if not reuse_forward:
             self._new_state()
-        return bd.swiftcl_cl_backward_timed(self.handle, self.inputs_struct(t), dC.data_ptr(), ptr["pk"],
-                                            ptr["bias"], ptr["nz"], ptr["D"], _flags(reuse_forward),
-                                            self._stream())
+        return bd.swiftcl_cl_backward_timed(self.handle, s, dC.data_ptr(), ptr["pk"], ptr["bias"], ptr["nz"],
+                                            ptr["D"], _flags(reuse_forward), self._stream())
 
     def backward_into(self, t, dC, outs, reuse_forward=False):
         """Backward into preallocated gradient tensors (no allocation)."""
-        ptr = {k: (outs[k].data_ptr() if outs.get(k) is not None else 0) for k in ("pk", "bias", "nz", "D")}
+        s, ptr = self._backward_args(t, dC, outs)
         if not reuse_forward:
             self._new_state()
-        bd.swiftcl_cl_backward(self.handle, self.inputs_struct(t), dC.data_ptr(), ptr["pk"], ptr["bias"],
-                               ptr["nz"], ptr["D"], _flags(reuse_forward), self._stream())
+        bd.swiftcl_cl_backward(self.handle, s, dC.data_ptr(), ptr["pk"], ptr["bias"], ptr["nz"], ptr["D"],
+                               _flags(reuse_forward), self._stream())
+
+    def _backward_args(self, t, dC, outs):
+        """Checked inputs struct and gradient pointers of the preallocating backward calls."""
+        s = self.inputs_struct(t)
+        self._cl_buffer("dC", dC, s.batch)
+        check_grads(outs, s.batch, self.dims, self.device)
+        ptr = {k: (outs[k].data_ptr() if outs.get(k) is not None else 0) for k in ("pk", "bias", "nz", "D")}
+        return s, ptr
 
     def autotune(self, t, dC=None, cache_path=None):
         """Choose the launch shapes for inputs like `t` (see swiftcl_autotune); returns the report."""
-        B = t["n_tracers"].shape[0]
+        s = self.inputs_struct(t)
+        if dC is not None:
+            self._cl_buffer("dC", dC, s.batch)
         self._new_state()
-        C = torch.empty((B, self.max_ell, self.n_pairs), dtype=self.out_dtype, device=self.device)
-        return bd.swiftcl_autotune(self.handle, self.inputs_struct(t), C.data_ptr(),
-                                   dC.data_ptr() if dC is not None else 0, self._stream(), cache_path)
+        C = self._cl_buffer("out", None, s.batch)
+        return bd.swiftcl_autotune(self.handle, s, C.data_ptr(), dC.data_ptr() if dC is not None else 0,
+                                   self._stream(), cache_path)
 
     def set_launch(self, fwd_mode=None, bwd_chunk_mul=None):
         """Force a launch configuration (what swiftcl_autotune would choose)."""
