@@ -156,3 +156,36 @@ def test_binding_struct_offsets_match_a_c_compiler(struct, tmp_path):
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(cls)] + [getattr(cls, name).offset for name, _ in cls._fields_]
     assert got == want
+
+
+def _header_prototypes():
+    """{name: [parameter declarations]} of every function include/swiftcl.h declares."""
+    text = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                             "include", "swiftcl.h")).read()
+    text = re.sub(r"//[^\n]*", "", re.sub(r"/\*.*?\*/", "", text, flags=re.S))
+    protos = {}
+    for m in re.finditer(r"(?:swiftcl_status|const\s+char\s*\*)\s*(swiftcl_\w+)\s*\(([^)]*)\)\s*;", text):
+        body = " ".join(m.group(2).split())
+        protos[m.group(1)] = [] if body == "void" else [p.strip() for p in body.split(",")]
+    return protos
+
+
+def test_binding_argtypes_match_the_header(lib):
+    """Every prototype's parameter count, and for each parameter pointer versus 32-bit integer (signed
+    or not), against the ctypes argtypes the binding declares; status returns are int, the error
+    message a C string."""
+    from paper_2505_22718_amd import binding as bd
+    protos = _header_prototypes()
+    assert set(protos) == set(bd.EXPORTED)
+    for name, params in protos.items():
+        f = getattr(lib, name)
+        argtypes = list(f.argtypes or [])
+        assert len(argtypes) == len(params), name
+        for p, a in zip(params, argtypes):
+            pointer = "*" in p or p.startswith("swiftcl_plan_t")
+            if pointer:
+                assert a in (ctypes.c_void_p, ctypes.c_char_p) or issubclass(a, ctypes._Pointer), (name, p)
+            else:
+                want = ctypes.c_uint32 if p.startswith("uint32_t") else ctypes.c_int32
+                assert a is want, (name, p)
+        assert f.restype is (ctypes.c_char_p if name == "swiftcl_last_error" else ctypes.c_int), name
