@@ -233,6 +233,24 @@ def test_limber_on_the_chi_grid_matches_the_integral(wl1):
     assert eps.max() < 1e-3
 
 
+def test_limber_rules_agree_with_intrinsic_alignment():
+    """The NLA term enters the two Limber oracles by separate code (the node rule through the
+    sampled kernels of geometry.f_of_z, the panel integral through its own integrand): with IA on
+    they agree as without it, while IA moves the lensing autos by percents."""
+    wl = synth.intrinsic_alignment(synth.make_workload("cfg1"))
+    m = fftlog.method_for(wl)
+    geo = geometry.point_geometry(wl, 0)
+    ells = fftlog.point_ells(wl, 0)[::12]
+    A = limber.cl_limber_grid(geo, ells, m, wl["pk"][0])
+    B = limber.cl_limber(geo, ells, m.k, wl["pk"][0])
+    d = np.sqrt(np.abs(np.einsum("ltt->lt", B)))
+    eps = np.abs(A - B) / (d[:, :, None] * d[:, None, :])
+    assert eps[ells <= 500].max() < 5e-6
+    B0 = limber.cl_limber(geometry.point_geometry(dict(wl, ia=None), 0), ells, m.k, wl["pk"][0])
+    lens = np.arange(10, 15)
+    assert np.max(np.abs(B[:, lens, lens] / B0[:, lens, lens] - 1)) > 1e-2
+
+
 # --- invariants of C_l -------------------------------------------------------------------------------
 
 def _full(Cp, T):
