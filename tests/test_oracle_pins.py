@@ -401,6 +401,31 @@ def test_gradients_against_finite_differences(wl2):
     assert abs(fd - dD) <= 1e-7 * abs(dD)
 
 
+def test_gradients_with_intrinsic_alignment():
+    """With IA on, n(z) of a lensing tracer enters its kernel twice (lens efficiency and the NLA
+    term) and both stay linear in n, D; the directional derivatives against central differences."""
+    wl = _small(synth.intrinsic_alignment(synth.make_workload("cfg2")), 51)
+    m = fftlog.method_for(wl)
+    rng = np.random.default_rng(11)
+    C = fftlog.cl(wl, 0, m)
+    G = rng.standard_normal(C.shape)
+    L = lambda w: float(np.sum(G * fftlog.cl(w, 0, m)))
+    eps = 1e-3
+    v = rng.standard_normal(wl["nz"].shape[-1]) * wl["nz"][0, 12].max() * 0.1
+    dn = gradients.directional_nz(wl, 0, G, 12, v, m)
+    wp, wm = dict(wl), dict(wl)
+    wp["nz"] = wl["nz"].copy(); wp["nz"][0, 12] += eps * v
+    wm["nz"] = wl["nz"].copy(); wm["nz"][0, 12] -= eps * v
+    assert abs((L(wp) - L(wm)) / (2 * eps) - dn) <= 1e-7 * abs(dn)
+    # the NLA term's share of the derivative is not negligible
+    dn0 = gradients.directional_nz(dict(wl, ia=None), 0, G, 12, v, m)
+    assert abs(dn / dn0 - 1) > 1e-3
+    vD = rng.standard_normal(wl["D_z"].shape[-1]) * 0.01
+    dD = gradients.directional_D(wl, 0, G, vD, m)
+    wp, wm = dict(wl, D_z=wl["D_z"] + eps * vD), dict(wl, D_z=wl["D_z"] - eps * vD)
+    assert abs((L(wp) - L(wm)) / (2 * eps) - dD) <= 1e-7 * abs(dD)
+
+
 def test_euler_identities(wl1):
     """sum_j P_j dC/dP_j = C, and sum_s D_s dC/dD_s = 2C (C is quadratic in D)."""
     wl = _small(wl1, 34)
