@@ -103,6 +103,17 @@ def sampled_kernels(geo: PointGeometry, method: Method, rsd=False, mag=False):
     w[-1] = 0.5 + theta if m1 > m0 else w[-1]
     for t in range(T):
         F[t, nodes] = w * (geo.f_rsd_of_z(t, z) if rsd else (geo.f_mag_of_z(t, z) if mag else geo.f_of_z(t, z)))
+    if np.any(geo.kinds == 2) and not (rsd or mag):
+        # CMB lensing (reading R21): the kernel falls to zero at chi_*, a corner rather than a jump,
+        # so the trapezoid rule of the cut kernel gives its last node below chi_* the weight
+        # 1/2 + theta_*/2 (the last panel's linear end) in place of the edge weight above
+        u_s = np.log(geo.chi_star / chi0) / d
+        ms = int(np.floor(u_s))
+        if ms > m0:
+            ws = 0.5 + 0.5 * (u_s - ms)
+            for t in np.nonzero(geo.kinds == 2)[0]:
+                F[t, ms + 1:] = 0.0
+                F[t, ms] = ws * geo.f_of_z(t, np.array([geo.z_of_chi(chi[ms])[0]]))[0]
     return chi0, chi, F
 
 
