@@ -330,7 +330,7 @@ def main():
                 "flops_per_launch": flops, "kernel_ms": kms}
 
     result = {
-        "metric": "C_l sets/s (15 tracers, 103 l) fwd & fwd+bwd at <=1e-3 rel err vs FP64",
+        "metric": "C_\u2113 sets/s (15 tracers,103 \u2113) fwd & fwd+bwd at \u22641e-3 rel err vs FP64",
         "value": B / (ms * 1e-3),
         "forward_sets_per_s": B / (ms_fwd * 1e-3),
         "forward_ms_per_step": ms_fwd,
