@@ -79,41 +79,51 @@ def chi_grid(geo: PointGeometry, method: Method):
     return chi0, chi0 * np.exp(np.arange(method.n_chi) * method.delta)
 
 
-def sampled_kernels(geo: PointGeometry, method: Method, rsd=False, mag=False):
-    """Step 1: w_m f_t(chi_m) on the grid, with the edge weights of reading R5 (with rsd=True the
-    RSD kernels of eq. RSD instead).
+def edge_weights(geo: PointGeometry, method: Method):
+    """Support nodes m0..m1 of the kernels and their trapezoid weights per tracer, [T, m1-m0+1].
 
-    Returns (chi0, chi_m, F) with F of shape [T, N].
+    Reading R5: 1/2 on the lower edge chi(z_min), 1/2 + theta on node m1 when chi(z_max) lies a
+    fraction theta of a step above it (the kernel is cut there: a jump).  Reading R21: a CMB-lensing
+    kernel falls linearly to zero at chi_*, a corner, so its last node below chi_* takes the weight
+    of a linear end, 1/2 + theta_*/2, and the nodes above it weight 0.
     """
-    chi0, chi = chi_grid(geo, method)
+    chi0, _ = chi_grid(geo, method)
     N, m0, d = method.n_chi, method.m0, method.delta
     u_hi = np.log(geo.chi_max / chi0) / d
     m1 = int(np.floor(u_hi))
     theta = u_hi - m1
     if m0 < 1 or m1 >= N:
         raise ValueError("kernel support does not fit in the chi box")
-    T = len(geo.kinds)
-    F = np.zeros((T, N))
     nodes = np.arange(m0, m1 + 1)
-    z = np.empty(len(nodes))
-    z[0] = geo.z_min  # node m0 sits on the lower edge by construction
-    z[1:] = geo.z_of_chi(np.minimum(chi[nodes[1:]], geo.chi_max))
     w = np.ones(len(nodes))
     w[0] = 0.5
     w[-1] = 0.5 + theta if m1 > m0 else w[-1]
-    for t in range(T):
-        F[t, nodes] = w * (geo.f_rsd_of_z(t, z) if rsd else (geo.f_mag_of_z(t, z) if mag else geo.f_of_z(t, z)))
-    if np.any(geo.kinds == 2) and not (rsd or mag):
-        # CMB lensing (reading R21): the kernel falls to zero at chi_*, a corner rather than a jump,
-        # so the trapezoid rule of the cut kernel gives its last node below chi_* the weight
-        # 1/2 + theta_*/2 (the last panel's linear end) in place of the edge weight above
+    W = np.repeat(w[None, :], len(geo.kinds), axis=0)
+    cmb = np.nonzero(geo.kinds == 2)[0]
+    if len(cmb):
         u_s = np.log(geo.chi_star / chi0) / d
         ms = int(np.floor(u_s))
         if ms > m0:
-            ws = 0.5 + 0.5 * (u_s - ms)
-            for t in np.nonzero(geo.kinds == 2)[0]:
-                F[t, ms + 1:] = 0.0
-                F[t, ms] = ws * geo.f_of_z(t, np.array([geo.z_of_chi(chi[ms])[0]]))[0]
+            W[cmb, ms - m0] = 0.5 + 0.5 * (u_s - ms)
+            W[cmb, ms - m0 + 1:] = 0.0
+    return nodes, W
+
+
+def sampled_kernels(geo: PointGeometry, method: Method, rsd=False, mag=False):
+    """Step 1: w_m f_t(chi_m) on the grid, with the edge weights of readings R5 and R21 (with
+    rsd=True the RSD kernels of eq. RSD instead, with mag=True the magnification kernels).
+
+    Returns (chi0, chi_m, F) with F of shape [T, N].
+    """
+    chi0, chi = chi_grid(geo, method)
+    nodes, W = edge_weights(geo, method)
+    T = len(geo.kinds)
+    F = np.zeros((T, method.n_chi))
+    z = np.empty(len(nodes))
+    z[0] = geo.z_min  # node m0 sits on the lower edge by construction
+    z[1:] = geo.z_of_chi(np.minimum(chi[nodes[1:]], geo.chi_max))
+    for t in range(T):
+        F[t, nodes] = W[t] * (geo.f_rsd_of_z(t, z) if rsd else (geo.f_mag_of_z(t, z) if mag else geo.f_of_z(t, z)))
     return chi0, chi, F
 
 

@@ -75,18 +75,16 @@ def cl_limber_grid(geo: PointGeometry, ells, method, pk):
     """eq. Limber on the log-chi grid of the FFTLog method: [L, T, T]."""
     k = method.k
     lp = CubicSpline(np.log(k), np.log(pk), bc_type="natural")
-    chi0, chi, F = fftlog.sampled_kernels(geo, method)  # F = w_m f_t(chi_m)
-    N, m0, d = method.n_chi, method.m0, method.delta
-    u_hi = np.log(geo.chi_max / chi0) / d
-    m1 = int(np.floor(u_hi))
-    theta = u_hi - m1
-    nodes = np.arange(m0, m1 + 1)
+    chi0, chi, F = fftlog.sampled_kernels(geo, method)  # F = w_t(m) f_t(chi_m)
+    d = method.delta
+    nodes, Wt = fftlog.edge_weights(geo, method)
+    x = chi[nodes]
+    f = np.divide(F[:, nodes], Wt, out=np.zeros_like(Wt), where=Wt > 0)
+    # the rule's own weights: those of the grid's support edges (R5)
     w = np.ones(len(nodes))
     w[0] = 0.5
-    if m1 > m0:
-        w[-1] = 0.5 + theta
-    x = chi[nodes]
-    f = F[:, nodes] / w[None, :]
+    if len(nodes) > 1:
+        w[-1] = 0.5 + (np.log(geo.chi_max / chi0) / d - nodes[-1])
     T = len(geo.kinds)
     out = np.zeros((len(ells), T, T))
     for li, ell in enumerate(ells):
