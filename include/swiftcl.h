@@ -96,7 +96,7 @@ typedef struct {
 
 /* Per-call inputs.  Device pointers owned by the caller, row-major, never written. */
 typedef struct {
-  int32_t batch;             /* B <= max_batch                                                   */
+  int32_t batch;             /* B, 1..max_batch (0 is refused with SWIFTCL_E_INVALID)            */
   const int32_t* n_tracers;  /* [B] tracers of each point, 1..max_tracers                       */
   const int32_t* kind;       /* [B][max_tracers] SWIFTCL_CLUSTERING or SWIFTCL_LENSING           */
   const int32_t* n_ell;      /* [B] multipoles of each point, 1..max_ell                         */
