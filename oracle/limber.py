@@ -71,20 +71,23 @@ def cl_limber(geo: PointGeometry, ells, k, pk, n_panels=4000):
     return out
 
 
+def _grid_terms(geo: PointGeometry, method):
+    """The chi-node rule's nodes x_m, kernel samples f_t(x_m) [T, M] and edge weights w_m (R5)."""
+    chi0, chi, F = fftlog.sampled_kernels(geo, method)  # F = w_t(m) f_t(chi_m)
+    nodes, Wt = fftlog.edge_weights(geo, method)
+    f = np.divide(F[:, nodes], Wt, out=np.zeros_like(Wt), where=Wt > 0)
+    w = np.ones(len(nodes))
+    w[0] = 0.5
+    if len(nodes) > 1:
+        w[-1] = 0.5 + (np.log(geo.chi_max / chi0) / method.delta - nodes[-1])
+    return chi[nodes], f, w
+
+
 def cl_limber_grid(geo: PointGeometry, ells, method, pk):
     """eq. Limber on the log-chi grid of the FFTLog method: [L, T, T]."""
     k = method.k
     lp = CubicSpline(np.log(k), np.log(pk), bc_type="natural")
-    chi0, chi, F = fftlog.sampled_kernels(geo, method)  # F = w_t(m) f_t(chi_m)
-    d = method.delta
-    nodes, Wt = fftlog.edge_weights(geo, method)
-    x = chi[nodes]
-    f = np.divide(F[:, nodes], Wt, out=np.zeros_like(Wt), where=Wt > 0)
-    # the rule's own weights: those of the grid's support edges (R5)
-    w = np.ones(len(nodes))
-    w[0] = 0.5
-    if len(nodes) > 1:
-        w[-1] = 0.5 + (np.log(geo.chi_max / chi0) / d - nodes[-1])
+    x, f, w = _grid_terms(geo, method)
     T = len(geo.kinds)
     out = np.zeros((len(ells), T, T))
     for li, ell in enumerate(ells):
@@ -94,5 +97,30 @@ def cl_limber_grid(geo: PointGeometry, ells, method, pk):
         P = np.where(inside, np.exp(lp(np.log(np.clip(kl, k[0], k[-1])))), 0.0)
         c = _limber_prefactor(geo.kinds, ell, x)
         g = f * c
-        out[li] = (g * (d * w * P / x)[None, :]) @ g.T
+        out[li] = (g * (method.delta * w * P / x)[None, :]) @ g.T
     return out
+
+
+def grad_pk_grid(G, geo: PointGeometry, ells, method, pk):
+    """dL/dP_j of L = sum_l sum_{s,t} G[l, s, t] C_l^{st} under the chi-node rule (G full [L, T, T]).
+
+    C is linear in P at the Limber k of every node, and ln P(k) is the natural cubic spline through
+    the (ln k_j, ln P_j), linear in the ln P_j: dP(k)/dP_j = P(k) B_j(ln k) / P_j, with B_j the
+    natural spline through the j-th unit vector.  Nodes whose Limber k leaves [k_min, k_max] have
+    P = 0 and no gradient.
+    """
+    k = method.k
+    lnk = np.log(k)
+    lp = CubicSpline(lnk, np.log(pk), bc_type="natural")
+    basis = CubicSpline(lnk, np.eye(len(k)), bc_type="natural")
+    x, f, w = _grid_terms(geo, method)
+    out = np.zeros(len(k))
+    for li, ell in enumerate(ells):
+        kl = (ell + 0.5) / x
+        inside = (kl >= k[0]) & (kl <= k[-1])
+        lkl = np.log(np.clip(kl, k[0], k[-1]))
+        P = np.where(inside, np.exp(lp(lkl)), 0.0)
+        g = f * _limber_prefactor(geo.kinds, ell, x)
+        a = np.einsum("sm,st,tm->m", g, G[li], g) * method.delta * w * P / x
+        out += a @ basis(lkl)
+    return out / np.asarray(pk, float)

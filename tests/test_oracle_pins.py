@@ -273,6 +273,28 @@ def test_limber_on_the_chi_grid_matches_the_integral(wl1):
     assert eps.max() < 1e-3
 
 
+def test_limber_grid_gradient_in_pk(wl1):
+    """dL/dP_j of the chi-node Limber rule through the natural spline of ln P: sum_j P_j dL/dP_j = L
+    (scaling every P_j scales P(k) exactly), and central differences at nodes across the k range,
+    those whose Limber k only some multipoles reach included."""
+    m = fftlog.method_for(wl1)
+    geo = geometry.point_geometry(wl1, 0)
+    ells = fftlog.point_ells(wl1, 0)[[0, 30, 60, 90, 102]]
+    pk = wl1["pk"][0]
+    rng = np.random.default_rng(12)
+    G = rng.standard_normal((len(ells), 15, 15))
+    L = lambda p: float(np.sum(G * limber.cl_limber_grid(geo, ells, m, p)))
+    gp = limber.grad_pk_grid(G, geo, ells, m, pk)
+    assert abs(gp @ pk - L(pk)) < 1e-10 * abs(L(pk))
+    for j in (40, 300, 600, 900, 1020):
+        h = 1e-5 * pk[j]
+        pp, pm = pk.copy(), pk.copy()
+        pp[j] += h
+        pm[j] -= h
+        fd = (L(pp) - L(pm)) / (2 * h)
+        assert abs(fd - gp[j]) <= 1e-6 * np.abs(gp).max(), j
+
+
 def test_limber_rules_agree_with_intrinsic_alignment():
     """The NLA term enters the two Limber oracles by separate code (the node rule through the
     sampled kernels of geometry.f_of_z, the panel integral through its own integrand): with IA on
