@@ -111,6 +111,8 @@ class Plan:
     def __init__(self, k, ell, z_geom, z_nz, n_chi, max_batch, max_tracers, max_ell, precision="fp32",
                  band_ell_lo=DEFAULT_BAND_ELL_LO, fftlog_b=DEFAULT_FFTLOG_B, taper_frac=0.0, edge_node=0,
                  device=0, n_interp=0, rsd=False, magnification=False):
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, got {precision!r}")
         self.k = _f64(k)
         self.ell = _f64(ell)
         self.z_geom = _f64(z_geom)

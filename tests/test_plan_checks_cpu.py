@@ -198,3 +198,9 @@ def test_every_plan_method_reaches_the_library_with_checked_buffers(cfg1, monkey
     pk._stream = lambda: 0
     Ck = pk.cl_kgrowth(pl.device_inputs(wk, CPU), torch.as_tensor(wk["D_kz"], dtype=torch.float64))
     assert Ck.dtype == torch.float64 and calls["swiftcl_cl_kgrowth"][3] == Ck.data_ptr()
+
+
+def test_unknown_precision_is_refused_before_the_library():
+    wl = synth.make_workload("cfg0")
+    with pytest.raises(ValueError, match="precision"):
+        pl.Plan.for_workload(wl, precision="fp16")
