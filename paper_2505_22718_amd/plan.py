@@ -113,6 +113,12 @@ class Plan:
                  device=0, n_interp=0, rsd=False, magnification=False):
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, got {precision!r}")
+        nb = len(band_ell_lo)
+        if not 1 <= nb <= bd.MAX_BANDS:
+            raise ValueError(f"band_ell_lo must have 1..{bd.MAX_BANDS} entries, got {nb}")
+        if len(fftlog_b) < 2 or any(len(fftlog_b[kind]) != nb for kind in (0, 1)):
+            # entries left unset would reach the library as b = 0
+            raise ValueError(f"fftlog_b needs a row of {nb} biases (one per band) for clustering and for lensing")
         self.k = _f64(k)
         self.ell = _f64(ell)
         self.z_geom = _f64(z_geom)

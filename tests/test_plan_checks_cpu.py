@@ -204,3 +204,14 @@ def test_unknown_precision_is_refused_before_the_library():
     wl = synth.make_workload("cfg0")
     with pytest.raises(ValueError, match="precision"):
         pl.Plan.for_workload(wl, precision="fp16")
+
+
+def test_band_table_shapes_are_refused_before_the_library():
+    """Every band needs a bias for both kinds (an unset entry would reach the library as b = 0)."""
+    wl = synth.make_workload("cfg0")
+    with pytest.raises(ValueError, match="fftlog_b"):
+        pl.Plan.for_workload(wl, band_ell_lo=(0.0, 3.0, 6.0, 50.0))
+    with pytest.raises(ValueError, match="fftlog_b"):
+        pl.Plan.for_workload(wl, fftlog_b=((0.1, -0.2, -0.5),))
+    with pytest.raises(ValueError, match="band_ell_lo"):
+        pl.Plan.for_workload(wl, band_ell_lo=(0.0, 3.0, 6.0, 9.0, 12.0), fftlog_b=((0.1,) * 5, (-1.5,) * 5))
