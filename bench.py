@@ -65,10 +65,12 @@ def sources_digest():
     return h.hexdigest()
 
 
-def traffic_bytes():
+def traffic_bytes(batch, launch):
     """HBM bytes per launch of k_bwd_windows from the committed rocprofv3 counter record
     (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain copy of known
-    size), or None if there is none or the kernel's sources changed since it was taken."""
+    size), or None if there is none, if the kernel's sources changed since it was taken, or if the
+    launch being timed is not the one it was taken on: the batch and the launch shape (the number
+    of multipole chunks per point, set by bwd_chunk_mul, sets how many partial rows are written)."""
     if not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = None
@@ -77,6 +79,8 @@ def traffic_bytes():
             if line.startswith("traffic-record: "):
                 rec = json.loads(line[len("traffic-record: "):])
     if not rec or rec.get("sources_sha256") != sources_digest():
+        return None
+    if rec.get("batch") != batch or rec.get("launch", {}).get("bwd_chunk_mul") != launch["bwd_chunk_mul"]:
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -101,6 +105,7 @@ def profile_pass(B):
         plan.cl(inp, out)
         plan.backward_into(inp, dC, grads, reuse_forward=True)
     torch.cuda.synchronize()
+    print(f"profile pass launch: batch {B}, {json.dumps(plan.launch_config())}", flush=True)
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -324,7 +329,7 @@ def main():
     name = max(kernels, key=lambda k: kernels[k][0])
     kms, flops = kernels[name]
     achieved = flops / (kms * 1e-3) / 1e12
-    traffic = traffic_bytes() if name.startswith("k_bwd_windows") else None
+    traffic = traffic_bytes(B, plan.launch_config()) if name.startswith("k_bwd_windows") else None
     roofline = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
                 "flops_per_launch": flops, "kernel_ms": kms}
