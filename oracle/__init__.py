@@ -13,7 +13,8 @@ Modules
               integral (eq. int_jl, corrected), the sum over n per k, the k-sum
   quadrature  the plain definition: windows by direct quadrature of
               j_l(k chi), used to pin the FFTLog oracle (method-error floor)
-  limber      the Limber limit (eq. Limber), a high-l check of the quadrature
+  limber      the Limber limit (eq. Limber), a high-l check of the quadrature, and the
+              rule on the FFTLog chi nodes with its dL/dP through the spline of ln P
   gradients   exact / directional derivatives of C_l for the adjoint tests
   kgrowth     scale-dependent growth D(k, z) (Sec. 3.2): coefficients at N_interp
               k nodes, continued along ln k by a natural cubic spline
