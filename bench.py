@@ -144,6 +144,77 @@ def time_ms(fn, steps, stream):
     return start.elapsed_time(end) / steps
 
 
+def capture(fn):
+    """fn() captured in a HIP graph (torch.cuda.CUDAGraph), after two eager calls on the capture's side
+    stream.  The library's calls launch kernels only (no allocation, no memset), so they capture."""
+    import gc
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    gc.collect()  # nothing may be freed while the capture runs
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def graph_ms(g, steps, warmup, stream):
+    """Mean device time of `steps` replays after `warmup` (HIP events around the whole region)."""
+    import torch
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        g.replay()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def graph_median_ms(g, n, stream):
+    """Median device time of n replays, each between its own pair of HIP events."""
+    import numpy as np
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record(stream)
+        g.replay()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def split_error(wl, C_gpu, points=(0,), ell_step=20):
+    """Q12 error (|dC^{ij}| / sqrt(C^{ii} C^{jj})) of the GPU C_l against the FP64 oracle on whole
+    points of the workload at every ell_step-th multipole: the maximum, and the maximum per multipole."""
+    import numpy as np
+    from oracle import fftlog
+    sub = dict(wl)
+    sub["ell_idx"] = np.ascontiguousarray(wl["ell_idx"][:, ::ell_step])
+    sub["n_ell"] = np.full(wl["batch"], sub["ell_idx"].shape[1], np.int32)
+    per_ell = None
+    for b in points:
+        C = fftlog.cl(sub, b)
+        T = int(wl["n_tracers"][b])
+        iu = np.triu_indices(T)
+        g = C_gpu[b, ::ell_step][:, :C.shape[1]]
+        diag = {int(i): C[:, p] for p, (i, j) in enumerate(zip(*iu)) if i == j}
+        e = np.zeros(C.shape[0])
+        for p, (i, j) in enumerate(zip(*iu)):
+            e = np.maximum(e, np.abs(g[:, p] - C[:, p]) / np.sqrt(diag[int(i)] * diag[int(j)]))
+        per_ell = e if per_ell is None else np.maximum(per_ell, e)
+    return float(per_ell.max()), per_ell
+
+
 def extra_configs(steps):
     """The other measured shapes: one point (latency), the ragged batch (256 points of 6, 10 or 15
     tracers and 50..103 multipoles), the 30-tracer split-precision batch (64 points, 465
@@ -159,6 +230,8 @@ def extra_configs(steps):
     f64 = dict(dtype=torch.float64, device="cuda:0")
 
     def fwd_bwd(wl, precision=None, backward=True, tune=False):
+        """Forward (and forward + backward): the median of 200 captured-graph replays, and the mean of
+        eager calls beside it."""
         plan = Plan.for_workload(wl, precision=precision)
         inp = device_inputs(wl, "cuda:0")
         B = int(wl["batch"])
@@ -167,7 +240,11 @@ def extra_configs(steps):
                              device="cuda:0")
         if tune:
             plan.autotune(inp, dC if backward else None)
-        r = {"forward_ms": time_ms(lambda: plan.cl(inp, C), steps, stream)}
+        r = {"forward_ms_eager": time_ms(lambda: plan.cl(inp, C), steps, stream)}
+        gf = capture(lambda: plan.cl(inp, C))
+        graph_ms(gf, 20, 0, stream)
+        r["forward_ms"] = graph_median_ms(gf, 200, stream)
+        del gf
         if backward:
             g = {"pk": torch.empty((B, len(wl["k"])), **f64), "bias": torch.empty((B, plan.max_tracers), **f64),
                  "nz": torch.empty((B, plan.max_tracers, len(wl["z_nz"])), **f64),
@@ -176,19 +253,45 @@ def extra_configs(steps):
             def step():
                 plan.cl(inp, C)
                 plan.backward_into(inp, dC, g, reuse_forward=True)
-            r["fwd_bwd_ms"] = time_ms(step, steps, stream)
-        return r, B
+            r["fwd_bwd_ms_eager"] = time_ms(step, steps, stream)
+            gb = capture(step)
+            graph_ms(gb, 20, 0, stream)
+            r["fwd_bwd_ms"] = graph_median_ms(gb, 200, stream)
+            del gb
+        r["timing"] = "median of 200 captured-graph replays after 20 (eager means beside)"
+        r["launch"] = plan.launch_config()
+        return r, B, C
 
-    r, B = fwd_bwd(synth.make_workload("cfg1"))
+    r, B, _ = fwd_bwd(synth.make_workload("cfg1"))
     out["one_point_latency"] = dict(r, workload="1 point, 15 tracers x 103 l, N_k = N_chi = 1024, FP32")
-    r, B = fwd_bwd(synth.make_workload("cfg3"), tune=True)
+    wl3 = synth.make_workload("cfg3")
+    r, B, _ = fwd_bwd(wl3, tune=True)
+    # algorithmic flops of the windows + projection over the ragged batch (each point its own T and L)
+    f3 = sum(fused_kernel_flops(int(T), int(L), 1, wl3["n_chi"], len(wl3["k"]))
+             for T, L in zip(wl3["n_tracers"], wl3["n_ell"]))
     out["ragged_batch"] = dict(r, points_per_s_fwd_bwd=B / (r["fwd_bwd_ms"] * 1e-3),
                                points_per_s_forward=B / (r["forward_ms"] * 1e-3),
+                               roofline={"bound": "alu", "scope": "whole forward call (assembly, coefficients, "
+                                         "windows + projection) against the windows' algorithmic flops",
+                                         "achieved": f3 / (r["forward_ms"] * 1e-3) / 1e12,
+                                         "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                         "frac": f3 / (r["forward_ms"] * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS},
                                workload="256 points of 6/10/15 tracers and 50..103 l, FP32, autotuned launch")
-    r, B = fwd_bwd(synth.make_workload("cfg4"), precision="split_bf16", backward=False)
-    out["split_bf16_30_tracers"] = dict(r, points_per_s_forward=B / (r["forward_ms"] * 1e-3),
-                                        workload="64 points x 30 tracers (465 spectra) x 200 l, N_k = N_chi = 2048, "
-                                                 "BF16 hi+lo projection")
+    wl4 = synth.make_workload("cfg4")
+    r, B, C4 = fwd_bwd(wl4, precision="split_bf16", backward=False)
+    f4 = fused_kernel_flops(30, 200, B, wl4["n_chi"], len(wl4["k"]))
+    err, per_ell = split_error(wl4, C4.cpu().numpy().astype(np.float64))
+    out["split_bf16_30_tracers"] = dict(
+        r, points_per_s_forward=B / (r["forward_ms"] * 1e-3),
+        max_rel_err_vs_oracle=err,
+        rel_err_per_sampled_ell=[float(x) for x in per_ell],
+        err_sample="point 0, all 465 spectra at every 20th of the 200 multipoles, FP64 FFTLog oracle, "
+                   "|dC^{ij}| / sqrt(C^{ii} C^{jj})",
+        roofline={"bound": "alu", "scope": "whole forward call against the windows' algorithmic flops",
+                  "achieved": f4 / (r["forward_ms"] * 1e-3) / 1e12, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                  "unit": "TFLOP/s", "frac": f4 / (r["forward_ms"] * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS},
+        workload="64 points x 30 tracers (465 spectra) x 200 l, N_k = N_chi = 2048, BF16 hi+lo projection")
+    del C4
     # scale-dependent growth D(k, z) at the paper's default of 200 k nodes (swiftcl_cl_kgrowth)
     wl = synth.scale_dependent_growth(synth.make_workload("cfg1_batch", batch=256), 200)
     plan = Plan.for_workload(wl, n_interp=200)
@@ -240,9 +343,19 @@ def cpu_baseline(wl, seconds, plan_out):
         if time.perf_counter() - t0 >= seconds or n >= wl["batch"]:
             break
     dt = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "sets/s", "cores": int(cores), "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": f"{n} point(s) of the benchmark batch, full 120 spectra x 103 l each, "
-                      f"FP64 FFTLog oracle (NumPy/SciPy), {dt:.1f} s"}, max(errs)
+                      f"FP64 FFTLog oracle (NumPy/SciPy, {int(cores)} BLAS threads on {model}), {dt:.1f} s"}, max(errs)
 
 
 def main():
@@ -301,24 +414,22 @@ def main():
         # the backward keeps the forward's assembly and FFTLog state (same inputs)
         plan.backward_into(inp, dC, grads, reuse_forward=True)
 
+    # eager calls (the mean of K after W), for reference
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for _ in range(args.steps):
-        step()
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / args.steps
-    # forward alone, same protocol
-    start.record(stream)
-    for _ in range(args.steps):
-        plan.cl(inp, out)
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms_fwd = start.elapsed_time(end) / args.steps
+    ms_eager = time_ms(step, args.steps, stream)
+    ms_fwd_eager = time_ms(lambda: plan.cl(inp, out), args.steps, stream)
+    # the timed steps: one step captured in a HIP graph, W warm-up replays, then K replays between two
+    # HIP events (value); the median of 200 individually timed replays beside it
+    g_step = capture(step)
+    ms = graph_ms(g_step, args.steps, args.warmup, stream)
+    ms_med = graph_median_ms(g_step, 200, stream)
+    del g_step
+    g_fwd = capture(lambda: plan.cl(inp, out))
+    ms_fwd = graph_ms(g_fwd, args.steps, args.warmup, stream)
+    ms_fwd_med = graph_median_ms(g_fwd, 200, stream)
+    del g_fwd
     flags = plan.device_flags()
 
     fstages = np.mean([plan.cl_timed(inp, out) for _ in range(args.steps)], axis=0)
@@ -339,6 +450,12 @@ def main():
         "value": B / (ms * 1e-3),
         "forward_sets_per_s": B / (ms_fwd * 1e-3),
         "forward_ms_per_step": ms_fwd,
+        "timing": "K replays of the step captured in a HIP graph after W warm-up replays (HIP events around "
+                  "the K); the median of 200 individually timed replays and the mean of K eager calls beside",
+        "ms_per_step_median200": ms_med,
+        "forward_ms_per_step_median200": ms_fwd_med,
+        "ms_per_step_eager": ms_eager,
+        "forward_ms_per_step_eager": ms_fwd_eager,
         "unit": "sets/s",
         "n_gpus": 1,
         "steps": args.steps,

@@ -9,6 +9,8 @@
  *   clustering  f = b n(z) (dz/dchi) D(z),          c = 1                     (Sec. 2.2)
  *   lensing     f = q(chi) D(z) / chi^2,             c = sqrt((l+2)!/(l-2)!) / k^2   (Sec. 2.3,
  *               q = eq. "tomographic lens efficiency")
+ *   CMB lensing f = 1.5 Om (H0/c)^2 (1+z) (chi_* - chi) / (chi chi_*) D(z),  c = l(l+1) / k^2
+ *               (Sec. 2.4: one source plane at the last-scattering distance chi_*)
  * The chi integral uses an FFTLog decomposition of f in ln chi (Sec. 3.1, eq. FFTLog) and the
  * analytic integral of chi^p j_l(k chi) (eq. int_jl, with the denominator Gamma((2+l-p)/2));
  * the k integral runs over the caller's k nodes (Sec. 3.2).
@@ -45,7 +47,12 @@ typedef enum {
   SWIFTCL_E_UNSUPPORTED = -5  /* a size this build does not handle (e.g. n_chi) */
 } swiftcl_status;
 
-enum { SWIFTCL_CLUSTERING = 0, SWIFTCL_LENSING = 1 };
+/* Tracer kinds.  The CMB-lensing kernel ends at chi_* = chi(z_geom[n_zg-1]): the top of the geometry
+ * grid is the last-scattering surface (z_*), so a plan that carries CMB lensing continues its
+ * geometry grid to z_*; the kernel falls linearly to zero there, so its last node takes the
+ * trapezoid weight of a linear end, 1/2 + theta/2, in place of a jump's 1/2 + theta. */
+enum { SWIFTCL_CLUSTERING = 0, SWIFTCL_LENSING = 1, SWIFTCL_CMB_LENSING = 2 };
+#define SWIFTCL_NKINDS 3
 
 typedef enum {
   SWIFTCL_FP64 = 0,       /* FFTs and contraction in double; outputs double */
@@ -64,8 +71,11 @@ typedef struct {
   int32_t n_bands;      /* number of multipole bands, 1..SWIFTCL_MAX_BANDS                      */
   double band_ell_lo[SWIFTCL_MAX_BANDS]; /* band j holds band_ell_lo[j] <= l < band_ell_lo[j+1];
                                             band_ell_lo[0] <= min(ell), strictly increasing     */
-  double fftlog_b[2][SWIFTCL_MAX_BANDS]; /* FFTLog bias b per kind and band (Sec. 3.1); every l of
-                                            the band needs -l-1 < b < 1 (eq. int_jl)            */
+  double fftlog_b[SWIFTCL_NKINDS][SWIFTCL_MAX_BANDS]; /* FFTLog bias b per tracer kind and band
+                                            (Sec. 3.1); every l of the band needs -l-1 < b < 1
+                                            (eq. int_jl); plans with rsd or magnification also need
+                                            1-l < b for the clustering row (they evaluate eq.
+                                            int_jl at l-2, and at b-2)                           */
   double taper_frac;    /* cosine taper of c_n over the top fraction of |n| ("smoothing at the
                            tails", Sec. 3.1); 0 = none; in [0, 1)                              */
   int32_t n_k;          /* number of k nodes (Sec. 3.2: the k integral runs over all of them)   */
@@ -98,13 +108,16 @@ typedef struct {
 typedef struct {
   int32_t batch;             /* B, 1..max_batch (0 is refused with SWIFTCL_E_INVALID)            */
   const int32_t* n_tracers;  /* [B] tracers of each point, 1..max_tracers                       */
-  const int32_t* kind;       /* [B][max_tracers] SWIFTCL_CLUSTERING or SWIFTCL_LENSING           */
+  const int32_t* kind;       /* [B][max_tracers] SWIFTCL_CLUSTERING, SWIFTCL_LENSING or
+                                SWIFTCL_CMB_LENSING; any other value raises FLAG_BAD_INDEX of
+                                swiftcl_device_flags and that tracer's windows and C_l are 0     */
   const int32_t* n_ell;      /* [B] multipoles of each point, 1..max_ell                         */
   const int32_t* ell_idx;    /* [B][max_ell] indices into the plan's ell union                   */
   const double* chi_z;       /* [B][n_zg] comoving distance chi(z_geom) in Mpc/h, increasing     */
   const double* D_z;         /* [B][n_zg] growth D(z_geom), D(0) = 1 (z_fid = 0)                 */
-  const double* omega_m;     /* [B] Omega_m of the lensing prefactor (eq. lens efficiency)       */
-  const double* nz;          /* [B][max_tracers][n_zs] n(z) samples per unit z                  */
+  const double* omega_m;     /* [B] Omega_m of the lensing prefactors (eq. lens efficiency, Sec. 2.4) */
+  const double* nz;          /* [B][max_tracers][n_zs] n(z) samples per unit z (ignored for
+                                CMB-lensing tracers)                                             */
   const double* bias;        /* [B][max_tracers] linear bias b_1 (clustering only)              */
   const double* pk;          /* [B][n_k] P(k, z_fid) on the plan's k nodes, (Mpc/h)^3, > 0      */
   const double* ia;          /* [B][n_zg] NLA amplitude A_IA(z_geom) of the lensing tracers, or NULL
@@ -115,6 +128,17 @@ typedef struct {
                                 tracers (eq. magnification bias: l(l+1)/k^2 C_g int dchi / chi^2
                                 q_g D j_l joins their window, q_g the lens efficiency of their own
                                 n(z)), or NULL; needs a plan built with magnification = 1            */
+  const double* kernel_chi;  /* [B][max_tracers][n_chi] or NULL: kernel samples in place of the
+                                assembly from n(z), D(z), bias and the lensing integrals.  Entry m
+                                is f_t(chi_m) of Sec. 2.1 (the radial kernel per unit chi, growth
+                                and bias included) at chi_m = chi(z_geom[0]) e^{(m - edge_node)
+                                Delta}, m = 0..n_chi-1 (chi(z_geom[0]) = chi_z[b][0]); the library
+                                applies the FFTLog tilt (chi_m / chi_0)^{-b} and nothing else (no
+                                support cut, no edge weights: the samples are used as the FFT takes
+                                them).  kind still selects c(l, k).  In this mode nz, bias, D_z, ia
+                                and mag are not read (may be NULL; omega_m too); swiftcl_cl_backward
+                                gives dpk only, and swiftcl_cl_kgrowth, swiftcl_cl_limber and plans
+                                with rsd or magnification refuse it with SWIFTCL_E_UNSUPPORTED    */
 } swiftcl_inputs;
 
 /* Build a plan: validates the descriptor, builds the log-chi grid, the FP64 table of Bessel

@@ -109,11 +109,12 @@ def edge_weights(geo: PointGeometry, method: Method):
     return nodes, W
 
 
-def sampled_kernels(geo: PointGeometry, method: Method, rsd=False, mag=False):
+def sampled_kernels(geo: PointGeometry, method: Method, rsd=False, mag=False, return_nodes=False):
     """Step 1: w_m f_t(chi_m) on the grid, with the edge weights of readings R5 and R21 (with
     rsd=True the RSD kernels of eq. RSD instead, with mag=True the magnification kernels).
 
-    Returns (chi0, chi_m, F) with F of shape [T, N].
+    Returns (chi0, chi_m, F) with F of shape [T, N]; with return_nodes=True also the support nodes
+    m0..m1 and their redshifts z(chi_m).
     """
     chi0, chi = chi_grid(geo, method)
     nodes, W = edge_weights(geo, method)
@@ -124,6 +125,8 @@ def sampled_kernels(geo: PointGeometry, method: Method, rsd=False, mag=False):
     z[1:] = geo.z_of_chi(np.minimum(chi[nodes[1:]], geo.chi_max))
     for t in range(T):
         F[t, nodes] = W[t] * (geo.f_rsd_of_z(t, z) if rsd else (geo.f_mag_of_z(t, z) if mag else geo.f_of_z(t, z)))
+    if return_nodes:
+        return chi0, chi, F, nodes, z
     return chi0, chi, F
 
 

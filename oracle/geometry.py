@@ -26,7 +26,7 @@ Readings (the paper does not fix them):
 from __future__ import annotations
 
 import numpy as np
-from scipy.interpolate import CubicSpline
+from scipy.interpolate import CubicSpline, PPoly
 
 H0_OVER_C = 1.0 / 2997.92458  # h/Mpc
 KIND_CLUSTERING, KIND_LENSING, KIND_CMB_LENSING = 0, 1, 2
@@ -67,14 +67,24 @@ class PointGeometry:
         return np.where(inside, self.n_spl[t](np.clip(z, self.z_nz[0], self.z_nz[-1])), 0.0)
 
     def z_of_chi(self, chi):
-        """Invert the chi(z) spline on the geometry range (one root per value)."""
+        """Invert the chi(z) spline on the geometry range (one root per value).
+
+        The root is that of the cubic piece whose end values bracket chi (the spline's values at
+        the knots are the chi samples, increasing); should that piece not give exactly one root,
+        the whole spline is solved and must give exactly one."""
         chi = np.atleast_1d(np.asarray(chi, float))
         out = np.empty_like(chi)
+        knots = self.chi_spl.x
+        at_knots = self.chi_spl(knots)
         for i, c in enumerate(chi):
-            r = self.chi_spl.solve(c, extrapolate=False)
-            r = r[(r >= self.z_min - 1e-12) & (r <= self.z_max + 1e-12)]
+            j = int(np.clip(np.searchsorted(at_knots, c, side="right") - 1, 0, len(knots) - 2))
+            piece = PPoly(self.chi_spl.c[:, j:j + 1], knots[j:j + 2])
+            r = piece.solve(c, extrapolate=False)
             if len(r) != 1:
-                raise ValueError(f"chi={c} is not inside the geometry range")
+                r = self.chi_spl.solve(c, extrapolate=False)
+                r = r[(r >= self.z_min - 1e-12) & (r <= self.z_max + 1e-12)]
+                if len(r) != 1:
+                    raise ValueError(f"chi={c} is not inside the geometry range")
             out[i] = r[0]
         return out
 

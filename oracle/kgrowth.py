@@ -11,8 +11,8 @@ The coefficients are computed at N_interp nodes in k and interpolated to the oth
 
 Steps, in that order:
   1. at every node kappa_a: the kernels f_t(chi) D(kappa_a, z(chi)) sampled on the log-chi grid
-     exactly as for scale-free growth, and their FFTLog coefficients c_n^(a) (per tracer kind and
-     multipole band, fftlog.fftlog_coefficients);
+     exactly as for scale-free growth (every kind: clustering, lensing, CMB lensing), and their
+     FFTLog coefficients c_n^(a) (per tracer kind and multipole band, fftlog.fftlog_coefficients);
   2. c_n(k_j) at every k of the user's grid by interpolation along ln k;
   3. Delta_l^t(k_j) by the direct sum over n of fftlog.py, with c_n(k_j) in place of c_n;
   4. C_l by the k-sum of fftlog.py.
@@ -47,7 +47,8 @@ def node_geometries(wl, b):
     T = int(wl["n_tracers"][b])
     ia = wl.get("ia")
     geos = [PointGeometry(wl["z_geom"], wl["chi_z"][b], wl["D_kz"][b, a], wl["omega_m"][b], wl["z_nz"],
-                          wl["nz"][b, :T], wl["kind"][b, :T], wl["bias"][b, :T], ia=None if ia is None else ia[b])
+                          wl["nz"][b, :T], wl["kind"][b, :T], wl["bias"][b, :T], ia=None if ia is None else ia[b],
+                          z_star=wl.get("z_star"))
             for a in range(wl["D_kz"].shape[1])]
     # every node has the point's chi(z): solve z(chi) once and share the roots
     solve = geos[0].z_of_chi
@@ -85,7 +86,7 @@ def windows_point(geos, ells, method: fftlog.Method):
     chi0, chi = sampled[0][0], sampled[0][1]
     W = np.zeros((len(ells), T, method.n_k))
     ells = np.asarray(ells, float)
-    for kind in (0, 1):
+    for kind in (0, 1, 2):
         ts = np.nonzero(kinds == kind)[0]
         if len(ts) == 0:
             continue

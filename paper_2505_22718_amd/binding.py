@@ -22,6 +22,8 @@ STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_DOMAIN", -3: "E_NOMEM", -4: "E_
 
 SWIFTCL_CLUSTERING = 0
 SWIFTCL_LENSING = 1
+SWIFTCL_CMB_LENSING = 2
+NKINDS = 3
 SWIFTCL_BWD_REUSE_FORWARD = 1
 SWIFTCL_FP64 = 0
 SWIFTCL_FP32 = 1
@@ -38,7 +40,7 @@ class swiftcl_plan_desc(ctypes.Structure):
         ("edge_node", ctypes.c_int32),
         ("n_bands", ctypes.c_int32),
         ("band_ell_lo", ctypes.c_double * MAX_BANDS),
-        ("fftlog_b", (ctypes.c_double * MAX_BANDS) * 2),
+        ("fftlog_b", (ctypes.c_double * MAX_BANDS) * NKINDS),
         ("taper_frac", ctypes.c_double),
         ("n_k", ctypes.c_int32),
         ("k", _dp),
@@ -74,6 +76,7 @@ class swiftcl_inputs(ctypes.Structure):
         ("pk", ctypes.c_void_p),
         ("ia", ctypes.c_void_p),
         ("mag", ctypes.c_void_p),
+        ("kernel_chi", ctypes.c_void_p),
     ]
 
 

@@ -5,6 +5,8 @@
 //   lensing    (Sec. 2.3, eq. tomographic lens efficiency written in z):
 //              f = q D / chi^2,  q = 1.5 Om (H0/c)^2 chi (1+z) [I0(z) - chi I1(z)],
 //              I0 = int_z^zmax n dz',  I1 = int_z^zmax n / chi(z') dz'
+//   CMB lensing (Sec. 2.4): f = 1.5 Om (H0/c)^2 (1+z) (chi_* - chi) / (chi chi_*) D, chi_* the top of
+//              the geometry grid; its last node takes the linear-end weight 1/2 + theta/2
 // Sampled inputs are continued by natural cubic splines; z(chi) inverts the chi(z) spline.
 // Output g[b][t][band][m] = w_m f(chi_m) exp(-b_band m Delta) on chi_m = chi_0 e^{m Delta},
 // with w = 1/2 on the lower support edge (node m0), 1/2 + theta on the last node m1 and zero
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
     pt[PT_LNK0CHI0] = log(P.k0) + lchi0;
     pt[PT_M1] = m1d;
     pt[PT_THETA] = theta;
-    for (int kind = 0; kind < 2; ++kind)
+    for (int kind = 0; kind < SWIFTCL_NKINDS; ++kind)
       for (int bi = 0; bi < SWIFTCL_MAX_BANDS; ++bi)
         pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] = exp(-P.fftlog_b[kind][bi] * lchi0);
   }
@@ -171,7 +173,9 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
     wave_spline(nzr + (size_t)c * nzs, P.lu_nz, nzs, mn + (size_t)c * nzs, lane);
   __syncthreads();
   for (int i = tid; i < (min(g1, Tb) - g0) * nzs; i += nth) P.m_n[((size_t)b * T + g0) * nzs + i] = mn[i];
-  // clustering tracers and padded slots
+  // clustering and CMB-lensing tracers, tracers of an unknown kind and padded slots
+  const double pref = 1.5 * in.omega_m[b] * SWIFTCL_H0_OVER_C * SWIFTCL_H0_OVER_C;
+  const double chis = chi[nzg - 1];  // chi_* of the CMB-lensing kernel: the top of the geometry grid
 #pragma unroll
   for (int k = 0; k < MAXN; ++k) {
     if (!ns[k].active) continue;
@@ -180,30 +184,38 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
     double dD = 0.0;
     if (P.rsd) (void)spline_at(zg, zgih, Dz, mD, ns[k].ig, ns[k].z, &dD);
     for (int t = g0; t < g1; ++t) {
-      const bool clus = t < Tb && in.kind[(size_t)b * T + t] == SWIFTCL_CLUSTERING;
-      if (t < Tb && !clus) {
+      const int kd = t < Tb ? in.kind[(size_t)b * T + t] : -1;  // -1: padded slot
+      if (kd == SWIFTCL_LENSING) {
         for (int bi = 0; bi < nb; ++bi) {
           if (P.rsd) ((R*)P.g_r)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
           if (P.mag) ((R*)P.g_mu)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
         }
         continue;
       }
+      const bool known = kd == SWIFTCL_CLUSTERING || kd == SWIFTCL_CMB_LENSING;
+      if (t < Tb && !known && m == m0) atomicOr(P.flags, FLAG_BAD_INDEX);  // its samples stay zero
       // (the magnification samples of clustering tracers come from k_geom_lens)
-      if (t >= Tb && P.mag)
+      if (kd != SWIFTCL_CLUSTERING && P.mag)
         for (int bi = 0; bi < nb; ++bi) ((R*)P.g_mu)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)0;
-      double f = 0.0, fr = 0.0;
-      if (t < Tb) {
+      double f = 0.0, fr = 0.0, w = ns[k].w;
+      if (kd == SWIFTCL_CLUSTERING) {
         const double n = ns[k].inz < 0 ? 0.0
                          : spline_at(zs, zsih, nzr + (size_t)(t - g0) * nzs, mn + (size_t)(t - g0) * nzs, ns[k].inz,
                                      ns[k].z, nullptr);
         f = in.bias[(size_t)b * T + t] * n * ns[k].D / ns[k].dchi;
         fr = (1.0 + ns[k].z) * dD * n / ns[k].dchi;
+      } else if (kd == SWIFTCL_CMB_LENSING) {
+        // Sec. 2.4: one source plane at chi_*; the kernel falls linearly to zero there, so the last
+        // node takes the trapezoid weight of a linear end, 1/2 + theta/2
+        const double x = ns[k].chiz;
+        f = pref * (1.0 + ns[k].z) * (chis - x) / (x * chis) * ns[k].D;
+        if (m == m1 && m1 > m0) w = 0.5 + 0.5 * theta;
       }
+      const int kc = known ? kd : SWIFTCL_CLUSTERING;
       for (int bi = 0; bi < nb; ++bi) {
-        g[(((size_t)b * T + t) * nb + bi) * N + m] =
-            (R)(ns[k].w * f * P.ebm[(size_t)bi * N + m]);
+        g[(((size_t)b * T + t) * nb + bi) * N + m] = (R)(w * f * P.ebm[((size_t)kc * nb + bi) * N + m]);
         if (P.rsd)
-          ((R*)P.g_r)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)(ns[k].w * fr * P.ebm[(size_t)bi * N + m]);
+          ((R*)P.g_r)[(((size_t)b * T + t) * nb + bi) * N + m] = (R)(w * fr * P.ebm[(size_t)bi * N + m]);
       }
     }
   }
@@ -229,8 +241,9 @@ __global__ __launch_bounds__(512) void k_geom_lens(plan_dev P, swiftcl_inputs in
   const int Tb = in.n_tracers[b] < T ? in.n_tracers[b] : T;
   if (t >= Tb) return;
   // lensing tracers, and clustering tracers whose magnification needs their own lens efficiency
-  const bool lensing = in.kind[(size_t)b * T + t] == SWIFTCL_LENSING;
-  if (!lensing && !(P.mag && in.mag)) return;
+  const int kd = in.kind[(size_t)b * T + t];
+  const bool lensing = kd == SWIFTCL_LENSING;
+  if (!lensing && !(kd == SWIFTCL_CLUSTERING && P.mag && in.mag)) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int nzg = P.n_zg, nzs = P.n_zs, nb = P.n_bands, N = P.N, nu = P.n_union;
   double* zg = sh;              // [nzg]
@@ -307,7 +320,71 @@ __global__ __launch_bounds__(512) void k_geom_lens(plan_dev P, swiftcl_inputs in
   }
 }
 
+// Kernel samples given by the caller (inputs.kernel_chi): the per-point scalars from chi(z_min) alone
+// (chi_0, the FFTLog phases and chi_0^{-b}), then g = f(chi_m) e^{-b m Delta} on every node, no support
+// cut and no edge weights.  One workgroup per point.
+template <typename R>
+__global__ __launch_bounds__(256) void k_kernel_samples(plan_dev P, swiftcl_inputs in) {
+  const int b = blockIdx.x;
+  if (b >= in.batch) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int T = P.max_tracers, nb = P.n_bands, N = P.N;
+  int Tb = in.n_tracers[b];
+  if (Tb < 1 || Tb > T) {
+    if (tid == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+    Tb = Tb < 1 ? 0 : T;
+  }
+  const double chi_min = in.chi_z[(size_t)b * P.n_zg];
+  const bool okchi = chi_min > 0.0 && isfinite(chi_min);
+  const double chi0 = okchi ? chi_min * exp(-(double)P.m0 * P.delta) : 1.0;
+  const double lchi0 = log(chi0);
+  const double dphi = -2.0 * M_PI * (log(P.k0) + lchi0) / ((double)N * P.delta);
+  double2* ph = (double2*)P.phase + (size_t)b * (N / 2);
+  for (int n = tid; n < N / 2; n += nth) {
+    double sn, cs;
+    sincos(dphi * (double)n, &sn, &cs);
+    ph[n] = make_double2(cs, sn);
+  }
+  if (tid == 0) {
+    if (!okchi) atomicOr(P.flags, FLAG_NONFINITE);
+    double* pt = P.pt + (size_t)b * PT_STRIDE;
+    pt[PT_CHI0] = chi0;
+    pt[PT_LNK0CHI0] = log(P.k0) + lchi0;
+    pt[PT_M1] = (double)(N - 1);
+    pt[PT_THETA] = 0.0;
+    for (int kind = 0; kind < SWIFTCL_NKINDS; ++kind)
+      for (int bi = 0; bi < SWIFTCL_MAX_BANDS; ++bi)
+        pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] = exp(-P.fftlog_b[kind][bi] * lchi0);
+  }
+  R* g = (R*)P.g;
+  bool bad = false;
+  for (int t = 0; t < T; ++t) {
+    const int kd = t < Tb ? in.kind[(size_t)b * T + t] : -1;
+    const bool known = kd >= 0 && kd < SWIFTCL_NKINDS;
+    if (t < Tb && !known && tid == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+    const double* src = in.kernel_chi + ((size_t)b * T + t) * N;
+    for (int m = tid; m < N; m += nth) {
+      double f = 0.0;
+      if (known) {
+        f = src[m];
+        if (!isfinite(f)) {
+          bad = true;
+          f = 0.0;
+        }
+      }
+      for (int bi = 0; bi < nb; ++bi)
+        g[(((size_t)b * T + t) * nb + bi) * N + m] = (R)(f * P.ebm[((size_t)(known ? kd : 0) * nb + bi) * N + m]);
+    }
+  }
+  if (bad) atomicOr(P.flags, FLAG_NONFINITE);
+}
+
 hipError_t launch_assemble(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s) {
+  if (in->kernel_chi) {
+    if (p.precision == SWIFTCL_FP64) hipLaunchKernelGGL(k_kernel_samples<double>, dim3(in->batch), dim3(256), 0, s, p, *in);
+    else hipLaunchKernelGGL(k_kernel_samples<float>, dim3(in->batch), dim3(256), 0, s, p, *in);
+    return hipGetLastError();
+  }
   const size_t lds = geometry_lds_bytes(p), ll = lens_lds_bytes(p);
   const dim3 gl((unsigned)((size_t)in->batch * p.max_tracers));
   if (p.precision == SWIFTCL_FP64) {

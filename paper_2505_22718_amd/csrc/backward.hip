@@ -67,8 +67,8 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   C2<R>* fbuf = stw_l + NTW;                                                              // [NW][FL]
   R* WY = (R*)(smem + ((size_t)NTW + (COMPACT ? 0 : (size_t)NW * FL)) * sizeof(C2<R>));  // [16][vs]
   R* dps = WY + (size_t)16 * vs;                                                          // [nk] (COMPACT)
-  R* kss = dps + nk;            // [2][nb][nk] k scale tables (COMPACT)
-  R* kdx = kss + 2 * nb * nk;   // [2][nb][nk] 2 s kscale of this point: the cotangent scale (COMPACT)
+  R* kss = dps + nk;                          // [kind][nb][nk] k scale tables (COMPACT)
+  R* sq2 = kss + SWIFTCL_NKINDS * nb * nk;     // [nk] 2 s of this point: dW = 2 s Y (COMPACT)
   // G in MFMA operand order: Gp[s][l] = G[l % 16][4 (l / 16) + s] is what lane l feeds at
   // reduction step s (the step covers tracers s, s + 4, s + 8, s + 12, so the W operand reads of
   // 4 rows x 16 k touch distinct banks with the row stride == 4 mod 64)
@@ -94,12 +94,8 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
     for (size_t i = threadIdx.x; i < (size_t)T * nb * M; i += NW * 64) part[i] = mk<R>(0, 0);
   const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
   if (COMPACT) {
-    for (int i = threadIdx.x; i < 2 * nb * nk; i += NW * 64) {
-      const R ks = ((const R*)P.kscale)[i];
-      const R s = sq[i % nk];
-      kss[i] = ks;
-      kdx[i] = (R)2 * s * s * ks;
-    }
+    for (int i = threadIdx.x; i < SWIFTCL_NKINDS * nb * nk; i += NW * 64) kss[i] = ((const R*)P.kscale)[i];
+    for (int i = threadIdx.x; i < nk; i += NW * 64) sq2[i] = (R)2 * sq[i] * sq[i];
   }
   const R* kscale = COMPACT ? (const R*)kss : (const R*)P.kscale;
   const int ntiles = (nk + 15) / 16;
@@ -127,15 +123,14 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   };
   __syncthreads();
 
-  // multipole slot -> (union index, band, F(l)); a bad index is flagged and read as 0
-  auto ell_of = [&](int li, int& ei, int& band, R& Fl) {
+  // multipole slot -> (union index, band); a bad index is flagged and read as 0
+  auto ell_of = [&](int li, int& ei, int& band) {
     ei = in.ell_idx[(size_t)b * Lm + li];
     if (ei < 0 || ei >= P.n_ell) {
       if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
       ei = 0;
     }
     band = P.ell_band[ei];
-    Fl = (R)P.fell[ei];
   };
   // G of multipole slot li (symmetrised cotangent)
   auto load_G = [&](int li) {
@@ -151,14 +146,14 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       Gp[j & 3][16 * (j >> 2) + i] = gv;
     }
   };
-  // (1) W of every tracer of multipole (ei, band, Fl) into its LDS row
-  auto windows = [&](int ei, int band, R Fl) {
+  // (1) W of every tracer of multipole (ei, band) into its LDS row
+  auto windows = [&](int ei, int band) {
     for (int t = wave; t < 16; t += NW) {
       if (t >= Tb) {
         for (int j = lane; j < nk; j += SWIFTCL_WAVE) WY[t * vs + j] = (R)0;
         continue;
       }
-      const int kind = in.kind[(size_t)b * T + t] & 1;
+      const int kind = tracer_kind(in, T, b, t);
       const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
       const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
       C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)t * vs) : fbuf + (size_t)wave * FL;
@@ -175,7 +170,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       wave_c2r<R, M>(v, mine, stw, ln);
       wave_sync();
       const R* ks = kscale + ((size_t)kind * nb + band) * nk;
-      const R F = kind ? Fl : (R)1;
+      const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
 #pragma unroll
       for (int e = 0; e < RL; ++e) {
         const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
@@ -191,11 +186,10 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   // transforms of slot li share a barrier interval with the windows of slot li + 1 (each wavefront
   // only touches its own LDS rows there).
   int ei = 0, band = 0;
-  R Fl = (R)0;
   if (l0 < l1) {
-    ell_of(l0, ei, band, Fl);
+    ell_of(l0, ei, band);
     load_G(l0);
-    windows(ei, band, Fl);
+    windows(ei, band);
   }
   __syncthreads();
   for (int li = l0; li < l1; ++li) {
@@ -238,9 +232,9 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
     }
     // (3) dx = 2 s F k^{-1-b} Y, r2c, dc += h_n conj(X_n) conj(U_l(n))
     for (int t = wave; t < Tb; t += NW) {
-      const int kind = in.kind[(size_t)b * T + t] & 1;
+      const int kind = tracer_kind(in, T, b, t);
       const R* ks = kscale + ((size_t)kind * nb + band) * nk;
-      const R F = kind ? Fl : (R)1;
+      const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
       C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)t * vs) : fbuf + (size_t)wave * FL;
       C2<R> v[RL];
 #pragma unroll
@@ -249,8 +243,9 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
         if (k0 < nk) {
           const C2<R> y2 = *(const C2<R>*)(WY + t * vs + k0);
           if constexpr (COMPACT) {
-            const C2<R> kx = *(const C2<R>*)(kdx + ((size_t)kind * nb + band) * nk + k0);
-            v[e] = mk<R>(F * kx.x * y2.x, F * kx.y * y2.y);
+            const C2<R> kk = *(const C2<R>*)(ks + k0);
+            const C2<R> s2 = *(const C2<R>*)(sq2 + k0);
+            v[e] = mk<R>(F * kk.x * s2.x * y2.x, F * kk.y * s2.y * y2.y);
           } else {
             const C2<R> kk = *(const C2<R>*)(ks + k0);
             const C2<R> s2 = *(const C2<R>*)(sq + k0);
@@ -293,9 +288,9 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
     }
     // (1) for the next slot
     if (li + 1 < l1) {
-      ell_of(li + 1, ei, band, Fl);
+      ell_of(li + 1, ei, band);
       load_G(li + 1);
-      windows(ei, band, Fl);
+      windows(ei, band);
     }
     __syncthreads();
   }
@@ -353,7 +348,7 @@ __global__ __launch_bounds__(256) void k_bwd_coeffs(plan_dev P, swiftcl_inputs i
     for (int e = 0; e < RL; ++e) v[e] = cadd(v[e], src[lane + SWIFTCL_WAVE * e]);
   }
   const double* pt = P.pt + (size_t)b * PT_STRIDE;
-  const int kind = in.kind[(size_t)b * T + t] & 1;
+  const int kind = tracer_kind(in, T, b, t);
   const double scale = pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] / (double)N;
   const double2* ph = (const double2*)P.phase + (size_t)b * M;
 #pragma unroll
@@ -410,7 +405,8 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
   double* seg1 = seg0 + nu;              // [nu]
   double* tmp = seg1 + nu;               // [64]
 
-  const int kind = in.kind[(size_t)b * T + t] & 1;
+  const int kd = in.kind[(size_t)b * T + t];
+  const int kind = tracer_kind(in, T, b, t);  // a tracer of an unknown kind has no cotangent below
   for (int i = tid; i < nzg; i += nth) {
     zg[i] = P.z_geom[i];
     zgih[i] = P.lu_geom[3 * nzg + i];
@@ -457,7 +453,7 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
   };
   const double pref = 1.5 * in.omega_m[b] * SWIFTCL_H0_OVER_C * SWIFTCL_H0_OVER_C;
   double dbl = 0.0;
-  if (kind == SWIFTCL_CLUSTERING) {
+  if (kd == SWIFTCL_CLUSTERING) {
     const double bias = in.bias[(size_t)b * T + t];
     for (int m = m0 + tid; m <= m1; m += nth) {
       node_state s;
@@ -468,7 +464,19 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
       if (s.inz >= 0) spline_value_adjoint(zs, zsih, s.inz, s.z, df * bias * s.D / s.dchi, dny, dnM);
       spline_value_adjoint(zg, zgih, s.ig, s.z, df * bias * n / s.dchi, dDy, dDM);
     }
-  } else {
+  } else if (kd == SWIFTCL_CMB_LENSING) {
+    // Sec. 2.4: f = pref (1+z) (chi_* - chi) / (chi chi_*) D is linear in D alone; its last node
+    // carries the linear-end weight 1/2 + theta/2
+    const double chis = chi[nzg - 1];
+    for (int m = m0 + tid; m <= m1; m += nth) {
+      node_state s;
+      fill(s, m);
+      const double w = (m == m1 && m1 > m0) ? 0.5 + 0.5 * theta : s.w;
+      const double df = df_at(m, w);
+      const double x = s.chiz;
+      spline_value_adjoint(zg, zgih, s.ig, s.z, df * pref * (1.0 + s.z) * (chis - x) / (x * chis), dDy, dDM);
+    }
+  } else if (kd == SWIFTCL_LENSING) {
     double dI0[MAXN], dI1[MAXN];
     int uu[MAXN];
 #pragma unroll
@@ -550,7 +558,7 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
   if (tid == 0 && dbias) {
     double s = 0.0;
     for (int w = 0; w < nth / SWIFTCL_WAVE; ++w) s += tmp[w];
-    dbias[(size_t)b * T + t] = kind == SWIFTCL_CLUSTERING ? s : 0.0;
+    dbias[(size_t)b * T + t] = kd == SWIFTCL_CLUSTERING ? s : 0.0;
   }
   // n spline transpose
   if (wave == 0) wave_spline_adjoint(dny, dnM, P.lu_nz, nzs, lane);
@@ -605,7 +613,7 @@ __global__ __launch_bounds__(256) void k_bwd_point(plan_dev P, swiftcl_inputs in
 size_t bwd_windows_lds(const plan_dev& p) {
   if (p.precision == SWIFTCL_FP64) return windows_cl_lds(p.M, 2, false, true, 8, p.n_k);
   const size_t tw = 2 * (size_t)p.M * 2 * sizeof(float);  // FP32 stages the twiddles (TW = !dp)
-  return tw + ((size_t)16 * compact_vs(p.n_k, p.M) + (size_t)(1 + 4 * p.n_bands) * p.n_k) * sizeof(float);
+  return tw + ((size_t)16 * compact_vs(p.n_k, p.M) + (size_t)(2 + SWIFTCL_NKINDS * p.n_bands) * p.n_k) * sizeof(float);
 }
 
 template <typename R, int M>

@@ -66,8 +66,8 @@ __global__ void k_sqrt_s(plan_dev P, swiftcl_inputs in) {
   const R sq = (R)sqrt(fmax(v, 0.0));
   ((R*)P.sqrt_s)[(size_t)b * P.n_k + j] = sq;
   // kscale * sqrt(s) for every kind and band: the projection scales its windows once
-  for (int kb = 0; kb < 2 * P.n_bands; ++kb)
-    ((R*)P.kss)[((size_t)b * 2 * P.n_bands + kb) * P.n_k + j] = ((const R*)P.kscale)[(size_t)kb * P.n_k + j] * sq;
+  for (int kb = 0; kb < SWIFTCL_NKINDS * P.n_bands; ++kb)
+    ((R*)P.kss)[((size_t)b * SWIFTCL_NKINDS * P.n_bands + kb) * P.n_k + j] = ((const R*)P.kscale)[(size_t)kb * P.n_k + j] * sq;
 }
 
 // FFTLog coefficients: one wavefront per (point, tracer, band) row.  SET 0: the kernels; 1: the RSD
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
   for (int e = 0; e < RL; ++e) v[e] = g2[lane + SWIFTCL_WAVE * e];
   wave_r2c<R, M>(v, lds[wave], tw, lane);
   const double* pt = P.pt + (size_t)b * PT_STRIDE;
-  const int kind = in.kind[(size_t)b * T + t] & 1;
+  const int kind = tracer_kind(in, T, b, t);
   double scale = pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] / (double)N;
   if (SET == 2) scale *= pt[PT_CHI0] * pt[PT_CHI0];
   const double2* ph = (const double2*)P.phase + (size_t)b * M;
@@ -152,7 +152,6 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
   }
   const int vs = COMPACT ? compact_vs(nk, M) : nk + 2;  // row stride of V: rows start on distinct banks
   const int band = P.ell_band[ei];
-  const R Fl = (R)P.fell[ei];
   const int trows = DO_CL ? 16 : T;
   for (int t = wave; t < trows; t += NW) {
     if (t >= Tb) {
@@ -162,7 +161,7 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
       }
       continue;
     }
-    const int kind = in.kind[(size_t)b * T + t] & 1;
+    const int kind = tracer_kind(in, T, b, t);
     const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
     const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
     C2<R>* mine = COMPACT ? (C2<R>*)(V + (size_t)t * vs) : fbuf + (size_t)wave * FL;
@@ -179,8 +178,8 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
     wave_c2r<R, M>(v, mine, stw, ln);
     wave_sync();
     const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
-    const R* kq = (const R*)P.kss + (((size_t)b * 2 + kind) * nb + band) * nk;
-    const R F = kind ? Fl : (R)1;
+    const R* kq = (const R*)P.kss + (((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk;
+    const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
 #pragma unroll
     for (int e = 0; e < RL; ++e) {
       const int j = lane + SWIFTCL_WAVE * e;
@@ -285,8 +284,8 @@ __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && DO_CL && M <= 512) ? 8 : 1
       __syncthreads();
     }
     const int stride = P.sched_stride;
-    const int* offs = P.sched + xcd * stride;
-    const int total = P.sched[SWIFTCL_NXCD * stride + xcd];
+    const int* offs = P.sched + sched_list_index(stride, xcd, 0);
+    const int total = P.sched[sched_total_index(stride, xcd)];
     const int nx = (in.batch - xcd + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
     const int g8 = gridDim.x / SWIFTCL_NXCD;
     // items rest, rest + g8, ...: the blocks of an XCD work on neighbouring items at any time, so
@@ -307,18 +306,18 @@ __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && DO_CL && M <= 512) ? 8 : 1
 }
 
 // Per-XCD compact work lists: offs[x][i] = sum of the multipole counts of points 8 j + x, j < i;
-// the totals follow the eight lists.
+// the totals follow the eight lists (layout: sched_layout.h).
 __global__ void k_schedule(plan_dev P, swiftcl_inputs in) {
   const int x = threadIdx.x;
   if (x >= SWIFTCL_NXCD) return;
-  int* offs = P.sched + x * P.sched_stride;
+  int* offs = P.sched + sched_list_index(P.sched_stride, x, 0);
   int acc = 0, i = 0;
   for (int b = x; b < in.batch; b += SWIFTCL_NXCD, ++i) {
     offs[i] = acc;
     acc += clampi(in.n_ell[b], 0, P.max_ell);
   }
   offs[i] = acc;
-  P.sched[SWIFTCL_NXCD * P.sched_stride + x] = acc;
+  P.sched[sched_total_index(P.sched_stride, x)] = acc;
 }
 
 // Zeros of the padded multipole slots (l >= n_ell[b]) for the persistent launch.
@@ -429,7 +428,6 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
     __syncthreads();
   }
   const int band = P.ell_band[ei];
-  const R Fl = (R)P.fell[ei];
   C2<R>* mine = fbuf + (size_t)wave * FL;
   for (int t = wave; t < 32; t += NW) {
     const size_t rb = (row0 + t) * nk;
@@ -440,7 +438,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
       }
       continue;
     }
-    const int kind = in.kind[(size_t)b * T + t] & 1;
+    const int kind = tracer_kind(in, T, b, t);
     const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
     const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
     C2<R> v[RL];
@@ -474,8 +472,8 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
     asm volatile("" : "+v"(ln));
     ln &= SWIFTCL_WAVE - 1;
     wave_c2r<R, M>(v, mine, stw, ln);
-    const R* kq = (const R*)P.kss + (((size_t)b * 2 + kind) * nb + band) * nk;  // kscale * sqrt(s)
-    const R F = kind ? Fl : (R)1;
+    const R* kq = (const R*)P.kss + (((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk;  // kscale * sqrt(s)
+    const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
 #pragma unroll
     for (int e = 0; e < RL; ++e) {
       const int k0 = 2 * (lane + SWIFTCL_WAVE * e);

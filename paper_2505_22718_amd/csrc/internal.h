@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/swiftcl.h"
+#include "sched_layout.h"
 
 // Per-point scalars written by the spline set-up kernel (FP64), PT_STRIDE doubles per point.
 enum {
@@ -15,9 +16,10 @@ enum {
   PT_LNK0CHI0 = 1,    // ln(k_0 chi_0)
   PT_M1 = 2,          // last node inside the support (as a double)
   PT_THETA = 3,       // fractional position of chi(z_max) above node m1
-  PT_CHI0B = 4,       // chi_0^{-b} for [kind][band]: 2 * SWIFTCL_MAX_BANDS entries
+  PT_CHI0B = 4,       // chi_0^{-b} for [kind][band]: SWIFTCL_NKINDS * SWIFTCL_MAX_BANDS entries
   PT_STRIDE = 16
 };
+static_assert(PT_CHI0B + SWIFTCL_NKINDS * SWIFTCL_MAX_BANDS <= PT_STRIDE, "per-point scalars overflow");
 
 // Device flag bits (swiftcl_device_flags)
 enum { FLAG_SUPPORT_OVERFLOW = 1, FLAG_NONFINITE = 2, FLAG_BAD_INDEX = 4 };
@@ -32,19 +34,19 @@ struct plan_dev {
   int n_union;
   double delta, k0, taper_frac;
   double band_ell_lo[SWIFTCL_MAX_BANDS];
-  double fftlog_b[2][SWIFTCL_MAX_BANDS];
+  double fftlog_b[SWIFTCL_NKINDS][SWIFTCL_MAX_BANDS];
 
   // --- plan-time device tables ---
-  void* U;          // [2][n_ell][M] complex real: Bessel power-law integral U_l(n) (taper folded in)
-  void* kscale;     // [2][n_bands][n_k] real: k^{-1-b} (times k^-2 for lensing)
+  void* U;          // [kind][n_ell][M] complex real: Bessel power-law integral U_l(n) (taper folded in)
+  void* kscale;     // [kind][n_bands][n_k] real: k^{-1-b} (times k^-2 for the lensing kinds)
   void* tw;         // [N] complex real: e^{-2 pi i m / N}
-  double* fell;     // [n_ell] F(l) for lensing
+  double* fell;     // [kind][n_ell] the multipole prefactor: 1, F(l) (lensing), l(l+1) (CMB lensing)
   int* ell_band;    // [n_ell]
   double* kw;       // [n_k] (2/pi) w_j k_j^3
   double* ell_v;    // [n_ell] the multipoles
   double* lnk;      // [n_k] ln k_j
   double* lu_k;     // [4][n_k] natural-spline Thomas factors of the ln k grid and 1/h (Limber P)
-  double* ebm;      // [2][n_bands][N] e^{-b m Delta}: the FFTLog bias factor of chi node m
+  double* ebm;      // [kind][n_bands][N] e^{-b m Delta}: the FFTLog bias factor of chi node m
   double* z_geom;   // [n_zg]
   double* z_nz;     // [n_zs]
   double* lu_geom;  // [4][n_zg] natural-spline Thomas factors (a, 1/pivot, c') and 1/h
@@ -68,7 +70,7 @@ struct plan_dev {
   void* g;          // [B][T][n_bands][N] real: tilted, edge-weighted kernel samples
   void* chat;       // [B][T][n_bands][M] complex real: FFTLog coefficients (phased)
   void* sqrt_s;     // [B][n_k] real: sqrt((2/pi) w k^3 P)
-  void* kss;        // [B][2][n_bands][n_k] real: kscale * sqrt_s, the window-to-V factor
+  void* kss;        // [B][kind][n_bands][n_k] real: kscale * sqrt_s, the window-to-V factor
   int* flags;       // [1]
   // backward workspace
   void* dchat_part; // [bwd_slots][T][n_bands][M] complex real: dc partials per (point, chunk)
@@ -79,7 +81,7 @@ struct plan_dev {
   int fwd_mode;       // 0: one workgroup per (point, multipole slot); 1: persistent, per-XCD lists
   int persist_blocks; // grid of the persistent launch (a multiple of 8)
   int bwd_chunk_mul;  // multiplier of the backward multipole-chunk count (1, 2 or 4)
-  int* sched;         // [8][sched_stride] + [8] totals: per-XCD work lists of the persistent launch
+  int* sched;         // sched_ints(sched_stride): per-XCD work lists of the persistent launch
   int sched_stride;
   // projection path: fused (windows in LDS, <= 16 tracers) or through the workspace below
   int fused;
@@ -105,12 +107,19 @@ struct plan_dev {
   int* kg_ia;         // [n_k] node interval a_j of k_j
   float* kg_w;        // [n_k][4] spline weights of c_a, c_{a+1}, M_a, M_{a+1} at k_j
   float* kg_ip;       // [n_interp] 1 / pivot of the node spline's tridiagonal system
-  float* kg_uh;       // [2][n_ell][M / 16][4][8] U in the GEMM's A-operand order (h_n and signs folded)
+  float* kg_uh;       // [kind][n_ell][M / 16][4][8] U in the GEMM's A-operand order (h_n and signs folded)
   void* kg_c;         // [vchunk][T][n_bands][n_interp][M] complex float: node coefficients
   void* kg_m;         // same layout: their second derivatives along ln k
   int* kg_perm;       // [vchunk][max_ell] multipole slots grouped by band
   int* kg_tile;       // [vchunk][kg_ntile][4] band, first entry of kg_perm, count, 0
 };
+
+// Tracer kind of slot t of point b as the kernels use it: a value outside the three kinds reads as
+// clustering (the assembly flags it, FLAG_BAD_INDEX, and writes zero kernel samples for it).
+__device__ __forceinline__ int tracer_kind(const swiftcl_inputs& in, int T, int b, int t) {
+  const int k = in.kind[(size_t)b * T + t];
+  return (unsigned)k < (unsigned)SWIFTCL_NKINDS ? k : SWIFTCL_CLUSTERING;
+}
 
 struct swiftcl_plan_s {
   plan_dev d{};

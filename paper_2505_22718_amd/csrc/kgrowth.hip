@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_kg_fft(plan_dev P, swiftcl_inputs in, c
     ln &= SWIFTCL_WAVE - 1;
     wave_sync();
     wave_r2c<R, M>(v, mine, stw, ln);
-    const int kind = in.kind[(size_t)b * T + t] & 1;
+    const int kind = tracer_kind(in, T, b, t);
     const double scale = pt[PT_CHI0B + kind * SWIFTCL_MAX_BANDS + bi] / (double)N;
     C2<R>* out = (C2<R>*)P.kg_c + ((((size_t)bl * T + t) * nb + bi) * A + a) * M;
 #pragma unroll
@@ -211,7 +211,7 @@ __device__ __forceinline__ unsigned short bf16_rne_kg(float x) {
 // chunk's 8 K steps as 8 consecutive floats.  Built once per plan.
 __global__ void k_kg_utab(plan_dev P) {
   const int M = P.M;
-  const size_t total = (size_t)2 * P.n_ell * 2 * M;
+  const size_t total = (size_t)SWIFTCL_NKINDS * P.n_ell * 2 * M;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
     const int s = (int)(i & 7), k = (int)((i >> 3) & 3);
     const size_t row_c = i >> 5;  // (kind, multipole, chunk)
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
   const int4 td = ((const int4*)P.kg_tile)[(size_t)bl * NT + tile];
   const int band = td.x, s0 = td.y, cnt = td.z;
   if (cnt <= 0) return;
-  const int kind = in.kind[(size_t)b * T + t] & 1;
+  const int kind = tracer_kind(in, T, b, t);
   const int tid = threadIdx.x, wave = tid / SWIFTCL_WAVE, lane = tid % SWIFTCL_WAVE;
   if (tid < KG_TILE) {
     int li = -1, ei = 0;
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
   }
   // V = F(l) kscale sqrt(s) W into the workspace rows (point, slot, tracer)
   if (!jok) return;
-  const float kqv = ((const float*)P.kss)[(((size_t)b * 2 + kind) * nb + band) * nk + j];
+  const float kqv = ((const float*)P.kss)[(((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk + j];
   const size_t lo_off = (size_t)P.vchunk * Lm * 32 * nk;
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) {
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
       const int r = 16 * rt + 4 * kq + q;
       if (r >= cnt) continue;
       const int li = lis[r];
-      const float F = kind ? (float)P.fell[eis[r]] : 1.f;
+      const float F = (float)P.fell[(size_t)kind * P.n_ell + eis[r]];
       const float x = F * kqv * acc[rt][q];
       const size_t o = (((size_t)bl * Lm + li) * 32 + t) * nk + j;
       if (SPLIT) {

@@ -1,7 +1,8 @@
 // The Limber limit (paper Sec. 2.6, eq. Limber): j_l(k chi) acts as a delta function at
 // k = (l + 1/2) / chi, so for every multipole
 //   C_l^{ij} = int dchi / chi^2 g_i(chi) g_j(chi) P((l + 1/2) / chi),   g = c(l, k) f,
-// with c = 1 for clustering and F(l) / k^2 = F(l) chi^2 / (l + 1/2)^2 for lensing.  The integral
+// with c = 1 for clustering, F(l) / k^2 = F(l) chi^2 / (l + 1/2)^2 for lensing and l(l+1) chi^2 /
+// (l + 1/2)^2 for CMB lensing (Sec. 2.4).  The integral
 // runs on the log-chi nodes of the FFTLog path (dchi = chi dln chi), with the same edge weights:
 //   C_l^{ij} = Delta sum_m w_m g_i(chi_m) g_j(chi_m) P((l + 1/2) / chi_m) / chi_m,
 // P by the natural cubic spline of ln P in ln k (zero outside the k nodes).  The kernels come from
@@ -39,16 +40,18 @@ __global__ __launch_bounds__(64) void k_limber_pk(plan_dev P, swiftcl_inputs in)
 }
 
 // One block per (point, multipole slot).  Per chunk of chi nodes: the weights
-// s_m = Delta P(nu / chi_m) / (chi_m w_m) and H_t(m) = w_m f_t(chi_m) [chi_m^2 for lensing] in LDS
-// (w_m f_t is the band-0 kernel sample without its tilt), then every thread sums its tracer pairs;
-// the lensing factor (F(l) / nu^2) per lensing tracer of the pair is applied at the end.
+// s_m = Delta P(nu / chi_m) / (chi_m w_m) and H_t(m) = w_m f_t(chi_m) [chi_m^2 for the lensing kinds]
+// in LDS (w_m f_t is the band-0 kernel sample without its tilt; the CMB-lensing sample of the last
+// node, which carries the linear-end weight, is brought to w_m), then every thread sums its tracer
+// pairs; the factor c(l) / nu^2 (F(l) or l(l+1)) per lensing-kind tracer of the pair is applied at
+// the end.
 template <typename R>
 __global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R* __restrict__ Cout) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int T = P.max_tracers, Lm = P.max_ell, N = P.N, nb = P.n_bands, nk = P.n_k;
   R* H = (R*)smem;             // [T][LB_CH]
   R* s = H + (size_t)T * LB_CH;  // [LB_CH]
-  int* lens = (int*)(s + LB_CH);  // [T]
+  int* kinds = (int*)(s + LB_CH);  // [T] tracer kinds
   const int b = blockIdx.x / Lm, li = blockIdx.x % Lm;
   if (b >= in.batch) return;
   const int npair = T * (T + 1) / 2;
@@ -64,7 +67,7 @@ __global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R
     if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
     ei = 0;
   }
-  for (int t = threadIdx.x; t < T; t += blockDim.x) lens[t] = t < Tb ? (in.kind[(size_t)b * T + t] & 1) : 0;
+  for (int t = threadIdx.x; t < T; t += blockDim.x) kinds[t] = t < Tb ? tracer_kind(in, T, b, t) : 0;
   __syncthreads();
   const double nu = P.ell_v[ei] + 0.5;
   const double lnu = log(nu);
@@ -109,13 +112,14 @@ __global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R
       const int m = mc + idx;
       double h = 0.0;
       if (t < Tb && m <= m1) {
-        const int kind = in.kind[(size_t)b * T + t] & 1;
+        const int kind = kinds[t];
         const double gv = (double)((const R*)P.g)[(((size_t)b * T + t) * nb) * N + m];
         h = gv / P.ebm[((size_t)kind * nb) * N + m];
-        if (kind) {
+        if (kind != SWIFTCL_CLUSTERING) {
           const double chi = exp(lchi0 + (double)m * P.delta);
           h *= chi * chi;
         }
+        if (kind == SWIFTCL_CMB_LENSING && m == m1 && m1 > m0) h *= (0.5 + theta) / (0.5 + 0.5 * theta);
       }
       H[(size_t)t * LB_CH + idx] = (R)h;
     }
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R
       acc[q] = a;
     }
   }
-  const double al = P.fell[ei] / (nu * nu);
+  const double inu2 = 1.0 / (nu * nu);
 #pragma unroll
   for (int q = 0; q < MAXP; ++q) {
     const int p = threadIdx.x + 256 * q;
@@ -140,8 +144,8 @@ __global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R
     R v = (R)0;
     if (i < Tb && j < Tb) {
       double f = (double)acc[q];
-      if (lens[i]) f *= al;
-      if (lens[j]) f *= al;
+      if (kinds[i]) f *= P.fell[(size_t)kinds[i] * P.n_ell + ei] * inu2;
+      if (kinds[j]) f *= P.fell[(size_t)kinds[j] * P.n_ell + ei] * inu2;
       v = (R)f;
     }
     c[p] = v;

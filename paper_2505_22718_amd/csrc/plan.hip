@@ -76,41 +76,50 @@ __device__ zd zlgamma(zd z) {
   return zsub(r, acc);
 }
 
-// U_l(n) = sqrt(pi) 2^{p-1} Gamma((1+l+p)/2) / Gamma((2+l-p)/2) * taper(n),  p = b + i eta_n,
-// eta_n = 2 pi n / (N Delta), n = 0..M-1.  (eq. int_jl with the corrected denominator; the
-// k^{-1-p} factor is applied on the k side.)
+// FFTLog biases of every kind and band, passed by value to the table kernels.
+struct bias_table {
+  double b[SWIFTCL_NKINDS][SWIFTCL_MAX_BANDS];
+};
+
+// U_l(n) = sqrt(pi) 2^{p-1} Gamma((1+l+p)/2) / Gamma((2+l-p)/2) at p = b + i eta (eq. int_jl with the
+// corrected denominator; the k^{-1-p} factor is applied on the k side).
+__device__ inline zd u_value(double l, double b, double eta) {
+  zd pa = {0.5 * (1.0 + l + b), 0.5 * eta};
+  zd pb = {0.5 * (2.0 + l - b), -0.5 * eta};
+  zd lg = zsub(zlgamma(pa), zlgamma(pb));
+  // 2^{p-1} = exp((p-1) ln 2)
+  lg.x += (b - 1.0) * 0.69314718055994530942;
+  lg.y += eta * 0.69314718055994530942;
+  const double mag = 1.7724538509055160273 * exp(lg.x);  // sqrt(pi)
+  double sn, cs;
+  sincos(lg.y, &sn, &cs);
+  return {mag * cs, mag * sn};
+}
+
+// the cosine taper of the top fraction of |n| ("smoothing at the tails", Sec. 3.1)
+__device__ inline double taper_of(int n, int M, double taper_frac) {
+  if (!(taper_frac > 0.0)) return 1.0;
+  const double x = (double)n / (double)M, x0 = 1.0 - taper_frac;
+  return x > x0 ? 0.5 * (1.0 + cos(M_PI * fmin((x - x0) / taper_frac, 1.0))) : 1.0;
+}
+
+// U_l(n) * taper(n) for every kind at eta_n = 2 pi n / (N Delta), n = 0..M-1, with the bias of the
+// kind's row in l's band.
 template <typename R>
 __global__ void k_u_table(C2<R>* __restrict__ U, const double* __restrict__ ell, const int* __restrict__ band,
-                          double b0, double b1, double b2, double b3, double c0, double c1, double c2, double c3,
-                          int n_ell, int M, double delta, double taper_frac) {
+                          bias_table bt, int n_ell, int M, double delta, double taper_frac) {
   const int li = blockIdx.x;
   const int n = blockIdx.y * blockDim.x + threadIdx.x;
   if (li >= n_ell || n >= M) return;
   const double l = ell[li];
   const int bi = band[li];
-  const double bclus[4] = {b0, b1, b2, b3};
-  const double blens[4] = {c0, c1, c2, c3};
   const double eta = 2.0 * M_PI * (double)n / (2.0 * M * delta);
-  double tap = 1.0;
-  if (taper_frac > 0.0) {
-    double x = (double)n / (double)M, x0 = 1.0 - taper_frac;
-    if (x > x0) tap = 0.5 * (1.0 + cos(M_PI * fmin((x - x0) / taper_frac, 1.0)));
-  }
-  for (int kind = 0; kind < 2; ++kind) {
-    const double b = kind == 0 ? bclus[bi] : blens[bi];
-    zd pa = {0.5 * (1.0 + l + b), 0.5 * eta};
-    zd pb = {0.5 * (2.0 + l - b), -0.5 * eta};
-    zd lg = zsub(zlgamma(pa), zlgamma(pb));
-    // 2^{p-1} = exp((p-1) ln 2)
-    lg.x += (b - 1.0) * 0.69314718055994530942;
-    lg.y += eta * 0.69314718055994530942;
-    double mag = 1.7724538509055160273 * exp(lg.x) * tap;  // sqrt(pi)
-    double sn, cs;
-    sincos(lg.y, &sn, &cs);
-    if (n == 0) sn = 0.0;
+  const double tap = taper_of(n, M, taper_frac);
+  for (int kind = 0; kind < SWIFTCL_NKINDS; ++kind) {
+    const zd u = u_value(l, bt.b[kind][bi], eta);
     C2<R> v;
-    v.x = (R)(mag * cs);
-    v.y = (R)(mag * sn);
+    v.x = (R)(u.x * tap);
+    v.y = (R)(n == 0 ? 0.0 : u.y * tap);
     U[((size_t)kind * n_ell + li) * M + n] = v;
   }
 }
@@ -118,33 +127,16 @@ __global__ void k_u_table(C2<R>* __restrict__ U, const double* __restrict__ ell,
 // The RSD table (eq. RSD): the integral of chi^p j_l'' is that of chi^p times
 // a j_{l-2} + b j_l + c j_{l+2} (j_l' = (l j_{l-1} - (l+1) j_{l+1}) / (2l+1) applied twice), i.e. the
 // same combination of three U values of eq. int_jl at the clustering bias of l's band.
-__device__ inline zd u_value(double l, double b, double eta) {
-  zd pa = {0.5 * (1.0 + l + b), 0.5 * eta};
-  zd pb = {0.5 * (2.0 + l - b), -0.5 * eta};
-  zd lg = zsub(zlgamma(pa), zlgamma(pb));
-  lg.x += (b - 1.0) * 0.69314718055994530942;
-  lg.y += eta * 0.69314718055994530942;
-  const double mag = 1.7724538509055160273 * exp(lg.x);
-  double sn, cs;
-  sincos(lg.y, &sn, &cs);
-  return {mag * cs, mag * sn};
-}
-
 template <typename R>
 __global__ void k_u_rsd(C2<R>* __restrict__ UR, const double* __restrict__ ell, const int* __restrict__ band,
-                        double b0, double b1, double b2, double b3, int n_ell, int M, double delta, double taper_frac) {
+                        bias_table bt, int n_ell, int M, double delta, double taper_frac) {
   const int li = blockIdx.x;
   const int n = blockIdx.y * blockDim.x + threadIdx.x;
   if (li >= n_ell || n >= M) return;
   const double l = ell[li];
-  const double bclus[4] = {b0, b1, b2, b3};
-  const double b = bclus[band[li]];
+  const double b = bt.b[SWIFTCL_CLUSTERING][band[li]];
   const double eta = 2.0 * M_PI * (double)n / (2.0 * M * delta);
-  double tap = 1.0;
-  if (taper_frac > 0.0) {
-    double x = (double)n / (double)M, x0 = 1.0 - taper_frac;
-    if (x > x0) tap = 0.5 * (1.0 + cos(M_PI * fmin((x - x0) / taper_frac, 1.0)));
-  }
+  const double tap = taper_of(n, M, taper_frac);
   const double am = l * (l - 1.0) / ((2.0 * l - 1.0) * (2.0 * l + 1.0));
   const double a0 = -(2.0 * l * l + 2.0 * l - 1.0) / ((2.0 * l - 1.0) * (2.0 * l + 3.0));
   const double ap = (l + 1.0) * (l + 2.0) / ((2.0 * l + 1.0) * (2.0 * l + 3.0));
@@ -162,21 +154,15 @@ __global__ void k_u_rsd(C2<R>* __restrict__ UR, const double* __restrict__ ell, 
 // that with the clustering k scale k^{-1-b} the window carries l(l+1) k^{-2} k^{-1-(b-2)-i eta}.
 template <typename R>
 __global__ void k_u_mag(C2<R>* __restrict__ Um, const double* __restrict__ ell, const int* __restrict__ band,
-                        double b0, double b1, double b2, double b3, int n_ell, int M, double delta, double taper_frac) {
+                        bias_table bt, int n_ell, int M, double delta, double taper_frac) {
   const int li = blockIdx.x;
   const int n = blockIdx.y * blockDim.x + threadIdx.x;
   if (li >= n_ell || n >= M) return;
   const double l = ell[li];
-  const double bclus[4] = {b0, b1, b2, b3};
-  const double b = bclus[band[li]] - 2.0;
+  const double b = bt.b[SWIFTCL_CLUSTERING][band[li]] - 2.0;
   const double eta = 2.0 * M_PI * (double)n / (2.0 * M * delta);
-  double tap = 1.0;
-  if (taper_frac > 0.0) {
-    double x = (double)n / (double)M, x0 = 1.0 - taper_frac;
-    if (x > x0) tap = 0.5 * (1.0 + cos(M_PI * fmin((x - x0) / taper_frac, 1.0)));
-  }
   const zd u = u_value(l, b, eta);
-  const double f = l * (l + 1.0) * tap;
+  const double f = l * (l + 1.0) * taper_of(n, M, taper_frac);
   C2<R> v;
   v.x = (R)(f * u.x);
   v.y = (R)(n == 0 ? 0.0 : f * u.y);
@@ -186,20 +172,21 @@ __global__ void k_u_mag(C2<R>* __restrict__ Um, const double* __restrict__ ell, 
 hipError_t launch_u_table(const plan_dev& pd, const double* d_ell, hipStream_t s) {
   const plan_dev* p = &pd;
   dim3 grid(p->n_ell, (p->M + 127) / 128);
-  const double* b = p->fftlog_b[0];
-  const double* c = p->fftlog_b[1];
+  bias_table bt;
+  for (int k = 0; k < SWIFTCL_NKINDS; ++k)
+    for (int j = 0; j < SWIFTCL_MAX_BANDS; ++j) bt.b[k][j] = p->fftlog_b[k][j];
   if (p->precision == SWIFTCL_FP64)
-    hipLaunchKernelGGL(k_u_table<double>, grid, dim3(128), 0, s, (double2*)p->U, d_ell, p->ell_band, b[0], b[1],
-                       b[2], b[3], c[0], c[1], c[2], c[3], p->n_ell, p->M, p->delta, p->taper_frac);
+    hipLaunchKernelGGL(k_u_table<double>, grid, dim3(128), 0, s, (double2*)p->U, d_ell, p->ell_band, bt, p->n_ell,
+                       p->M, p->delta, p->taper_frac);
   else
-    hipLaunchKernelGGL(k_u_table<float>, grid, dim3(128), 0, s, (float2*)p->U, d_ell, p->ell_band, b[0], b[1],
-                       b[2], b[3], c[0], c[1], c[2], c[3], p->n_ell, p->M, p->delta, p->taper_frac);
+    hipLaunchKernelGGL(k_u_table<float>, grid, dim3(128), 0, s, (float2*)p->U, d_ell, p->ell_band, bt, p->n_ell,
+                       p->M, p->delta, p->taper_frac);
   if (p->rsd)  // RSD and magnification plans are FP32 / split
-    hipLaunchKernelGGL(k_u_rsd<float>, grid, dim3(128), 0, s, (float2*)p->UR, d_ell, p->ell_band, b[0], b[1], b[2],
-                       b[3], p->n_ell, p->M, p->delta, p->taper_frac);
+    hipLaunchKernelGGL(k_u_rsd<float>, grid, dim3(128), 0, s, (float2*)p->UR, d_ell, p->ell_band, bt, p->n_ell, p->M,
+                       p->delta, p->taper_frac);
   if (p->mag)
-    hipLaunchKernelGGL(k_u_mag<float>, grid, dim3(128), 0, s, (float2*)p->Umu, d_ell, p->ell_band, b[0], b[1], b[2],
-                       b[3], p->n_ell, p->M, p->delta, p->taper_frac);
+    hipLaunchKernelGGL(k_u_mag<float>, grid, dim3(128), 0, s, (float2*)p->Umu, d_ell, p->ell_band, bt, p->n_ell,
+                       p->M, p->delta, p->taper_frac);
   return hipGetLastError();
 }
 
@@ -252,12 +239,18 @@ static swiftcl_status validate_desc(const swiftcl_plan_desc* d) {
   for (int i = 0; i < d->n_ell; ++i) {
     int bi = 0;
     while (bi + 1 < d->n_bands && d->ell[i] >= d->band_ell_lo[bi + 1]) ++bi;
-    for (int kind = 0; kind < 2; ++kind) {
+    for (int kind = 0; kind < SWIFTCL_NKINDS; ++kind) {
       const double b = d->fftlog_b[kind][bi];
       if (!(b > -d->ell[i] - 1.0 && b < 1.0) || !std::isfinite(b)) {
         set_error("FFTLog bias b outside (-l-1, 1) for some multipole");
         return SWIFTCL_E_DOMAIN;
       }
+    }
+    // RSD evaluates eq. int_jl at l - 2 and magnification at the bias b - 2 (both with the
+    // clustering row): each converges only for b > 1 - l
+    if ((d->rsd || d->magnification) && !(d->fftlog_b[SWIFTCL_CLUSTERING][bi] > 1.0 - d->ell[i])) {
+      set_error("with rsd or magnification the clustering FFTLog bias must exceed 1 - l for every multipole");
+      return SWIFTCL_E_DOMAIN;
     }
   }
   if (!(d->taper_frac >= 0.0 && d->taper_frac < 1.0)) { set_error("taper_frac must be in [0, 1)"); return SWIFTCL_E_INVALID; }
@@ -416,8 +409,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   }
   for (int j = 0; j < SWIFTCL_MAX_BANDS; ++j) {
     p->d.band_ell_lo[j] = j < d->n_bands ? d->band_ell_lo[j] : 1e300;
-    p->d.fftlog_b[0][j] = j < d->n_bands ? d->fftlog_b[0][j] : 0.0;
-    p->d.fftlog_b[1][j] = j < d->n_bands ? d->fftlog_b[1][j] : 0.0;
+    for (int kind = 0; kind < SWIFTCL_NKINDS; ++kind) p->d.fftlog_b[kind][j] = j < d->n_bands ? d->fftlog_b[kind][j] : 0.0;
   }
   p->ell_host.assign(d->ell, d->ell + d->n_ell);
   p->real_size = d->precision == SWIFTCL_FP64 ? 8 : 4;
@@ -425,22 +417,25 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   const int N = p->d.N, M = p->d.M, nk = p->d.n_k, T = p->d.max_tracers, B = p->d.max_batch, nb = p->d.n_bands;
 
   // --- host tables ---
-  std::vector<int> band(p->d.n_ell);
-  std::vector<double> fell(p->d.n_ell);
-  for (int i = 0; i < p->d.n_ell; ++i) {
+  const int nl = p->d.n_ell;
+  std::vector<int> band(nl);
+  std::vector<double> fell((size_t)SWIFTCL_NKINDS * nl);
+  for (int i = 0; i < nl; ++i) {
     int bi = 0;
     while (bi + 1 < nb && d->ell[i] >= d->band_ell_lo[bi + 1]) ++bi;
     band[i] = bi;
     const double l = d->ell[i];
-    fell[i] = std::sqrt((l + 2.0) * (l + 1.0) * l * (l - 1.0));
+    fell[i] = 1.0;                                                                   // clustering
+    fell[(size_t)SWIFTCL_LENSING * nl + i] = std::sqrt((l + 2.0) * (l + 1.0) * l * (l - 1.0));  // shear
+    fell[(size_t)SWIFTCL_CMB_LENSING * nl + i] = l * (l + 1.0);                      // convergence
   }
-  std::vector<double> kscale((size_t)2 * nb * nk), kw(nk);
-  for (int kind = 0; kind < 2; ++kind)
+  std::vector<double> kscale((size_t)SWIFTCL_NKINDS * nb * nk), kw(nk);
+  for (int kind = 0; kind < SWIFTCL_NKINDS; ++kind)
     for (int bi = 0; bi < nb; ++bi)
       for (int j = 0; j < nk; ++j) {
         const double lk = std::log(d->k[0]) + j * p->d.delta;  // the grid node k_0 e^{j Delta}
         double v = std::exp((-1.0 - p->d.fftlog_b[kind][bi]) * lk);
-        if (kind == 1) v *= std::exp(-2.0 * lk);
+        if (kind != SWIFTCL_CLUSTERING) v *= std::exp(-2.0 * lk);  // the 1/k^2 of both lensing kinds
         kscale[((size_t)kind * nb + bi) * nk + j] = v;
       }
   for (int j = 0; j < nk; ++j) {
@@ -448,8 +443,8 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     kw[j] = (2.0 / M_PI) * w * d->k[j] * d->k[j] * d->k[j];
   }
   // FFTLog bias factors e^{-b m Delta} per kind, band and chi node
-  std::vector<double> ebm((size_t)2 * nb * N);
-  for (int kind = 0; kind < 2; ++kind)
+  std::vector<double> ebm((size_t)SWIFTCL_NKINDS * nb * N);
+  for (int kind = 0; kind < SWIFTCL_NKINDS; ++kind)
     for (int bi = 0; bi < nb; ++bi)
       for (int m = 0; m < N; ++m)
         ebm[((size_t)kind * nb + bi) * N + m] = std::exp(-d->fftlog_b[kind][bi] * (double)m * p->d.delta);
@@ -502,17 +497,17 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     }                                                                       \
     p->d.ptr = (decltype(p->d.ptr))tmp_;                                        \
   } while (0)
-  ALLOC(U, char, (size_t)2 * p->d.n_ell * M * 2 * rs);
+  ALLOC(U, char, (size_t)SWIFTCL_NKINDS * p->d.n_ell * M * 2 * rs);
   ALLOC(kscale, char, kscale.size() * rs);
   ALLOC(tw, char, (size_t)N * 2 * rs);
-  ALLOC(fell, double, p->d.n_ell);
+  ALLOC(fell, double, fell.size());
   ALLOC(ell_band, int, p->d.n_ell);
   ALLOC(kw, double, nk);
   ALLOC(ell_v, double, p->d.n_ell);
   ALLOC(lnk, double, nk);
   ALLOC(lu_k, double, luk.size());
   ALLOC(lnp, double, (size_t)B * 2 * nk);
-  ALLOC(ebm, double, (size_t)2 * nb * N);
+  ALLOC(ebm, double, ebm.size());
   ALLOC(z_geom, double, p->d.n_zg);
   ALLOC(z_nz, double, p->d.n_zs);
   ALLOC(lu_geom, double, lug.size());
@@ -542,7 +537,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     ALLOC(chat_r, char, (size_t)B * T * nb * M * 2 * rs);
   }
   ALLOC(sqrt_s, char, (size_t)B * nk * rs);
-  ALLOC(kss, char, (size_t)B * 2 * nb * nk * rs);
+  ALLOC(kss, char, (size_t)B * SWIFTCL_NKINDS * nb * nk * rs);
   ALLOC(flags, int, 1);
   {
     // (point, chunk) slots of the backward partials: the most any batch size and chunk
@@ -579,7 +574,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     ALLOC(kg_ia, int, nk);
     ALLOC(kg_w, float, (size_t)4 * nk);
     ALLOC(kg_ip, float, A);
-    ALLOC(kg_uh, float, (size_t)2 * p->d.n_ell * 2 * M);
+    ALLOC(kg_uh, float, (size_t)SWIFTCL_NKINDS * p->d.n_ell * 2 * M);
     ALLOC(kg_c, char, chunk * T * nb * A * M * 8);
     ALLOC(kg_m, char, chunk * T * nb * A * M * 8);
     ALLOC(kg_perm, int, chunk * p->d.max_ell);
@@ -607,8 +602,8 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     }
     kg_ones.assign((size_t)B * p->d.n_zg, 1.0);
   }
-  p->d.sched_stride = B / SWIFTCL_NXCD + 2;
-  ALLOC(sched, int, (size_t)(SWIFTCL_NXCD + 1) * p->d.sched_stride);
+  p->d.sched_stride = sched_stride_for(B);
+  ALLOC(sched, int, sched_ints(p->d.sched_stride));
   ALLOC(dchat_part, char, (size_t)p->d.bwd_slots * T * nb * M * 2 * rs);
   ALLOC(dpk_part, char, (size_t)p->d.bwd_slots * nk * rs);
   ALLOC(dg, char, (size_t)B * T * nb * N * rs);
@@ -695,10 +690,20 @@ static swiftcl_status check_inputs(swiftcl_plan_t p, const swiftcl_inputs* in) {
   if (!in) { set_error("inputs is NULL"); return SWIFTCL_E_INVALID; }
   if (in->mag && !p->d.mag) { set_error("inputs carry magnification; build the plan with magnification = 1"); return SWIFTCL_E_INVALID; }
   if (in->batch < 1 || in->batch > p->d.max_batch) { set_error("batch outside 1..max_batch"); return SWIFTCL_E_INVALID; }
-  const void* req[] = {in->n_tracers, in->kind, in->n_ell, in->ell_idx, in->chi_z, in->D_z,
-                       in->omega_m, in->nz, in->bias, in->pk};
+  const void* req[] = {in->n_tracers, in->kind, in->n_ell, in->ell_idx, in->chi_z, in->pk};
   for (const void* q : req)
     if (!q) { set_error("a required input pointer is NULL"); return SWIFTCL_E_INVALID; }
+  if (in->kernel_chi) {
+    // kernel samples replace the assembly: n(z), bias, D(z), Omega_m, A_IA and C_g are not read
+    if (p->d.rsd || p->d.mag) {
+      set_error("kernel samples (kernel_chi) are not built with redshift-space distortions or magnification");
+      return SWIFTCL_E_UNSUPPORTED;
+    }
+    return SWIFTCL_OK;
+  }
+  const void* req_asm[] = {in->D_z, in->omega_m, in->nz, in->bias};
+  for (const void* q : req_asm)
+    if (!q) { set_error("a required input pointer is NULL (nz, bias, D_z and omega_m unless kernel_chi is given)"); return SWIFTCL_E_INVALID; }
   return SWIFTCL_OK;
 }
 
@@ -712,7 +717,7 @@ static void note_forward(swiftcl_plan_t p, const swiftcl_inputs* in) {
 static bool same_inputs(const swiftcl_inputs& a, const swiftcl_inputs& b) {
   return a.batch == b.batch && a.n_tracers == b.n_tracers && a.kind == b.kind && a.n_ell == b.n_ell &&
          a.ell_idx == b.ell_idx && a.chi_z == b.chi_z && a.D_z == b.D_z && a.omega_m == b.omega_m && a.nz == b.nz &&
-         a.bias == b.bias && a.pk == b.pk && a.ia == b.ia && a.mag == b.mag;
+         a.bias == b.bias && a.pk == b.pk && a.ia == b.ia && a.mag == b.mag && a.kernel_chi == b.kernel_chi;
 }
 
 static swiftcl_status run_forward(swiftcl_plan_t p, const swiftcl_inputs* in, void* W, void* C, void* stream) {
@@ -784,6 +789,10 @@ extern "C" swiftcl_status swiftcl_cl_kgrowth(swiftcl_plan_t p, const swiftcl_inp
     set_error("scale-dependent growth is not built with redshift-space distortions or magnification");
     return SWIFTCL_E_UNSUPPORTED;
   }
+  if (in->kernel_chi) {
+    set_error("scale-dependent growth assembles its kernels per k node; kernel samples (kernel_chi) are refused");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
   // the kernels are assembled without growth (D = 1); growth enters per node
   swiftcl_inputs in1 = *in;
   in1.D_z = p->d.kg_ones;
@@ -807,6 +816,10 @@ extern "C" swiftcl_status swiftcl_cl_limber(swiftcl_plan_t p, const swiftcl_inpu
     set_error("the Limber path does not include redshift-space distortions or magnification");
     return SWIFTCL_E_UNSUPPORTED;
   }
+  if (in->kernel_chi) {
+    set_error("the Limber path takes its kernels from the assembly; kernel samples (kernel_chi) are refused");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
   if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
@@ -818,10 +831,14 @@ extern "C" swiftcl_status swiftcl_cl_limber(swiftcl_plan_t p, const swiftcl_inpu
 
 // Checks shared by the two backward entry points; `reuse` is set when the forward state is kept.
 static swiftcl_status backward_checks(swiftcl_plan_t p, const swiftcl_inputs* in, const void* dC, uint32_t flags,
-                                      bool* reuse) {
+                                      bool* reuse, const double* dbias, const double* dnz, const double* dD) {
   swiftcl_status st = check_inputs(p, in);
   if (st != SWIFTCL_OK) return st;
   if (!dC) { set_error("dC is NULL"); return SWIFTCL_E_INVALID; }
+  if (in->kernel_chi && (dbias || dnz || dD)) {
+    set_error("with kernel samples (kernel_chi) the backward gives dpk only: dbias, dnz and dD must be NULL");
+    return SWIFTCL_E_INVALID;
+  }
   if (flags & ~(uint32_t)SWIFTCL_BWD_REUSE_FORWARD) { set_error("unknown backward flag"); return SWIFTCL_E_INVALID; }
   if (!p->d.adjoint) {
     set_error("the adjoint is built for plans whose windows fit in LDS (<= 16 tracers) in FP32 or FP64, "
@@ -840,7 +857,7 @@ extern "C" swiftcl_status swiftcl_cl_backward(swiftcl_plan_t p, const swiftcl_in
                                               double* dpk, double* dbias, double* dnz, double* dD, uint32_t flags,
                                               void* stream) {
   bool reuse = false;
-  swiftcl_status st = backward_checks(p, in, dC, flags, &reuse);
+  swiftcl_status st = backward_checks(p, in, dC, flags, &reuse, dbias, dnz, dD);
   if (st != SWIFTCL_OK) return st;
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
@@ -860,7 +877,7 @@ extern "C" swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t p, const swif
                                                     uint32_t flags, void* stream, float* stage_ms) {
   if (!stage_ms) { set_error("stage_ms is NULL"); return SWIFTCL_E_INVALID; }
   bool reuse = false;
-  swiftcl_status st = backward_checks(p, in, dC, flags, &reuse);
+  swiftcl_status st = backward_checks(p, in, dC, flags, &reuse, dbias, dnz, dD);
   if (st != SWIFTCL_OK) return st;
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;

@@ -15,9 +15,9 @@ import torch
 from . import binding as bd
 
 # Default FFTLog bias bands of the library: bands start at l = 0, 3 and 6; per band the bias b
-# (paper Sec. 3.1) of clustering and of lensing tracers.
+# (paper Sec. 3.1) of clustering, lensing and CMB-lensing tracers.
 DEFAULT_BAND_ELL_LO = (0.0, 3.0, 6.0)
-DEFAULT_FFTLOG_B = ((0.1, -0.2, -0.5), (-1.5, -2.0, -2.5))
+DEFAULT_FFTLOG_B = ((0.1, -0.2, -0.5), (-1.5, -2.0, -2.5), (-1.0, -1.0, -2.0))
 
 PRECISIONS = {"fp64": bd.SWIFTCL_FP64, "fp32": bd.SWIFTCL_FP32, "split_bf16": bd.SWIFTCL_SPLIT_BF16}
 
@@ -43,7 +43,10 @@ INPUT_LAYOUT = (
 OPTIONAL_INPUT_LAYOUT = (
     ("ia", torch.float64, ("B", "n_zg")),
     ("mag", torch.float64, ("B", "max_tracers")),
+    ("kernel_chi", torch.float64, ("B", "max_tracers", "n_chi")),
 )
+# inputs the kernel-samples mode (kernel_chi given) does not read: optional there
+KERNEL_MODE_OPTIONAL = ("D_z", "omega_m", "nz", "bias")
 # gradient outputs of the backward calls
 GRAD_LAYOUT = (
     ("pk", ("B", "n_k")),
@@ -70,12 +73,15 @@ def check_tensor(name, x, shape, dtype, device):
 
 def check_inputs(t, dims, device):
     """Check a dict of per-call input tensors against INPUT_LAYOUT before its pointers are handed
-    over.  dims: the plan's max_tracers, max_ell, n_zg, n_zs and n_k.  Returns the batch B."""
+    over.  dims: the plan's max_tracers, max_ell, n_zg, n_zs, n_k and n_chi.  Returns the batch B."""
     n = t.get("n_tracers")
     if not isinstance(n, torch.Tensor) or n.dim() != 1:
         raise ValueError("inputs need n_tracers, a 1-d tensor of the batch's tracer counts")
     size = dict(dims, B=int(n.shape[0]))
+    kernel_mode = t.get("kernel_chi") is not None
     for name, dtype, layout in INPUT_LAYOUT:
+        if t.get(name) is None and kernel_mode and name in KERNEL_MODE_OPTIONAL:
+            continue
         if name not in t:
             raise ValueError(f"inputs lack {name!r}")
         check_tensor(name, t[name], [size[d] for d in layout], dtype, device)
@@ -116,9 +122,10 @@ class Plan:
         nb = len(band_ell_lo)
         if not 1 <= nb <= bd.MAX_BANDS:
             raise ValueError(f"band_ell_lo must have 1..{bd.MAX_BANDS} entries, got {nb}")
-        if len(fftlog_b) < 2 or any(len(fftlog_b[kind]) != nb for kind in (0, 1)):
+        if len(fftlog_b) != bd.NKINDS or any(len(fftlog_b[kind]) != nb for kind in range(bd.NKINDS)):
             # entries left unset would reach the library as b = 0
-            raise ValueError(f"fftlog_b needs a row of {nb} biases (one per band) for clustering and for lensing")
+            raise ValueError(f"fftlog_b needs a row of {nb} biases (one per band) for each of the {bd.NKINDS} "
+                             "tracer kinds (clustering, lensing, CMB lensing)")
         self.k = _f64(k)
         self.ell = _f64(ell)
         self.z_geom = _f64(z_geom)
@@ -135,7 +142,7 @@ class Plan:
         d.n_bands = len(band_ell_lo)
         for j, v in enumerate(band_ell_lo):
             d.band_ell_lo[j] = float(v)
-        for kind in (0, 1):
+        for kind in range(bd.NKINDS):
             for j, v in enumerate(fftlog_b[kind]):
                 d.fftlog_b[kind][j] = float(v)
         d.taper_frac = float(taper_frac)
@@ -194,7 +201,7 @@ class Plan:
     def dims(self):
         """The plan sizes that the input, output and gradient layouts are written in."""
         return dict(max_tracers=self.max_tracers, max_ell=self.max_ell, n_zg=len(self.z_geom),
-                    n_zs=len(self.z_nz), n_k=len(self.k))
+                    n_zs=len(self.z_nz), n_k=len(self.k), n_chi=self.n_chi)
 
     def _cl_buffer(self, name, x, B):
         """A [B][max_ell][n_pairs] buffer of the output type: checked if given, else allocated."""
@@ -209,11 +216,14 @@ class Plan:
         s = bd.swiftcl_inputs()
         s.batch = check_inputs(t, self.dims, self.device)
         for name in ("n_tracers", "kind", "n_ell", "ell_idx", "chi_z", "D_z", "omega_m", "nz", "bias", "pk"):
-            setattr(s, name, t[name].data_ptr())
+            x = t.get(name)  # (the kernel-samples mode leaves D_z, omega_m, nz and bias optional)
+            setattr(s, name, x.data_ptr() if x is not None else None)
         ia = t.get("ia")  # NLA amplitude A_IA(z) of the lensing tracers, optional
         s.ia = ia.data_ptr() if ia is not None else None
         mag = t.get("mag")  # lensing-bias coefficients C_g of the clustering tracers, optional
         s.mag = mag.data_ptr() if mag is not None else None
+        kc = t.get("kernel_chi")  # kernel samples on the chi nodes in place of the assembly, optional
+        s.kernel_chi = kc.data_ptr() if kc is not None else None
         return s
 
     # Every call that (re)computes the workspace's forward state sets a fresh token; autograd keeps
@@ -358,4 +368,6 @@ def device_inputs(wl, device="cuda:0", points=None):
         out["ia"] = f(wl["ia"], torch.float64)
     if wl.get("mag") is not None:
         out["mag"] = f(wl["mag"], torch.float64)
+    if wl.get("kernel_chi") is not None:
+        out["kernel_chi"] = f(wl["kernel_chi"], torch.float64)
     return out

@@ -47,7 +47,7 @@ def _desc(**over):
     d.n_bands = 3
     for j, v in enumerate((0.0, 3.0, 6.0)):
         d.band_ell_lo[j] = v
-    for kind, row in enumerate(((0.1, -0.2, -0.5), (-1.5, -2.0, -2.5))):
+    for kind, row in enumerate(((0.1, -0.2, -0.5), (-1.5, -2.0, -2.5), (-1.0, -1.0, -2.0))):
         for j, v in enumerate(row):
             d.fftlog_b[kind][j] = v
     dp = ctypes.POINTER(ctypes.c_double)
@@ -57,8 +57,8 @@ def _desc(**over):
     d.n_zs, d.z_nz = len(keep["z_nz"]), keep["z_nz"].ctypes.data_as(dp)
     d.max_batch, d.max_tracers, d.max_ell, d.precision, d.device = 1, 2, 20, 0, 0
     for key, v in over.items():
-        if key == "fftlog_b00":
-            d.fftlog_b[0][0] = v
+        if key.startswith("fftlog_b"):  # fftlog_b<kind><band>
+            d.fftlog_b[int(key[-2])][int(key[-1])] = v
         else:
             setattr(d, key, v)
     return d, keep
@@ -73,6 +73,11 @@ def _desc(**over):
     (dict(ell=np.geomspace(1.5, 200, 20)), -2),              # l < 2
     (dict(ell=np.array([2.0, 5.0, 4.0])), -1),               # not increasing
     (dict(fftlog_b00=1.2), -2),                              # b >= 1 outside eq. int_jl range
+    (dict(fftlog_b20=1.0), -2),                              # the CMB-lensing row is checked too
+    (dict(fftlog_b12=-7.8), -2),                             # b <= -l-1 at l = 6.72 (band 2)
+    # RSD needs U at l - 2, magnification U at b - 2: the clustering b must exceed 1 - l
+    (dict(precision=1, rsd=1, fftlog_b00=-1.5), -2),         # l = 2: b = -1.5 <= -1
+    (dict(precision=1, magnification=1, fftlog_b01=-2.5), -2),  # l = 3.1: b = -2.5 <= -2.1
     (dict(n_bands=0), -1),
     (dict(taper_frac=1.0), -1),
     (dict(max_tracers=33), -5),

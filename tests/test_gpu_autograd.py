@@ -1,7 +1,9 @@
 """The adjoint behind torch.autograd against central finite differences of the HIP forward.
 
-FP64 (the 2-bin workload): torch.autograd.gradcheck over P(k), biases, n(z) samples and
-D(z) samples (central differences, eps 1e-6 relative to the input scale).
+FP64: torch.autograd.gradcheck with the full Jacobian (fast_mode=False: every input entry by
+central differences, eps 1e-6 relative to the input scale) over P(k), biases, n(z) samples and
+D(z) samples, on the 2-bin workload and on one clustering plus one lensing bin of the 15-tracer
+set (N_chi = N_k = 1024, five multipoles).
 FP32 (15 tracers, biases scaled by U(0.9, 1.1)): central differences with a 1e-4 relative step
 along seeded directions that move every entry of P(k) (random signs), of one tracer's n(z) or
 of D(z) (by (0.5 + U(0, 1)) times the entry, so C moves by ~1e-4 relative; a single k node or
@@ -35,10 +37,21 @@ def dev():
     return torch.device("cuda:0")
 
 
-def test_gradcheck_fp64(dev):
+def _one_clustering_one_lensing():
+    wl = synth.make_workload("cfg1")
+    for key in ("nz", "kind", "bias"):
+        wl[key] = np.ascontiguousarray(wl[key][:, [4, 12]])
+    wl["n_tracers"] = np.array([2], np.int32)
+    wl["ell_idx"] = np.ascontiguousarray(wl["ell_idx"][:, [0, 10, 40, 70, 100]])
+    wl["n_ell"] = np.array([5], np.int32)
+    return wl
+
+
+@pytest.mark.parametrize("name", ["cfg0", "clustering+lensing"])
+def test_gradcheck_fp64(dev, name):
     from paper_2505_22718_amd.autograd import cl
     from paper_2505_22718_amd.plan import Plan, device_inputs
-    wl = synth.make_workload("cfg0")
+    wl = synth.make_workload("cfg0") if name == "cfg0" else _one_clustering_one_lensing()
     plan = Plan.for_workload(wl, precision="fp64")
     t = device_inputs(wl, dev)
     rng = np.random.default_rng(3)
@@ -54,12 +67,17 @@ def test_gradcheck_fp64(dev):
             return (cl(plan, t, args["pk"], args["bias"], args["nz"], args["D"]) * G).sum()
         return f, (base[name] / scale[name]).clone().requires_grad_(True)
 
-    for name in ("pk", "bias", "nz", "D"):
-        _say(f"gradcheck {name}")
-        f, x = make(name)
-        scale_f = float(abs(f(x.detach()))) + 1e-300
-        assert torch.autograd.gradcheck(f, (x,), eps=1e-6, atol=1e-9 * scale_f, rtol=1e-5, fast_mode=True,
-                                        nondet_tol=1e-12 * scale_f)
+    for arg in ("pk", "bias", "nz", "D"):
+        _say(f"gradcheck {name} {arg}")
+        f, x = make(arg)
+        # the tolerance follows the gradient's own scale: a central difference of step eps carries
+        # ~1e-16 sum|G C| / eps of rounding, ~1e-7 of the largest entry here, while L itself may be
+        # small by cancellation between the random cotangent's terms
+        xg = x.detach().clone().requires_grad_(True)
+        f(xg).backward()
+        gmax = float(xg.grad.abs().max()) + 1e-300
+        assert torch.autograd.gradcheck(f, (x,), eps=1e-6, atol=1e-6 * gmax, rtol=1e-6, fast_mode=False,
+                                        nondet_tol=1e-10 * gmax)
 
 
 def test_central_differences_fp32(dev):

@@ -204,3 +204,47 @@ def test_backward_bench_config(dev):
         eb = np.max(np.abs(out["bias"][b, :T] - gb)) / np.max(np.abs(gb))
         _say(f"  point {b}: dP rel err {e:.2e}, db rel err {eb:.2e}")
         assert e < 1e-4 and eb < 1e-4
+
+
+def _with_padded_slot(wl):
+    """The workload with one more tracer slot, left empty (n_tracers unchanged)."""
+    B, T, ns = wl["nz"].shape
+    nz = np.zeros((B, T + 1, ns))
+    nz[:, :T] = wl["nz"]
+    kind = np.zeros((B, T + 1), np.int32)
+    kind[:, :T] = wl["kind"]
+    bias = np.ones((B, T + 1))
+    bias[:, :T] = wl["bias"]
+    wl.update(nz=nz, kind=kind, bias=bias)
+    return wl
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_backward_nz_and_D_entry_by_entry(dev, precision, tol):
+    """dL/dn(z) of every tracer at every one of its 200 samples and dL/dD at every geometry sample,
+    against the oracle's full gradient vectors (the chain rule through its own linear steps, pinned in
+    tests/test_oracle_gradients_full.py): the 15-tracer set with perturbed biases, intrinsic
+    alignment on, ten multipoles, and one empty tracer slot whose rows must be 0.  Tolerance
+    relative to each vector's largest entry."""
+    wl = _with_padded_slot(synth.intrinsic_alignment(synth.make_workload("cfg2")))
+    wl["ell_idx"] = np.ascontiguousarray(wl["ell_idx"][:, ::11])
+    wl["n_ell"] = np.array([wl["ell_idx"].shape[1]], np.int32)
+    _say(f"backward {precision}: dn(z) and dD entry by entry, {wl['ell_idx'].shape[1]} multipoles, IA on")
+    G, out = _run(wl, dev, precision, seed=17)
+    T = 15
+    iu_full = {(i, j): p for p, (i, j) in enumerate(zip(*np.triu_indices(T + 1)))}
+    Gb = np.array([[G[0, l, iu_full[(i, j)]] for (i, j) in zip(*np.triu_indices(T))]
+                   for l in range(wl["ell_idx"].shape[1])])
+    m = fftlog.method_for(wl)
+    kern = gradients.grad_kernels(wl, 0, Gb, m)
+    gn = gradients.grad_nz_full(wl, 0, Gb, m, kern=kern)
+    gD = gradients.grad_D_full(wl, 0, Gb, m, kern=kern)
+    worst = 0.0
+    for t in range(T):
+        e = np.max(np.abs(out["nz"][0, t] - gn[t])) / np.max(np.abs(gn[t]))
+        worst = max(worst, e)
+        assert e < tol, (t, e)
+    eD = np.max(np.abs(out["D"][0] - gD)) / np.max(np.abs(gD))
+    _say(f"  dn(z): worst tracer {worst:.3e}; dD {eD:.3e}")
+    assert eD < tol
+    assert np.all(out["nz"][0, T] == 0) and out["bias"][0, T] == 0

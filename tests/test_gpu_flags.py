@@ -60,3 +60,31 @@ def test_device_flags_and_isolation(dev):
         assert torch.equal(g[k][4], g_clean[k][4]) or \
             float((g[k][4] - g_clean[k][4]).abs().max()) <= 1e-12 * float(g_clean[k][4].abs().max()), k
         assert torch.all(g[k][2] == 0), k
+
+
+def test_unknown_tracer_kind_is_flagged_and_zeroed(dev):
+    """A tracer whose kind is none of the three raises FLAG_BAD_INDEX; its windows are zero, so every
+    pair holding it is 0, the point's other pairs and the other points are as in a clean call, and the
+    adjoint gives it no gradient."""
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    from tests.helpers import full_from_packed
+    wl = synth.make_workload("cfg3", batch=3)
+    plan = Plan.for_workload(wl)
+    clean = device_inputs(wl, dev)
+    C_clean = plan.cl(clean).clone()
+    assert plan.device_flags() == 0
+    bad = {k: v.clone() for k, v in clean.items()}
+    bad["kind"][1, 0] = 3
+    C_bad = plan.cl(bad)
+    flags = plan.device_flags()
+    _say(f"  flags with a tracer of kind 3: {flags}")
+    assert flags == FLAG_BAD_INDEX
+    assert torch.equal(C_bad[0], C_clean[0]) and torch.equal(C_bad[2], C_clean[2])
+    T = plan.max_tracers
+    fb = full_from_packed(C_bad[1].cpu().numpy(), T)
+    fc = full_from_packed(C_clean[1].cpu().numpy(), T)
+    assert np.all(fb[:, 0, :] == 0)
+    assert np.array_equal(fb[:, 1:, 1:], fc[:, 1:, 1:])
+    g = plan.backward(bad, torch.ones_like(C_bad))
+    assert plan.device_flags() == FLAG_BAD_INDEX
+    assert float(g["bias"][1, 0]) == 0.0 and bool(torch.all(g["nz"][1, 0] == 0))

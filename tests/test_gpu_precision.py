@@ -83,3 +83,24 @@ def test_unfused_ragged_tracers(dev):
     assert e.max() < 1e-4
     full[:, :12, :12] = 0
     assert np.all(full == 0)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("split_bf16", 1e-3)])
+def test_unfused_30_tracers_across_workspace_chunks(dev, precision, tol):
+    """The 30-tracer shape with all 200 multipoles at 12 points: the workspace holds 10 points, so the
+    call runs two chunks (the second from point 10 on), as the benchmark's 64-point batch runs seven.
+    Points at both ends of each chunk against the oracle on every twentieth multipole."""
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    B = 12
+    wl = synth.make_workload("cfg4", batch=B)
+    plan = Plan.for_workload(wl, precision=precision)
+    Cg = plan.cl(device_inputs(wl, dev)).cpu().numpy().astype(np.float64)
+    assert plan.device_flags() == 0
+    sub = dict(wl)
+    sub["ell_idx"] = wl["ell_idx"][:, ::20].copy()
+    sub["n_ell"] = np.full(B, sub["ell_idx"].shape[1], np.int32)
+    for b in (0, 9, 10, 11):
+        C = fftlog.cl(sub, b)
+        e = _per_ell(Cg[b, ::20], C, 30)
+        _say(f"{precision}, 30 tracers x 200 l, point {b}: max eps per sampled l: " + " ".join(f"{x:.1e}" for x in e))
+        assert e.max() < tol

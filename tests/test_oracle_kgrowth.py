@@ -51,6 +51,25 @@ def test_scale_free_growth_is_fftlog_with_intrinsic_alignment(wl1s):
     assert _eps(kgrowth.cl(wl, 0, m), fftlog.cl(wl, 0, m)) < 1e-12
 
 
+def test_scale_free_growth_is_fftlog_with_cmb_lensing():
+    """A CMB-lensing tracer (kind 2, its kernel linear in D) takes the node growth like the others."""
+    wl = synth.cmb_lensing(synth.make_workload("cfg0"))
+    wl["D_kz"] = np.repeat(wl["D_z"][:, None, :], 4, 1)
+    m = fftlog.method_for(wl)
+    assert _eps(kgrowth.cl(wl, 0, m), fftlog.cl(wl, 0, m)) < 1e-12
+
+
+def test_growth_linear_in_ln_k_rescales_pk_with_cmb_lensing():
+    wl0 = synth.cmb_lensing(synth.make_workload("cfg0"))
+    wl = dict(wl0)
+    m = fftlog.method_for(wl)
+    x = kgrowth.ln_nodes(m, 5)
+    wl["D_kz"] = wl["D_z"][:, None, :] * (1.0 + 0.03 * (x - np.log(0.05)))[None, :, None]
+    ref_wl = dict(wl0)
+    ref_wl["pk"] = wl0["pk"] * (1.0 + 0.03 * np.log(m.k / 0.05))[None, :] ** 2
+    assert _eps(kgrowth.cl(wl, 0, m), fftlog.cl(ref_wl, 0, m)) < 1e-11
+
+
 def test_growth_linear_in_ln_k_rescales_pk(wl1s):
     wl = dict(wl1s)
     m = fftlog.method_for(wl)

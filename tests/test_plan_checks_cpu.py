@@ -15,7 +15,7 @@ CPU = torch.device("cpu")
 def _dims(wl):
     """The sizes Plan.for_workload gives a plan of this workload."""
     return dict(max_tracers=wl["nz"].shape[1], max_ell=wl["ell_idx"].shape[1], n_zg=len(wl["z_geom"]),
-                n_zs=len(wl["z_nz"]), n_k=len(wl["k"]))
+                n_zs=len(wl["z_nz"]), n_k=len(wl["k"]), n_chi=int(wl["n_chi"]))
 
 
 def _workloads():
@@ -40,6 +40,7 @@ def _plan_without_device(wl, precision="fp32", n_interp=0):
     p.handle = None
     p.k, p.ell, p.z_geom, p.z_nz = wl["k"], wl["ell"], wl["z_geom"], wl["z_nz"]
     p.max_batch, p.max_tracers, p.max_ell = int(wl["batch"]), wl["nz"].shape[1], wl["ell_idx"].shape[1]
+    p.n_chi = int(wl["n_chi"])
     p.n_interp = n_interp
     p.device = CPU
     p.out_dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -207,11 +208,14 @@ def test_unknown_precision_is_refused_before_the_library():
 
 
 def test_band_table_shapes_are_refused_before_the_library():
-    """Every band needs a bias for both kinds (an unset entry would reach the library as b = 0)."""
+    """Every band needs a bias for each of the three kinds (an unset entry would reach the library as
+    b = 0)."""
     wl = synth.make_workload("cfg0")
     with pytest.raises(ValueError, match="fftlog_b"):
         pl.Plan.for_workload(wl, band_ell_lo=(0.0, 3.0, 6.0, 50.0))
     with pytest.raises(ValueError, match="fftlog_b"):
         pl.Plan.for_workload(wl, fftlog_b=((0.1, -0.2, -0.5),))
+    with pytest.raises(ValueError, match="fftlog_b"):  # no CMB-lensing row
+        pl.Plan.for_workload(wl, fftlog_b=((0.1, -0.2, -0.5), (-1.5, -2.0, -2.5)))
     with pytest.raises(ValueError, match="band_ell_lo"):
         pl.Plan.for_workload(wl, band_ell_lo=(0.0, 3.0, 6.0, 9.0, 12.0), fftlog_b=((0.1,) * 5, (-1.5,) * 5))
