@@ -168,6 +168,20 @@ swiftcl_status swiftcl_windows(swiftcl_plan_t plan, const swiftcl_inputs* in, vo
  * No allocation and no synchronisation: safe inside hipGraph capture. */
 swiftcl_status swiftcl_cl(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation) and would rather not keep a workspace per plan: swiftcl_cl with
+ * the call's workspace (kernel samples, FFTLog coefficients, node geometry, phases, work lists) in a
+ * static device array of the library, 64 MiB per device, held until the process ends, instead of
+ * the plan's.  Same arguments, kernels and results (bit for bit) as swiftcl_cl; calls no allocating
+ * routine and synchronises nothing.  Only for plans with the fused projection (<= 16 tracers, no
+ * rsd or magnification; else SWIFTCL_E_UNSUPPORTED).  A batch whose workspace exceeds the array
+ * (about 0.6 MiB per point at 15 tracers, N_chi = N_k = 1024, FP32: some 100 points) is refused
+ * with SWIFTCL_E_INVALID before any launch.  Every call on a device shares that device's array:
+ * calls that overlap on one device (other streams, other threads, other plans) race and must be
+ * ordered by the caller.  The array's address on a device is taken when the first plan there is
+ * built. */
+swiftcl_status swiftcl_cl_noalloc(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C, void* stream);
+
 /* Measurement variant of swiftcl_cl: the same launches, with HIP events recorded on `stream`
  * between its stages; writes the device time in ms of [0] kernel assembly (FP64 splines, lensing
  * integrals, sampling on the chi grid), [1] forward FFTLog coefficients, [2] windows + projection.

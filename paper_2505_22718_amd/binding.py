@@ -83,7 +83,7 @@ class swiftcl_inputs(ctypes.Structure):
 EXPORTED = ["swiftcl_plan", "swiftcl_plan_destroy", "swiftcl_last_error", "swiftcl_device_flags",
             "swiftcl_windows", "swiftcl_cl", "swiftcl_cl_timed", "swiftcl_cl_backward",
             "swiftcl_cl_backward_timed", "swiftcl_autotune", "swiftcl_set_launch", "swiftcl_get_launch",
-            "swiftcl_cl_kgrowth", "swiftcl_cl_limber"]
+            "swiftcl_cl_kgrowth", "swiftcl_cl_limber", "swiftcl_cl_noalloc"]
 
 _lib = None
 
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.swiftcl_device_flags.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
     lib.swiftcl_windows.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
     lib.swiftcl_cl.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
+    lib.swiftcl_cl_noalloc.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
     lib.swiftcl_cl_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, ctypes.POINTER(ctypes.c_float)]
     lib.swiftcl_cl_kgrowth.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp]
     lib.swiftcl_cl_limber.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
@@ -160,6 +161,10 @@ def swiftcl_windows(plan, inputs: swiftcl_inputs, W: int, stream: int = 0):
 
 def swiftcl_cl(plan, inputs: swiftcl_inputs, C: int, stream: int = 0):
     _check(load().swiftcl_cl(plan, ctypes.byref(inputs), ctypes.c_void_p(C), ctypes.c_void_p(stream)))
+
+
+def swiftcl_cl_noalloc(plan, inputs: swiftcl_inputs, C: int, stream: int = 0):
+    _check(load().swiftcl_cl_noalloc(plan, ctypes.byref(inputs), ctypes.c_void_p(C), ctypes.c_void_p(stream)))
 
 
 def swiftcl_cl_kgrowth(plan, inputs: swiftcl_inputs, D_kz: int, C: int, stream: int = 0):

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswiftcl.so")
-SOURCES = ["plan.hip", "assemble.hip", "forward.hip", "backward.hip", "kgrowth.hip", "limber.hip"]
+SOURCES = ["plan.hip", "assemble.hip", "forward.hip", "backward.hip", "kgrowth.hip", "limber.hip", "noalloc.hip"]
 ARCH = os.environ.get("SWIFTCL_OFFLOAD_ARCH", "gfx950")
 
 

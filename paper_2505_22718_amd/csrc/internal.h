@@ -131,6 +131,10 @@ struct swiftcl_plan_s {
 };
 
 void set_error(const std::string& msg);
+// host checks of a call's inputs against the plan (no device work)
+swiftcl_status check_inputs(swiftcl_plan_t p, const swiftcl_inputs* in);
+// takes the device address of swiftcl_cl_noalloc's static workspace on `device` (current), once
+swiftcl_status noalloc_setup(int device);
 size_t bwd_windows_lds(const plan_dev& p);  // dynamic LDS of the adjoint windows kernel
 size_t windows_cl_lds(int M, int NW, bool tw_lds, bool do_cl, size_t rs, int n_k);
 bool unfused_tw_lds(int M);

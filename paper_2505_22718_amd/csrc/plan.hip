@@ -337,6 +337,8 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   if (st != SWIFTCL_OK) return st;
   if ((st = hip_check(hipSetDevice(d->device), "hipSetDevice")) != SWIFTCL_OK) return st;
   (void)hipGetLastError();  // drop a stale error of an earlier, unrelated call
+  // the device address of the static workspace of swiftcl_cl_noalloc, once per device
+  if ((st = noalloc_setup(d->device)) != SWIFTCL_OK) return st;
   int lds_max = 0;
   if ((st = hip_check(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, d->device),
                       "device attribute")) != SWIFTCL_OK)
@@ -685,7 +687,7 @@ extern "C" swiftcl_status swiftcl_device_flags(swiftcl_plan_t p, void* stream, i
   return SWIFTCL_OK;
 }
 
-static swiftcl_status check_inputs(swiftcl_plan_t p, const swiftcl_inputs* in) {
+swiftcl_status check_inputs(swiftcl_plan_t p, const swiftcl_inputs* in) {
   if (!p) { set_error("plan is NULL"); return SWIFTCL_E_INVALID; }
   if (!in) { set_error("inputs is NULL"); return SWIFTCL_E_INVALID; }
   if (in->mag && !p->d.mag) { set_error("inputs carry magnification; build the plan with magnification = 1"); return SWIFTCL_E_INVALID; }
