@@ -129,6 +129,11 @@ def profile_kgrowth_pass(B):
     print("kgrowth profile pass done: 2 calls", flush=True)
 
 
+def progress(msg):
+    """One line on stderr per finished stage (the JSON line alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def time_ms(fn, steps, stream):
     """Average device time of fn() over `steps` calls (HIP events on `stream`), after one warm-up."""
     import torch
@@ -263,6 +268,7 @@ def extra_configs(steps):
         return r, B, C
 
     r, B, _ = fwd_bwd(synth.make_workload("cfg1"))
+    progress("one point timed")
     out["one_point_latency"] = dict(r, workload="1 point, 15 tracers x 103 l, N_k = N_chi = 1024, FP32")
     wl3 = synth.make_workload("cfg3")
     r, B, _ = fwd_bwd(wl3, tune=True)
@@ -277,8 +283,10 @@ def extra_configs(steps):
                                          "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                                          "frac": f3 / (r["forward_ms"] * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS},
                                workload="256 points of 6/10/15 tracers and 50..103 l, FP32, autotuned launch")
+    progress("ragged batch timed")
     wl4 = synth.make_workload("cfg4")
     r, B, C4 = fwd_bwd(wl4, precision="split_bf16", backward=False)
+    progress("30-tracer split batch timed; its error against the oracle next")
     f4 = fused_kernel_flops(30, 200, B, wl4["n_chi"], len(wl4["k"]))
     err, per_ell = split_error(wl4, C4.cpu().numpy().astype(np.float64))
     out["split_bf16_30_tracers"] = dict(
@@ -292,6 +300,7 @@ def extra_configs(steps):
                   "unit": "TFLOP/s", "frac": f4 / (r["forward_ms"] * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS},
         workload="64 points x 30 tracers (465 spectra) x 200 l, N_k = N_chi = 2048, BF16 hi+lo projection")
     del C4
+    progress("30-tracer split batch error done")
     # scale-dependent growth D(k, z) at the paper's default of 200 k nodes (swiftcl_cl_kgrowth)
     wl = synth.scale_dependent_growth(synth.make_workload("cfg1_batch", batch=256), 200)
     plan = Plan.for_workload(wl, n_interp=200)
@@ -301,6 +310,7 @@ def extra_configs(steps):
     ms = time_ms(lambda: plan.cl_kgrowth(inp, D, C), steps, stream)
     # the windows GEMM: [103 l] x [N_chi real K] x [N_k] per tracer
     gemm_flop = 2.0 * 103 * wl["n_chi"] * len(wl["k"]) * 15 * 256
+    progress("scale-dependent growth timed")
     out["scale_dependent_growth"] = dict(
         forward_ms=ms, points_per_s_forward=256 / (ms * 1e-3), windows_gemm_tflop=gemm_flop / 1e12,
         whole_call_tflops=gemm_flop / (ms * 1e-3) / 1e12, device_flags=plan.device_flags(),
@@ -408,6 +418,7 @@ def main():
 
     # launch shapes picked by the library's autotuner on this batch (outside the timed region)
     tune_report = plan.autotune(inp, dC)
+    progress("autotuned: " + tune_report)
 
     def step():
         plan.cl(inp, out)
@@ -431,6 +442,7 @@ def main():
     ms_fwd_med = graph_median_ms(g_fwd, 200, stream)
     del g_fwd
     flags = plan.device_flags()
+    progress(f"headline timed: {ms:.4f} ms per step ({B / (ms * 1e-3):.0f} sets/s)")
 
     fstages = np.mean([plan.cl_timed(inp, out) for _ in range(args.steps)], axis=0)
     bstages = np.mean([plan.backward_timed(inp, dC, grads, reuse_forward=True) for _ in range(args.steps)], axis=0)
@@ -480,6 +492,7 @@ def main():
     if not args.no_extras:
         result["other_shapes"] = extra_configs(max(3, args.steps // 4))
     if not args.no_cpu_baseline:
+        progress("oracle baseline")
         gpu_out = out.cpu().numpy().astype(np.float64)
         cb, err = cpu_baseline(wl, args.cpu_seconds, gpu_out)
         result["cpu_baseline"] = cb
