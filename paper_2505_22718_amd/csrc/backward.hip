@@ -171,12 +171,18 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       wave_sync();
       const R* ks = kscale + ((size_t)kind * nb + band) * nk;
       const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
+      auto w_pair = [&](int k0, int e) {
+        const C2<R> kk = *(const C2<R>*)(ks + k0);
+        *(C2<R>*)(WY + t * vs + k0) = mk<R>(F * kk.x * v[e].x, F * kk.y * v[e].y);
+      };
+      if (2 * M <= nk) {  // every pair inside the row: no guard between the loads
 #pragma unroll
-      for (int e = 0; e < RL; ++e) {
-        const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
-        if (k0 < nk) {
-          const C2<R> kk = *(const C2<R>*)(ks + k0);
-          *(C2<R>*)(WY + t * vs + k0) = mk<R>(F * kk.x * v[e].x, F * kk.y * v[e].y);
+        for (int e = 0; e < RL; ++e) w_pair(2 * (lane + SWIFTCL_WAVE * e), e);
+      } else {
+#pragma unroll
+        for (int e = 0; e < RL; ++e) {
+          const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
+          if (k0 < nk) w_pair(k0, e);
         }
       }
     }
@@ -237,22 +243,27 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
       C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)t * vs) : fbuf + (size_t)wave * FL;
       C2<R> v[RL];
-#pragma unroll
-      for (int e = 0; e < RL; ++e) {
-        const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
-        if (k0 < nk) {
-          const C2<R> y2 = *(const C2<R>*)(WY + t * vs + k0);
-          if constexpr (COMPACT) {
-            const C2<R> kk = *(const C2<R>*)(ks + k0);
-            const C2<R> s2 = *(const C2<R>*)(sq2 + k0);
-            v[e] = mk<R>(F * kk.x * s2.x * y2.x, F * kk.y * s2.y * y2.y);
-          } else {
-            const C2<R> kk = *(const C2<R>*)(ks + k0);
-            const C2<R> s2 = *(const C2<R>*)(sq + k0);
-            v[e] = mk<R>((R)2 * s2.x * s2.x * F * kk.x * y2.x, (R)2 * s2.y * s2.y * F * kk.y * y2.y);
-          }
+      // 2 s F k^{-1-b} Y per output pair; when every pair lies inside the row (N <= nk) the loads
+      // carry no guard, so they are issued together
+      auto dx_pair = [&](int k0) {
+        const C2<R> y2 = *(const C2<R>*)(WY + t * vs + k0);
+        const C2<R> kk = *(const C2<R>*)(ks + k0);
+        if constexpr (COMPACT) {
+          const C2<R> s2 = *(const C2<R>*)(sq2 + k0);
+          return mk<R>(F * kk.x * s2.x * y2.x, F * kk.y * s2.y * y2.y);
         } else {
-          v[e] = mk<R>(0, 0);
+          const C2<R> s2 = *(const C2<R>*)(sq + k0);
+          return mk<R>((R)2 * s2.x * s2.x * F * kk.x * y2.x, (R)2 * s2.y * s2.y * F * kk.y * y2.y);
+        }
+      };
+      if (2 * M <= nk) {
+#pragma unroll
+        for (int e = 0; e < RL; ++e) v[e] = dx_pair(2 * (lane + SWIFTCL_WAVE * e));
+      } else {
+#pragma unroll
+        for (int e = 0; e < RL; ++e) {
+          const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
+          v[e] = k0 < nk ? dx_pair(k0) : mk<R>(0, 0);
         }
       }
       const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;

@@ -129,6 +129,8 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
                                                 R* V) {
   constexpr int RL = M / SWIFTCL_WAVE;
   constexpr int FL = fft_lds_size(M, sizeof(R));
+  // W and V = sqrt(s) W take different k scales (kscale, kss); one call produces one of them
+  static_assert(!(WRITE_W && DO_CL), "windows and C_l come from separate instantiations");
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
   const int Tb = clampi(in.n_tracers[b], 0, T);
@@ -177,22 +179,24 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
     ln &= SWIFTCL_WAVE - 1;  // the compiler may assume 0 <= ln < 64 again
     wave_c2r<R, M>(v, mine, stw, ln);
     wave_sync();
-    const R* ks = (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
-    const R* kq = (const R*)P.kss + (((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk;
+    // the k scale of the output pairs, loads issued in groups of KG (the index is clamped into
+    // the row, nk is even; only the stores are guarded)
+    const R* kscl = DO_CL ? (const R*)P.kss + (((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk
+                          : (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
     const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
+    constexpr int KG = RL < 4 ? RL : 4;
 #pragma unroll
-    for (int e = 0; e < RL; ++e) {
-      const int j = lane + SWIFTCL_WAVE * e;
-      const int k0 = 2 * j;
-      if (k0 < nk) {
-        if (WRITE_W) {
-          const C2<R> kk = *(const C2<R>*)(ks + k0);
-          C2<R>* dst = (C2<R>*)(Wout + (((size_t)b * Lm + li) * T + t) * nk + k0);
-          *dst = mk<R>(F * kk.x * v[e].x, F * kk.y * v[e].y);
-        }
-        if (DO_CL) {  // V = sqrt(s) W
-          const C2<R> kk = *(const C2<R>*)(kq + k0);
-          *(C2<R>*)(V + t * vs + k0) = mk<R>(F * kk.x * v[e].x, F * kk.y * v[e].y);
+    for (int e0 = 0; e0 < RL; e0 += KG) {
+      C2<R> kk[KG];
+#pragma unroll
+      for (int e = 0; e < KG; ++e) kk[e] = *(const C2<R>*)(kscl + min(2 * (ln + SWIFTCL_WAVE * (e0 + e)), nk - 2));
+#pragma unroll
+      for (int e = 0; e < KG; ++e) {
+        const int k0 = 2 * (ln + SWIFTCL_WAVE * (e0 + e));
+        if (k0 < nk) {
+          const C2<R> x = mk<R>(F * kk[e].x * v[e0 + e].x, F * kk[e].y * v[e0 + e].y);
+          if (WRITE_W) *(C2<R>*)(Wout + (((size_t)b * Lm + li) * T + t) * nk + k0) = x;
+          if (DO_CL) *(C2<R>*)(V + t * vs + k0) = x;  // V = sqrt(s) W
         }
       }
     }
@@ -474,12 +478,17 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
     wave_c2r<R, M>(v, mine, stw, ln);
     const R* kq = (const R*)P.kss + (((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk;  // kscale * sqrt(s)
     const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
+    constexpr int KG = RL < 4 ? RL : 4;  // loads issued in groups (index clamped into the row, nk even)
 #pragma unroll
-    for (int e = 0; e < RL; ++e) {
-      const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
+    for (int e0 = 0; e0 < RL; e0 += KG) {
+    C2<R> kk[KG];
+#pragma unroll
+    for (int e = 0; e < KG; ++e) kk[e] = *(const C2<R>*)(kq + min(2 * (ln + SWIFTCL_WAVE * (e0 + e)), nk - 2));
+#pragma unroll
+    for (int e = 0; e < KG; ++e) {
+      const int k0 = 2 * (ln + SWIFTCL_WAVE * (e0 + e));
       if (k0 < nk) {
-        const C2<R> kk = *(const C2<R>*)(kq + k0);
-        const float x0 = F * kk.x * v[e].x, x1 = F * kk.y * v[e].y;
+        const float x0 = F * kk[e].x * v[e0 + e].x, x1 = F * kk[e].y * v[e0 + e].y;
         if (SPLIT) {
           unsigned short h0, l0, h1, l1;
           split_bf16(x0, &h0, &l0);
@@ -491,6 +500,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
         }
       }
     }
+    }
   }
 }
 
@@ -499,8 +509,10 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_contract(plan_dev P, swiftcl_inputs in, float* __restrict__ Cout, int b0,
                                                   int nbp) {
-  __shared__ float red[4][3][256];
-  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  // [wave][tile][col][row] partial Gram tiles: lane (p, r) stores its accumulator (rows 4p..4p+3 of
+  // column r) as one 16-byte LDS store
+  __shared__ __align__(16) float red[4][3][256];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / SWIFTCL_WAVE), lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k;
   const int bl = blockIdx.x / Lm, li = blockIdx.x % Lm;
   if (bl >= nbp) return;
@@ -515,57 +527,91 @@ __global__ __launch_bounds__(256) void k_contract(plan_dev P, swiftcl_inputs in,
   }
   const size_t row0 = ((size_t)bl * Lm + li) * 32;
   const size_t lo_off = (size_t)P.vchunk * Lm * 32 * nk;
-  const bool two = Tb > 16;
   v4f a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
-  const int r = lane & 15;
-  if constexpr (SPLIT) {
-    const unsigned short* vh = (const unsigned short*)P.vbuf;
-    const int nsteps = (nk + 31) / 32;
-    for (int s = wave; s < nsteps; s += 4) {
-      const int k0 = 32 * s + 8 * (lane / 16);
-      v8us h0, l0, h1, l1;
+  const int r = lane & 15, q = lane / 16;
+  // the k loop, instantiated for one or two 16-row tracer tiles so that no branch separates the MFMAs
+  auto kloop = [&](auto two_c) {
+    constexpr bool TWO = decltype(two_c)::value;
+    if constexpr (SPLIT) {
+      // 16x16x32 bf16: lane (r, q) feeds k = 32 s + 8 q .. + 7 of row r, split into hi + lo; 8
+      // consecutive k of a row are one 16-byte load when nk is a multiple of 8
+      const unsigned short* vh = (const unsigned short*)P.vbuf;
+      const int nsteps = (nk + 31) / 32;
+      const bool vec = (nk & 7) == 0;
+      auto load8 = [&](size_t at, int k0) {
+        v8us x;
+        if (vec && k0 + 8 <= nk) {
+          x = *(const v8us*)(vh + at);
+        } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const bool ok = k0 + e < nk;
-        h0[e] = ok ? vh[(row0 + r) * nk + k0 + e] : 0;
-        l0[e] = ok ? vh[lo_off + (row0 + r) * nk + k0 + e] : 0;
-        h1[e] = ok ? vh[(row0 + 16 + r) * nk + k0 + e] : 0;
-        l1[e] = ok ? vh[lo_off + (row0 + 16 + r) * nk + k0 + e] : 0;
+          for (int e = 0; e < 8; ++e) x[e] = k0 + e < nk ? vh[at + e] : (unsigned short)0;
+        }
+        return x;
+      };
+      for (int s = wave; s < nsteps; s += 4) {
+        const int k0 = 32 * s + 8 * q;
+        const v8us h0 = load8((row0 + r) * nk + k0, k0);
+        const v8us l0 = load8(lo_off + (row0 + r) * nk + k0, k0);
+        a00 = mfma_bf16(h0, h0, a00);
+        a00 = mfma_bf16(h0, l0, a00);
+        a00 = mfma_bf16(l0, h0, a00);
+        if constexpr (TWO) {
+          const v8us h1 = load8((row0 + 16 + r) * nk + k0, k0);
+          const v8us l1 = load8(lo_off + (row0 + 16 + r) * nk + k0, k0);
+          a01 = mfma_bf16(h0, h1, a01);
+          a01 = mfma_bf16(h0, l1, a01);
+          a01 = mfma_bf16(l0, h1, a01);
+          a11 = mfma_bf16(h1, h1, a11);
+          a11 = mfma_bf16(h1, l1, a11);
+          a11 = mfma_bf16(l1, h1, a11);
+        }
       }
-      a00 = mfma_bf16(h0, h0, a00);
-      a00 = mfma_bf16(h0, l0, a00);
-      a00 = mfma_bf16(l0, h0, a00);
-      if (two) {
-        a01 = mfma_bf16(h0, h1, a01);
-        a01 = mfma_bf16(h0, l1, a01);
-        a01 = mfma_bf16(l0, h1, a01);
-        a11 = mfma_bf16(h1, h1, a11);
-        a11 = mfma_bf16(h1, l1, a11);
-        a11 = mfma_bf16(l1, h1, a11);
+    } else {
+      // 16x16x4 f32 with V as both operands, so the order in which the k nodes enter the sum is
+      // free: lane (r, q) feeds k = 16 s + 4 q + j at step j of block s, four consecutive floats
+      // of its row per load
+      const float* vf = (const float*)P.vbuf;
+      const int nblk = (nk + 15) / 16;
+      const bool vec = (nk & 3) == 0;
+      auto load4 = [&](size_t at, int k0) {
+        float4 x;
+        if (vec && k0 + 4 <= nk) {
+          x = *(const float4*)(vf + at);
+        } else {
+          x.x = k0 < nk ? vf[at] : 0.f;
+          x.y = k0 + 1 < nk ? vf[at + 1] : 0.f;
+          x.z = k0 + 2 < nk ? vf[at + 2] : 0.f;
+          x.w = k0 + 3 < nk ? vf[at + 3] : 0.f;
+        }
+        return x;
+      };
+      for (int s = wave; s < nblk; s += 4) {
+        const int k0 = 16 * s + 4 * q;
+        const float4 x0 = load4((row0 + r) * nk + k0, k0);
+        const float a0[4] = {x0.x, x0.y, x0.z, x0.w};
+        if constexpr (TWO) {
+          const float4 x1 = load4((row0 + 16 + r) * nk + k0, k0);
+          const float a1[4] = {x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            a00 = mfma_acc<float>::step(a0[j], a0[j], a00);
+            a01 = mfma_acc<float>::step(a0[j], a1[j], a01);
+            a11 = mfma_acc<float>::step(a1[j], a1[j], a11);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) a00 = mfma_acc<float>::step(a0[j], a0[j], a00);
+        }
       }
     }
-  } else {
-    const float* vf = (const float*)P.vbuf;
-    const int nsteps = (nk + 3) / 4;
-    for (int s = wave; s < nsteps; s += 4) {
-      const int kk = 4 * s + lane / 16;
-      const bool ok = kk < nk;
-      const float x0 = ok ? vf[(row0 + r) * nk + kk] : 0.f;
-      const float x1 = ok ? vf[(row0 + 16 + r) * nk + kk] : 0.f;
-      a00 = mfma_acc<float>::step(x0, x0, a00);
-      if (two) {
-        a01 = mfma_acc<float>::step(x0, x1, a01);
-        a11 = mfma_acc<float>::step(x1, x1, a11);
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int idx = mfma_acc<float>::row(lane, q) * 16 + r;
-    red[wave][0][idx] = a00[q];
-    red[wave][1][idx] = a01[q];
-    red[wave][2][idx] = a11[q];
-  }
+  };
+  const bool two = Tb > 16;
+  if (two) kloop(std::true_type{});
+  else kloop(std::false_type{});
+  // rows 4q..4q+3 of column r: red[wave][tile][16 r + 4 q + 0..3]
+  *(v4f*)&red[wave][0][16 * r + 4 * q] = a00;
+  *(v4f*)&red[wave][1][16 * r + 4 * q] = a01;
+  *(v4f*)&red[wave][2][16 * r + 4 * q] = a11;
   __syncthreads();
   for (int idx = threadIdx.x; idx < npair; idx += 256) {
     int i = 0, rem = idx;
@@ -574,7 +620,7 @@ __global__ __launch_bounds__(256) void k_contract(plan_dev P, swiftcl_inputs in,
     float val = 0.f;
     if (i < Tb && j < Tb) {
       const int tile = (i < 16) ? (j < 16 ? 0 : 1) : 2;
-      const int e = (i % 16) * 16 + (j % 16);
+      const int e = (j % 16) * 16 + (i % 16);  // row i, column j of the tile
 #pragma unroll
       for (int w = 0; w < 4; ++w) val += red[w][tile][e];
     }
