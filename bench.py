@@ -243,7 +243,8 @@ def split_error(wl, C_gpu, points=(0,), ell_step=20):
 def extra_configs(steps):
     """The other measured shapes: one point (latency), the ragged batch (256 points of 6, 10 or 15
     tracers and 50..103 multipoles), the 30-tracer split-precision batch (64 points, 465
-    spectra x 200 l, N_k = N_chi = 2048; forward only: the adjoint is built for <= 16 tracers) and
+    spectra x 200 l, N_k = N_chi = 2048; forward, and forward + the FP32 adjoint through the
+    workspace) and
     scale-dependent growth (the benchmark batch with D(k, z) at 200 k nodes, forward only) and the
     Limber limit of the benchmark batch."""
     import numpy as np
@@ -305,12 +306,12 @@ def extra_configs(steps):
                                workload="256 points of 6/10/15 tracers and 50..103 l, FP32, autotuned launch")
     progress("ragged batch timed")
     wl4 = synth.make_workload("cfg4")
-    r, B, C4 = fwd_bwd(wl4, precision="split_bf16", backward=False)
+    r, B, C4 = fwd_bwd(wl4, precision="split_bf16")
     progress("30-tracer split batch timed; its error against the oracle next")
     f4 = fused_kernel_flops(30, 200, B, wl4["n_chi"], len(wl4["k"]))
     err, per_ell = split_error(wl4, C4.cpu().numpy().astype(np.float64))
     out["split_bf16_30_tracers"] = dict(
-        r, points_per_s_forward=B / (r["forward_ms"] * 1e-3),
+        r, points_per_s_forward=B / (r["forward_ms"] * 1e-3), points_per_s_fwd_bwd=B / (r["fwd_bwd_ms"] * 1e-3),
         max_rel_err_vs_oracle=err,
         rel_err_per_sampled_ell=[float(x) for x in per_ell],
         err_sample="point 0, all 465 spectra at every 20th of the 200 multipoles, FP64 FFTLog oracle, "
@@ -318,7 +319,8 @@ def extra_configs(steps):
         roofline={"bound": "alu", "scope": "whole forward call against the windows' algorithmic flops",
                   "achieved": f4 / (r["forward_ms"] * 1e-3) / 1e12, "peak": PEAK_FP32_VECTOR_TFLOPS,
                   "unit": "TFLOP/s", "frac": f4 / (r["forward_ms"] * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS},
-        workload="64 points x 30 tracers (465 spectra) x 200 l, N_k = N_chi = 2048, BF16 hi+lo projection")
+        workload="64 points x 30 tracers (465 spectra) x 200 l, N_k = N_chi = 2048, BF16 hi+lo projection, "
+                 "FP32 adjoint")
     del C4
     progress("30-tracer split batch error done")
     # scale-dependent growth D(k, z) at the paper's default of 200 k nodes (swiftcl_cl_kgrowth)

@@ -233,6 +233,14 @@ swiftcl_status swiftcl_autotune(swiftcl_plan_t plan, const swiftcl_inputs* in, v
 swiftcl_status swiftcl_set_launch(swiftcl_plan_t plan, int32_t fwd_mode, int32_t bwd_chunk_mul);
 swiftcl_status swiftcl_get_launch(swiftcl_plan_t plan, int32_t* fwd_mode, int32_t* bwd_chunk_mul);
 
+/* What a built plan runs (host only, no device work): *fused = 1 when the C_l projection keeps the
+ * windows of a (point, multipole) in one workgroup's LDS, 0 when it goes through the device
+ * workspace in chunks of *point_chunk points (0 when the plan has no workspace); *adjoint = which
+ * swiftcl_cl_backward the plan runs: 0 none (RSD or magnification plans, FP64 windows that do not
+ * fit LDS), 1 the fused adjoint (windows recomputed in LDS), 2 the adjoint through the workspace
+ * (FP32, more than 16 tracers or windows too large for LDS).  Any pointer may be NULL. */
+swiftcl_status swiftcl_plan_info(swiftcl_plan_t plan, int32_t* fused, int32_t* adjoint, int32_t* point_chunk);
+
 /* Measurement variant of swiftcl_cl_backward: the same launches with HIP events between its
  * stages; writes the device time in ms of [0] kernel assembly, [1] forward FFTLog coefficients
  * (both 0 with SWIFTCL_BWD_REUSE_FORWARD), [2] backward windows (recomputed W, G W on MFMA,

@@ -83,7 +83,7 @@ class swiftcl_inputs(ctypes.Structure):
 EXPORTED = ["swiftcl_plan", "swiftcl_plan_destroy", "swiftcl_last_error", "swiftcl_device_flags",
             "swiftcl_windows", "swiftcl_cl", "swiftcl_cl_timed", "swiftcl_cl_backward",
             "swiftcl_cl_backward_timed", "swiftcl_autotune", "swiftcl_set_launch", "swiftcl_get_launch",
-            "swiftcl_cl_kgrowth", "swiftcl_cl_limber", "swiftcl_cl_noalloc"]
+            "swiftcl_cl_kgrowth", "swiftcl_cl_limber", "swiftcl_cl_noalloc", "swiftcl_plan_info"]
 
 _lib = None
 
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
                                      ctypes.c_char_p, ctypes.c_int32]
     lib.swiftcl_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     lib.swiftcl_get_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.swiftcl_plan_info.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 3
     lib.swiftcl_cl_backward_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp,
                                               ctypes.c_uint32, vp, ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTED:
@@ -211,6 +212,12 @@ def swiftcl_autotune(plan, inputs: swiftcl_inputs, C: int, dC: int = 0, stream: 
 
 def swiftcl_set_launch(plan, fwd_mode: int = -1, bwd_chunk_mul: int = -1):
     _check(load().swiftcl_set_launch(plan, fwd_mode, bwd_chunk_mul))
+
+
+def swiftcl_plan_info(plan):
+    f, a, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().swiftcl_plan_info(plan, ctypes.byref(f), ctypes.byref(a), ctypes.byref(c)))
+    return {"fused": f.value, "adjoint": a.value, "point_chunk": c.value}
 
 
 def swiftcl_get_launch(plan):

@@ -321,6 +321,190 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
     for (int k = threadIdx.x; k < nk; k += NW * 64) dpp[k] = dps[k];  // the loop ended on a barrier
 }
 
+// ---------------------------------------------------------------------------------------------
+// Adjoint through the workspace (more than 16 tracers, windows too large for LDS, split plans
+// whose fused adjoint does not fit): for a chunk of points the FP32 rows W of every (point,
+// multipole, tracer slot) are recomputed into the workspace (k_windows_v, w_only), k_bwd_gv
+// replaces them by Y = G W and sums W Y into the dP partials, and k_bwd_adj runs the adjoint
+// transforms of each tracer over a chunk of multipoles.  The partial rows have the layout of the
+// fused kernel's with nchunk = bwd_nlc, so k_bwd_coeffs, k_bwd_tracer and k_bwd_point follow
+// unchanged.
+// ---------------------------------------------------------------------------------------------
+
+// (a5) Y = G W on MFMA 16x16x4 for one (point, multipole chunk, 64-wide k tile); wave w owns
+// the columns 64 tile + 16 w + (0..15) of every multipole's 32 workspace rows.  G (symmetrised
+// cotangent, 32 x 32 with zeros past the point's tracers) is staged in LDS, double-buffered, the
+// next multipole's entries loaded during this one's products.  Y overwrites W in place: each lane
+// stores only after the MFMAs (which consumed every W read of the wave) and after its own reads
+// of the same addresses.  TWO: a second 16-row tracer tile (more than 16 tracers).
+template <bool TWO>
+__global__ __launch_bounds__(256) void k_bwd_gv(plan_dev P, swiftcl_inputs in, const float* __restrict__ dC,
+                                                 int b0, int nbp, int nlc) {
+  __shared__ float Gs[2][32][33];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / SWIFTCL_WAVE), lane = tid % SWIFTCL_WAVE;
+  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k;
+  const int ntile = (nk + 63) / 64;
+  const int tile = blockIdx.x % ntile;
+  const int rest = blockIdx.x / ntile;
+  const int c = rest % nlc;
+  const int bl = rest / nlc;
+  if (bl >= nbp) return;
+  const int b = b0 + bl;
+  const int Tb = clampb(in.n_tracers[b], 0, T);
+  const int Lb = clampb(in.n_ell[b], 0, Lm);
+  const int l0 = (int)(((long)c * Lb) / nlc), l1 = (int)(((long)(c + 1) * Lb) / nlc);
+  const int npair = T * (T + 1) / 2;
+  const int q = lane >> 4, r = lane & 15;
+  const int col = 64 * tile + 16 * wave + r;
+  const bool cok = col < nk;
+  // entry e = tid + 256 m of the 32 x 32 G of multipole slot li
+  auto gval = [&](int li, int e) -> float {
+    const int i = e >> 5, j = e & 31;
+    if (i >= Tb || j >= Tb) return 0.f;
+    const int a = i < j ? i : j, cc = i < j ? j : i;
+    const float g = dC[((size_t)b * Lm + li) * npair + (a * T - a * (a - 1) / 2 + (cc - a))];
+    return i == j ? g : 0.5f * g;
+  };
+  float gn[4] = {0.f, 0.f, 0.f, 0.f};
+  if (l0 < l1)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) gn[m] = gval(l0, tid + 256 * m);
+  float dp = 0.f;  // sum over the chunk of sum_t W Y at column col, over this lane's rows
+  for (int li = l0; li < l1; ++li) {
+    const int buf = (li - l0) & 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = tid + 256 * m;
+      Gs[buf][e >> 5][e & 31] = gn[m];
+    }
+    __syncthreads();  // (the other buffer was last read before the previous iteration's barrier)
+    if (li + 1 < l1)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) gn[m] = gval(li + 1, tid + 256 * m);
+    float* w = (float*)P.vbuf + ((size_t)bl * Lm + li) * 32 * nk;
+    v4f y0 = {0.f, 0.f, 0.f, 0.f}, y1 = {0.f, 0.f, 0.f, 0.f};
+    constexpr int NJ = TWO ? 8 : 4;  // steps of 4 tracer rows j
+#pragma unroll
+    for (int st = 0; st < NJ; ++st) {
+      const float bv = cok ? w[(size_t)(4 * st + q) * nk + col] : 0.f;  // B: W[4 st + q][col]
+      y0 = __builtin_amdgcn_mfma_f32_16x16x4f32(Gs[buf][r][4 * st + q], bv, y0, 0, 0, 0);
+      if constexpr (TWO) y1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Gs[buf][16 + r][4 * st + q], bv, y1, 0, 0, 0);
+    }
+    // y0[m] = Y[4 q + m][col], y1[m] = Y[16 + 4 q + m][col]
+    if (cok) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        float* a0 = w + (size_t)(4 * q + m) * nk + col;
+        dp += *a0 * y0[m];
+        *a0 = y0[m];
+        if constexpr (TWO) {
+          float* a1 = w + (size_t)(16 + 4 * q + m) * nk + col;
+          dp += *a1 * y1[m];
+          *a1 = y1[m];
+        }
+      }
+    }
+  }
+  dp += __shfl_xor(dp, 16);
+  dp += __shfl_xor(dp, 32);
+  if (q == 0 && cok) ((float*)P.dpk_part)[((size_t)b * nlc + c) * nk + col] = dp;
+}
+
+// (a6) Adjoint transforms for one (point, multipole chunk, group of 4 tracers): wave w takes
+// tracer 4 g + w through the chunk's multipoles, dx = 2 s F k^{-1-b} Y from its workspace row,
+// r2c, dc += h conj(X) conj(U_l) in registers, flushed to the (point, chunk, tracer, band)
+// partial row when the band changes; rows of bands the chunk never reaches are zeroed.
+template <int M, bool TW_LDS>
+__global__ __launch_bounds__(256) void k_bwd_adj(plan_dev P, swiftcl_inputs in, int b0, int nbp, int nlc) {
+  constexpr int RL = M / SWIFTCL_WAVE;
+  constexpr int N = 2 * M;
+  __shared__ C2<float> lds[4][fft_lds_size(M, sizeof(float))];
+  __shared__ C2<float> stw_s[TW_LDS ? N : 1];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / SWIFTCL_WAVE), lane = tid % SWIFTCL_WAVE;
+  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
+  const int ng = (T + 3) / 4;
+  const int g = blockIdx.x % ng;
+  const int rest = blockIdx.x / ng;
+  const int c = rest % nlc;
+  const int bl = rest / nlc;
+  if (bl >= nbp) return;
+  if constexpr (TW_LDS) {
+    for (int i = tid; i < N; i += 256) stw_s[i] = ((const C2<float>*)P.tw)[i];
+    __syncthreads();
+  }
+  const C2<float>* stw = TW_LDS ? (const C2<float>*)stw_s : (const C2<float>*)P.tw;
+  const int b = b0 + bl;
+  const int t = 4 * g + wave;
+  const int Tb = clampb(in.n_tracers[b], 0, T);
+  if (t >= Tb) return;  // k_bwd_coeffs writes zeros for these tracers and reads no partial row
+  const int Lb = clampb(in.n_ell[b], 0, Lm);
+  const int l0 = (int)(((long)c * Lb) / nlc), l1 = (int)(((long)(c + 1) * Lb) / nlc);
+  const int kind = tracer_kind(in, T, b, t);
+  C2<float>* part = (C2<float>*)P.dchat_part + (((size_t)b * nlc + c) * T + t) * nb * M;
+  const float* sq = (const float*)P.sqrt_s + (size_t)b * nk;
+  C2<float> acc[RL];
+#pragma unroll
+  for (int e = 0; e < RL; ++e) acc[e] = mk<float>(0.f, 0.f);
+  int cur_band = -1;
+  unsigned flushed = 0;
+  auto flush = [&]() {
+    C2<float>* dst = part + (size_t)cur_band * M;
+    const bool again = (flushed >> cur_band) & 1u;
+#pragma unroll
+    for (int e = 0; e < RL; ++e) {
+      const int n = lane + SWIFTCL_WAVE * e;
+      dst[n] = again ? cadd(dst[n], acc[e]) : acc[e];
+      acc[e] = mk<float>(0.f, 0.f);
+    }
+    flushed |= 1u << cur_band;
+  };
+  for (int li = l0; li < l1; ++li) {
+    int ei = in.ell_idx[(size_t)b * Lm + li];
+    if (ei < 0 || ei >= P.n_ell) {
+      if (lane == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+      ei = 0;
+    }
+    const int band = P.ell_band[ei];
+    if (band != cur_band) {
+      if (cur_band >= 0) flush();
+      cur_band = band;
+    }
+    const float* y = (const float*)P.vbuf + (((size_t)bl * Lm + li) * 32 + t) * nk;
+    const float* ks = (const float*)P.kscale + ((size_t)kind * nb + band) * nk;
+    const float F = (float)P.fell[(size_t)kind * P.n_ell + ei];
+    C2<float> v[RL];
+#pragma unroll
+    for (int e = 0; e < RL; ++e) {
+      const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
+      if (k0 < nk) {
+        const C2<float> y2 = *(const C2<float>*)(y + k0);
+        const C2<float> kk = *(const C2<float>*)(ks + k0);
+        const C2<float> s2 = *(const C2<float>*)(sq + k0);
+        v[e] = mk<float>(2.f * s2.x * s2.x * F * kk.x * y2.x, 2.f * s2.y * s2.y * F * kk.y * y2.y);
+      } else {
+        v[e] = mk<float>(0.f, 0.f);
+      }
+    }
+    wave_sync();
+    wave_r2c<float, M>(v, lds[wave], stw, lane);
+    const C2<float>* Ur = (const C2<float>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
+#pragma unroll
+    for (int e = 0; e < RL; ++e) {
+      const int n = lane + SWIFTCL_WAVE * e;
+      const float h = n == 0 ? 1.f : 2.f;
+      acc[e] = cadd(acc[e], cscale(cmul(cconj(v[e]), cconj(Ur[n])), h));
+    }
+  }
+  if (cur_band >= 0) flush();
+  for (int bi = 0; bi < nb; ++bi) {
+    if ((flushed >> bi) & 1u) continue;
+#pragma unroll
+    for (int e = 0; e < RL; ++e) part[(size_t)bi * M + lane + SWIFTCL_WAVE * e] = mk<float>(0.f, 0.f);
+  }
+}
+
 // Reduce dc over chunks and take it back through the forward real transform: dg per
 // (point, tracer, band), one wavefront per row.
 template <typename R, int M>
@@ -657,8 +841,51 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   return hipGetLastError();
 }
 
+// The adjoint through the workspace (FP32; plans with adjoint == 2)
+template <int M>
+static hipError_t launch_bwd_ws(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,
+                                double* dbias, double* dnz, double* dD, hipStream_t s, hipEvent_t* ev) {
+  const int nlc = p.bwd_nlc, T = p.max_tracers;
+  const int ntile = (p.n_k + 63) / 64, ng = (T + 3) / 4;
+  hipError_t e;
+  for (int b0 = 0; b0 < in->batch; b0 += p.vchunk) {
+    const int nbp = in->batch - b0 < p.vchunk ? in->batch - b0 : p.vchunk;
+    if ((e = launch_windows_w(p, in, b0, nbp, s)) != hipSuccess) return e;
+    const dim3 g1((unsigned)((size_t)nbp * nlc * ntile));
+    if (T > 16) hipLaunchKernelGGL(k_bwd_gv<true>, g1, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+    else hipLaunchKernelGGL(k_bwd_gv<false>, g1, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bwd_adj<M, (M <= 1024)>), dim3((unsigned)((size_t)nbp * nlc * ng)), dim3(256), 0, s, p,
+                       *in, b0, nbp, nlc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+  const long rows = (long)in->batch * T * p.n_bands;
+  hipLaunchKernelGGL((k_bwd_coeffs<float, M>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in, nlc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+  if (dbias || dnz || dD) {
+    const size_t lg = bwd_geometry_lds_bytes(p);
+    hipLaunchKernelGGL(k_bwd_tracer<float>, dim3((unsigned)((size_t)in->batch * T)), dim3(512), lg, s, p, *in,
+                       dbias, dnz);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_bwd_point<float>, dim3(in->batch), dim3(256), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
+                     nlc, dpk, dD);
+  return hipGetLastError();
+}
+
 hipError_t launch_backward(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk, double* dbias,
                            double* dnz, double* dD, hipStream_t s, hipEvent_t* ev) {
+  if (p.adjoint == 2) {
+    switch (p.M) {
+      case 128: return launch_bwd_ws<128>(p, in, dC, dpk, dbias, dnz, dD, s, ev);
+      case 256: return launch_bwd_ws<256>(p, in, dC, dpk, dbias, dnz, dD, s, ev);
+      case 512: return launch_bwd_ws<512>(p, in, dC, dpk, dbias, dnz, dD, s, ev);
+      case 1024: return launch_bwd_ws<1024>(p, in, dC, dpk, dbias, dnz, dD, s, ev);
+    }
+    return hipErrorInvalidValue;
+  }
   const bool dp = p.precision == SWIFTCL_FP64;
   switch (p.M) {
     case 128: return dp ? launch_bwd_t<double, 128>(p, in, dC, dpk, dbias, dnz, dD, s, ev)

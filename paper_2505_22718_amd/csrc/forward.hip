@@ -388,9 +388,11 @@ bool unfused_tw_lds(int M) { return unfused_tw(M); }
 // workspace, k_contract forms the 32 x 32 Gram matrix from three 16 x 16 MFMA tile pairs
 // (0,0), (0,1), (1,1).  Points are processed in chunks of P.vchunk.
 // ---------------------------------------------------------------------------------------------
-// EXTRA bit 1: the plan carries RSD, bit 2: magnification (used when the inputs give C_g)
+// EXTRA bit 1: the plan carries RSD, bit 2: magnification (used when the inputs give C_g).
+// w_only = 1 (FP32, the adjoint's recompute): the rows hold W = F(l) kscale c2r(...) itself, not
+// sqrt(s) W.
 template <int M, int NW, bool TW_LDS, bool SPLIT, int EXTRA>
-__global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
+__global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_inputs in, int b0, int nbp, int w_only) {
   extern __shared__ __align__(16) unsigned char smem[];
   typedef float R;
   constexpr int RL = M / SWIFTCL_WAVE;
@@ -476,7 +478,8 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
     asm volatile("" : "+v"(ln));
     ln &= SWIFTCL_WAVE - 1;
     wave_c2r<R, M>(v, mine, stw, ln);
-    const R* kq = (const R*)P.kss + (((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk;  // kscale * sqrt(s)
+    const R* kq = w_only ? (const R*)P.kscale + ((size_t)kind * nb + band) * nk
+                         : (const R*)P.kss + (((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk;  // kscale sqrt(s)
     const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
     constexpr int KG = RL < 4 ? RL : 4;  // loads issued in groups (index clamped into the row, nk even)
 #pragma unroll
@@ -653,7 +656,7 @@ static hipError_t launch_unfused(const plan_dev& p, const swiftcl_inputs* in, vo
     const int nbp = in->batch - b0 < p.vchunk ? in->batch - b0 : p.vchunk;
     const size_t groups = (size_t)(nbp + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
     const dim3 g1((unsigned)(groups * p.max_ell * SWIFTCL_NXCD));
-#define SWIFTCL_WV(SP, EX) hipLaunchKernelGGL((k_windows_v<M, NW, TW, SP, EX>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp)
+#define SWIFTCL_WV(SP, EX) hipLaunchKernelGGL((k_windows_v<M, NW, TW, SP, EX>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp, 0)
     switch ((p.rsd ? 1 : 0) | (p.mag ? 2 : 0)) {
       case 0: if (split) SWIFTCL_WV(true, 0); else SWIFTCL_WV(false, 0); break;
       case 1: if (split) SWIFTCL_WV(true, 1); else SWIFTCL_WV(false, 1); break;
@@ -669,6 +672,27 @@ static hipError_t launch_unfused(const plan_dev& p, const swiftcl_inputs* in, vo
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <int M>
+static hipError_t launch_ww_t(const plan_dev& p, const swiftcl_inputs* in, int b0, int nbp, hipStream_t s) {
+  constexpr int NW = 16;
+  constexpr bool TW = unfused_tw(M);
+  const size_t lds = windows_cl_lds(M, NW, TW, false, sizeof(float), p.n_k);
+  const size_t groups = (size_t)(nbp + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
+  hipLaunchKernelGGL((k_windows_v<M, NW, TW, false, 0>), dim3((unsigned)(groups * p.max_ell * SWIFTCL_NXCD)),
+                     dim3(NW * 64), lds, s, p, *in, b0, nbp, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_windows_w(const plan_dev& p, const swiftcl_inputs* in, int b0, int nbp, hipStream_t s) {
+  switch (p.M) {
+    case 128: return launch_ww_t<128>(p, in, b0, nbp, s);
+    case 256: return launch_ww_t<256>(p, in, b0, nbp, s);
+    case 512: return launch_ww_t<512>(p, in, b0, nbp, s);
+    case 1024: return launch_ww_t<1024>(p, in, b0, nbp, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename R, int M, bool WRITE_W, bool DO_CL>

@@ -85,7 +85,8 @@ struct plan_dev {
   int sched_stride;
   // projection path: fused (windows in LDS, <= 16 tracers) or through the workspace below
   int fused;
-  int adjoint;        // swiftcl_cl_backward available (fused, FP32/FP64, its LDS fits the device)
+  int adjoint;        // swiftcl_cl_backward: 0 not built, 1 fused (windows in LDS), 2 through the workspace
+  int bwd_nlc;        // multipole chunks per point of the workspace adjoint
   int vchunk;         // points per chunk of the unfused path
   void* vbuf;         // [vchunk][max_ell][32][n_k] FP32, or bf16 hi then lo (unfused and kgrowth paths)
   // scale-dependent growth (swiftcl_cl_kgrowth); points run in chunks of vchunk
@@ -151,6 +152,8 @@ hipError_t launch_assemble(const plan_dev& p, const swiftcl_inputs* in, hipStrea
 hipError_t launch_forward_fft(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s);
 hipError_t launch_windows_cl(const plan_dev& p, const swiftcl_inputs* in, void* W, void* C, hipStream_t s);
 hipError_t launch_sqrt_s(const plan_dev& p, const swiftcl_inputs* in, hipStream_t s);
+// FP32 rows W (not sqrt(s) W) of points [b0, b0 + nbp) into the workspace (vbuf), for the adjoint
+hipError_t launch_windows_w(const plan_dev& p, const swiftcl_inputs* in, int b0, int nbp, hipStream_t s);
 // C of points [b0, b0 + nbp) from the V rows in the workspace (vbuf)
 hipError_t launch_contract(const plan_dev& p, const swiftcl_inputs* in, void* C, int b0, int nbp, hipStream_t s);
 hipError_t launch_kgrowth(const plan_dev& p, const swiftcl_inputs* in, const double* D_kz, void* C, hipStream_t s);

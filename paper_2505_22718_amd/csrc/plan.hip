@@ -398,9 +398,11 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   p->d.fused = fused ? 1 : 0;
   p->d.rsd = d->rsd;
   p->d.mag = d->magnification;
-  p->d.adjoint = (fused && d->precision != SWIFTCL_SPLIT_BF16 &&
-                  bwd_windows_lds(p->d) + 4096 <= (size_t)lds_max)  // + the kernel's static LDS
-                     ? 1 : 0;
+  // the adjoint: the fused kernel when its LDS fits (+ the kernel's static LDS), else (FP32 and
+  // split plans) through the workspace; not built with RSD or magnification
+  if (d->rsd || d->magnification) p->d.adjoint = 0;
+  else if (fused && bwd_windows_lds(p->d) + 4096 <= (size_t)lds_max) p->d.adjoint = 1;
+  else p->d.adjoint = d->precision == SWIFTCL_FP64 ? 0 : 2;
   {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d->device) != hipSuccess || ncu < 8)
@@ -525,7 +527,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(phase, double, (size_t)B * N);
   ALLOC(node_f, double, (size_t)B * 4 * N);
   ALLOC(node_i, int, (size_t)B * 3 * N);
-  if (fused && d->precision != SWIFTCL_SPLIT_BF16) ALLOC(ddD_part, double, (size_t)B * T * 2 * p->d.n_zg);
+  if (p->d.adjoint) ALLOC(ddD_part, double, (size_t)B * T * 2 * p->d.n_zg);
   ALLOC(g, char, (size_t)B * T * nb * N * rs);
   ALLOC(chat, char, (size_t)B * T * nb * M * 2 * rs);
   if (p->d.mag) {
@@ -551,7 +553,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     p->d.bwd_slots = (int)slots;
   }
   p->d.n_interp = d->n_interp;
-  if (!p->d.fused || p->d.n_interp > 0) {
+  if (!p->d.fused || p->d.n_interp > 0 || p->d.adjoint == 2) {
     // workspace of the unfused projection (V of up to 32 tracer slots) and of scale-dependent
     // growth (node coefficients and their spline moments), a chunk of points at a time
     const size_t per_point = (size_t)p->d.max_ell * 32 * nk * 4;
@@ -606,6 +608,15 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   }
   p->d.sched_stride = sched_stride_for(B);
   ALLOC(sched, int, sched_ints(p->d.sched_stride));
+  if (p->d.adjoint == 2) {
+    // multipole chunks per point of the workspace adjoint: about 2048 wavefronts of adjoint
+    // transforms per chunk of points (one per point, chunk and tracer)
+    const long pts = std::min(p->d.vchunk, B);
+    long nlc = (2048 + pts * T - 1) / (pts * T);
+    nlc = std::max(1L, std::min(nlc, (long)p->d.max_ell));
+    p->d.bwd_nlc = (int)nlc;
+    p->d.bwd_slots = std::max(p->d.bwd_slots, (int)(nlc * B));
+  }
   ALLOC(dchat_part, char, (size_t)p->d.bwd_slots * T * nb * M * 2 * rs);
   ALLOC(dpk_part, char, (size_t)p->d.bwd_slots * nk * rs);
   ALLOC(dg, char, (size_t)B * T * nb * N * rs);
@@ -843,8 +854,9 @@ static swiftcl_status backward_checks(swiftcl_plan_t p, const swiftcl_inputs* in
   }
   if (flags & ~(uint32_t)SWIFTCL_BWD_REUSE_FORWARD) { set_error("unknown backward flag"); return SWIFTCL_E_INVALID; }
   if (!p->d.adjoint) {
-    set_error("the adjoint is built for plans whose windows fit in LDS (<= 16 tracers) in FP32 or FP64, "
-              "without redshift-space distortions or magnification");
+    set_error(p->d.rsd || p->d.mag ? "the adjoint is not built with redshift-space distortions or magnification"
+                                   : "the FP64 adjoint keeps the windows of <= 16 tracers in LDS; this n_chi / n_k "
+                                     "does not fit");
     return SWIFTCL_E_UNSUPPORTED;
   }
   *reuse = (flags & SWIFTCL_BWD_REUSE_FORWARD) != 0;
@@ -1043,6 +1055,14 @@ extern "C" swiftcl_status swiftcl_set_launch(swiftcl_plan_t p, int32_t fwd_mode,
     }
     p->d.bwd_chunk_mul = bwd_chunk_mul;
   }
+  return SWIFTCL_OK;
+}
+
+extern "C" swiftcl_status swiftcl_plan_info(swiftcl_plan_t p, int32_t* fused, int32_t* adjoint, int32_t* point_chunk) {
+  if (!p) { set_error("plan is NULL"); return SWIFTCL_E_INVALID; }
+  if (fused) *fused = p->d.fused;
+  if (adjoint) *adjoint = p->d.adjoint;
+  if (point_chunk) *point_chunk = p->d.vbuf ? p->d.vchunk : 0;
   return SWIFTCL_OK;
 }
 

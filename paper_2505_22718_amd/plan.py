@@ -336,6 +336,16 @@ class Plan:
     def launch_config(self):
         return bd.swiftcl_get_launch(self.handle)
 
+    @property
+    def adjoint_mode(self):
+        """0: no adjoint, 1: fused (windows recomputed in LDS), 2: through the workspace."""
+        return bd.swiftcl_plan_info(self.handle)["adjoint"]
+
+    @property
+    def vchunk(self):
+        """Points per chunk of the workspace paths (0 without a workspace)."""
+        return bd.swiftcl_plan_info(self.handle)["point_chunk"]
+
     def device_flags(self):
         return bd.swiftcl_device_flags(self.handle, self._stream())
 

@@ -156,22 +156,22 @@ def test_backward_reuse_forward(dev):
 
 
 def test_backward_unsupported_plans(dev):
-    """The adjoint is built for plans whose windows of all tracers fit in one workgroup's LDS
-    (<= 16 tracers, n_chi <= 1024 here) in FP32 or FP64; other plans refuse it with
-    SWIFTCL_E_UNSUPPORTED before launching anything."""
+    """The adjoint is not built with redshift-space distortions or magnification: such plans refuse
+    it with SWIFTCL_E_UNSUPPORTED before launching anything (split-precision plans, more than 16
+    tracers and n_chi = 2048 have it: tests/test_gpu_backward_ws.py)."""
     from paper_2505_22718_amd.binding import SwiftclError, SWIFTCL_E_UNSUPPORTED
     from paper_2505_22718_amd.plan import Plan, device_inputs
     wl = synth.make_workload("cfg3", batch=2)
     inp = device_inputs(wl, dev)
-    cases = [("split_bf16", wl["n_chi"]), ("fp32", 2 * wl["n_chi"])]
-    for precision, n_chi in cases:
-        p = Plan(wl["k"], wl["ell"], wl["z_geom"], wl["z_nz"], n_chi, 2, wl["nz"].shape[1], wl["ell_idx"].shape[1],
-                 precision=precision)
+    for opt in ({"rsd": True}, {"magnification": True}):
+        p = Plan(wl["k"], wl["ell"], wl["z_geom"], wl["z_nz"], wl["n_chi"], 2, wl["nz"].shape[1],
+                 wl["ell_idx"].shape[1], precision="fp32", **opt)
+        assert p.adjoint_mode == 0
         dC = torch.zeros((2, wl["ell_idx"].shape[1], p.n_pairs), dtype=torch.float32, device=dev)
         with pytest.raises(SwiftclError) as ei:
             p.backward(inp, dC)
         assert ei.value.status == SWIFTCL_E_UNSUPPORTED
-        _say(f"  {precision} n_chi={n_chi}: {ei.value}")
+        _say(f"  {opt}: {ei.value}")
 
 
 def test_backward_bench_config(dev):
