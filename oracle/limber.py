@@ -124,3 +124,30 @@ def grad_pk_grid(G, geo: PointGeometry, ells, method, pk):
         a = np.einsum("sm,st,tm->m", g, G[li], g) * method.delta * w * P / x
         out += a @ basis(lkl)
     return out / np.asarray(pk, float)
+
+
+def grad_kernels_grid(G, geo: PointGeometry, ells, method, pk):
+    """dL/dF_t(chi_m) [T, N] under the chi-node rule, with F = w_t(m) f_t(chi_m) the sampled kernels
+    of fftlog.sampled_kernels (G full [L, T, T]); returns (dF, F, nodes, z) like
+    gradients.grad_kernels, so that gradients.grad_nz_full and grad_D_full take it as `kern`.
+
+    C_l is the quadratic form sum_m g_s g_t Delta w_m P_l(m) / chi_m in g_t(m) = c_t(l, chi_m) f_t,
+    f_t = F_t(m) / W_t(m) (the tracer's own node weight, R5 / R21), so
+    dL/dF_t(m) = sum_l c_t sum_s (G_ts + G_st) g_s Delta w_m P_l(m) / (chi_m W_t(m)).
+    """
+    k = method.k
+    lp = CubicSpline(np.log(k), np.log(pk), bc_type="natural")
+    chi0, chi, F, nodes, z = fftlog.sampled_kernels(geo, method, return_nodes=True)
+    _, Wt = fftlog.edge_weights(geo, method)
+    x, f, w = _grid_terms(geo, method)
+    dF = np.zeros_like(F)
+    inv_w = np.divide(1.0, Wt, out=np.zeros_like(Wt), where=Wt > 0)
+    for li, ell in enumerate(ells):
+        kl = (ell + 0.5) / x
+        inside = (kl >= k[0]) & (kl <= k[-1])
+        P = np.where(inside, np.exp(lp(np.log(np.clip(kl, k[0], k[-1])))), 0.0)
+        c = _limber_prefactor(geo.kinds, ell, x)
+        g = f * c
+        Gs = G[li] + G[li].T
+        dF[:, nodes] += c * (Gs @ g) * (method.delta * w * P / x)[None, :] * inv_w
+    return dF, F, nodes, z
