@@ -277,6 +277,19 @@ swiftcl_status swiftcl_cl_kgrowth(swiftcl_plan_t plan, const swiftcl_inputs* in,
  * and no synchronisation: safe inside hipGraph capture. */
 swiftcl_status swiftcl_cl_limber(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C, void* stream);
 
+/* Adjoint of swiftcl_cl_limber (Sec. 2.6, eq. Limber, on the same nodes; the paper differentiates
+ * every step, Sec. 1): for L = sum over points, multipoles and pairs of dC * C_limber, with dC laid
+ * out like C (device, the plan's real type), writes dL/dP (dpk [batch][n_k]), dL/db (dbias
+ * [batch][max_tracers], 0 for lensing-kind tracers and empty slots), dL/dn(z) (dnz
+ * [batch][max_tracers][n_zs]) and dL/dD(z) (dD [batch][n_zg]); device FP64 arrays, each optional
+ * (NULL skips it).  The ln P spline is differentiated exactly (k nodes whose Limber k no node
+ * reaches get 0; samples at or below 1e-300, where ln P is clamped, get 0).  Recomputes the kernel
+ * assembly.  Same plan and input restrictions as swiftcl_cl_limber (no RSD or magnification, no
+ * kernel samples); SWIFTCL_E_UNSUPPORTED if its LDS (about 8 (2 T 128 + T^2 + 2 n_k) bytes) exceeds
+ * the device's.  No allocation and no synchronisation: safe inside hipGraph capture. */
+swiftcl_status swiftcl_cl_limber_backward(swiftcl_plan_t plan, const swiftcl_inputs* in, const void* dC,
+                                          double* dpk, double* dbias, double* dnz, double* dD, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

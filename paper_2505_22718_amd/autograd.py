@@ -40,3 +40,33 @@ class ClFunction(torch.autograd.Function):
 def cl(plan, inputs, pk, bias, nz, D_z):
     """Differentiable C_l (see ClFunction)."""
     return ClFunction.apply(plan, inputs, pk, bias, nz, D_z)
+
+
+class ClLimberFunction(torch.autograd.Function):
+    """The Limber limit (swiftcl_cl_limber) with its hand-written adjoint
+    (swiftcl_cl_limber_backward); same arguments and gradients as ClFunction."""
+
+    @staticmethod
+    def forward(ctx, plan, inputs, pk, bias, nz, D_z):
+        t = dict(inputs)
+        t.update(pk=pk.detach().contiguous(), bias=bias.detach().contiguous(), nz=nz.detach().contiguous(),
+                 D_z=D_z.detach().contiguous())
+        C = plan.cl_limber(t)
+        ctx.plan = plan
+        ctx.t = t
+        ctx.save_for_backward(pk, bias, nz, D_z)
+        return C
+
+    @staticmethod
+    def backward(ctx, dC):
+        want = [name for name, need in zip(("pk", "bias", "nz", "D"), ctx.needs_input_grad[2:]) if need]
+        if not want:
+            return None, None, None, None, None, None
+        ctx.saved_tensors
+        g = ctx.plan.limber_backward(ctx.t, dC.to(ctx.plan.out_dtype).contiguous(), want=tuple(want))
+        return None, None, g.get("pk"), g.get("bias"), g.get("nz"), g.get("D")
+
+
+def cl_limber(plan, inputs, pk, bias, nz, D_z):
+    """Differentiable Limber C_l (see ClLimberFunction)."""
+    return ClLimberFunction.apply(plan, inputs, pk, bias, nz, D_z)

@@ -841,6 +841,27 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   return hipGetLastError();
 }
 
+template <typename R>
+static hipError_t launch_chain_t(const plan_dev& p, const swiftcl_inputs* in, double* dbias, double* dnz, double* dD,
+                                 hipStream_t s) {
+  if (dbias || dnz || dD) {
+    hipLaunchKernelGGL(k_bwd_tracer<R>, dim3((unsigned)((size_t)in->batch * p.max_tracers)), dim3(512),
+                       bwd_geometry_lds_bytes(p), s, p, *in, dbias, dnz);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (dD)
+    hipLaunchKernelGGL(k_bwd_point<R>, dim3(in->batch), dim3(256), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
+                       0, nullptr, dD);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_chain(const plan_dev& p, const swiftcl_inputs* in, double* dbias, double* dnz, double* dD,
+                            hipStream_t s) {
+  return p.precision == SWIFTCL_FP64 ? launch_chain_t<double>(p, in, dbias, dnz, dD, s)
+                                     : launch_chain_t<float>(p, in, dbias, dnz, dD, s);
+}
+
 // The adjoint through the workspace (FP32; plans with adjoint == 2)
 template <int M>
 static hipError_t launch_bwd_ws(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,

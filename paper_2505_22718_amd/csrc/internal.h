@@ -62,6 +62,7 @@ struct plan_dev {
   double* m_n;      // [B][T][n_zs]
   double* lens_q;   // [B][T][N] lensing efficiency q at the active chi nodes (forward assembly)
   double* lnp;      // [B][2][n_k] ln P and its spline moments in ln k (Limber)
+  double* lim_acc;  // [B][2][n_k] Limber adjoint: cotangents of the ln P samples and of their moments
   double* phase;    // [B][N/2] complex e^{-2 pi i n ln(k_0 chi_0) / (N Delta)}: the FFTLog phase
                     // of coefficient n (forward assembly)
   double* node_f;   // [B][4][N] z, chi, dchi/dz, D at the active chi nodes (forward assembly)
@@ -159,6 +160,13 @@ hipError_t launch_contract(const plan_dev& p, const swiftcl_inputs* in, void* C,
 hipError_t launch_kgrowth(const plan_dev& p, const swiftcl_inputs* in, const double* D_kz, void* C, hipStream_t s);
 size_t kgrowth_fft_lds(int M, int n_zg);  // dynamic LDS of the node-coefficient kernel
 hipError_t launch_limber(const plan_dev& p, const swiftcl_inputs* in, void* C, hipStream_t s);
+// adjoint of launch_limber (after launch_assemble): dpk, dbias, dnz, dD each optional (NULL)
+hipError_t launch_limber_backward(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,
+                                  double* dbias, double* dnz, double* dD, hipStream_t s);
+// chain rule from the kernel-sample cotangents dg (P.dg) to dbias, dnz (k_bwd_tracer) and dD
+// (k_bwd_point), as the FFTLog adjoint ends; dP is left to the caller
+hipError_t launch_bwd_chain(const plan_dev& p, const swiftcl_inputs* in, double* dbias, double* dnz, double* dD,
+                            hipStream_t s);
 hipError_t launch_kgrowth_tables(const plan_dev& p, hipStream_t s);  // plan time, after the U table
 // ev (optional): two events recorded after the first and second backward kernels
 hipError_t launch_backward(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,

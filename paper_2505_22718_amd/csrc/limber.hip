@@ -152,7 +152,191 @@ __global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Adjoint of the Limber rule.  With H_t(m) and s_l(m) as above and a_t = c_t(l) / nu^2 (1 for
+// clustering), C_l^{ij} = a_i a_j sum_m H_i H_j s_l, so for L = sum_l sum_{ij} G_ij C_l^{ij} (G the
+// symmetrised cotangent) and Q_t = sum_j G_tj a_j H_j:
+//   dL/dH_t(m)      = sum_l 2 a_t s_l(m) Q_t(m)
+//   dL/dln P(k_lm)  = s_l(m) sum_t a_t H_t(m) Q_t(m)        (s is P at the node's Limber k)
+// The second goes through the spline of ln P (value weights of each node, then the moments'
+// adjoint), the first through H = g / e^{-b m Delta} [chi^2] back to the kernel-sample cotangents
+// dg, from which the FFTLog adjoint's chain rule (k_bwd_tracer, k_bwd_point) gives db, dn(z), dD.
+// ---------------------------------------------------------------------------------------------
+
+__global__ void k_limber_zero(plan_dev P, swiftcl_inputs in) {
+  const size_t n = (size_t)in.batch * 2 * P.n_k;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    P.lim_acc[i] = 0.0;
+}
+
+// One block per (point, chunk of LB_CH chi nodes), looping over the point's multipoles: dH of the
+// chunk's nodes accumulates per thread (node idx = tid / 2, tracer half tid % 2: no atomics), the
+// ln P cotangents in LDS (FP64 atomics) and then once per block in the point's global rows.
+// Writes the dg rows of the chunk (band 0; the other bands 0).
+template <typename R>
+__global__ __launch_bounds__(256) void k_limber_bwd(plan_dev P, swiftcl_inputs in, const R* __restrict__ dC) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = P.max_tracers, Lm = P.max_ell, N = P.N, nb = P.n_bands, nk = P.n_k;
+  double* H = (double*)smem;                  // [T][LB_CH]
+  double* dH = H + (size_t)T * LB_CH;          // [T][LB_CH]
+  double* Gs = dH + (size_t)T * LB_CH;         // [T][T]
+  double* a = Gs + (size_t)T * T;              // [T]
+  double* s = a + T;                           // [LB_CH]
+  double* sw = s + LB_CH;                      // [LB_CH][4] spline value weights
+  double* dy = sw + 4 * LB_CH;                 // [nk]
+  double* dM = dy + nk;                        // [nk]
+  int* iv = (int*)(dM + nk);                   // [LB_CH]
+  int* kinds = iv + LB_CH;                     // [T]
+  const int nch = (N + LB_CH - 1) / LB_CH;
+  const int b = blockIdx.x / nch, mc = (blockIdx.x % nch) * LB_CH;
+  if (b >= in.batch) return;
+  const int tid = threadIdx.x;
+  const int Tb = clamp_l(in.n_tracers[b], 0, T);
+  const int Lb = clamp_l(in.n_ell[b], 0, Lm);
+  const int npair = T * (T + 1) / 2;
+  const double* pt = P.pt + (size_t)b * PT_STRIDE;
+  const double lchi0 = log(pt[PT_CHI0]), theta = pt[PT_THETA];
+  const int m0 = P.m0, m1 = (int)pt[PT_M1];
+  for (int t = tid; t < T; t += blockDim.x) kinds[t] = t < Tb ? tracer_kind(in, T, b, t) : 0;
+  __syncthreads();
+  // H of the chunk (as the forward) and zeroed accumulators
+  for (int e = tid; e < T * LB_CH; e += blockDim.x) {
+    const int t = e / LB_CH, idx = e % LB_CH, m = mc + idx;
+    double h = 0.0;
+    if (t < Tb && m >= m0 && m <= m1) {
+      const int kind = kinds[t];
+      h = (double)((const R*)P.g)[(((size_t)b * T + t) * nb) * N + m] / P.ebm[((size_t)kind * nb) * N + m];
+      if (kind != SWIFTCL_CLUSTERING) {
+        const double chi = exp(lchi0 + (double)m * P.delta);
+        h *= chi * chi;
+      }
+      if (kind == SWIFTCL_CMB_LENSING && m == m1 && m1 > m0) h *= (0.5 + theta) / (0.5 + 0.5 * theta);
+    }
+    H[e] = h;
+    dH[e] = 0.0;
+  }
+  for (int j = tid; j < nk; j += blockDim.x) dy[j] = dM[j] = 0.0;
+  const bool live = mc <= m1 && mc + LB_CH - 1 >= m0;  // the chunk holds support nodes
+  const double* lnp = P.lnp + (size_t)b * 2 * nk;
+  const double* lnk = P.lnk;
+  const double* lkih = P.lu_k + 3 * (size_t)nk;
+  const int idx = tid >> 1, half = tid & 1;
+  const int th = (T + 1) / 2, t_lo = half * th, t_hi = half ? T : th;
+  for (int li = 0; live && li < Lb; ++li) {
+    __syncthreads();  // the previous multipole's readers are done
+    int ei = in.ell_idx[(size_t)b * Lm + li];
+    if (ei < 0 || ei >= P.n_ell) {
+      if (tid == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+      ei = 0;
+    }
+    const double nu = P.ell_v[ei] + 0.5;
+    const double lnu = log(nu);
+    for (int t = tid; t < T; t += blockDim.x)
+      a[t] = (t < Tb && kinds[t]) ? P.fell[(size_t)kinds[t] * P.n_ell + ei] / (nu * nu) : 1.0;
+    for (int e = tid; e < T * T; e += blockDim.x) {
+      const int i = e / T, j = e % T;
+      double gv = 0.0;
+      if (i < Tb && j < Tb) {
+        const int lo = i < j ? i : j, hi = i < j ? j : i;
+        gv = (double)dC[((size_t)b * Lm + li) * npair + (lo * T - lo * (lo - 1) / 2 + (hi - lo))];
+        if (i != j) gv *= 0.5;
+      }
+      Gs[e] = gv;
+    }
+    for (int q = tid; q < LB_CH; q += blockDim.x) {
+      const int m = mc + q;
+      double sv = 0.0;
+      int ivq = -1;
+      if (m >= m0 && m <= m1) {
+        const double lchi = lchi0 + (double)m * P.delta;
+        const double w = m == m0 ? 0.5 : (m == m1 ? 0.5 + theta : 1.0);
+        const double x = lnu - lchi;
+        if (x >= lnk[0] && x <= lnk[nk - 1]) {
+          ivq = clamp_l((int)floor((x - lnk[0]) / P.delta), 0, nk - 2);
+          const spline_w wt(lnk, lkih, ivq, x);
+          const double lv = wt.wa * lnp[ivq] + wt.wb * lnp[ivq + 1] + wt.wc * lnp[nk + ivq] + wt.wd * lnp[nk + ivq + 1];
+          sv = P.delta * exp(lv - lchi) / w;
+          sw[4 * q] = wt.wa;
+          sw[4 * q + 1] = wt.wb;
+          sw[4 * q + 2] = wt.wc;
+          sw[4 * q + 3] = wt.wd;
+        }
+      }
+      s[q] = sv;
+      iv[q] = ivq;
+    }
+    __syncthreads();
+    const double sq = s[idx];
+    double ap = 0.0;
+    if (sq != 0.0) {
+      for (int t = t_lo; t < t_hi; ++t) {
+        double Q = 0.0;
+        for (int j = 0; j < Tb; ++j) Q += Gs[t * T + j] * a[j] * H[(size_t)j * LB_CH + idx];
+        dH[(size_t)t * LB_CH + idx] += 2.0 * sq * a[t] * Q;
+        ap += a[t] * H[(size_t)t * LB_CH + idx] * Q;
+      }
+    }
+    ap += __shfl_xor(ap, 1);
+    if (half == 0 && sq != 0.0) {
+      const double d = ap * sq;
+      const int i0 = iv[idx];
+      atomicAdd(&dy[i0], sw[4 * idx] * d);
+      atomicAdd(&dy[i0 + 1], sw[4 * idx + 1] * d);
+      atomicAdd(&dM[i0], sw[4 * idx + 2] * d);
+      atomicAdd(&dM[i0 + 1], sw[4 * idx + 3] * d);
+    }
+  }
+  __syncthreads();
+  // dg of the chunk's nodes: band 0 from dH, the other bands 0
+  R* dg = (R*)P.dg;
+  for (int e = tid; e < T * LB_CH; e += blockDim.x) {
+    const int t = e / LB_CH, q = e % LB_CH, m = mc + q;
+    if (m >= N) continue;
+    double v = 0.0;
+    if (t < Tb && m >= m0 && m <= m1) {
+      const int kind = kinds[t];
+      v = dH[e] / P.ebm[((size_t)kind * nb) * N + m];
+      if (kind != SWIFTCL_CLUSTERING) {
+        const double chi = exp(lchi0 + (double)m * P.delta);
+        v *= chi * chi;
+      }
+      if (kind == SWIFTCL_CMB_LENSING && m == m1 && m1 > m0) v *= (0.5 + theta) / (0.5 + 0.5 * theta);
+    }
+    for (int bi = 0; bi < nb; ++bi) dg[(((size_t)b * T + t) * nb + bi) * N + m] = (R)(bi == 0 ? v : 0.0);
+  }
+  if (live)
+    for (int j = tid; j < nk; j += blockDim.x) {
+      if (dy[j] != 0.0) atomicAdd(&P.lim_acc[((size_t)b * 2) * nk + j], dy[j]);
+      if (dM[j] != 0.0) atomicAdd(&P.lim_acc[((size_t)b * 2 + 1) * nk + j], dM[j]);
+    }
+}
+
+// dL/dP per point: the moments' cotangents through the spline solve, then ln P -> P.  One
+// wavefront per point.
+__global__ __launch_bounds__(64) void k_limber_bwd_pk(plan_dev P, swiftcl_inputs in, double* dpk) {
+  extern __shared__ double sh[];
+  const int b = blockIdx.x, lane = threadIdx.x, nk = P.n_k;
+  double* dy = sh;
+  double* dM = sh + nk;
+  for (int j = lane; j < nk; j += SWIFTCL_WAVE) {
+    dy[j] = P.lim_acc[((size_t)b * 2) * nk + j];
+    dM[j] = P.lim_acc[((size_t)b * 2 + 1) * nk + j];
+  }
+  wave_sync();
+  wave_spline_adjoint(dy, dM, P.lu_k, nk, lane);
+  for (int j = lane; j < nk; j += SWIFTCL_WAVE) {
+    const double v = in.pk[(size_t)b * nk + j];
+    // ln P is taken of max(P, 1e-300): no gradient below that floor
+    dpk[(size_t)b * nk + j] = v > 1e-300 ? dy[j] / v : 0.0;
+  }
+}
+
 }  // namespace
+
+size_t limber_bwd_lds_bytes(const plan_dev& p) {
+  const size_t T = p.max_tracers;
+  return sizeof(double) * (2 * T * LB_CH + T * T + T + 5 * LB_CH + 2 * (size_t)p.n_k) + sizeof(int) * (LB_CH + T);
+}
 
 size_t limber_lds_bytes(const plan_dev& p) {
   const size_t rs = p.precision == SWIFTCL_FP64 ? 8 : 4;
@@ -169,4 +353,26 @@ hipError_t launch_limber(const plan_dev& p, const swiftcl_inputs* in, void* C, h
   else
     hipLaunchKernelGGL(k_limber<float>, grid, dim3(256), limber_lds_bytes(p), s, p, *in, (float*)C);
   return hipGetLastError();
+}
+
+hipError_t launch_limber_backward(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,
+                                  double* dbias, double* dnz, double* dD, hipStream_t s) {
+  hipLaunchKernelGGL(k_limber_pk, dim3(in->batch), dim3(64), sizeof(double) * 2 * (size_t)p.n_k, s, p, *in);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_limber_zero, dim3(256), dim3(256), 0, s, p, *in);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int nch = (p.N + LB_CH - 1) / LB_CH;
+  const dim3 grid((unsigned)((size_t)in->batch * nch));
+  if (p.precision == SWIFTCL_FP64)
+    hipLaunchKernelGGL(k_limber_bwd<double>, grid, dim3(256), limber_bwd_lds_bytes(p), s, p, *in, (const double*)dC);
+  else
+    hipLaunchKernelGGL(k_limber_bwd<float>, grid, dim3(256), limber_bwd_lds_bytes(p), s, p, *in, (const float*)dC);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (dpk) {
+    hipLaunchKernelGGL(k_limber_bwd_pk, dim3(in->batch), dim3(64), sizeof(double) * 2 * (size_t)p.n_k, s, p, *in,
+                       dpk);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return launch_bwd_chain(p, in, dbias, dnz, dD, s);
 }

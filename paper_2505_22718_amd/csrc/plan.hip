@@ -320,7 +320,7 @@ template <typename T> static swiftcl_status dalloc(T** ptr, size_t count, const 
 static void free_plan(swiftcl_plan_s* p) {
   if (!p) return;
   void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.ell_v, p->d.lnk, p->d.lu_k,
-                  p->d.lnp, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
+                  p->d.lnp, p->d.lim_acc, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_ia, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
                   p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf,
                   p->d.kg_ones, p->d.kg_ia, p->d.kg_w, p->d.kg_ip, p->d.kg_uh, p->d.kg_c, p->d.kg_m, p->d.kg_perm,
@@ -527,7 +527,8 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(phase, double, (size_t)B * N);
   ALLOC(node_f, double, (size_t)B * 4 * N);
   ALLOC(node_i, int, (size_t)B * 3 * N);
-  if (p->d.adjoint) ALLOC(ddD_part, double, (size_t)B * T * 2 * p->d.n_zg);
+  ALLOC(ddD_part, double, (size_t)B * T * 2 * p->d.n_zg);  // the FFTLog and Limber adjoints
+  ALLOC(lim_acc, double, (size_t)B * 2 * nk);
   ALLOC(g, char, (size_t)B * T * nb * N * rs);
   ALLOC(chat, char, (size_t)B * T * nb * M * 2 * rs);
   if (p->d.mag) {
@@ -840,6 +841,40 @@ extern "C" swiftcl_status swiftcl_cl_limber(swiftcl_plan_t p, const swiftcl_inpu
   hipError_t e = launch_assemble(p->d, in, s);
   if (e == hipSuccess) e = launch_limber(p->d, in, C, s);
   return hip_check(e, "Limber launch");
+}
+
+size_t limber_bwd_lds_bytes(const plan_dev& p);
+
+extern "C" swiftcl_status swiftcl_cl_limber_backward(swiftcl_plan_t p, const swiftcl_inputs* in, const void* dC,
+                                                     double* dpk, double* dbias, double* dnz, double* dD,
+                                                     void* stream) {
+  swiftcl_status st = check_inputs(p, in);
+  if (st != SWIFTCL_OK) return st;
+  if (!dC) { set_error("dC is NULL"); return SWIFTCL_E_INVALID; }
+  if (p->d.rsd || p->d.mag) {
+    set_error("the Limber path does not include redshift-space distortions or magnification");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
+  if (in->kernel_chi) {
+    set_error("the Limber path takes its kernels from the assembly; kernel samples (kernel_chi) are refused");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
+  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  int lds_max = 0;
+  if ((st = hip_check(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->d.device),
+                      "device attribute")) != SWIFTCL_OK)
+    return st;
+  if (limber_bwd_lds_bytes(p->d) > (size_t)lds_max) {
+    set_error("the Limber adjoint needs " + std::to_string(limber_bwd_lds_bytes(p->d)) +
+              " bytes of LDS per workgroup (max_tracers, n_k); the device has " + std::to_string(lds_max));
+    return SWIFTCL_E_UNSUPPORTED;
+  }
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  p->fwd_valid = false;
+  hipError_t e = launch_assemble(p->d, in, s);
+  if (e == hipSuccess) e = launch_limber_backward(p->d, in, dC, dpk, dbias, dnz, dD, s);
+  return hip_check(e, "Limber backward launch");
 }
 
 // Checks shared by the two backward entry points; `reuse` is set when the forward state is kept.

@@ -280,19 +280,34 @@ class Plan:
         s = self.inputs_struct(t)
         B = s.batch
         dC = self._cl_buffer("dC", dC.contiguous(), B)
-        f64 = dict(dtype=torch.float64, device=self.device)
-        outs = {
-            "pk": torch.empty((B, len(self.k)), **f64) if "pk" in want else None,
-            "bias": torch.empty((B, self.max_tracers), **f64) if "bias" in want else None,
-            "nz": torch.empty((B, self.max_tracers, len(self.z_nz)), **f64) if "nz" in want else None,
-            "D": torch.empty((B, len(self.z_geom)), **f64) if "D" in want else None,
-        }
+        outs = self._grad_outputs(B, want)
         ptr = {k: (v.data_ptr() if v is not None else 0) for k, v in outs.items()}
         if not reuse_forward:
             self._new_state()
         bd.swiftcl_cl_backward(self.handle, s, dC.data_ptr(), ptr["pk"], ptr["bias"], ptr["nz"], ptr["D"],
                                _flags(reuse_forward), self._stream())
         return {k: v for k, v in outs.items() if v is not None}
+
+    def limber_backward(self, t, dC, want=("pk", "bias", "nz", "D")):
+        """Gradients of sum(dC * C_limber) (swiftcl_cl_limber_backward)."""
+        s = self.inputs_struct(t)
+        B = s.batch
+        dC = self._cl_buffer("dC", dC.contiguous(), B)
+        outs = self._grad_outputs(B, want)
+        ptr = {k: (v.data_ptr() if v is not None else 0) for k, v in outs.items()}
+        self._new_state()
+        bd.swiftcl_cl_limber_backward(self.handle, s, dC.data_ptr(), ptr["pk"], ptr["bias"], ptr["nz"], ptr["D"],
+                                      self._stream())
+        return {k: v for k, v in outs.items() if v is not None}
+
+    def _grad_outputs(self, B, want):
+        f64 = dict(dtype=torch.float64, device=self.device)
+        return {
+            "pk": torch.empty((B, len(self.k)), **f64) if "pk" in want else None,
+            "bias": torch.empty((B, self.max_tracers), **f64) if "bias" in want else None,
+            "nz": torch.empty((B, self.max_tracers, len(self.z_nz)), **f64) if "nz" in want else None,
+            "D": torch.empty((B, len(self.z_geom)), **f64) if "D" in want else None,
+        }
 
     def backward_timed(self, t, dC, outs, reuse_forward=False):
         """Backward with per-stage device times (ms); outs: dict of preallocated gradient tensors."""

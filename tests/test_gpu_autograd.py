@@ -3,7 +3,7 @@
 FP64: torch.autograd.gradcheck with the full Jacobian (fast_mode=False: every input entry by
 central differences, eps 1e-6 relative to the input scale) over P(k), biases, n(z) samples and
 D(z) samples, on the 2-bin workload and on one clustering plus one lensing bin of the 15-tracer
-set (N_chi = N_k = 1024, five multipoles).
+set (N_chi = N_k = 1024, five multipoles), for the FFTLog C_l and for the Limber limit.
 FP32 (15 tracers, biases scaled by U(0.9, 1.1)): central differences with a 1e-4 relative step
 along seeded directions that move every entry of P(k) (random signs), of one tracer's n(z) or
 of D(z) (by (0.5 + U(0, 1)) times the entry, so C moves by ~1e-4 relative; a single k node or
@@ -47,10 +47,12 @@ def _one_clustering_one_lensing():
     return wl
 
 
+@pytest.mark.parametrize("path", ["fftlog", "limber"])
 @pytest.mark.parametrize("name", ["cfg0", "clustering+lensing"])
-def test_gradcheck_fp64(dev, name):
-    from paper_2505_22718_amd.autograd import cl
+def test_gradcheck_fp64(dev, name, path):
+    from paper_2505_22718_amd import autograd
     from paper_2505_22718_amd.plan import Plan, device_inputs
+    cl = autograd.cl if path == "fftlog" else autograd.cl_limber
     wl = synth.make_workload("cfg0") if name == "cfg0" else _one_clustering_one_lensing()
     plan = Plan.for_workload(wl, precision="fp64")
     t = device_inputs(wl, dev)
@@ -68,7 +70,7 @@ def test_gradcheck_fp64(dev, name):
         return f, (base[name] / scale[name]).clone().requires_grad_(True)
 
     for arg in ("pk", "bias", "nz", "D"):
-        _say(f"gradcheck {name} {arg}")
+        _say(f"gradcheck {path} {name} {arg}")
         f, x = make(arg)
         # the tolerance follows the gradient's own scale: a central difference of step eps carries
         # ~1e-16 sum|G C| / eps of rounding, ~1e-7 of the largest entry here, while L itself may be
