@@ -109,44 +109,65 @@ __host__ __device__ constexpr int fft_radix(int M, int p) {
 // the pass blocks tile [M, 2M - 1) since sum over passes of (r - 1) Ls = M - 1.
 __host__ __device__ constexpr int fft_tw_index(int M, int Ls, int i, int j) { return M + Ls - 1 + (i - 1) * Ls + j; }
 
-// LDS scratch layout of the wave FFT (64 banks of 4 bytes; a 64-bit access is served per half
-// wavefront, so 32 lanes conflict-free means 32 distinct complex slots mod 32).  Both layouts add
-// to the complex index c a sum of its shifted bits, so every access of a pass is a per-lane base
-// plus a compile-time offset (no per-access address arithmetic):
-//  * FP32, M = 512 (radix 8, 8, 8): c + (c >> 5) + 2 (c >> 6), 540 slots.  The reads (32 consecutive
-//    slots) are conflict-free, the strided writes of the first two passes 2-way, and the scratch
-//    is small enough for two 1024-thread workgroups per CU.
-//  * FP32, M = 1024 (radix 16, 8, 8): c + (c >> 5), 1055 slots: reads and the first pass's writes
-//    conflict-free, the second pass's writes 2-way; 16 wavefronts' scratch and the twiddles fit
-//    one workgroup's LDS.
-//  * otherwise: c + (c >> 3) (the stride-8 writes of radix 8 and the quarter-wave 128-bit accesses
-//    of FP64 spread over all banks).
+// LDS scratch layouts of the wave FFT.  Measured on gfx950 (rocprofv3 SQ_LDS_BANK_CONFLICT of
+// single-pattern kernels): a 64-bit read serves 32 lanes per cycle from 32 slots of 8 bytes, a
+// 64-bit write 16 lanes per cycle from 16 slots, so a read is conflict-free when each half
+// wavefront hits 32 distinct slots mod 32 and a write when each quarter hits 16 distinct slots
+// mod 16.  Every layout adds to the complex index c a function of its bits that is additive over
+// disjoint bit sets, so every access of a pass is a per-lane base plus a compile-time offset (no
+// per-access address arithmetic).  The buffer between two passes and the real transforms'
+// exchange each take their own layout (BUF 0: written by pass 1, read by pass 2; BUF 1: written
+// by pass 2, read by pass 3; BUF 2: the exchange, consecutive writes and mirrored reads):
+//  * FP32, M = 512 (radix 8, 8, 8): BUF 0 c + (c >> 4) (the stride-8 writes of pass 1 land on 16
+//    distinct slots; one 2-way slot per half-wave read), BUF 1 c XOR 8 bit6(c) (a bijection: the two
+//    runs of 8 of each pass-2 write quarter land on the two halves of the 16 slots, the reads stay
+//    runs of 32), BUF 2 c: at most 543 slots, small enough for two 1024-thread workgroups per CU.
+//  * FP32, M = 1024 (radix 16, 8, 8): BUF 0 c + (c >> 4), BUF 1 c + (c >> 5), BUF 2 c (1087 slots).
+//  * otherwise: c + (c >> 3) for every buffer.
 // A wavefront's scratch holds fft_lds_size(M, sizeof(R)) complex values.
 __host__ __device__ constexpr bool fft_compact_layout(int M, int rs) { return rs == 4 && (M == 512 || M == 1024); }
-__host__ __device__ constexpr int fft_lds_size(int M, int rs) { return fft_compact_layout(M, rs) ? (M == 512 ? M + 32 : M + M / 32) : M + M / 8; }
+__host__ __device__ constexpr int fft_lds_size(int M, int rs) { return fft_compact_layout(M, rs) ? M + M / 16 : M + M / 8; }
 // Row stride (floats) of a [16][n_k] LDS tile whose row t doubles as the FFT scratch of the
 // wavefront that owns tracer t: room for both, and == 4 (mod 64) so that an MFMA operand read of
 // 16 rows x 4 consecutive k touches 64 distinct banks.
 __host__ __device__ constexpr int compact_vs(int n_k, int M) {
   return (((n_k > 2 * fft_lds_size(M, 4) ? n_k : 2 * fft_lds_size(M, 4)) + 63) / 64) * 64 + 4;
 }
-// Both layouts are sums of right shifts of c, so fft_at(x + K) = fft_at(x) + fft_at(K) whenever x
-// and K have no bit in common, and fft_at is linear on multiples of 64.  The passes split every
-// index into a per-lane part (lane < 64) and a compile-time part that way, so that the compiler
-// folds the latter into the LDS instruction's offset; the mirrored read of the real transforms,
-// M - n = (64 - lane) + 64 (RL - 1 - e), uses the linearity for lane 0.
-template <typename R, int M> __device__ __forceinline__ int fft_at(int c) {
-  if constexpr (fft_compact_layout(M, (int)sizeof(R)) && M == 512) return c + (c >> 5) + 2 * (c >> 6);
-  else if constexpr (fft_compact_layout(M, (int)sizeof(R))) return c + (c >> 5);
-  else return c + (c >> 3);
+// fft_idx<R, M, BUF>(lp, K): the slot of complex index lp + K, lp a per-lane part and K a
+// compile-time part with no bit in common (the unrolled loops make K a constant).  The additive
+// layouts give fft_at(lp) + fft_at(K); BUF 2 (the identity, or c + (c >> 3)) is also linear on
+// multiples of 64, which the mirrored read of the real transforms, M - n = (64 - lane) +
+// 64 (RL - 1 - e), uses for lane 0.  The XOR layout flips bit 3 where bit 6 is set: with K's bits
+// known, the slot is one of lp, lp ^ 8, lp - 8 bit6(lp), lp ^ (8 bit6(lp)) plus a constant, so the
+// compiler keeps at most two bases per pass and folds the rest into the instruction offsets.
+template <typename R, int M, int BUF> __device__ __forceinline__ int fft_at(int c) {
+  if constexpr (fft_compact_layout(M, (int)sizeof(R))) {
+    if constexpr (BUF == 0) return c + (c >> 4);
+    else if constexpr (BUF == 1) return c + (c >> 5);  // (M = 1024; M = 512 takes the XOR layout)
+    else return c;
+  } else {
+    return c + (c >> 3);
+  }
+}
+template <typename R, int M, int BUF> __device__ __forceinline__ int fft_idx(int lp, int K) {
+  if constexpr (fft_compact_layout(M, (int)sizeof(R)) && M == 512 && BUF == 1) {
+    const int k6 = (K >> 6) & 1, k3 = (K >> 3) & 1;
+    const int l6 = (lp >> 6) & 1;
+    if (k6) return k3 ? lp + K - 8 : (lp ^ 8) + K;
+    return k3 ? lp - 8 * l6 + K : (lp ^ (8 * l6)) + K;
+  } else {
+    return fft_at<R, M, BUF>(lp) + fft_at<R, M, BUF>(K);
+  }
 }
 
 // One Stockham pass (self-sorting, natural-order output) of radix r on an M-point sequence.
 // Butterfly q (q = lane + 64 u) reads x[q + i M/r], applies twiddles e^{S 2 pi i i j / (Ls r)}
 // with j = q mod Ls, runs dft<r> and writes Y_i to (q / Ls) Ls r + j + i Ls.
 // tw is the table described at fft_tw_index (global memory or LDS).
-template <typename R, int M, int r, int Ls, int S, bool FIRST, bool LAST>
+template <typename R, int M, int r, int Ls, int S, bool FIRST, bool LAST, int PASS>
 __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
+  constexpr int BR = PASS - 1 < 1 ? PASS - 1 : 1;  // buffer this pass reads (passes beyond 3 share
+  constexpr int BW = PASS < 1 ? PASS : 1;          // BUF 1: only the compact layouts differ)
   constexpr int RL = M / SWIFTCL_WAVE;
   constexpr int BPL = RL / r;
   constexpr int L = Ls * r;
@@ -161,7 +182,7 @@ __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>*
 #pragma unroll
     for (int u = 0; u < BPL; ++u) {
 #pragma unroll
-      for (int i = 0; i < r; ++i) b[u * r + i] = lds[fft_at<R, M>(lane) + fft_at<R, M>(SWIFTCL_WAVE * u + i * (M / r))];
+      for (int i = 0; i < r; ++i) b[u * r + i] = lds[fft_idx<R, M, BR>(lane, SWIFTCL_WAVE * u + i * (M / r))];
     }
     wave_sync();
   }
@@ -191,7 +212,7 @@ __device__ __forceinline__ void stockham_pass(C2<R>* v, C2<R>* lds, const C2<R>*
       const int j = q & (Ls - 1);
       const int base = (q / Ls) * L + j;
 #pragma unroll
-      for (int i = 0; i < r; ++i) lds[fft_at<R, M>(base) + fft_at<R, M>(i * Ls)] = b[u * r + i];
+      for (int i = 0; i < r; ++i) lds[fft_idx<R, M, BW>(base, i * Ls)] = b[u * r + i];
     }
     wave_sync();
   }
@@ -205,22 +226,22 @@ __device__ __forceinline__ void wave_fft(C2<R>* v, C2<R>* lds, const C2<R>* __re
   using P = fft_plan<M>;
   if constexpr (P::NP == 3) {
     constexpr int r0 = P::rad[0], r1 = P::rad[1], r2 = P::rad[2];
-    stockham_pass<R, M, r0, 1, S, true, false>(v, lds, tw, lane);
-    stockham_pass<R, M, r1, r0, S, false, false>(v, lds, tw, lane);
-    stockham_pass<R, M, r2, r0 * r1, S, false, true>(v, lds, tw, lane);
+    stockham_pass<R, M, r0, 1, S, true, false, 0>(v, lds, tw, lane);
+    stockham_pass<R, M, r1, r0, S, false, false, 1>(v, lds, tw, lane);
+    stockham_pass<R, M, r2, r0 * r1, S, false, true, 2>(v, lds, tw, lane);
   } else if constexpr (P::NP == 4) {
-    stockham_pass<R, M, 4, 1, S, true, false>(v, lds, tw, lane);
-    stockham_pass<R, M, 4, 4, S, false, false>(v, lds, tw, lane);
-    stockham_pass<R, M, 4, 16, S, false, false>(v, lds, tw, lane);
-    stockham_pass<R, M, 4, 64, S, false, true>(v, lds, tw, lane);
+    stockham_pass<R, M, 4, 1, S, true, false, 0>(v, lds, tw, lane);
+    stockham_pass<R, M, 4, 4, S, false, false, 1>(v, lds, tw, lane);
+    stockham_pass<R, M, 4, 16, S, false, false, 2>(v, lds, tw, lane);
+    stockham_pass<R, M, 4, 64, S, false, true, 3>(v, lds, tw, lane);
   } else {
-    stockham_pass<R, M, 2, 1, S, true, false>(v, lds, tw, lane);
-    stockham_pass<R, M, 2, 2, S, false, false>(v, lds, tw, lane);
-    stockham_pass<R, M, 2, 4, S, false, false>(v, lds, tw, lane);
-    stockham_pass<R, M, 2, 8, S, false, false>(v, lds, tw, lane);
-    stockham_pass<R, M, 2, 16, S, false, false>(v, lds, tw, lane);
-    stockham_pass<R, M, 2, 32, S, false, false>(v, lds, tw, lane);
-    stockham_pass<R, M, 2, 64, S, false, true>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 1, S, true, false, 0>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 2, S, false, false, 1>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 4, S, false, false, 2>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 8, S, false, false, 3>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 16, S, false, false, 4>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 32, S, false, false, 5>(v, lds, tw, lane);
+    stockham_pass<R, M, 2, 64, S, false, true, 6>(v, lds, tw, lane);
   }
 }
 
@@ -236,7 +257,7 @@ __device__ __forceinline__ void wave_r2c(C2<R>* v, C2<R>* lds, const C2<R>* __re
   constexpr int RL = M / SWIFTCL_WAVE;
   wave_fft<R, M, -1>(v, lds, tw, lane);
 #pragma unroll
-  for (int e = 0; e < RL; ++e) lds[fft_at<R, M>(lane) + fft_at<R, M>(SWIFTCL_WAVE * e)] = v[e];
+  for (int e = 0; e < RL; ++e) lds[fft_idx<R, M, 2>(lane, SWIFTCL_WAVE * e)] = v[e];
   wave_sync();
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
@@ -245,7 +266,7 @@ __device__ __forceinline__ void wave_r2c(C2<R>* v, C2<R>* lds, const C2<R>* __re
     if (n == 0) {
       v[e] = mk<R>(Zn.x + Zn.y, (R)0);
     } else {
-      const C2<R> Zm = cconj(lds[fft_at<R, M>(SWIFTCL_WAVE - lane) + fft_at<R, M>(SWIFTCL_WAVE * (RL - 1 - e))]);
+      const C2<R> Zm = cconj(lds[fft_idx<R, M, 2>(SWIFTCL_WAVE - lane, SWIFTCL_WAVE * (RL - 1 - e))]);
       const C2<R> A = cscale(cadd(Zn, Zm), (R)0.5);
       const C2<R> Bd = cscale(csub(Zn, Zm), (R)0.5);
       const C2<R> t2 = cmul(tw[n], Bd);
@@ -262,7 +283,7 @@ template <typename R, int M>
 __device__ __forceinline__ void wave_c2r(C2<R>* v, C2<R>* lds, const C2<R>* __restrict__ tw, int lane) {
   constexpr int RL = M / SWIFTCL_WAVE;
 #pragma unroll
-  for (int e = 0; e < RL; ++e) lds[fft_at<R, M>(lane) + fft_at<R, M>(SWIFTCL_WAVE * e)] = v[e];
+  for (int e = 0; e < RL; ++e) lds[fft_idx<R, M, 2>(lane, SWIFTCL_WAVE * e)] = v[e];
   wave_sync();
 #pragma unroll
   for (int e = 0; e < RL; ++e) {
@@ -270,7 +291,7 @@ __device__ __forceinline__ void wave_c2r(C2<R>* v, C2<R>* lds, const C2<R>* __re
     if (n == 0) {
       v[e] = mk<R>(v[e].x, v[e].x);  // X_0 (1 + i)
     } else {
-      const C2<R> Xm = cconj(lds[fft_at<R, M>(SWIFTCL_WAVE - lane) + fft_at<R, M>(SWIFTCL_WAVE * (RL - 1 - e))]);  // X_{n+M} = conj(X_{M-n})
+      const C2<R> Xm = cconj(lds[fft_idx<R, M, 2>(SWIFTCL_WAVE - lane, SWIFTCL_WAVE * (RL - 1 - e))]);  // X_{n+M} = conj(X_{M-n})
       const C2<R> A = cadd(v[e], Xm);
       const C2<R> Bd = csub(v[e], Xm);
       const C2<R> t2 = cmul(cconj(tw[n]), Bd);
