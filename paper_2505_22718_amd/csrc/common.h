@@ -128,10 +128,17 @@ __host__ __device__ constexpr int fft_tw_index(int M, int Ls, int i, int j) { re
 __host__ __device__ constexpr bool fft_compact_layout(int M, int rs) { return rs == 4 && (M == 512 || M == 1024); }
 __host__ __device__ constexpr int fft_lds_size(int M, int rs) { return fft_compact_layout(M, rs) ? M + M / 16 : M + M / 8; }
 // Row stride (floats) of a [16][n_k] LDS tile whose row t doubles as the FFT scratch of the
-// wavefront that owns tracer t: room for both, and == 4 (mod 64) so that an MFMA operand read of
-// 16 rows x 4 consecutive k touches 64 distinct banks.
+// wavefront that owns tracer t: room for both.  A 32-bit LDS read serves 32 lanes per cycle from
+// 32 banks (measured like the 64-bit accesses above), so the stride is chosen per access pattern:
+//  * the adjoint (compact_vs) reads MFMA operands of rows 4 (lane / 16) + s, 16 consecutive k:
+//    stride == 4 (mod 32) puts the two row groups of a half-wave 16 banks apart;
+//  * the forward projection (compact_vs_fwd) reads rows lane % 16 at k + lane / 16: stride == 2
+//    (mod 32) gives the 32 lanes of a half-wave 32 distinct banks.
 __host__ __device__ constexpr int compact_vs(int n_k, int M) {
   return (((n_k > 2 * fft_lds_size(M, 4) ? n_k : 2 * fft_lds_size(M, 4)) + 63) / 64) * 64 + 4;
+}
+__host__ __device__ constexpr int compact_vs_fwd(int n_k, int M) {
+  return (((n_k > 2 * fft_lds_size(M, 4) ? n_k : 2 * fft_lds_size(M, 4)) + 31) / 32) * 32 + 2;
 }
 // fft_idx<R, M, BUF>(lp, K): the slot of complex index lp + K, lp a per-lane part and K a
 // compile-time part with no bit in common (the unrolled loops make K a constant).  The additive

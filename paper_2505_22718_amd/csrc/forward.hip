@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
 // Windows and / or C_l of one (point, multipole slot) by a workgroup of NW wavefronts (wave t
 // handles tracer t); stw: twiddles (LDS or global), fbuf: per-wave FFT scratch, V: sqrt(s) W.
 // COMPACT (FP32 projection): the FFT scratch of tracer t lives in V's row t (the wavefront writes
-// the row only after its transform): twiddles + 16 x compact_vs floats of LDS, which for
+// the row only after its transform): twiddles + 16 x compact_vs_fwd floats of LDS, which for
 // n_chi <= 1024 and n_k <= 1024 is 72 KiB, so two 1024-thread workgroups share a CU.
 template <typename R, int M, int NW, bool WRITE_W, bool DO_CL, bool SPLIT, bool COMPACT>
 __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl_inputs& in, R* __restrict__ Wout,
@@ -152,7 +152,7 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
     if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
     ei = 0;
   }
-  const int vs = COMPACT ? compact_vs(nk, M) : nk + 2;  // row stride of V: rows start on distinct banks
+  const int vs = COMPACT ? compact_vs_fwd(nk, M) : nk + 2;  // row stride of V: rows start on distinct banks
   const int band = P.ell_band[ei];
   const int trows = DO_CL ? 16 : T;
   for (int t = wave; t < trows; t += NW) {
@@ -700,7 +700,7 @@ static hipError_t launch_wcl_t(const plan_dev& p, const swiftcl_inputs* in, void
   constexpr int NW = wcl_shape<R, M>::NW;
   constexpr bool TW = wcl_shape<R, M>::TW;
   const size_t lds = (sizeof(R) == 4 && DO_CL)
-                         ? (TW ? 2 * (size_t)M * sizeof(C2<R>) : 0) + (size_t)16 * compact_vs(p.n_k, M) * sizeof(R)
+                         ? (TW ? 2 * (size_t)M * sizeof(C2<R>) : 0) + (size_t)16 * compact_vs_fwd(p.n_k, M) * sizeof(R)
                          : windows_cl_lds(M, NW, TW, DO_CL, sizeof(R), p.n_k);
   const bool split = p.precision == SWIFTCL_SPLIT_BF16;
   if (DO_CL && !WRITE_W && p.fwd_mode == 1) {
