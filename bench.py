@@ -135,8 +135,10 @@ def progress(msg):
 
 
 def profile_split_pass(B):
-    """Two forward calls of the 30-tracer split-precision batch (465 spectra x 200 l, N_k = N_chi =
-    2048), then a 256 MiB device copy (the FETCH_SIZE / WRITE_SIZE reference); run under rocprofv3."""
+    """Two forward + backward steps of the 30-tracer split-precision batch (465 spectra x 200 l,
+    N_k = N_chi = 2048; the adjoint through the workspace), then a 256 MiB device copy (the
+    FETCH_SIZE / WRITE_SIZE reference); run under rocprofv3."""
+    import numpy as np
     import torch
     import synth
     from paper_2505_22718_amd.plan import Plan, device_inputs
@@ -144,14 +146,16 @@ def profile_split_pass(B):
     plan = Plan.for_workload(wl, precision="split_bf16")
     inp = device_inputs(wl, "cuda:0")
     C = torch.empty((B, plan.max_ell, plan.n_pairs), dtype=torch.float32, device="cuda:0")
+    dC = torch.as_tensor(np.random.default_rng(0).standard_normal(tuple(C.shape)), dtype=torch.float32, device="cuda:0")
     for _ in range(2):
         plan.cl(inp, C)
+        plan.backward(inp, dC, reuse_forward=True)
     torch.cuda.synchronize()
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(f"split profile pass done: 2 calls of {B} points, then a 268435456-byte copy", flush=True)
+    print(f"split profile pass done: 2 steps of {B} points, then a 268435456-byte copy", flush=True)
 
 
 def time_ms(fn, steps, stream):
@@ -404,7 +408,7 @@ def main():
     ap.add_argument("--profile-kgrowth", action="store_true",
                     help="run two scale-dependent-growth calls of the batch for rocprofv3; no JSON line")
     ap.add_argument("--profile-split", action="store_true",
-                    help="run two calls of the 64-point, 30-tracer split-precision batch for rocprofv3; no JSON line")
+                    help="run two forward + backward steps of the 64-point, 30-tracer split-precision batch for rocprofv3; no JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
