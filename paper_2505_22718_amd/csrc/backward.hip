@@ -411,6 +411,102 @@ __global__ __launch_bounds__(256) void k_bwd_gv(plan_dev P, swiftcl_inputs in, c
   if (q == 0 && cok) ((float*)P.dpk_part)[((size_t)b * nlc + c) * nk + col] = dp;
 }
 
+// k_bwd_gv with 16-byte accesses (n_k a multiple of 4): one workgroup per (point, multipole chunk,
+// 256-wide k tile); lane (r, q) of wave w owns the columns 256 tile + 64 w + 4 r + (0..3) and reads
+// 4 consecutive W values of a row per load.  Column j of the four is the B operand of MFMA tile j,
+// so tile j holds the columns {4 r + j}, and every lane stores its 4 columns of a Y row as one
+// 16-byte store.  Same in-place order as k_bwd_gv.
+template <bool TWO>
+__global__ __launch_bounds__(256) void k_bwd_gv4(plan_dev P, swiftcl_inputs in, const float* __restrict__ dC,
+                                                  int b0, int nbp, int nlc) {
+  __shared__ float Gs[2][32][33];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / SWIFTCL_WAVE), lane = tid % SWIFTCL_WAVE;
+  const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k;
+  const int ntile = (nk + 255) / 256;
+  const int tile = blockIdx.x % ntile;
+  const int rest = blockIdx.x / ntile;
+  const int c = rest % nlc;
+  const int bl = rest / nlc;
+  if (bl >= nbp) return;
+  const int b = b0 + bl;
+  const int Tb = clampb(in.n_tracers[b], 0, T);
+  const int Lb = clampb(in.n_ell[b], 0, Lm);
+  const int l0 = (int)(((long)c * Lb) / nlc), l1 = (int)(((long)(c + 1) * Lb) / nlc);
+  const int npair = T * (T + 1) / 2;
+  const int q = lane >> 4, r = lane & 15;
+  const int col = 256 * tile + 64 * wave + 4 * r;  // first of this lane's 4 columns
+  const bool cok = col < nk;                       // (nk % 4 == 0: all four or none)
+  auto gval = [&](int li, int e) -> float {
+    const int i = e >> 5, j = e & 31;
+    if (i >= Tb || j >= Tb) return 0.f;
+    const int a = i < j ? i : j, cc = i < j ? j : i;
+    const float g = dC[((size_t)b * Lm + li) * npair + (a * T - a * (a - 1) / 2 + (cc - a))];
+    return i == j ? g : 0.5f * g;
+  };
+  float gn[4] = {0.f, 0.f, 0.f, 0.f};
+  if (l0 < l1)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) gn[m] = gval(l0, tid + 256 * m);
+  float4 dp = make_float4(0.f, 0.f, 0.f, 0.f);
+  constexpr int NI = TWO ? 2 : 1;  // 16-row tracer tiles
+  for (int li = l0; li < l1; ++li) {
+    const int buf = (li - l0) & 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = tid + 256 * m;
+      Gs[buf][e >> 5][e & 31] = gn[m];
+    }
+    __syncthreads();
+    if (li + 1 < l1)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) gn[m] = gval(li + 1, tid + 256 * m);
+    float* w = (float*)P.vbuf + ((size_t)bl * Lm + li) * 32 * nk;
+    v4f y[4][NI];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int it = 0; it < NI; ++it) y[j][it] = (v4f){0.f, 0.f, 0.f, 0.f};
+    constexpr int NJ = TWO ? 8 : 4;
+#pragma unroll
+    for (int st = 0; st < NJ; ++st) {
+      const float4 wv = cok ? *(const float4*)(w + (size_t)(4 * st + q) * nk + col) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float bw[4] = {wv.x, wv.y, wv.z, wv.w};
+      const float a0 = Gs[buf][r][4 * st + q];
+      const float a1 = TWO ? Gs[buf][16 + r][4 * st + q] : 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        y[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bw[j], y[j][0], 0, 0, 0);
+        if constexpr (TWO) y[j][NI - 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bw[j], y[j][NI - 1], 0, 0, 0);
+      }
+    }
+    // y[j][it][m] = Y[16 it + 4 q + m][col + j]
+    if (cok) {
+#pragma unroll
+      for (int it = 0; it < NI; ++it)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          float4* a = (float4*)(w + (size_t)(16 * it + 4 * q + m) * nk + col);
+          const float4 wo = *a;
+          dp.x += wo.x * y[0][it][m];
+          dp.y += wo.y * y[1][it][m];
+          dp.z += wo.z * y[2][it][m];
+          dp.w += wo.w * y[3][it][m];
+          *a = make_float4(y[0][it][m], y[1][it][m], y[2][it][m], y[3][it][m]);
+        }
+    }
+  }
+  dp.x += __shfl_xor(dp.x, 16);
+  dp.y += __shfl_xor(dp.y, 16);
+  dp.z += __shfl_xor(dp.z, 16);
+  dp.w += __shfl_xor(dp.w, 16);
+  dp.x += __shfl_xor(dp.x, 32);
+  dp.y += __shfl_xor(dp.y, 32);
+  dp.z += __shfl_xor(dp.z, 32);
+  dp.w += __shfl_xor(dp.w, 32);
+  if (q == 0 && cok) *(float4*)((float*)P.dpk_part + ((size_t)b * nlc + c) * nk + col) = dp;
+}
+
 // (a6) Adjoint transforms for one (point, multipole chunk, group of 4 tracers): wave w takes
 // tracer 4 g + w through the chunk's multipoles, dx = 2 s F k^{-1-b} Y from its workspace row,
 // r2c, dc += h conj(X) conj(U_l) in registers, flushed to the (point, chunk, tracer, band)
@@ -872,9 +968,15 @@ static hipError_t launch_bwd_ws(const plan_dev& p, const swiftcl_inputs* in, con
   for (int b0 = 0; b0 < in->batch; b0 += p.vchunk) {
     const int nbp = in->batch - b0 < p.vchunk ? in->batch - b0 : p.vchunk;
     if ((e = launch_windows_w(p, in, b0, nbp, s)) != hipSuccess) return e;
-    const dim3 g1((unsigned)((size_t)nbp * nlc * ntile));
-    if (T > 16) hipLaunchKernelGGL(k_bwd_gv<true>, g1, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
-    else hipLaunchKernelGGL(k_bwd_gv<false>, g1, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+    if (p.n_k % 4 == 0) {  // 16-byte rows
+      const dim3 g4((unsigned)((size_t)nbp * nlc * ((p.n_k + 255) / 256)));
+      if (T > 16) hipLaunchKernelGGL(k_bwd_gv4<true>, g4, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+      else hipLaunchKernelGGL(k_bwd_gv4<false>, g4, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+    } else {
+      const dim3 g1((unsigned)((size_t)nbp * nlc * ntile));
+      if (T > 16) hipLaunchKernelGGL(k_bwd_gv<true>, g1, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+      else hipLaunchKernelGGL(k_bwd_gv<false>, g1, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((k_bwd_adj<M, (M <= 1024)>), dim3((unsigned)((size_t)nbp * nlc * ng)), dim3(256), 0, s, p,
                        *in, b0, nbp, nlc);

@@ -610,10 +610,10 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   p->d.sched_stride = sched_stride_for(B);
   ALLOC(sched, int, sched_ints(p->d.sched_stride));
   if (p->d.adjoint == 2) {
-    // multipole chunks per point of the workspace adjoint: about 2048 wavefronts of adjoint
+    // multipole chunks per point of the workspace adjoint: about 4096 wavefronts of adjoint
     // transforms per chunk of points (one per point, chunk and tracer)
     const long pts = std::min(p->d.vchunk, B);
-    long nlc = (2048 + pts * T - 1) / (pts * T);
+    long nlc = (4096 + pts * T - 1) / (pts * T);
     nlc = std::max(1L, std::min(nlc, (long)p->d.max_ell));
     p->d.bwd_nlc = (int)nlc;
     p->d.bwd_slots = std::max(p->d.bwd_slots, (int)(nlc * B));
