@@ -215,8 +215,9 @@ swiftcl_status swiftcl_cl_backward(swiftcl_plan_t plan, const swiftcl_inputs* in
 
 /* Launch-shape autotuner (used by batched callers, e.g. many parameter points of uneven tracer and
  * multipole counts).  Times, on the caller's inputs, the forward projection launched as one
- * workgroup per (point, multipole slot) or as a persistent grid walking per-XCD compact work
- * lists, and (if dC is not NULL) the adjoint with 1, 2 or 4 times its base number of multipole
+ * workgroup per (point, multipole slot), as a persistent grid walking per-XCD compact work lists,
+ * or as a persistent grid walking per-XCD packed lists (two (point, multipole) items whose tracer
+ * counts sum to at most 16 share a workgroup), and (if dC is not NULL) the adjoint with 1, 2 or 4 times its base number of multipole
  * chunks; keeps the fastest in the plan (a variant other than the default, fwd_mode 0 and
  * bwd_chunk_mul 1, must be at least 2% faster).  With cache_path (may be NULL) the choice is read from,
  * or appended to, a file with one JSON object per line keyed by architecture and shape.  `C`
@@ -228,7 +229,8 @@ swiftcl_status swiftcl_autotune(swiftcl_plan_t plan, const swiftcl_inputs* in, v
 
 /* Set (values < 0 leave a field unchanged) or read the launch configuration the autotuner chooses:
  * fwd_mode 0 = one workgroup per (point, multipole slot), 1 = persistent grid over per-XCD compact
- * work lists; bwd_chunk_mul in {1, 2, 4} scales the adjoint's number of multipole chunks.  Every
+ * work lists, 2 = persistent grid over per-XCD packed lists (plans whose projection is fused; the
+ * others run mode 0 whatever is set); bwd_chunk_mul in {1, 2, 4} scales the adjoint's number of multipole chunks.  Every
  * configuration computes the same C_l bit for bit. */
 swiftcl_status swiftcl_set_launch(swiftcl_plan_t plan, int32_t fwd_mode, int32_t bwd_chunk_mul);
 swiftcl_status swiftcl_get_launch(swiftcl_plan_t plan, int32_t* fwd_mode, int32_t* bwd_chunk_mul);

@@ -123,10 +123,13 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
 // COMPACT (FP32 projection): the FFT scratch of tracer t lives in V's row t (the wavefront writes
 // the row only after its transform): twiddles + 16 x compact_vs_fwd floats of LDS, which for
 // n_chi <= 1024 and n_k <= 1024 is 72 KiB, so two 1024-thread workgroups share a CU.
-template <typename R, int M, int NW, bool WRITE_W, bool DO_CL, bool SPLIT, bool COMPACT>
+// PACK (C_l only): a second item (b2, li2), b2 >= 0, takes the rows T_b .. T_b + T_b2 - 1 of the
+// same 16-row Gram tile; its spectra are the tile's diagonal block at that offset (the two items'
+// cross block is computed and dropped).  The packed work list guarantees T_b + T_b2 <= 16.
+template <typename R, int M, int NW, bool WRITE_W, bool DO_CL, bool SPLIT, bool COMPACT, bool PACK = false>
 __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl_inputs& in, R* __restrict__ Wout,
                                                 R* __restrict__ Cout, int b, int li, const C2<R>* stw, C2<R>* fbuf,
-                                                R* V) {
+                                                R* V, int b2 = -1, int li2 = 0) {
   constexpr int RL = M / SWIFTCL_WAVE;
   constexpr int FL = fft_lds_size(M, sizeof(R));
   // W and V = sqrt(s) W take different k scales (kscale, kss); one call produces one of them
@@ -147,26 +150,46 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
     }
     return;
   }
-  int ei = in.ell_idx[(size_t)b * Lm + li];
-  if (ei < 0 || ei >= P.n_ell) {
-    if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
-    ei = 0;
+  static_assert(!PACK || (DO_CL && !WRITE_W), "packing applies to the C_l projection");
+  auto ell_index = [&](int pb, int pl) {
+    int e = in.ell_idx[(size_t)pb * Lm + pl];
+    if (e < 0 || e >= P.n_ell) {
+      if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+      e = 0;
+    }
+    return e;
+  };
+  const int ei1 = ell_index(b, li);
+  // the second item's rows start at o2 (no second item: o2 = 16, no row is its)
+  int o2 = 16, Tb2 = 0, ei2 = 0;
+  if (PACK && b2 >= 0) {
+    Tb2 = clampi(in.n_tracers[b2], 0, T);
+    ei2 = ell_index(b2, li2);
+    o2 = Tb;
+    if (o2 + Tb2 > 16) {  // not produced by the list builder
+      if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+      o2 = 16;
+      Tb2 = 0;
+      b2 = -1;
+    }
   }
   const int vs = COMPACT ? compact_vs_fwd(nk, M) : nk + 2;  // row stride of V: rows start on distinct banks
-  const int band = P.ell_band[ei];
   const int trows = DO_CL ? 16 : T;
-  for (int t = wave; t < trows; t += NW) {
-    if (t >= Tb) {
+  for (int r = wave; r < trows; r += NW) {
+    const bool sec = PACK && r >= o2;  // row of the second item
+    const int t = sec ? r - o2 : r, bt = sec ? b2 : b, ei = sec ? ei2 : ei1;
+    if (t >= (sec ? Tb2 : Tb)) {
       for (int j = lane; j < nk; j += SWIFTCL_WAVE) {
-        if (DO_CL) V[t * vs + j] = (R)0;
+        if (DO_CL) V[r * vs + j] = (R)0;
         if (WRITE_W && t < T) Wout[(((size_t)b * Lm + li) * T + t) * nk + j] = (R)0;
       }
       continue;
     }
-    const int kind = tracer_kind(in, T, b, t);
-    const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
+    const int band = P.ell_band[ei];
+    const int kind = tracer_kind(in, T, bt, t);
+    const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)bt * T + t) * nb + band) * M;
     const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
-    C2<R>* mine = COMPACT ? (C2<R>*)(V + (size_t)t * vs) : fbuf + (size_t)wave * FL;
+    C2<R>* mine = COMPACT ? (C2<R>*)(V + (size_t)r * vs) : fbuf + (size_t)wave * FL;
     C2<R> v[RL];
     wave_sync();
 #pragma unroll
@@ -181,7 +204,7 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
     wave_sync();
     // the k scale of the output pairs, loads issued in groups of KG (the index is clamped into
     // the row, nk is even; only the stores are guarded)
-    const R* kscl = DO_CL ? (const R*)P.kss + (((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk
+    const R* kscl = DO_CL ? (const R*)P.kss + (((size_t)bt * SWIFTCL_NKINDS + kind) * nb + band) * nk
                           : (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
     const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
     constexpr int KG = RL < 4 ? RL : 4;
@@ -196,7 +219,7 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
         if (k0 < nk) {
           const C2<R> x = mk<R>(F * kk[e].x * v[e0 + e].x, F * kk[e].y * v[e0 + e].y);
           if (WRITE_W) *(C2<R>*)(Wout + (((size_t)b * Lm + li) * T + t) * nk + k0) = x;
-          if (DO_CL) *(C2<R>*)(V + t * vs + k0) = x;  // V = sqrt(s) W
+          if (DO_CL) *(C2<R>*)(V + r * vs + k0) = x;  // V = sqrt(s) W
         }
       }
     }
@@ -236,27 +259,32 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[wave * 256 + mfma_acc<R>::row(lane, r) * 16 + (lane & 15)] = acc[r];
   __syncthreads();
-  R* c = Cout + ((size_t)b * Lm + li) * npair;
-  for (int idx = threadIdx.x; idx < npair; idx += NW * 64) {
-    int i = 0, rem = idx;
+  const int nout = (PACK && b2 >= 0) ? 2 * npair : npair;
+  for (int idx = threadIdx.x; idx < nout; idx += NW * 64) {
+    const bool sec = PACK && idx >= npair;
+    const int o = sec ? o2 : 0, tb = sec ? Tb2 : Tb;
+    int i = 0, rem = sec ? idx - npair : idx;
+    const int at = rem;
     while (rem >= T - i) { rem -= T - i; ++i; }
     const int j = i + rem;
     R val = (R)0;
-    if (i < Tb && j < Tb) {
+    if (i < tb && j < tb) {
 #pragma unroll
-      for (int w = 0; w < NW; ++w) val += red[w * 256 + i * 16 + j];
+      for (int w = 0; w < NW; ++w) val += red[w * 256 + (o + i) * 16 + o + j];
     }
-    c[idx] = val;
+    Cout[((size_t)(sec ? b2 : b) * Lm + (sec ? li2 : li)) * npair + at] = val;
   }
 }
 
-// Launch modes.  PERSIST = false: one workgroup per (point, multipole slot), blocks mapped so that
-// all multipoles of one point run on one XCD (block = ((b / 8) * Lm + l) * 8 + b % 8); padded
-// slots write zeros.  PERSIST = true: a grid sized to the chip; the blocks of XCD x walk the
-// compact list of (point b = 8 i + x, multipole) items built by k_schedule with the grid stride
-// (ragged multipole counts leave no idle workgroup, and every block loads the twiddles once);
-// padded slots are zeroed by k_zero_padded.
-template <typename R, int M, int NW, bool TW_LDS, bool WRITE_W, bool DO_CL, bool PERSIST, bool SPLIT>
+// Launch modes.  MODE 0: one workgroup per (point, multipole slot), blocks mapped so that all
+// multipoles of one point run on one XCD (block = ((b / 8) * Lm + l) * 8 + b % 8); padded slots
+// write zeros.  MODE 1: a grid sized to the chip; the blocks of XCD x walk the compact list of
+// (point b = 8 i + x, multipole) items built by k_schedule with the grid stride (ragged multipole
+// counts leave no idle workgroup, and every block loads the twiddles once).  MODE 2: as MODE 1 over
+// the packed list of k_schedule_packed, whose tasks hold one or two items of the XCD's points with
+// at most 16 tracers between them (points of few tracers leave no idle wavefronts).  Persistent
+// modes: padded slots are zeroed by k_zero_padded.
+template <typename R, int M, int NW, bool TW_LDS, bool WRITE_W, bool DO_CL, int MODE, bool SPLIT>
 __global__ __launch_bounds__(NW * 64)
 __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && DO_CL && M <= 512) ? 8 : 1))) void k_windows_cl(
     plan_dev P, swiftcl_inputs in, R* __restrict__ Wout, R* __restrict__ Cout) {
@@ -271,7 +299,7 @@ __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && DO_CL && M <= 512) ? 8 : 1
   const int xcd = blockIdx.x % SWIFTCL_NXCD;
   const int rest = blockIdx.x / SWIFTCL_NXCD;
   const C2<R>* stw = TW_LDS ? stw_l : (const C2<R>*)P.tw;
-  if constexpr (!PERSIST) {
+  if constexpr (MODE == 0) {
     const int li = rest % P.max_ell;
     const int b = (rest / P.max_ell) * SWIFTCL_NXCD + xcd;
     if (b >= in.batch) return;
@@ -282,29 +310,64 @@ __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && DO_CL && M <= 512) ? 8 : 1
     }
     windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT, COMPACT>(P, in, Wout, Cout, b, li, stw, fbuf, V);
   } else {
-    if constexpr (TW_LDS) {
-      const C2<R>* gtw = (const C2<R>*)P.tw;
-      for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
-      __syncthreads();
-    }
     const int stride = P.sched_stride;
     const int* offs = P.sched + sched_list_index(stride, xcd, 0);
     const int total = P.sched[sched_total_index(stride, xcd)];
     const int nx = (in.batch - xcd + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
     const int g8 = gridDim.x / SWIFTCL_NXCD;
-    // items rest, rest + g8, ...: the blocks of an XCD work on neighbouring items at any time, so
-    // the coefficients of the few points in flight stay in that XCD's L2
     if (rest >= total) return;
-    int i = 0, hi = nx;  // largest i with offs[i] <= rest
-    while (hi - i > 1) {
-      const int mid = (i + hi) >> 1;
-      if (offs[mid] <= rest) i = mid; else hi = mid;
-    }
-    for (int k = rest; k < total; k += g8) {
-      windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT, COMPACT>(P, in, Wout, Cout, i * SWIFTCL_NXCD + xcd,
-                                                                k - offs[i], stw, fbuf, V);
+    if constexpr (TW_LDS) {
+      const C2<R>* gtw = (const C2<R>*)P.tw;
+      for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
       __syncthreads();
-      while (i + 1 < nx && offs[i + 1] <= k + g8) ++i;  // the point holding item k + g8
+    }
+    // largest i with offs[i] <= q: the position of the point holding stream item q
+    auto locate = [&](int q) {
+      int i = 0, hi = nx;
+      while (hi - i > 1) {
+        const int mid = (i + hi) >> 1;
+        if (offs[mid] <= q) i = mid; else hi = mid;
+      }
+      return i;
+    };
+    if constexpr (MODE == 1) {
+      // items rest, rest + g8, ...: the blocks of an XCD work on neighbouring items at any time, so
+      // the coefficients of the few points in flight stay in that XCD's L2
+      int i = locate(rest);
+      for (int k = rest; k < total; k += g8) {
+        windows_cl_item<R, M, NW, WRITE_W, DO_CL, SPLIT, COMPACT>(P, in, Wout, Cout, i * SWIFTCL_NXCD + xcd,
+                                                                  k - offs[i], stw, fbuf, V);
+        __syncthreads();
+        while (i + 1 < nx && offs[i + 1] <= k + g8) ++i;  // the point holding item k + g8
+      }
+    } else {
+      static_assert(MODE != 2 || (DO_CL && !WRITE_W), "the packed list serves the C_l projection");
+      // tasks of uneven cost: after its first task (rest) a block takes the next one from the XCD's
+      // counter (zeroed by the list builder), requested one task ahead; next[] alternates so that
+      // the slot written during task i was last read before the barrier that ended task i - 1
+      __shared__ int next[2];
+      int* ctr = P.sched + sched_ctr_index(stride, xcd);
+      const int* pts = P.sched + sched_pts_index(stride, xcd, 0);
+      const int* seg = P.sched + sched_seg_index(stride, xcd, 0);
+      const int nseg = min(seg[0], SCHED_MAXSEG);
+      int sg = 0, par = 0;
+      for (int k = rest; k < total; par ^= 1) {
+        if (threadIdx.x == 0) next[par] = g8 + atomicAdd(ctr, 1);
+        while (sg + 1 < nseg && seg[1 + 3 * (sg + 1)] <= k) ++sg;  // the segment holding task k
+        const int d = k - seg[1 + 3 * sg];
+        const int qa = seg[2 + 3 * sg] + d, qb0 = seg[3 + 3 * sg];
+        const int ia = locate(qa);
+        int b2 = -1, l2 = 0;
+        if (qb0 >= 0) {
+          const int ib = locate(qb0 + d);
+          b2 = pts[ib];
+          l2 = qb0 + d - offs[ib];
+        }
+        windows_cl_item<R, M, NW, false, true, SPLIT, COMPACT, true>(P, in, Wout, Cout, pts[ia], qa - offs[ia], stw,
+                                                                     fbuf, V, b2, l2);
+        __syncthreads();
+        k = next[par];  // increasing: the counter only grows and starts above every first task
+      }
     }
   }
 }
@@ -322,6 +385,63 @@ __global__ void k_schedule(plan_dev P, swiftcl_inputs in) {
   }
   offs[i] = acc;
   P.sched[sched_total_index(P.sched_stride, x)] = acc;
+}
+
+// Packed per-XCD work lists (layout: sched_layout.h): XCD x's points ordered by descending
+// tracer count (a counting sort, stable within a count), the multipole prefix offsets over that
+// order, the pairing segments of sched_pack, and the XCD's task counter zeroed.  One 64-thread
+// workgroup per XCD: the lanes stage the points' tracer and multipole counts in LDS, lane 0 builds
+// the list from there.
+__global__ __launch_bounds__(64) void k_schedule_packed(plan_dev P, swiftcl_inputs in) {
+  constexpr int NC = SCHED_ROWS + 1;
+  __shared__ int s_t[SCHED_PACK_MAXNX], s_l[SCHED_PACK_MAXNX];
+  __shared__ int cnt[NC], rem[NC], cur[NC];
+  const int x = blockIdx.x, lane = threadIdx.x;
+  const int st = P.sched_stride, Tm = min(P.max_tracers, SCHED_ROWS), Lm = P.max_ell;
+  const int nx = min((in.batch - x + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD, SCHED_PACK_MAXNX);
+  for (int i = lane; i < nx; i += 64) {
+    const int b = i * SWIFTCL_NXCD + x;
+    s_t[i] = clampi(in.n_tracers[b], 0, Tm);
+    s_l[i] = clampi(in.n_ell[b], 0, Lm);
+  }
+  __syncthreads();
+  if (lane != 0) return;
+  for (int c = 0; c < NC; ++c) cnt[c] = rem[c] = 0;
+  for (int i = 0; i < nx; ++i) {
+    ++cnt[s_t[i]];
+    rem[s_t[i]] += s_l[i];
+  }
+  // first position of each count in the point order, and first stream index of its items
+  int pos = 0, items = 0;
+  for (int c = SCHED_ROWS; c >= 0; --c) {
+    const int n = cnt[c];
+    cnt[c] = pos;
+    cur[c] = items;
+    pos += n;
+    items += rem[c];
+  }
+  // place the points; offs over the new order from the position of each point's first item
+  int* pts = P.sched + sched_pts_index(st, x, 0);
+  int* offs = P.sched + sched_list_index(st, x, 0);
+  for (int i = 0; i < nx; ++i) {
+    const int c = s_t[i], at = cnt[c]++;
+    pts[at] = i * SWIFTCL_NXCD + x;
+    offs[at] = cur[c];
+    cur[c] += s_l[i];
+  }
+  offs[pos] = items;
+  for (int c = SCHED_ROWS, at = 0; c >= 0; --c) {  // rewind: cur[c] = first item of count c
+    cur[c] = at;
+    at += rem[c];
+  }
+  int* seg = P.sched + sched_seg_index(st, x, 0);
+  int total = sched_pack(rem, cur, seg);
+  if (seg[0] > SCHED_MAXSEG) {  // cannot happen (at most 43 segments); run nothing rather than misread
+    atomicOr(P.flags, FLAG_BAD_INDEX);
+    total = 0;
+  }
+  P.sched[sched_total_index(st, x)] = total;
+  P.sched[sched_ctr_index(st, x)] = 0;
 }
 
 // Zeros of the padded multipole slots (l >= n_ell[b]) for the persistent launch.
@@ -703,22 +823,37 @@ static hipError_t launch_wcl_t(const plan_dev& p, const swiftcl_inputs* in, void
                          ? (TW ? 2 * (size_t)M * sizeof(C2<R>) : 0) + (size_t)16 * compact_vs_fwd(p.n_k, M) * sizeof(R)
                          : windows_cl_lds(M, NW, TW, DO_CL, sizeof(R), p.n_k);
   const bool split = p.precision == SWIFTCL_SPLIT_BF16;
-  if (DO_CL && !WRITE_W && p.fwd_mode == 1) {
-    hipLaunchKernelGGL(k_schedule, dim3(1), dim3(64), 0, s, p, *in);
+  if (DO_CL && !WRITE_W && p.fwd_mode >= 1) {
+    // (the packed builder stages up to SCHED_PACK_MAXNX points per XCD; larger batches run mode 1)
+    const bool packed = p.fwd_mode == 2 && in->batch <= SCHED_PACK_MAXNX * SWIFTCL_NXCD;
+    if (packed) hipLaunchKernelGGL(k_schedule_packed, dim3(SWIFTCL_NXCD), dim3(64), 0, s, p, *in);
+    else hipLaunchKernelGGL(k_schedule, dim3(1), dim3(64), 0, s, p, *in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_padded<R>, dim3(p.max_ell, in->batch), dim3(128), 0, s, p, *in, (R*)C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // the FP32 projection runs two workgroups per CU
     const dim3 pgrid((unsigned)(p.persist_blocks * ((sizeof(R) == 4 && M <= 512) ? 2 : 1)));
+    if (packed) {
+      if constexpr (sizeof(R) == 4) {
+        if (split) {
+          hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, 2, true>), pgrid, dim3(NW * 64), lds, s, p,
+                             *in, (R*)W, (R*)C);
+          return hipGetLastError();
+        }
+      }
+      hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, 2, false>), pgrid, dim3(NW * 64), lds, s, p, *in,
+                         (R*)W, (R*)C);
+      return hipGetLastError();
+    }
     if constexpr (sizeof(R) == 4) {
       if (split) {
-        hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, true, true>), pgrid, dim3(NW * 64), lds, s, p,
+        hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, 1, true>), pgrid, dim3(NW * 64), lds, s, p,
                            *in, (R*)W, (R*)C);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, true, false>), pgrid, dim3(NW * 64), lds, s, p, *in,
+    hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, false, true, 1, false>), pgrid, dim3(NW * 64), lds, s, p, *in,
                        (R*)W, (R*)C);
     return hipGetLastError();
   }
@@ -726,12 +861,12 @@ static hipError_t launch_wcl_t(const plan_dev& p, const swiftcl_inputs* in, void
   const dim3 grid((unsigned)(groups * p.max_ell * SWIFTCL_NXCD));
   if constexpr (sizeof(R) == 4 && DO_CL) {
     if (split) {
-      hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, WRITE_W, DO_CL, false, true>), grid, dim3(NW * 64), lds, s, p,
+      hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, WRITE_W, DO_CL, 0, true>), grid, dim3(NW * 64), lds, s, p,
                          *in, (R*)W, (R*)C);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, WRITE_W, DO_CL, false, false>), grid, dim3(NW * 64), lds, s, p, *in,
+  hipLaunchKernelGGL((k_windows_cl<R, M, NW, TW, WRITE_W, DO_CL, 0, false>), grid, dim3(NW * 64), lds, s, p, *in,
                      (R*)W, (R*)C);
   return hipGetLastError();
 }

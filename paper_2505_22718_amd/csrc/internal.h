@@ -78,8 +78,11 @@ struct plan_dev {
   void* dpk_part;   // [bwd_slots][n_k] real: sum_t W Y partials per (point, chunk)
   void* dg;         // [B][T][n_bands][N] real
   int bwd_slots;    // capacity of (point, chunk) slots
+  int* bwd_order;   // [bwd_order_n] workgroup -> (point, chunk) item of the fused adjoint, heaviest first
+  int bwd_order_n;  // its capacity (the largest fused-adjoint grid)
   // launch configuration (autotuned; see swiftcl_autotune)
-  int fwd_mode;       // 0: one workgroup per (point, multipole slot); 1: persistent, per-XCD lists
+  int fwd_mode;       // 0: one workgroup per (point, multipole slot); 1: persistent, per-XCD lists;
+                      // 2: persistent, packed per-XCD lists (two items of few tracers per task)
   int persist_blocks; // grid of the persistent launch (a multiple of 8)
   int bwd_chunk_mul;  // multiplier of the backward multipole-chunk count (1, 2 or 4)
   int* sched;         // sched_ints(sched_stride): per-XCD work lists of the persistent launch

@@ -322,7 +322,7 @@ static void free_plan(swiftcl_plan_s* p) {
   void* ptrs[] = {p->d.U, p->d.kscale, p->d.tw, p->d.fell, p->d.ell_band, p->d.kw, p->d.ell_v, p->d.lnk, p->d.lu_k,
                   p->d.lnp, p->d.lim_acc, p->d.ebm, p->d.z_geom, p->d.z_nz, p->d.lu_geom,
                   p->d.lu_nz, p->d.z_union, p->d.union_iv, p->d.pt, p->d.m_chi, p->d.m_D, p->d.m_ia, p->d.m_n, p->d.lens_q, p->d.phase, p->d.node_f, p->d.node_i, p->d.ddD_part, p->d.g,
-                  p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.vbuf,
+                  p->d.chat, p->d.sqrt_s, p->d.kss, p->d.flags, p->d.dchat_part, p->d.dpk_part, p->d.dg, p->d.sched, p->d.bwd_order, p->d.vbuf,
                   p->d.kg_ones, p->d.kg_ia, p->d.kg_w, p->d.kg_ip, p->d.kg_uh, p->d.kg_c, p->d.kg_m, p->d.kg_perm,
                   p->d.kg_tile, p->d.UR, p->d.g_r, p->d.chat_r, p->d.Umu, p->d.g_mu, p->d.chat_mu};
   for (void* q : ptrs)
@@ -550,8 +550,13 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     long slots = 0;
     plan_dev probe = p->d;
     probe.bwd_chunk_mul = 4;
-    for (int bb = 1; bb <= B; ++bb) slots = std::max(slots, (long)bb * backward_chunks(probe, bb));
+    long grid = 0;
+    for (int bb = 1; bb <= B; ++bb) {
+      slots = std::max(slots, (long)bb * backward_chunks(probe, bb));
+      grid = std::max(grid, (long)((bb + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD) * SWIFTCL_NXCD * backward_chunks(probe, bb));
+    }
     p->d.bwd_slots = (int)slots;
+    p->d.bwd_order_n = (int)grid;
   }
   p->d.n_interp = d->n_interp;
   if (!p->d.fused || p->d.n_interp > 0 || p->d.adjoint == 2) {
@@ -609,6 +614,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   }
   p->d.sched_stride = sched_stride_for(B);
   ALLOC(sched, int, sched_ints(p->d.sched_stride));
+  if (p->d.adjoint == 1) ALLOC(bwd_order, int, p->d.bwd_order_n);
   if (p->d.adjoint == 2) {
     // multipole chunks per point of the workspace adjoint: about 4096 wavefronts of adjoint
     // transforms per chunk of points (one per point, chunk and tracer)
@@ -955,8 +961,8 @@ extern "C" swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t p, const swif
 
 // ---------------------------------------------------------------------------------------------
 // Autotuner: times the launch variants on the caller's inputs and keeps the fastest in the plan.
-// Choices: fwd_mode (one workgroup per slot / persistent per-XCD lists) and bwd_chunk_mul (1, 2,
-// 4 x the base multipole-chunk count of the adjoint).  Results are cached, one JSON object per
+// Choices: fwd_mode (one workgroup per slot / persistent per-XCD lists / persistent packed lists)
+// and bwd_chunk_mul (1, 2, 4 x the base multipole-chunk count of the adjoint).  Results are cached, one JSON object per
 // line, keyed by device architecture and shape.
 // ---------------------------------------------------------------------------------------------
 static std::string tune_key(const swiftcl_plan_s* p, int batch) {
@@ -985,7 +991,7 @@ static bool cache_lookup(const char* path, const std::string& key, int* fwd_mode
     if (a && b) {
       *fwd_mode = atoi(a + 12);
       *chunk_mul = atoi(b + 17);
-      found = (*fwd_mode == 0 || *fwd_mode == 1) && (*chunk_mul == 1 || *chunk_mul == 2 || *chunk_mul == 4);
+      found = (*fwd_mode >= 0 && *fwd_mode <= 2) && (*chunk_mul == 1 || *chunk_mul == 2 || *chunk_mul == 4);
     }
   }
   fclose(f);
@@ -1033,14 +1039,17 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
     hipError_t e = launch_assemble(p->d, in, s);
     if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
     if (e == hipSuccess) note_forward(p, in);
-    float tf[2] = {1e30f, 1e30f};
-    for (int m = 0; m < (p->d.fused ? 2 : 1) && e == hipSuccess; ++m) {
+    float tf[3] = {1e30f, 1e30f, 1e30f};
+    for (int m = 0; m < (p->d.fused ? 3 : 1) && e == hipSuccess; ++m) {
       p->d.fwd_mode = m;
       tf[m] = time_ms(s, [&]() { return launch_windows_cl(p->d, in, nullptr, C, s); }, &e);
     }
     if (e != hipSuccess) { p->d.fwd_mode = 0; return hip_check(e, "autotune forward"); }
     // a variant other than the default must win by 2% (run-to-run noise is ~1%)
-    p->d.fwd_mode = tf[1] < 0.98f * tf[0] ? 1 : 0;
+    int fb = 0;
+    for (int m = 1; m < 3; ++m)
+      if (tf[m] < tf[fb]) fb = m;
+    p->d.fwd_mode = tf[fb] < 0.98f * tf[0] ? fb : 0;
     float tb[3] = {1e30f, 1e30f, 1e30f};
     const int muls[3] = {1, 2, 4};
     if (dC && p->d.fused && p->d.precision != SWIFTCL_SPLIT_BF16) {
@@ -1057,9 +1066,9 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
     }
     char buf[512];
     snprintf(buf, sizeof(buf),
-             "{\"key\": \"%s\", \"fwd_mode\": %d, \"bwd_chunk_mul\": %d, \"fwd_ms\": [%.4f, %.4f], "
+             "{\"key\": \"%s\", \"fwd_mode\": %d, \"bwd_chunk_mul\": %d, \"fwd_ms\": [%.4f, %.4f, %.4f], "
              "\"bwd_ms\": [%.4f, %.4f, %.4f]}",
-             key.c_str(), p->d.fwd_mode, p->d.bwd_chunk_mul, tf[0], tf[1], dC ? tb[0] : 0.f, dC ? tb[1] : 0.f,
+             key.c_str(), p->d.fwd_mode, p->d.bwd_chunk_mul, tf[0], tf[1], tf[2], dC ? tb[0] : 0.f, dC ? tb[1] : 0.f,
              dC ? tb[2] : 0.f);
     rep = buf;
     if (cache_path) {
@@ -1080,7 +1089,7 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
 extern "C" swiftcl_status swiftcl_set_launch(swiftcl_plan_t p, int32_t fwd_mode, int32_t bwd_chunk_mul) {
   if (!p) { set_error("plan is NULL"); return SWIFTCL_E_INVALID; }
   if (fwd_mode >= 0) {
-    if (fwd_mode > 1) { set_error("fwd_mode must be 0 or 1"); return SWIFTCL_E_INVALID; }
+    if (fwd_mode > 2) { set_error("fwd_mode must be 0, 1 or 2"); return SWIFTCL_E_INVALID; }
     p->d.fwd_mode = fwd_mode;
   }
   if (bwd_chunk_mul >= 0) {

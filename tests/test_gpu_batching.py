@@ -1,7 +1,10 @@
 """Batched, ragged launches: the persistent launch, the autotuner and hipGraph capture.
 
 * The persistent projection (per-XCD compact work lists) gives bit-identical C_l to the
-  one-workgroup-per-slot launch on a ragged batch, padded slots included.
+  one-workgroup-per-slot launch on a ragged batch, padded slots included; so does the packed
+  persistent launch (two items of few tracers per workgroup) in every precision, on counts that
+  include points with no multipoles, one tracer, and pairs that fill all 16 rows (a point
+  without tracers is an input error, flagged; the host test of the list builder covers it).
 * The autotuner picks a configuration, reports it, and reads it back from its cache.
 * forward + backward captured in a hipGraph (torch.cuda.CUDAGraph) and replayed several times,
   with eager work between the replays: every replay reproduces the eager forward bit for bit and
@@ -53,6 +56,35 @@ def test_persistent_matches_per_slot(dev):
     assert plan.device_flags() == 0
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16", "fp64"])
+def test_packed_matches_per_slot(dev, precision):
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    wl = synth.make_workload("cfg3", batch=40)
+    plan = Plan.for_workload(wl, precision=precision)
+    t = device_inputs(wl, dev)
+    nt, nl = t["n_tracers"], t["n_ell"]
+    nt[torch.tensor([0, 9])] = 2
+    nt[torch.tensor([1, 17])] = 1
+    nt[torch.tensor([2, 10, 18, 26])] = 8
+    nt[torch.tensor([3, 11])] = 13
+    nt[torch.tensor([19, 27])] = 3
+    nl[4] = 0
+    nl[12] = 1
+    _say(f"packed vs per-slot, cfg3 B=40 {precision}: T={nt.tolist()[:20]}..., L={nl.tolist()[:14]}...")
+    C0 = plan.cl(t).clone()
+    plan.set_launch(fwd_mode=1)
+    C1 = plan.cl(t).clone()
+    plan.set_launch(fwd_mode=2)
+    C2 = plan.cl(t).clone()
+    C2b = plan.cl(t)  # a second call over the same lists
+    torch.cuda.synchronize()
+    assert plan.device_flags() == 0
+    assert torch.equal(C0, C1)
+    assert torch.equal(C0, C2)
+    assert torch.equal(C0, C2b)
+    assert C0.abs().sum().item() > 0
+
+
 def test_autotune_and_cache(dev, tmp_path):
     from paper_2505_22718_amd.plan import Plan, device_inputs
     wl = synth.make_workload("cfg3", batch=32)
@@ -74,7 +106,7 @@ def test_autotune_and_cache(dev, tmp_path):
     assert torch.equal(plan3.cl(t), C_tuned)
 
 
-@pytest.mark.parametrize("fwd_mode,reuse", [(0, False), (1, False), (1, True)])
+@pytest.mark.parametrize("fwd_mode,reuse", [(0, False), (1, False), (1, True), (2, True)])
 def test_graph_capture_replay(dev, fwd_mode, reuse):
     from paper_2505_22718_amd.plan import Plan, device_inputs
     B = 16

@@ -37,10 +37,10 @@ def _noalloc(plan, t, out):
 
 
 @pytest.mark.parametrize("name,precision,fwd_mode", [("cfg1_batch", "fp32", 0), ("cfg1_batch", "fp32", 1),
-                                                     ("cfg0", "fp64", 0)])
+                                                     ("cfg3", "fp32", 2), ("cfg0", "fp64", 0)])
 def test_noalloc_matches_swiftcl_cl(dev, name, precision, fwd_mode):
     from paper_2505_22718_amd.plan import Plan, device_inputs
-    wl = synth.make_workload(name, batch=24) if name == "cfg1_batch" else synth.make_workload(name)
+    wl = synth.make_workload(name, batch=24) if name in ("cfg1_batch", "cfg3") else synth.make_workload(name)
     B = int(wl["batch"])
     plan = Plan.for_workload(wl, precision=precision)
     plan.set_launch(fwd_mode=fwd_mode)
