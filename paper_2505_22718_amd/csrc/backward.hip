@@ -43,6 +43,79 @@ int backward_chunks(const plan_dev& p, int batch) {
   return c < 1 ? 1 : c;
 }
 
+// Work items of the fused adjoint: item j = (rest = j / 8, XCD j % 8) is point
+// b = (rest / nchunk) * 8 + j % 8 and multipole chunk rest % nchunk (the chunks of a point share an
+// XCD's L2).  With ragged tracer and multipole counts their costs differ several-fold, and one
+// 1024-thread workgroup fills a CU, so the workgroups are dispatched heaviest first (longest
+// processing time first keeps the last CUs from idling): k_bwd_order writes order[w] = the item of
+// workgroup w, a stable counting sort on a cost bucket of T_b x (multipoles of the chunk), so
+// that uniform batches keep the natural order.  Buckets: lane l of each wavefront counts bucket l
+// over its segment of items; 63 cost levels, highest first, and a last bucket for items past the
+// batch.
+constexpr int BWD_ORDER_MAX = 32768;  // items sorted in LDS (one byte each); larger grids run unsorted
+
+__global__ __launch_bounds__(1024) void k_bwd_order(plan_dev P, swiftcl_inputs in, int nchunk, int n) {
+  __shared__ unsigned int bk4[BWD_ORDER_MAX / 4];  // four item buckets per word; 255 pads the tail
+  __shared__ int cnt[16][64];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int T = P.max_tracers, Lm = P.max_ell, n4 = (n + 3) / 4;
+  const int maxcost = T * ((Lm + nchunk - 1) / nchunk);
+  for (int w = tid; w < n4; w += 1024) {
+    unsigned int word = 0;
+    for (int q = 0; q < 4; ++q) {
+      const int j = 4 * w + q;
+      int key = 255;
+      if (j < n) {
+        const int rest = j / SWIFTCL_NXCD, chunk = rest % nchunk;
+        const int b = (rest / nchunk) * SWIFTCL_NXCD + j % SWIFTCL_NXCD;
+        key = 63;
+        if (b < in.batch) {
+          const int Tb = clampb(in.n_tracers[b], 0, T), Lb = clampb(in.n_ell[b], 0, Lm);
+          const int cost = Tb * ((chunk + 1) * Lb / nchunk - chunk * Lb / nchunk);
+          key = 62 - (maxcost > 0 ? cost * 62 / maxcost : 0);
+        }
+      }
+      word |= (unsigned int)key << (8 * q);
+    }
+    bk4[w] = word;
+  }
+  __syncthreads();
+  // wave w scans words [w0, w1); lane l counts (then places) the items of bucket l
+  const int seg = (n4 + 15) / 16, w0 = wave * seg, w1 = min(n4, w0 + seg);
+  int c = 0;
+  for (int w = w0; w < w1; ++w) {
+    const unsigned int u = bk4[w];
+    c += ((u & 255u) == (unsigned)lane) + (((u >> 8) & 255u) == (unsigned)lane) +
+         (((u >> 16) & 255u) == (unsigned)lane) + ((u >> 24) == (unsigned)lane);
+  }
+  cnt[wave][lane] = c;
+  __syncthreads();
+  if (wave == 0) {
+    // first position of (bucket lane, segment w): the earlier buckets, then earlier segments
+    int tot = 0;
+    for (int w = 0; w < 16; ++w) tot += cnt[w][lane];
+    int incl = tot;  // inclusive prefix over the buckets up to this lane
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    int at = incl - tot;
+    for (int w = 0; w < 16; ++w) {
+      const int k = cnt[w][lane];
+      cnt[w][lane] = at;
+      at += k;
+    }
+  }
+  __syncthreads();
+  int pos = cnt[wave][lane];
+  for (int w = w0; w < w1; ++w) {
+    const unsigned int u = bk4[w];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (((u >> (8 * q)) & 255u) == (unsigned)lane) P.bwd_order[pos++] = 4 * w + q;
+  }
+}
+
 // (a5, a6) One workgroup per (point, chunk of multipole slots), NW wavefronts, wave t = tracer t.
 // Per multipole: recompute W (forward FFT), Y = G W on MFMA, dP partial, dx, r2c, accumulate dc.
 // Partial dc per (point, chunk, tracer, band) and partial sum_t W Y per (point, chunk, k) go to
@@ -54,7 +127,7 @@ int backward_chunks(const plan_dev& p, int batch) {
 // in spills than the occupancy gains).
 template <typename R, int M, int NW, bool TW_LDS>
 __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inputs in, const R* __restrict__ dC,
-                                                         int nchunk) {
+                                                         int nchunk, int ordered) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr bool COMPACT = sizeof(R) == 4 && NW == 16;
   constexpr int RL = M / SWIFTCL_WAVE;
@@ -74,8 +147,9 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   // 4 rows x 16 k touch distinct banks with the row stride == 4 mod 64)
   __shared__ R Gp[4][64];
   const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
-  const int xcd = blockIdx.x % SWIFTCL_NXCD;
-  const int rest = blockIdx.x / SWIFTCL_NXCD;
+  const int item = ordered ? P.bwd_order[blockIdx.x] : (int)blockIdx.x;
+  const int xcd = item % SWIFTCL_NXCD;
+  const int rest = item / SWIFTCL_NXCD;
   const int chunk = rest % nchunk;
   const int b = (rest / nchunk) * SWIFTCL_NXCD + xcd;
   if (b >= in.batch) return;
@@ -918,8 +992,13 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   auto k1 = k_bwd_windows<R, M, NW, TW>;
   hipError_t e;
   const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
-  hipLaunchKernelGGL(k1, dim3((unsigned)(groups * nchunk * SWIFTCL_NXCD)), dim3(NW * 64), lds, s, p, *in,
-                     (const R*)dC, nchunk);
+  const long n = (long)groups * nchunk * SWIFTCL_NXCD;
+  const int ordered = p.bwd_order && n <= p.bwd_order_n && n <= BWD_ORDER_MAX;
+  if (ordered) {
+    hipLaunchKernelGGL(k_bwd_order, dim3(1), dim3(1024), 0, s, p, *in, nchunk, (int)n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k1, dim3((unsigned)n), dim3(NW * 64), lds, s, p, *in, (const R*)dC, nchunk, ordered);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
   const long rows = (long)in->batch * p.max_tracers * p.n_bands;
