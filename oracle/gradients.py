@@ -44,6 +44,27 @@ def grad_bias(G, C, kinds, bias):
     return out
 
 
+def grad_bias_windows(wl, b, G, method=None):
+    """dL/db_t of point b for windows that also hold terms the bias does not scale (the RSD term of
+    eq. RSD, the magnification term of eq. magnification bias): a clustering window is
+    b_t D_t + R_t, with D_t the density window at unit bias, so
+    dC^{ij}/db_t = sum_j s_j (delta_it D_t W_j + W_i delta_jt D_t).  Zero for lensing tracers."""
+    method = method or fftlog.method_for(wl)
+    W = fftlog.windows(wl, b, method)
+    unit = dict(wl, rsd=False, mag=None, bias=np.ones_like(np.asarray(wl["bias"], float)))
+    D = fftlog.windows(unit, b, method)
+    T = W.shape[1]
+    kinds = np.asarray(wl["kind"])[b, :T]
+    out = np.zeros(T)
+    for t in range(T):
+        if kinds[t] != 0:
+            continue
+        dW = np.zeros_like(W)
+        dW[:, t] = D[:, t]
+        out[t] = _dL(G, W, dW, wl["pk"][b], method)
+    return out
+
+
 def _dL(G, W, dW, pk, method):
     """sum_l sum_{i<=j} G^{ij} sum_j s_j (dW_i W_j + W_i dW_j)."""
     iu = pair_index(W.shape[1])
