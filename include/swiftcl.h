@@ -208,6 +208,10 @@ enum {
  *   dnz   [B][max_tracers][n_zs]    dL/dn_t(z_s) through the n(z) spline (and the lensing q)
  *   dD    [B][n_zg]                 dL/dD(z_s) through the D(z) spline
  * `dC` has the layout and type of swiftcl_cl's output; `flags` is 0 or SWIFTCL_BWD_REUSE_FORWARD.
+ * Plans with rsd or magnification: the recomputed windows carry the RSD and magnification terms
+ * (eq. RSD, eq. magnification bias), so dpk is complete, and dbias (which scales the density term
+ * alone) too; dnz and dD must be NULL (else SWIFTCL_E_UNSUPPORTED): the adjoints of those kernels'
+ * assemblies are not built.
  * No allocation and no synchronisation: safe inside hipGraph capture. */
 swiftcl_status swiftcl_cl_backward(swiftcl_plan_t plan, const swiftcl_inputs* in, const void* dC,
                                    double* dpk, double* dbias, double* dnz, double* dD, uint32_t flags,
@@ -217,12 +221,12 @@ swiftcl_status swiftcl_cl_backward(swiftcl_plan_t plan, const swiftcl_inputs* in
  * multipole counts).  Times, on the caller's inputs, the forward projection launched as one
  * workgroup per (point, multipole slot), as a persistent grid walking per-XCD compact work lists,
  * or as a persistent grid walking per-XCD packed lists (two (point, multipole) items whose tracer
- * counts sum to at most 16 share a workgroup), and (if dC is not NULL) the adjoint with 1, 2 or 4 times its base number of multipole
- * chunks; keeps the fastest in the plan (a variant other than the default, fwd_mode 0 and
- * bwd_chunk_mul 1, must be at least 2% faster).  With cache_path (may be NULL) the choice is read from,
- * or appended to, a file with one JSON object per line keyed by architecture and shape.  `C`
- * (output-shaped scratch, overwritten) and `dC` are device buffers laid out as for swiftcl_cl /
- * swiftcl_cl_backward.  `report` (may be NULL) receives a one-line summary.  Synchronises `stream`;
+ * counts sum to at most 16 share a workgroup), and (if dC is not NULL) the adjoint with 1, 2 or 4
+ * times its base number of multipole chunks; keeps the fastest in the plan (a variant other than
+ * the default, fwd_mode 0 and bwd_chunk_mul 1, must be at least 2% faster).  With cache_path (may
+ * be NULL) the choice is read from, or appended to, a file with one JSON object per line keyed by
+ * architecture and shape.  `C` (output-shaped scratch, overwritten) and `dC` are device buffers
+ * laid out as for swiftcl_cl / swiftcl_cl_backward.  `report` (may be NULL) receives a one-line summary.  Synchronises `stream`;
  * call it outside graph capture, then capture or call swiftcl_cl / swiftcl_cl_backward as usual. */
 swiftcl_status swiftcl_autotune(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C, const void* dC,
                                 void* stream, const char* cache_path, char* report, int32_t report_len);
@@ -238,9 +242,9 @@ swiftcl_status swiftcl_get_launch(swiftcl_plan_t plan, int32_t* fwd_mode, int32_
 /* What a built plan runs (host only, no device work): *fused = 1 when the C_l projection keeps the
  * windows of a (point, multipole) in one workgroup's LDS, 0 when it goes through the device
  * workspace in chunks of *point_chunk points (0 when the plan has no workspace); *adjoint = which
- * swiftcl_cl_backward the plan runs: 0 none (RSD or magnification plans, FP64 windows that do not
- * fit LDS), 1 the fused adjoint (windows recomputed in LDS), 2 the adjoint through the workspace
- * (FP32, more than 16 tracers or windows too large for LDS).  Any pointer may be NULL. */
+ * swiftcl_cl_backward the plan runs: 0 none (FP64 windows that do not fit LDS), 1 the fused adjoint
+ * (windows recomputed in LDS), 2 the adjoint through the workspace (FP32 and split: more than 16
+ * tracers, windows too large for LDS, RSD or magnification).  Any pointer may be NULL. */
 swiftcl_status swiftcl_plan_info(swiftcl_plan_t plan, int32_t* fused, int32_t* adjoint, int32_t* point_chunk);
 
 /* Measurement variant of swiftcl_cl_backward: the same launches with HIP events between its

@@ -800,8 +800,14 @@ static hipError_t launch_ww_t(const plan_dev& p, const swiftcl_inputs* in, int b
   constexpr bool TW = unfused_tw(M);
   const size_t lds = windows_cl_lds(M, NW, TW, false, sizeof(float), p.n_k);
   const size_t groups = (size_t)(nbp + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
-  hipLaunchKernelGGL((k_windows_v<M, NW, TW, false, 0>), dim3((unsigned)(groups * p.max_ell * SWIFTCL_NXCD)),
-                     dim3(NW * 64), lds, s, p, *in, b0, nbp, 1);
+  const dim3 g1((unsigned)(groups * p.max_ell * SWIFTCL_NXCD));
+  // the recomputed W carries the RSD and magnification terms of plans built with them
+  switch ((p.rsd ? 1 : 0) | (p.mag ? 2 : 0)) {
+    case 0: hipLaunchKernelGGL((k_windows_v<M, NW, TW, false, 0>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp, 1); break;
+    case 1: hipLaunchKernelGGL((k_windows_v<M, NW, TW, false, 1>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp, 1); break;
+    case 2: hipLaunchKernelGGL((k_windows_v<M, NW, TW, false, 2>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp, 1); break;
+    default: hipLaunchKernelGGL((k_windows_v<M, NW, TW, false, 3>), g1, dim3(NW * 64), lds, s, p, *in, b0, nbp, 1); break;
+  }
   return hipGetLastError();
 }
 

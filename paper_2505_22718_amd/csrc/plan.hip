@@ -399,9 +399,10 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   p->d.rsd = d->rsd;
   p->d.mag = d->magnification;
   // the adjoint: the fused kernel when its LDS fits (+ the kernel's static LDS), else (FP32 and
-  // split plans) through the workspace; not built with RSD or magnification
-  if (d->rsd || d->magnification) p->d.adjoint = 0;
-  else if (fused && bwd_windows_lds(p->d) + 4096 <= (size_t)lds_max) p->d.adjoint = 1;
+  // split plans) through the workspace.  RSD and magnification plans (FP32 / split, never fused)
+  // take the workspace adjoint, whose recomputed W carries their terms: dL/dP and dL/db only
+  // (dL/dn and dL/dD would need the adjoints of their kernel assemblies)
+  if (fused && bwd_windows_lds(p->d) + 4096 <= (size_t)lds_max) p->d.adjoint = 1;
   else p->d.adjoint = d->precision == SWIFTCL_FP64 ? 0 : 2;
   {
     int ncu = 0;
@@ -895,9 +896,12 @@ static swiftcl_status backward_checks(swiftcl_plan_t p, const swiftcl_inputs* in
   }
   if (flags & ~(uint32_t)SWIFTCL_BWD_REUSE_FORWARD) { set_error("unknown backward flag"); return SWIFTCL_E_INVALID; }
   if (!p->d.adjoint) {
-    set_error(p->d.rsd || p->d.mag ? "the adjoint is not built with redshift-space distortions or magnification"
-                                   : "the FP64 adjoint keeps the windows of <= 16 tracers in LDS; this n_chi / n_k "
-                                     "does not fit");
+    set_error("the FP64 adjoint keeps the windows of <= 16 tracers in LDS; this n_chi / n_k does not fit");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
+  if ((p->d.rsd || p->d.mag) && (dnz || dD)) {
+    set_error("with redshift-space distortions or magnification the backward gives dpk and dbias only: dnz and dD "
+              "must be NULL");
     return SWIFTCL_E_UNSUPPORTED;
   }
   *reuse = (flags & SWIFTCL_BWD_REUSE_FORWARD) != 0;

@@ -156,9 +156,9 @@ def test_backward_reuse_forward(dev):
 
 
 def test_backward_unsupported_plans(dev):
-    """The adjoint is not built with redshift-space distortions or magnification: such plans refuse
-    it with SWIFTCL_E_UNSUPPORTED before launching anything (split-precision plans, more than 16
-    tracers and n_chi = 2048 have it: tests/test_gpu_backward_ws.py)."""
+    """Plans with redshift-space distortions or magnification run the workspace adjoint, which gives
+    dL/dP and dL/db only (tests/test_gpu_backward_rsd.py): asking them for dL/dn or dL/dD is refused
+    with SWIFTCL_E_UNSUPPORTED before launching anything."""
     from paper_2505_22718_amd.binding import SwiftclError, SWIFTCL_E_UNSUPPORTED
     from paper_2505_22718_amd.plan import Plan, device_inputs
     wl = synth.make_workload("cfg3", batch=2)
@@ -166,7 +166,7 @@ def test_backward_unsupported_plans(dev):
     for opt in ({"rsd": True}, {"magnification": True}):
         p = Plan(wl["k"], wl["ell"], wl["z_geom"], wl["z_nz"], wl["n_chi"], 2, wl["nz"].shape[1],
                  wl["ell_idx"].shape[1], precision="fp32", **opt)
-        assert p.adjoint_mode == 0
+        assert p.adjoint_mode == 2
         dC = torch.zeros((2, wl["ell_idx"].shape[1], p.n_pairs), dtype=torch.float32, device=dev)
         with pytest.raises(SwiftclError) as ei:
             p.backward(inp, dC)

@@ -1,7 +1,8 @@
 """Redshift-space distortions of the clustering tracers (eq. RSD) on the GPU: plans with rsd = 1
 add -int dchi f(z) n dz/dchi D j_l''(k chi) to every clustering window (through the workspace
 projection path), compared element by element with the FFTLog oracle on the Q12 metric (1e-4 FP32,
-1e-3 BF16 hi+lo).  The paths that do not carry RSD refuse such plans."""
+1e-3 BF16 hi+lo).  The paths that do not carry RSD (Limber, windows output, the n(z) and D(z)
+gradients) refuse such plans."""
 import sys
 
 import numpy as np
@@ -79,7 +80,8 @@ def test_rsd_refused_where_not_built(dev):
     t = device_inputs(wl, dev)
     p.cl(t)
     dC = torch.ones((1, p.max_ell, p.n_pairs), dtype=p.out_dtype, device=dev)
-    for call in (lambda: p.backward(t, dC, want=("pk",)), lambda: p.cl_limber(t), lambda: p.windows(t)):
+    # (the adjoint gives dL/dP and dL/db on such plans, tests/test_gpu_backward_rsd.py; not dL/dn)
+    for call in (lambda: p.backward(t, dC, want=("nz",)), lambda: p.cl_limber(t), lambda: p.windows(t)):
         with pytest.raises(bd.SwiftclError) as ei:
             call()
         assert ei.value.status == bd.SWIFTCL_E_UNSUPPORTED
