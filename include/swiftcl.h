@@ -274,6 +274,23 @@ swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t plan, const swiftcl_inpu
 swiftcl_status swiftcl_cl_kgrowth(swiftcl_plan_t plan, const swiftcl_inputs* in, const double* D_kz, void* C,
                                   void* stream);
 
+/* Reverse-mode derivative of L = sum dC C for the scale-dependent growth path (the paper
+ * differentiates its pipeline end to end, Sec. 1): the windows of swiftcl_cl_kgrowth are
+ * recomputed (as W, FP32), Y = G W on MFMA gives dL/dP(k_j) = (2/pi) w_j k_j^3 sum_l sum_t W Y, and
+ * dL/db_t follows from the forward output, since every node's kernel is linear in the bias:
+ * dC^{ij}/db_t = C^{ij} (delta_it + delta_jt) / b_t.
+ *   D_kz  as for swiftcl_cl_kgrowth (the same inputs as the forward call).
+ *   C     device, float: swiftcl_cl_kgrowth's output for these inputs (read for dbias; may be NULL
+ *         if dbias is NULL).
+ *   dC    device, float, laid out as C.
+ *   dpk   device, double, [B][n_k], or NULL.    dbias  device, double, [B][max_tracers], or NULL
+ *         (0 for lensing tracers and padded slots).
+ * The gradients with respect to n(z) and D(k, z) are not built.  Same plans and refusals as
+ * swiftcl_cl_kgrowth.  No allocation and no synchronisation: safe inside hipGraph capture. */
+swiftcl_status swiftcl_cl_kgrowth_backward(swiftcl_plan_t plan, const swiftcl_inputs* in, const double* D_kz,
+                                           const void* C, const void* dC, double* dpk, double* dbias,
+                                           void* stream);
+
 /* The Limber limit (Sec. 2.6, eq. Limber): j_l(k chi) taken as a delta function at k = (l + 1/2)/chi,
  *   C_l^{ij} = int dchi / chi^2 g_i g_j P((l + 1/2)/chi),  g = f (clustering), F(l) f / k^2 (lensing),
  * integrated on the plan's log-chi nodes with the FFTLog path's edge weights (dchi = chi dln chi),

@@ -70,3 +70,37 @@ class ClLimberFunction(torch.autograd.Function):
 def cl_limber(plan, inputs, pk, bias, nz, D_z):
     """Differentiable Limber C_l (see ClLimberFunction)."""
     return ClLimberFunction.apply(plan, inputs, pk, bias, nz, D_z)
+
+
+class ClKgrowthFunction(torch.autograd.Function):
+    """Scale-dependent growth (swiftcl_cl_kgrowth) with its hand-written adjoint
+    (swiftcl_cl_kgrowth_backward): gradients for pk [B, n_k] and bias [B, T]; D_kz [B, n_interp,
+    n_zg] is an input without gradient."""
+
+    @staticmethod
+    def forward(ctx, plan, inputs, D_kz, pk, bias):
+        t = dict(inputs)
+        t.update(pk=pk.detach().contiguous(), bias=bias.detach().contiguous())
+        D = D_kz.detach().contiguous()
+        C = plan.cl_kgrowth(t, D)
+        ctx.plan = plan
+        ctx.t = t
+        ctx.D = D
+        ctx.save_for_backward(pk, bias, C)
+        return C
+
+    @staticmethod
+    def backward(ctx, dC):
+        if ctx.needs_input_grad[2]:
+            raise RuntimeError("the scale-dependent growth adjoint has no gradient with respect to D(k, z)")
+        want = [name for name, need in zip(("pk", "bias"), ctx.needs_input_grad[3:]) if need]
+        if not want:
+            return None, None, None, None, None
+        _, _, C = ctx.saved_tensors
+        g = ctx.plan.kgrowth_backward(ctx.t, ctx.D, C, dC.to(ctx.plan.out_dtype).contiguous(), want=tuple(want))
+        return None, None, None, g.get("pk"), g.get("bias")
+
+
+def cl_kgrowth(plan, inputs, D_kz, pk, bias):
+    """Differentiable C_l with scale-dependent growth (see ClKgrowthFunction)."""
+    return ClKgrowthFunction.apply(plan, inputs, D_kz, pk, bias)

@@ -84,7 +84,7 @@ EXPORTED = ["swiftcl_plan", "swiftcl_plan_destroy", "swiftcl_last_error", "swift
             "swiftcl_windows", "swiftcl_cl", "swiftcl_cl_timed", "swiftcl_cl_backward",
             "swiftcl_cl_backward_timed", "swiftcl_autotune", "swiftcl_set_launch", "swiftcl_get_launch",
             "swiftcl_cl_kgrowth", "swiftcl_cl_limber", "swiftcl_cl_noalloc", "swiftcl_plan_info",
-            "swiftcl_cl_limber_backward"]
+            "swiftcl_cl_limber_backward", "swiftcl_cl_kgrowth_backward"]
 
 _lib = None
 
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
     lib.swiftcl_cl_limber.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp]
     lib.swiftcl_cl_backward.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, ctypes.c_uint32, vp]
     lib.swiftcl_cl_limber_backward.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, vp]
+    lib.swiftcl_cl_kgrowth_backward.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, vp]
     lib.swiftcl_autotune.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, ctypes.c_char_p,
                                      ctypes.c_char_p, ctypes.c_int32]
     lib.swiftcl_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
@@ -184,6 +185,13 @@ def swiftcl_cl_limber_backward(plan, inputs: swiftcl_inputs, dC: int, dpk: int =
     vp = ctypes.c_void_p
     _check(load().swiftcl_cl_limber_backward(plan, ctypes.byref(inputs), vp(dC), vp(dpk or None), vp(dbias or None),
                                              vp(dnz or None), vp(dD or None), vp(stream)))
+
+
+def swiftcl_cl_kgrowth_backward(plan, inputs: swiftcl_inputs, D_kz: int, C: int, dC: int, dpk: int = 0,
+                                dbias: int = 0, stream: int = 0):
+    vp = ctypes.c_void_p
+    _check(load().swiftcl_cl_kgrowth_backward(plan, ctypes.byref(inputs), vp(D_kz), vp(C or None), vp(dC),
+                                              vp(dpk or None), vp(dbias or None), vp(stream)))
 
 
 def swiftcl_cl_timed(plan, inputs: swiftcl_inputs, C: int, stream: int = 0):

@@ -1037,26 +1037,40 @@ hipError_t launch_bwd_chain(const plan_dev& p, const swiftcl_inputs* in, double*
                                      : launch_chain_t<float>(p, in, dbias, dnz, dD, s);
 }
 
+// Y = G W over the workspace rows of points b0 .. b0 + nbp - 1 (FP32 W rows written by the caller)
+// with the dP partials of nchunk = bwd_nlc multipole chunks per point
+hipError_t launch_bwd_gv(const plan_dev& p, const swiftcl_inputs* in, const void* dC, int b0, int nbp, hipStream_t s) {
+  const int nlc = p.bwd_nlc, T = p.max_tracers;
+  if (p.n_k % 4 == 0) {  // 16-byte rows
+    const dim3 g4((unsigned)((size_t)nbp * nlc * ((p.n_k + 255) / 256)));
+    if (T > 16) hipLaunchKernelGGL(k_bwd_gv4<true>, g4, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+    else hipLaunchKernelGGL(k_bwd_gv4<false>, g4, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+  } else {
+    const dim3 g1((unsigned)((size_t)nbp * nlc * ((p.n_k + 63) / 64)));
+    if (T > 16) hipLaunchKernelGGL(k_bwd_gv<true>, g1, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+    else hipLaunchKernelGGL(k_bwd_gv<false>, g1, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
+  }
+  return hipGetLastError();
+}
+
+// dL/dP from the partials of launch_bwd_gv (every point of the batch)
+hipError_t launch_bwd_dpk(const plan_dev& p, const swiftcl_inputs* in, double* dpk, hipStream_t s) {
+  hipLaunchKernelGGL(k_bwd_point<float>, dim3(in->batch), dim3(256), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
+                     p.bwd_nlc, dpk, nullptr);
+  return hipGetLastError();
+}
+
 // The adjoint through the workspace (FP32; plans with adjoint == 2)
 template <int M>
 static hipError_t launch_bwd_ws(const plan_dev& p, const swiftcl_inputs* in, const void* dC, double* dpk,
                                 double* dbias, double* dnz, double* dD, hipStream_t s, hipEvent_t* ev) {
   const int nlc = p.bwd_nlc, T = p.max_tracers;
-  const int ntile = (p.n_k + 63) / 64, ng = (T + 3) / 4;
+  const int ng = (T + 3) / 4;
   hipError_t e;
   for (int b0 = 0; b0 < in->batch; b0 += p.vchunk) {
     const int nbp = in->batch - b0 < p.vchunk ? in->batch - b0 : p.vchunk;
     if ((e = launch_windows_w(p, in, b0, nbp, s)) != hipSuccess) return e;
-    if (p.n_k % 4 == 0) {  // 16-byte rows
-      const dim3 g4((unsigned)((size_t)nbp * nlc * ((p.n_k + 255) / 256)));
-      if (T > 16) hipLaunchKernelGGL(k_bwd_gv4<true>, g4, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
-      else hipLaunchKernelGGL(k_bwd_gv4<false>, g4, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
-    } else {
-      const dim3 g1((unsigned)((size_t)nbp * nlc * ntile));
-      if (T > 16) hipLaunchKernelGGL(k_bwd_gv<true>, g1, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
-      else hipLaunchKernelGGL(k_bwd_gv<false>, g1, dim3(256), 0, s, p, *in, (const float*)dC, b0, nbp, nlc);
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_bwd_gv(p, in, dC, b0, nbp, s)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_bwd_adj<M, (M <= 1024)>), dim3((unsigned)((size_t)nbp * nlc * ng)), dim3(256), 0, s, p,
                        *in, b0, nbp, nlc);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -161,6 +161,10 @@ hipError_t launch_windows_w(const plan_dev& p, const swiftcl_inputs* in, int b0,
 // C of points [b0, b0 + nbp) from the V rows in the workspace (vbuf)
 hipError_t launch_contract(const plan_dev& p, const swiftcl_inputs* in, void* C, int b0, int nbp, hipStream_t s);
 hipError_t launch_kgrowth(const plan_dev& p, const swiftcl_inputs* in, const double* D_kz, void* C, hipStream_t s);
+hipError_t launch_kgrowth_backward(const plan_dev& p, const swiftcl_inputs* in, const double* D_kz, const void* C,
+                                   const void* dC, double* dpk, double* dbias, hipStream_t s);
+hipError_t launch_bwd_gv(const plan_dev& p, const swiftcl_inputs* in, const void* dC, int b0, int nbp, hipStream_t s);
+hipError_t launch_bwd_dpk(const plan_dev& p, const swiftcl_inputs* in, double* dpk, hipStream_t s);
 size_t kgrowth_fft_lds(int M, int n_zg);  // dynamic LDS of the node-coefficient kernel
 hipError_t launch_limber(const plan_dev& p, const swiftcl_inputs* in, void* C, hipStream_t s);
 // adjoint of launch_limber (after launch_assemble): dpk, dbias, dnz, dD each optional (NULL)

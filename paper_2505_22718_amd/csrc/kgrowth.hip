@@ -234,7 +234,9 @@ __global__ void k_kg_utab(plan_dev P) {
 constexpr int KG_XP = 36;  // floats per k-node row of the X strip: [4 groups][8 steps] + 4 (banks)
 constexpr int KG_UP = 36;  // floats per slot row of the U tile: [4 groups][8 steps] + 4 (banks)
 
-template <bool SPLIT>
+// W_ONLY (the adjoint's recompute, FP32 rows): the rows hold W = F(l) kscale (...) itself, not
+// sqrt(s) W.
+template <bool SPLIT, bool W_ONLY = false>
 __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
   __shared__ __align__(16) float Xs[4][16][KG_XP];
   __shared__ __align__(16) float Us[2][KG_TILE][KG_UP];
@@ -359,7 +361,9 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
   }
   // V = F(l) kscale sqrt(s) W into the workspace rows (point, slot, tracer)
   if (!jok) return;
-  const float kqv = ((const float*)P.kss)[(((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk + j];
+  static_assert(!(SPLIT && W_ONLY), "the recompute writes FP32 rows");
+  const float kqv = W_ONLY ? ((const float*)P.kscale)[((size_t)kind * nb + band) * nk + j]
+                           : ((const float*)P.kss)[(((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk + j];
   const size_t lo_off = (size_t)P.vchunk * Lm * 32 * nk;
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) {
@@ -382,6 +386,44 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
       }
     }
   }
+}
+
+// The adjoint's recompute leaves the workspace rows of absent tracers (t >= T_b, up to the 16 or
+// 32 rows the Gram tiles read) as they were: zero them, so that Y = G W reads no stale value.  One
+// workgroup per (point, multipole slot < L_b) of the chunk.
+__global__ __launch_bounds__(256) void k_kg_zero(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
+  const int Lm = P.max_ell, nk = P.n_k, T = P.max_tracers;
+  const int bl = blockIdx.x / Lm, li = blockIdx.x % Lm;
+  if (bl >= nbp) return;
+  const int b = b0 + bl;
+  if (li >= clamp_i(in.n_ell[b], 0, Lm)) return;
+  const int Tb = clamp_i(in.n_tracers[b], 0, T), rows = T > 16 ? 32 : 16;
+  float* w = (float*)P.vbuf + ((size_t)bl * Lm + li) * 32 * nk;
+  for (size_t i = (size_t)Tb * nk + threadIdx.x; i < (size_t)rows * nk; i += blockDim.x) w[i] = 0.f;
+}
+
+// dL/db_t of the scale-dependent growth path from the forward output: the windows of a clustering
+// tracer are linear in its bias (every k node's kernel is b_t n_t dz/dchi D(k, z)), so
+// dC^{ij}/db_t = C^{ij} (delta_it + delta_jt) / b_t, summed against dC over the point's multipoles
+// and the pairs holding t (in a fixed order: reproducible).  One wavefront per (point, tracer).
+__global__ __launch_bounds__(64) void k_kg_dbias(plan_dev P, swiftcl_inputs in, const float* __restrict__ C,
+                                                 const float* __restrict__ dC, double* __restrict__ dbias) {
+  const int T = P.max_tracers, Lm = P.max_ell, npair = T * (T + 1) / 2;
+  const int b = blockIdx.x / T, t = blockIdx.x % T, lane = threadIdx.x;
+  if (b >= in.batch) return;
+  const int Tb = clamp_i(in.n_tracers[b], 0, T), Lb = clamp_i(in.n_ell[b], 0, Lm);
+  double acc = 0.0;
+  if (t < Tb && in.kind[(size_t)b * T + t] == SWIFTCL_CLUSTERING) {
+    for (int q = lane; q < Lb * Tb; q += SWIFTCL_WAVE) {
+      const int li = q / Tb, j = q % Tb;
+      const int a = t < j ? t : j, c = t < j ? j : t;
+      const size_t at = ((size_t)b * Lm + li) * npair + (size_t)a * T - a * (a - 1) / 2 + (c - a);
+      acc += (double)dC[at] * (double)C[at] * (j == t ? 2.0 : 1.0);
+    }
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    acc /= in.bias[(size_t)b * T + t];
+  }
+  if (lane == 0) dbias[(size_t)b * T + t] = acc;
 }
 
 template <int M>
@@ -420,7 +462,57 @@ hipError_t launch_kg_t(const plan_dev& p, const swiftcl_inputs* in, const double
   return hipSuccess;
 }
 
+// Adjoint (dL/dP, dL/db): the windows recomputed as W rows, then Y = G W with the dP partials
+// (the workspace adjoint's kernels), their reduction, and dL/db from the forward output C.
+template <int M>
+hipError_t launch_kg_bwd_t(const plan_dev& p, const swiftcl_inputs* in, const double* D_kz, const void* C,
+                           const void* dC, double* dpk, double* dbias, hipStream_t s) {
+  const int T = p.max_tracers, nb = p.n_bands, A = p.n_interp;
+  const double h = (double)(p.n_k - 1) * p.delta / (double)(A - 1);
+  const float s6 = (float)(6.0 / (h * h));
+  const int NJ = (p.n_k + KG_TILE - 1) / KG_TILE;
+  hipError_t e;
+  if (dpk) {
+    for (int b0 = 0; b0 < in->batch; b0 += p.vchunk) {
+      const int nbp = in->batch - b0 < p.vchunk ? in->batch - b0 : p.vchunk;
+      hipLaunchKernelGGL(k_kg_slots, dim3((nbp + 63) / 64), dim3(64), 0, s, p, *in, b0, nbp);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_kg_fft<M>, dim3((unsigned)((size_t)nbp * A)), dim3(256), kg_fft_lds<M>(p.n_zg), s, p,
+                         *in, D_kz, b0, nbp);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_kg_cspline, dim3((unsigned)((size_t)nbp * T * nb), (M + 255) / 256), dim3(256), 0, s, p,
+                         *in, b0, nbp, s6);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_kg_zero, dim3((unsigned)((size_t)nbp * p.max_ell)), dim3(256), 0, s, p, *in, b0, nbp);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const size_t groups = ((size_t)nbp * T + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
+      const dim3 gw((unsigned)(groups * p.kg_ntile * NJ * SWIFTCL_NXCD));
+      hipLaunchKernelGGL((k_kg_windows<false, true>), gw, dim3(256), 0, s, p, *in, b0, nbp);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = launch_bwd_gv(p, in, dC, b0, nbp, s)) != hipSuccess) return e;
+    }
+    if ((e = launch_bwd_dpk(p, in, dpk, s)) != hipSuccess) return e;
+  }
+  if (dbias) {
+    hipLaunchKernelGGL(k_kg_dbias, dim3((unsigned)((size_t)in->batch * T)), dim3(64), 0, s, p, *in,
+                       (const float*)C, (const float*)dC, dbias);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
+
+hipError_t launch_kgrowth_backward(const plan_dev& p, const swiftcl_inputs* in, const double* D_kz, const void* C,
+                                   const void* dC, double* dpk, double* dbias, hipStream_t s) {
+  switch (p.M) {
+    case 128: return launch_kg_bwd_t<128>(p, in, D_kz, C, dC, dpk, dbias, s);
+    case 256: return launch_kg_bwd_t<256>(p, in, D_kz, C, dC, dpk, dbias, s);
+    case 512: return launch_kg_bwd_t<512>(p, in, D_kz, C, dC, dpk, dbias, s);
+    case 1024: return launch_kg_bwd_t<1024>(p, in, D_kz, C, dC, dpk, dbias, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 size_t kgrowth_fft_lds(int M, int n_zg) {
   switch (M) {

@@ -616,9 +616,10 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   p->d.sched_stride = sched_stride_for(B);
   ALLOC(sched, int, sched_ints(p->d.sched_stride));
   if (p->d.adjoint == 1) ALLOC(bwd_order, int, p->d.bwd_order_n);
-  if (p->d.adjoint == 2) {
-    // multipole chunks per point of the workspace adjoint: about 4096 wavefronts of adjoint
-    // transforms per chunk of points (one per point, chunk and tracer)
+  if (p->d.adjoint == 2 || p->d.n_interp > 0) {
+    // multipole chunks per point of the workspace adjoint (and of the scale-dependent growth
+    // adjoint): about 4096 wavefronts of adjoint transforms per chunk of points (one per point,
+    // chunk and tracer)
     const long pts = std::min(p->d.vchunk, B);
     long nlc = (4096 + pts * T - 1) / (pts * T);
     nlc = std::max(1L, std::min(nlc, (long)p->d.max_ell));
@@ -827,6 +828,42 @@ extern "C" swiftcl_status swiftcl_cl_kgrowth(swiftcl_plan_t p, const swiftcl_inp
   if (e == hipSuccess) e = launch_sqrt_s(p->d, &in1, s);
   if (e == hipSuccess) e = launch_kgrowth(p->d, &in1, D_kz, C, s);
   return hip_check(e, "scale-dependent growth launch");
+}
+
+extern "C" swiftcl_status swiftcl_cl_kgrowth_backward(swiftcl_plan_t p, const swiftcl_inputs* in, const double* D_kz,
+                                                      const void* C, const void* dC, double* dpk, double* dbias,
+                                                      void* stream) {
+  if (!p) { set_error("plan is NULL"); return SWIFTCL_E_INVALID; }
+  if (!in) { set_error("inputs is NULL"); return SWIFTCL_E_INVALID; }
+  if (!D_kz || !dC) { set_error("D_kz or dC is NULL"); return SWIFTCL_E_INVALID; }
+  if (dbias && !C) { set_error("dbias needs C, the forward output"); return SWIFTCL_E_INVALID; }
+  if (p->d.n_interp < 2) {
+    set_error("the plan has no interpolation nodes in k (n_interp = 0)");
+    return SWIFTCL_E_INVALID;
+  }
+  if (p->d.rsd || p->d.mag) {
+    set_error("scale-dependent growth is not built with redshift-space distortions or magnification");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
+  if (in->kernel_chi) {
+    set_error("scale-dependent growth assembles its kernels per k node; kernel samples (kernel_chi) are refused");
+    return SWIFTCL_E_UNSUPPORTED;
+  }
+  swiftcl_inputs in1 = *in;
+  in1.D_z = p->d.kg_ones;
+  swiftcl_status st = check_inputs(p, &in1);
+  if (st != SWIFTCL_OK) return st;
+  if ((st = hip_check(hipSetDevice(p->d.device), "hipSetDevice")) != SWIFTCL_OK) return st;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  p->fwd_valid = false;
+  hipError_t e = hipSuccess;
+  if (dpk) {
+    e = launch_assemble(p->d, &in1, s);
+    if (e == hipSuccess) e = launch_sqrt_s(p->d, &in1, s);
+  }
+  if (e == hipSuccess) e = launch_kgrowth_backward(p->d, &in1, D_kz, C, dC, dpk, dbias, s);
+  return hip_check(e, "scale-dependent growth backward launch");
 }
 
 extern "C" swiftcl_status swiftcl_cl_limber(swiftcl_plan_t p, const swiftcl_inputs* in, void* C, void* stream) {

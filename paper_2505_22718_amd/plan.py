@@ -248,6 +248,24 @@ class Plan:
         bd.swiftcl_cl_kgrowth(self.handle, s, D_kz.data_ptr(), out.data_ptr(), self._stream())
         return out
 
+    def kgrowth_backward(self, t, D_kz, C, dC, want=("pk", "bias")):
+        """Gradients of sum(dC * C_kgrowth) with respect to pk and bias (swiftcl_cl_kgrowth_backward);
+        C is cl_kgrowth's output for the same inputs."""
+        s = self.inputs_struct(t)
+        B = s.batch
+        check_tensor("D_kz", D_kz, (B, self.n_interp, len(self.z_geom)), torch.float64, self.device)
+        C = self._cl_buffer("C", C.contiguous(), B)
+        dC = self._cl_buffer("dC", dC.contiguous(), B)
+        bad = set(want) - {"pk", "bias"}
+        if bad:
+            raise ValueError(f"the scale-dependent growth adjoint gives pk and bias gradients, not {sorted(bad)}")
+        outs = self._grad_outputs(B, want)
+        self._new_state()
+        bd.swiftcl_cl_kgrowth_backward(self.handle, s, D_kz.data_ptr(), C.data_ptr(), dC.data_ptr(),
+                                       outs["pk"].data_ptr() if outs["pk"] is not None else 0,
+                                       outs["bias"].data_ptr() if outs["bias"] is not None else 0, self._stream())
+        return {k: v for k, v in outs.items() if v is not None}
+
     def cl_limber(self, t, out=None):
         """C_l in the Limber limit on the plan's chi nodes (same layout as cl)."""
         s = self.inputs_struct(t)
