@@ -146,7 +146,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   // reduction step s (the step covers tracers s, s + 4, s + 8, s + 12, so the W operand reads of
   // 4 rows x 16 k touch distinct banks with the row stride == 4 mod 64)
   __shared__ R Gp[4][64];
-  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / SWIFTCL_WAVE), lane = threadIdx.x % SWIFTCL_WAVE;
   const int item = ordered ? P.bwd_order[blockIdx.x] : (int)blockIdx.x;
   const int xcd = item % SWIFTCL_NXCD;
   const int rest = item / SWIFTCL_NXCD;
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(256) void k_bwd_coeffs(plan_dev P, swiftcl_inputs i
   }
   const C2<R>* twp = TWS ? (const C2<R>*)stw_s : (const C2<R>*)P.tw;
   constexpr int RL = M / SWIFTCL_WAVE;
-  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / SWIFTCL_WAVE), lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, nb = P.n_bands, N = P.N;
   const long rows = (long)in.batch * T * nb;
   const long row = (long)blockIdx.x * 4 + wave;

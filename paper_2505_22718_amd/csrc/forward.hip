@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_forward_fft(plan_dev P, swiftcl_inputs 
   }
   const C2<R>* twp = TWS ? (const C2<R>*)stw_s : (const C2<R>*)P.tw;
   constexpr int RL = M / SWIFTCL_WAVE;
-  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / SWIFTCL_WAVE), lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, nb = P.n_bands, N = P.N;
   const long rows = (long)in.batch * T * nb;
   const long row = (long)blockIdx.x * 4 + wave;
@@ -134,7 +134,7 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
   constexpr int FL = fft_lds_size(M, sizeof(R));
   // W and V = sqrt(s) W take different k scales (kscale, kss); one call produces one of them
   static_assert(!(WRITE_W && DO_CL), "windows and C_l come from separate instantiations");
-  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / SWIFTCL_WAVE), lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
   const int Tb = clampi(in.n_tracers[b], 0, T);
   const int Lb = clampi(in.n_ell[b], 0, Lm);
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
   constexpr int NTW = TW_LDS ? N : 0;
   C2<R>* stw_l = (C2<R>*)smem;
   C2<R>* fbuf = stw_l + NTW;
-  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / SWIFTCL_WAVE), lane = threadIdx.x % SWIFTCL_WAVE;
   const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands;
   const int xcd = blockIdx.x % SWIFTCL_NXCD;
   const int rest = blockIdx.x / SWIFTCL_NXCD;

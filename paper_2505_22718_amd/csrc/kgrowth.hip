@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_kg_fft(plan_dev P, swiftcl_inputs in, c
   const int b = b0 + bl;
   const int T = P.max_tracers, nb = P.n_bands;
   const int Tb = clamp_i(in.n_tracers[b], 0, T);
-  const int wave = threadIdx.x / SWIFTCL_WAVE, lane = threadIdx.x % SWIFTCL_WAVE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / SWIFTCL_WAVE), lane = threadIdx.x % SWIFTCL_WAVE;
   for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = ((const C2<R>*)P.tw)[i];
   const double* src = Dkz + ((size_t)b * A + a) * nzg;
   bool bad = false;
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
   const int band = td.x, s0 = td.y, cnt = td.z;
   if (cnt <= 0) return;
   const int kind = tracer_kind(in, T, b, t);
-  const int tid = threadIdx.x, wave = tid / SWIFTCL_WAVE, lane = tid % SWIFTCL_WAVE;
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / SWIFTCL_WAVE), lane = tid % SWIFTCL_WAVE;
   if (tid < KG_TILE) {
     int li = -1, ei = 0;
     if (tid < cnt) {
