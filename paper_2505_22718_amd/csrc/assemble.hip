@@ -225,7 +225,7 @@ __global__ __launch_bounds__(GEOM_THREADS) void k_geometry(plan_dev P, swiftcl_i
 }
 
 size_t lens_lds_bytes(const plan_dev& p) {
-  return sizeof(double) * ((size_t)4 * p.n_zg + (size_t)4 * p.n_zs + (size_t)2 * p.n_union + 64);
+  return sizeof(double) * ((size_t)4 * p.n_zs + (size_t)2 * p.n_union + 64);
 }
 
 // Lensing tracers (Sec. 2.3, eq. tomographic lens efficiency): one workgroup of 512 threads per
@@ -246,23 +246,19 @@ __global__ __launch_bounds__(512) void k_geom_lens(plan_dev P, swiftcl_inputs in
   if (!lensing && !(kd == SWIFTCL_CLUSTERING && P.mag && in.mag)) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int nzg = P.n_zg, nzs = P.n_zs, nb = P.n_bands, N = P.N, nu = P.n_union;
-  double* zg = sh;              // [nzg]
-  double* zgih = zg + nzg;      // [nzg]
-  double* chi = zgih + nzg;     // [nzg]
-  double* mchi = chi + nzg;     // [nzg]
-  double* zs = mchi + nzg;      // [nzs]
+  // the read-only grids (z, 1/h, chi and its spline moments) are read through the cache: LDS holds
+  // this tracer's rows and the interval sums (~27 KB)
+  const double* zg = P.z_geom;                          // [nzg]
+  const double* zgih = P.lu_geom + 3 * (size_t)nzg;     // [nzg]
+  const double* chi = in.chi_z + (size_t)b * nzg;       // [nzg]
+  const double* mchi = P.m_chi + (size_t)b * nzg;       // [nzg]
+  double* zs = sh;              // [nzs]
   double* zsih = zs + nzs;      // [nzs]
   double* nt = zsih + nzs;      // [nzs] this tracer's n samples
   double* mt = nt + nzs;        // [nzs] and their spline moments
   double* seg0 = mt + nzs;      // [nu]
   double* seg1 = seg0 + nu;     // [nu]
   double* tmp = seg1 + nu;      // [64]
-  for (int i = tid; i < nzg; i += nth) {
-    zg[i] = P.z_geom[i];
-    zgih[i] = P.lu_geom[3 * nzg + i];
-    chi[i] = in.chi_z[(size_t)b * nzg + i];
-    mchi[i] = P.m_chi[(size_t)b * nzg + i];
-  }
   for (int i = tid; i < nzs; i += nth) {
     zs[i] = P.z_nz[i];
     zsih[i] = P.lu_nz[3 * nzs + i];

@@ -730,7 +730,7 @@ __global__ __launch_bounds__(256) void k_bwd_coeffs(plan_dev P, swiftcl_inputs i
 }
 
 size_t bwd_geometry_lds_bytes(const plan_dev& p) {
-  return sizeof(double) * ((size_t)6 * p.n_zg + (size_t)6 * p.n_zs + (size_t)2 * p.n_union + 64);
+  return sizeof(double) * ((size_t)2 * p.n_zg + (size_t)6 * p.n_zs + (size_t)2 * p.n_union + 64);
 }
 
 // (a7) Chain rule through the kernel assembly for one (point, tracer) per workgroup of 512
@@ -738,8 +738,15 @@ size_t bwd_geometry_lds_bytes(const plan_dev& p) {
 // and this tracer's share of the cotangents of the D samples and of D'' (summed over tracers by
 // k_bwd_point).  The chi nodes' geometry (z, chi, dchi/dz, D and their intervals) comes from the
 // forward assembly; the chi spline (for the lensing quadrature) sits in LDS.
-template <typename R>
-__global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs in, double* dbias, double* dnz) {
+// MAXN: chi nodes per thread (n_chi <= 512 MAXN; 2 at n_chi <= 1024 keeps the per-node lensing
+// registers to what that needs).  Latency-bound FP64 work: registers capped for six waves per SIMD
+// (three workgroups per CU, which the ~47 KB of LDS allows; a few words spill), 23% faster on the
+// benchmark batch than at the four waves the uncapped register count gives.
+template <typename R, int MAXN>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k_bwd_tracer(plan_dev P,
+                                                                                           swiftcl_inputs in,
+                                                                                           double* dbias,
+                                                                                           double* dnz) {
   extern __shared__ double sh[];
   const int T = P.max_tracers;
   const int b = blockIdx.x / T, t = blockIdx.x % T;
@@ -754,11 +761,14 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
       for (int i = tid; i < nzs; i += nth) dnz[((size_t)b * T + t) * nzs + i] = 0.0;
     return;
   }
-  double* zg = sh;                       // [nzg]
-  double* zgih = zg + nzg;               // [nzg] 1/h
-  double* chi = zgih + nzg;              // [nzg]
-  double* mchi = chi + nzg;              // [nzg]
-  double* dDy = mchi + nzg;              // [nzg] cotangent of D samples (value terms)
+  // the read-only grids (z, 1/h, chi and its spline moments) are read through the cache: LDS
+  // holds the accumulators and this tracer's rows only (~47 KB at n_zg = 1024: three workgroups
+  // per CU)
+  const double* zg = P.z_geom;                              // [nzg]
+  const double* zgih = P.lu_geom + 3 * (size_t)nzg;         // [nzg] 1/h
+  const double* chi = in.chi_z + (size_t)b * nzg;           // [nzg]
+  const double* mchi = P.m_chi + (size_t)b * nzg;           // [nzg]
+  double* dDy = sh;                      // [nzg] cotangent of D samples (value terms)
   double* dDM = dDy + nzg;               // [nzg] cotangent of D'' (spline terms)
   double* zs = dDM + nzg;                // [nzs]
   double* zsih = zs + nzs;               // [nzs]
@@ -773,10 +783,6 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
   const int kd = in.kind[(size_t)b * T + t];
   const int kind = tracer_kind(in, T, b, t);  // a tracer of an unknown kind has no cotangent below
   for (int i = tid; i < nzg; i += nth) {
-    zg[i] = P.z_geom[i];
-    zgih[i] = P.lu_geom[3 * nzg + i];
-    chi[i] = in.chi_z[(size_t)b * nzg + i];
-    mchi[i] = P.m_chi[(size_t)b * nzg + i];
     dDy[i] = 0.0;
     dDM[i] = 0.0;
   }
@@ -793,7 +799,6 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
   const int m0 = P.m0, m1 = (int)pt[PT_M1];
   __syncthreads();
 
-  constexpr int MAXN = 4;  // n_chi <= 2048 with 512 threads
   // dL/df at node m: sum over bands of dg w e^{-b m Delta}
   auto df_at = [&](int m, double w) {
     double s = 0.0;
@@ -937,11 +942,22 @@ __global__ __launch_bounds__(512) void k_bwd_tracer(plan_dev P, swiftcl_inputs i
   }
 }
 
-// Per point: dL/dP (the chunk partials times (2/pi) w k^3) and dL/dD (the tracers' shares summed
-// in tracer order, then the D spline transpose), one workgroup of 256 threads (FP64).
 template <typename R>
-__global__ __launch_bounds__(256) void k_bwd_point(plan_dev P, swiftcl_inputs in, int nchunk, double* dpk,
-                                                    double* dD) {
+static hipError_t launch_bwd_tracer(const plan_dev& p, const swiftcl_inputs* in, double* dbias, double* dnz,
+                                    hipStream_t s) {
+  const dim3 grid((unsigned)((size_t)in->batch * p.max_tracers));
+  const size_t lg = bwd_geometry_lds_bytes(p);
+  if (p.N <= 1024) hipLaunchKernelGGL((k_bwd_tracer<R, 2>), grid, dim3(512), lg, s, p, *in, dbias, dnz);
+  else hipLaunchKernelGGL((k_bwd_tracer<R, 4>), grid, dim3(512), lg, s, p, *in, dbias, dnz);
+  return hipGetLastError();
+}
+
+// Per point: dL/dP (the chunk partials times (2/pi) w k^3) and dL/dD (the tracers' shares summed
+// in tracer order, then the D spline transpose), one workgroup of 1024 threads (FP64): one
+// geometry sample per thread, its tracer loads issued together.
+template <typename R>
+__global__ __launch_bounds__(1024) void k_bwd_point(plan_dev P, swiftcl_inputs in, int nchunk, double* dpk,
+                                                     double* dD) {
   extern __shared__ double sh[];
   const int b = blockIdx.x;
   if (b >= in.batch) return;
@@ -961,7 +977,8 @@ __global__ __launch_bounds__(256) void k_bwd_point(plan_dev P, swiftcl_inputs in
   double* dDM = dDy + nzg; // [nzg]
   for (int i = tid; i < nzg; i += nth) {
     double sy = 0.0, sm = 0.0;
-    for (int t = 0; t < Tb; ++t) {
+#pragma unroll 8
+    for (int t = 0; t < Tb; ++t) {  // (unrolled: the loads of 8 tracers in flight; the sum stays in order)
       const double* part = P.ddD_part + ((size_t)b * T + t) * 2 * nzg;
       sy += part[i];
       sm += part[nzg + i];
@@ -1005,13 +1022,8 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   hipLaunchKernelGGL((k_bwd_coeffs<R, M>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in, nchunk);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-  if (dbias || dnz || dD) {
-    const size_t lg = bwd_geometry_lds_bytes(p);
-    hipLaunchKernelGGL(k_bwd_tracer<R>, dim3((unsigned)((size_t)in->batch * p.max_tracers)), dim3(512), lg, s, p,
-                       *in, dbias, dnz);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_bwd_point<R>, dim3(in->batch), dim3(256), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
+  if ((dbias || dnz || dD) && (e = launch_bwd_tracer<R>(p, in, dbias, dnz, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bwd_point<R>, dim3(in->batch), dim3(1024), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
                      nchunk, dpk, dD);
   return hipGetLastError();
 }
@@ -1020,13 +1032,11 @@ template <typename R>
 static hipError_t launch_chain_t(const plan_dev& p, const swiftcl_inputs* in, double* dbias, double* dnz, double* dD,
                                  hipStream_t s) {
   if (dbias || dnz || dD) {
-    hipLaunchKernelGGL(k_bwd_tracer<R>, dim3((unsigned)((size_t)in->batch * p.max_tracers)), dim3(512),
-                       bwd_geometry_lds_bytes(p), s, p, *in, dbias, dnz);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_bwd_tracer<R>(p, in, dbias, dnz, s);
     if (e != hipSuccess) return e;
   }
   if (dD)
-    hipLaunchKernelGGL(k_bwd_point<R>, dim3(in->batch), dim3(256), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
+    hipLaunchKernelGGL(k_bwd_point<R>, dim3(in->batch), dim3(1024), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
                        0, nullptr, dD);
   return hipGetLastError();
 }
@@ -1055,7 +1065,7 @@ hipError_t launch_bwd_gv(const plan_dev& p, const swiftcl_inputs* in, const void
 
 // dL/dP from the partials of launch_bwd_gv (every point of the batch)
 hipError_t launch_bwd_dpk(const plan_dev& p, const swiftcl_inputs* in, double* dpk, hipStream_t s) {
-  hipLaunchKernelGGL(k_bwd_point<float>, dim3(in->batch), dim3(256), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
+  hipLaunchKernelGGL(k_bwd_point<float>, dim3(in->batch), dim3(1024), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
                      p.bwd_nlc, dpk, nullptr);
   return hipGetLastError();
 }
@@ -1080,13 +1090,8 @@ static hipError_t launch_bwd_ws(const plan_dev& p, const swiftcl_inputs* in, con
   hipLaunchKernelGGL((k_bwd_coeffs<float, M>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in, nlc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-  if (dbias || dnz || dD) {
-    const size_t lg = bwd_geometry_lds_bytes(p);
-    hipLaunchKernelGGL(k_bwd_tracer<float>, dim3((unsigned)((size_t)in->batch * T)), dim3(512), lg, s, p, *in,
-                       dbias, dnz);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_bwd_point<float>, dim3(in->batch), dim3(256), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
+  if ((dbias || dnz || dD) && (e = launch_bwd_tracer<float>(p, in, dbias, dnz, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bwd_point<float>, dim3(in->batch), dim3(1024), 2 * (size_t)p.n_zg * sizeof(double), s, p, *in,
                      nlc, dpk, dD);
   return hipGetLastError();
 }
