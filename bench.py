@@ -85,9 +85,11 @@ def traffic_bytes(batch, launch):
     return rec["hbm_bytes_per_launch"]
 
 
-def profile_pass(B):
-    """One warm-up step and one step of the benchmark batch, then a 256 MiB device copy (the
-    reference for the FETCH_SIZE / WRITE_SIZE scale); run under rocprofv3."""
+def profile_pass(B, steps=2):
+    """`steps` forward + backward steps of the benchmark batch, then a 256 MiB device copy (the
+    reference for the FETCH_SIZE / WRITE_SIZE scale); run under rocprofv3.  The big kernels run
+    ~12% slower in the first steps of a fresh process than from about the eighth step on, where the
+    bench's timed replays run, so a trace for durations takes ~10 steps and reads the last ones."""
     import numpy as np
     import torch
     import synth
@@ -101,11 +103,11 @@ def profile_pass(B):
     grads = {"pk": torch.empty((B, len(wl["k"])), **f64), "bias": torch.empty((B, plan.max_tracers), **f64),
              "nz": torch.empty((B, plan.max_tracers, len(wl["z_nz"])), **f64),
              "D": torch.empty((B, len(wl["z_geom"])), **f64)}
-    for _ in range(2):
+    for _ in range(steps):
         plan.cl(inp, out)
         plan.backward_into(inp, dC, grads, reuse_forward=True)
     torch.cuda.synchronize()
-    print(f"profile pass launch: batch {B}, {json.dumps(plan.launch_config())}", flush=True)
+    print(f"profile pass launch: batch {B}, {steps} steps, {json.dumps(plan.launch_config())}", flush=True)
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -156,6 +158,27 @@ def profile_split_pass(B):
     dst.copy_(src)
     torch.cuda.synchronize()
     print(f"split profile pass done: 2 steps of {B} points, then a 268435456-byte copy", flush=True)
+
+
+def profile_ragged_pass(B, steps=2):
+    """Two forward + backward steps of the ragged batch (B points of 6, 10 or 15 tracers and
+    50..103 multipoles) in the launch shapes the autotuner picks for it in the bench (per-slot
+    forward, two times the base multipole chunks of the adjoint); run under rocprofv3."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    wl = synth.make_workload("cfg3", batch=B)
+    plan = Plan.for_workload(wl)
+    plan.set_launch(fwd_mode=0, bwd_chunk_mul=2)
+    inp = device_inputs(wl, "cuda:0")
+    C = torch.empty((B, plan.max_ell, plan.n_pairs), dtype=torch.float32, device="cuda:0")
+    dC = torch.as_tensor(np.random.default_rng(0).standard_normal(tuple(C.shape)), dtype=torch.float32, device="cuda:0")
+    for _ in range(steps):
+        plan.cl(inp, C)
+        plan.backward(inp, dC, reuse_forward=True)
+    torch.cuda.synchronize()
+    print(f"ragged profile pass done: {steps} steps of {B} points", flush=True)
 
 
 def time_ms(fn, steps, stream):
@@ -405,10 +428,13 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the one-point, ragged and split-precision lines")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run two steps and a 256 MiB copy for rocprofv3 counters; no JSON line")
+    ap.add_argument("--profile-steps", type=int, default=2, help="forward + backward steps of --profile-pass and --profile-ragged")
     ap.add_argument("--profile-kgrowth", action="store_true",
                     help="run two scale-dependent-growth calls of the batch for rocprofv3; no JSON line")
     ap.add_argument("--profile-split", action="store_true",
                     help="run two forward + backward steps of the 64-point, 30-tracer split-precision batch for rocprofv3; no JSON line")
+    ap.add_argument("--profile-ragged", action="store_true",
+                    help="run two forward + backward steps of the 256-point ragged batch for rocprofv3; no JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -417,13 +443,16 @@ def main():
         sys.exit(2)
 
     if args.profile_pass:
-        profile_pass(args.batch)
+        profile_pass(args.batch, args.profile_steps)
         return
     if args.profile_kgrowth:
         profile_kgrowth_pass(args.batch)
         return
     if args.profile_split:
         profile_split_pass(64)
+        return
+    if args.profile_ragged:
+        profile_ragged_pass(256, args.profile_steps)
         return
 
     import numpy as np
