@@ -53,6 +53,12 @@ def bwd_kernel_flops(T, L, B, N, n_k):
 KERNEL_SOURCES = ["paper_2505_22718_amd/csrc/backward.hip", "paper_2505_22718_amd/csrc/common.h",
                   "paper_2505_22718_amd/csrc/internal.h"]
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pmc_k_bwd_windows_cfg1_batch256.md")
+# the same for the forward windows + projection kernel
+FWD_KERNEL_SOURCES = ["paper_2505_22718_amd/csrc/forward.hip", "paper_2505_22718_amd/csrc/common.h",
+                      "paper_2505_22718_amd/csrc/internal.h", "paper_2505_22718_amd/csrc/sched_layout.h"]
+FWD_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pmc_k_windows_cl_cfg1_batch256.md")
+PEAK_HBM_GBPS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
 
 
 def sources_digest():
@@ -63,6 +69,43 @@ def sources_digest():
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def fwd_sources_digest():
+    """SHA-256 over the forward windows kernel's sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in FWD_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _read_record(path):
+    rec = None
+    if os.path.exists(path):
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("traffic-record: "):
+                    rec = json.loads(line[len("traffic-record: "):])
+    return rec
+
+
+def fwd_traffic_bytes(batch, launch):
+    """HBM bytes per launch of k_windows_cl from its committed counter record, under the same
+    rules as traffic_bytes (its sources, the batch, and the forward launch mode)."""
+    rec = _read_record(FWD_TRAFFIC_RECORD)
+    if not rec or rec.get("sources_sha256") != fwd_sources_digest():
+        return None
+    if rec.get("batch") != batch or rec.get("launch", {}).get("fwd_mode") != launch["fwd_mode"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def contraction_flops(T, L, B, n_k):
+    """Flops of the projection C = W diag(s) W^T in one windows launch: algorithmic (the T(T+1)/2
+    pairs, 2 per node) and as issued on MFMA (the full 16 x 16 Gram tile per (point, multipole))."""
+    return T * (T + 1) * n_k * L * B, 2 * 16 * 16 * n_k * L * B
 
 
 def traffic_bytes(batch, launch):
@@ -516,6 +559,24 @@ def main():
     roofline = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
                 "flops_per_launch": flops, "kernel_ms": kms}
+    # both windows kernels against each roofline: FP32 VALU, the projection's MFMA share, HBM
+    detail = {}
+    for kname, (kt, kf) in kernels.items():
+        tb = traffic_bytes(B, plan.launch_config()) if kname.startswith("k_bwd") else fwd_traffic_bytes(B, plan.launch_config())
+        d = {"kernel_ms": kt, "alu_tflops": kf / (kt * 1e-3) / 1e12,
+             "alu_frac": kf / (kt * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+             "hbm_bytes_per_launch": tb,
+             "hbm_GBps": None if tb is None else tb / (kt * 1e-3) / 1e9,
+             "hbm_frac": None if tb is None else tb / (kt * 1e-3) / 1e9 / PEAK_HBM_GBPS}
+        if kname.startswith("k_windows_cl"):
+            ca, ci = contraction_flops(T, L, B, nk)
+            d.update(mfma_tflops_algorithmic=ca / (kt * 1e-3) / 1e12, mfma_tflops_issued=ci / (kt * 1e-3) / 1e12,
+                     mfma_frac_issued=ci / (kt * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS)
+        detail[kname.split(" ")[0]] = d
+    detail["note"] = ("alu: algorithmic flops over the whole kernel time against the FP32 vector peak; mfma: the "
+                      "projection's flops (T(T+1) n_k per point and multipole algorithmic, the 16 x 16 Gram tile "
+                      "issued) over the same time against the FP32 MFMA peak; hbm: bytes from the committed "
+                      "rocprofv3 counter record (null when the kernel changed since) against 8 TB/s")
 
     result = {
         "metric": "C_\u2113 sets/s (15 tracers,103 \u2113) fwd & fwd+bwd at \u22641e-3 rel err vs FP64",
@@ -546,6 +607,7 @@ def main():
                      "bwd_fftlog_coeffs": float(bstages[1]), "bwd_windows": float(bstages[2]),
                      "bwd_coeffs": float(bstages[3]), "bwd_geometry": float(bstages[4])},
         "device_flags": flags,
+        "roofline_detail": detail,
         "launch": dict(plan.launch_config(), autotune=tune_report),
         "roofline": roofline,
     }

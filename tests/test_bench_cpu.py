@@ -53,3 +53,22 @@ def test_traffic_record_is_dropped_for_another_launch(monkeypatch):
     assert bench.traffic_bytes(rec["batch"] // 16, rec["launch"]) is None
     other = 2 if rec["launch"]["bwd_chunk_mul"] != 2 else 4
     assert bench.traffic_bytes(rec["batch"], dict(rec["launch"], bwd_chunk_mul=other)) is None
+
+
+def test_forward_traffic_record(monkeypatch):
+    """The forward windows kernel's record: reported for its own sources, batch and launch mode."""
+    rec = bench._read_record(bench.FWD_TRAFFIC_RECORD)
+    assert rec is not None and rec["kernel"] == "k_windows_cl"
+    monkeypatch.setattr(bench, "fwd_sources_digest", lambda: rec["sources_sha256"])
+    got = bench.fwd_traffic_bytes(rec["batch"], rec["launch"])
+    # coefficient rows, U rows, k scales and C of 256 points: tens of MB per launch
+    assert got is not None and 2.0e7 < got < 2.0e8
+    assert bench.fwd_traffic_bytes(rec["batch"] // 2, rec["launch"]) is None
+    assert bench.fwd_traffic_bytes(rec["batch"], {"fwd_mode": 1 - rec["launch"]["fwd_mode"]}) is None
+    monkeypatch.setattr(bench, "fwd_sources_digest", lambda: "0" * 64)
+    assert bench.fwd_traffic_bytes(rec["batch"], rec["launch"]) is None
+
+
+def test_contraction_flops():
+    alg, issued = bench.contraction_flops(15, 103, 256, 1024)
+    assert alg == 15 * 16 * 1024 * 103 * 256 and issued == 2 * 256 * 1024 * 103 * 256
