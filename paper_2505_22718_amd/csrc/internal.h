@@ -108,6 +108,7 @@ struct plan_dev {
   void* g_mu;         // [B][T][n_bands][N] real: tilted, edge-weighted C_g q D / chi^2 samples
   void* chat_mu;      // [B][T][n_bands][M] complex: their FFTLog coefficients
   int kg_ntile;       // slot tiles per (point, tracer): ceil(max_ell / 64) + n_bands
+  int kg_stage;       // 1: every 64-node k tile spans <= KG_NA node rows, which the GEMM stages in LDS
   double* kg_ones;    // [max_batch][n_zg] ones: the assembly's D(z) while growth sits at the nodes
   int* kg_ia;         // [n_k] node interval a_j of k_j
   float* kg_w;        // [n_k][4] spline weights of c_a, c_{a+1}, M_a, M_{a+1} at k_j

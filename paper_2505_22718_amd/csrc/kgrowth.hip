@@ -234,12 +234,19 @@ __global__ void k_kg_utab(plan_dev P) {
 constexpr int KG_XP = 36;  // floats per k-node row of the X strip: [4 groups][8 steps] + 4 (banks)
 constexpr int KG_UP = 36;  // floats per slot row of the U tile: [4 groups][8 steps] + 4 (banks)
 
+constexpr int KG_NA = 16;  // node rows a staged 64-node k tile may span (its intervals + 1)
+
 // W_ONLY (the adjoint's recompute, FP32 rows): the rows hold W = F(l) kscale (...) itself, not
-// sqrt(s) W.
-template <bool SPLIT, bool W_ONLY = false>
+// sqrt(s) W.  STAGE (plans whose 64-node k tiles span <= KG_NA node rows): the node coefficients
+// and moments of the tile's node rows for each chunk of 16 coefficients are staged in LDS by the
+// whole block, one chunk ahead with the U rows, instead of being gathered by every lane when it
+// builds X (the gathered loads' latency was exposed once per chunk).
+template <bool SPLIT, bool W_ONLY = false, bool STAGE = false>
 __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
   __shared__ __align__(16) float Xs[4][16][KG_XP];
   __shared__ __align__(16) float Us[2][KG_TILE][KG_UP];
+  __shared__ __align__(16) float2 Cs[STAGE ? 2 : 1][STAGE ? KG_NA : 1][KG_KC];  // node coefficients
+  __shared__ __align__(16) float2 Ms[STAGE ? 2 : 1][STAGE ? KG_NA : 1][KG_KC];  // and moments
   __shared__ int eis[KG_TILE];
   __shared__ int lis[KG_TILE];
   const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands, M = P.M, A = P.n_interp;
@@ -294,6 +301,15 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
   const size_t cbase = (((size_t)bl * T + t) * nb + band) * A;
   const float2* kc = (const float2*)P.kg_c + (cbase + ia) * M + kq;
   const float2* km = (const float2*)P.kg_m + (cbase + ia) * M + kq;
+  // STAGE: the tile's first node row, this lane's row in the staged rows, and the entry thread tid
+  // stages (node row ia0 + tid / 16, coefficient tid % 16 of the chunk)
+  const int ia0 = P.kg_ia[min(KG_TILE * jt, nk - 1)];
+  const int na = P.kg_ia[min(KG_TILE * jt + KG_TILE - 1, nk - 1)] - ia0 + 2;
+  const int irow = ia - ia0;
+  const int sa = tid >> 4, sn = tid & 15;
+  const bool sok = STAGE && sa < na;
+  const float2* sc = (const float2*)P.kg_c + (cbase + ia0 + (sok ? sa : 0)) * M + sn;
+  const float2* sm = (const float2*)P.kg_m + (cbase + ia0 + (sok ? sa : 0)) * M + sn;
   float2 eq[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) eq[q] = twid((kq + 4 * q) * j);
@@ -307,23 +323,42 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
     {
       *(float4*)&Us[0][ur][uc] = *(const float4*)(uh + uoff0);
       if (NRT > 2) *(float4*)&Us[0][ur + 32][uc] = ul1 ? *(const float4*)(uh + uoff1) : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (sok) {
+        Cs[0][sa][sn] = sc[0];
+        Ms[0][sa][sn] = sm[0];
+      }
     }
     __syncthreads();
     int buf = 0;
     for (int n0 = 0; n0 < M; n0 += KG_KC) {
-      // next chunk's U rows, in flight during this chunk
+      // next chunk's U rows (and staged node rows), in flight during this chunk
       float4 un0 = make_float4(0.f, 0.f, 0.f, 0.f), un1 = un0;
+      float2 cn = make_float2(0.f, 0.f), mn = cn;
       const bool more = n0 + KG_KC < M;
       if (more) {
         un0 = *(const float4*)(uh + uoff0 + 2 * (n0 + KG_KC));
         if (NRT > 2 && ul1) un1 = *(const float4*)(uh + uoff1 + 2 * (n0 + KG_KC));
+        if (sok) {
+          cn = sc[n0 + KG_KC];
+          mn = sm[n0 + KG_KC];
+        }
       }
       const float2 e0 = twid(n0 * j);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int nl = kq + 4 * q;
-        const float2 ca = kc[n0 + 4 * q], cb = kc[M + n0 + 4 * q];
-        const float2 ma = km[n0 + 4 * q], mb = km[M + n0 + 4 * q];
+        float2 ca, cb, ma, mb;
+        if constexpr (STAGE) {
+          ca = Cs[buf][irow][nl];
+          cb = Cs[buf][irow + 1][nl];
+          ma = Ms[buf][irow][nl];
+          mb = Ms[buf][irow + 1][nl];
+        } else {
+          ca = kc[n0 + 4 * q];
+          cb = kc[M + n0 + 4 * q];
+          ma = km[n0 + 4 * q];
+          mb = km[M + n0 + 4 * q];
+        }
         float2 c;
         c.x = wb.x * ca.x + wb.y * cb.x + wb.z * ma.x + wb.w * mb.x;
         c.y = wb.x * ca.y + wb.y * cb.y + wb.z * ma.y + wb.w * mb.y;
@@ -348,6 +383,12 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
       if (more) {
         *(float4*)&Us[buf ^ 1][ur][uc] = un0;
         if (NRT > 2) *(float4*)&Us[buf ^ 1][ur + 32][uc] = un1;
+        if constexpr (STAGE) {
+          if (sok) {
+            Cs[buf ^ 1][sa][sn] = cn;
+            Ms[buf ^ 1][sa][sn] = mn;
+          }
+        }
       }
       __syncthreads();
       buf ^= 1;
@@ -454,8 +495,13 @@ hipError_t launch_kg_t(const plan_dev& p, const swiftcl_inputs* in, const double
     const size_t pairs = (size_t)nbp * T;
     const size_t groups = (pairs + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
     const dim3 gw((unsigned)(groups * p.kg_ntile * NJ * SWIFTCL_NXCD));
-    if (split) hipLaunchKernelGGL(k_kg_windows<true>, gw, dim3(256), 0, s, p, *in, b0, nbp);
-    else hipLaunchKernelGGL(k_kg_windows<false>, gw, dim3(256), 0, s, p, *in, b0, nbp);
+    if (p.kg_stage) {
+      if (split) hipLaunchKernelGGL((k_kg_windows<true, false, true>), gw, dim3(256), 0, s, p, *in, b0, nbp);
+      else hipLaunchKernelGGL((k_kg_windows<false, false, true>), gw, dim3(256), 0, s, p, *in, b0, nbp);
+    } else {
+      if (split) hipLaunchKernelGGL(k_kg_windows<true>, gw, dim3(256), 0, s, p, *in, b0, nbp);
+      else hipLaunchKernelGGL(k_kg_windows<false>, gw, dim3(256), 0, s, p, *in, b0, nbp);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_contract(p, in, C, b0, nbp, s)) != hipSuccess) return e;
   }
@@ -487,7 +533,8 @@ hipError_t launch_kg_bwd_t(const plan_dev& p, const swiftcl_inputs* in, const do
       if ((e = hipGetLastError()) != hipSuccess) return e;
       const size_t groups = ((size_t)nbp * T + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
       const dim3 gw((unsigned)(groups * p.kg_ntile * NJ * SWIFTCL_NXCD));
-      hipLaunchKernelGGL((k_kg_windows<false, true>), gw, dim3(256), 0, s, p, *in, b0, nbp);
+      if (p.kg_stage) hipLaunchKernelGGL((k_kg_windows<false, true, true>), gw, dim3(256), 0, s, p, *in, b0, nbp);
+      else hipLaunchKernelGGL((k_kg_windows<false, true>), gw, dim3(256), 0, s, p, *in, b0, nbp);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if ((e = launch_bwd_gv(p, in, dC, b0, nbp, s)) != hipSuccess) return e;
     }

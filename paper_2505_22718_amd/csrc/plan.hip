@@ -605,6 +605,10 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
       kg_w[4 * (size_t)j + 2] = (float)(h * h / 6.0 * (ut * ut * ut - ut));
       kg_w[4 * (size_t)j + 3] = (float)(h * h / 6.0 * (tt * tt * tt - tt));
     }
+    // node rows a 64-node k tile of the windows GEMM reads (its intervals and the one after the last)
+    int rows = 0;
+    for (int j0 = 0; j0 < nk; j0 += 64) rows = std::max(rows, kg_ia[std::min(j0 + 63, nk - 1)] - kg_ia[j0] + 2);
+    p->d.kg_stage = rows <= 16 ? 1 : 0;
     kg_ip.assign(A, 0.f);
     double ip = 0.0;
     for (int a = 1; a + 1 < A; ++a) {

@@ -64,6 +64,20 @@ def test_kgrowth_cfg0_fp32(dev):
     assert e.max() < 1e-4
 
 
+def test_kgrowth_dense_nodes(dev):
+    """200 nodes over 256 k nodes: a 64-node k tile spans more node rows than the windows GEMM
+    stages in LDS, so the plan runs the GEMM that gathers them per lane."""
+    wl = synth.make_workload("cfg0")
+    synth.scale_dependent_growth(wl, 200, f_nu=0.3)
+    _say("kgrowth cfg0 fp32, 200 nodes over 256 k")
+    p, C = _run(wl, dev)
+    assert p.device_flags() == 0
+    slots = np.arange(wl["n_ell"][0])
+    e = _eps(C[0], _oracle(wl, 0, slots), slots, 2)
+    _say(f"  max eps {e.max():.3e}")
+    assert e.max() < 1e-4
+
+
 def test_kgrowth_cfg1_200_nodes(dev):
     """15 tracers (10 clustering, 5 lensing), 103 l, N_k = N_chi = 1024, the paper's N_interp = 200."""
     wl = synth.make_workload("cfg1")
