@@ -204,9 +204,9 @@ def profile_split_pass(B):
 
 
 def profile_ragged_pass(B, steps=2):
-    """Two forward + backward steps of the ragged batch (B points of 6, 10 or 15 tracers and
-    50..103 multipoles) in the launch shapes the autotuner picks for it in the bench (per-slot
-    forward, two times the base multipole chunks of the adjoint); run under rocprofv3."""
+    """Forward + backward steps of the ragged batch (B points of 6, 10 or 15 tracers and 50..103
+    multipoles) in launch shapes the autotuner picks for it in the bench (per-slot forward, two
+    times the base multipole chunks of the adjoint); run under rocprofv3."""
     import numpy as np
     import torch
     import synth

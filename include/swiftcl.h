@@ -221,21 +221,23 @@ swiftcl_status swiftcl_cl_backward(swiftcl_plan_t plan, const swiftcl_inputs* in
  * multipole counts).  Times, on the caller's inputs, the forward projection launched as one
  * workgroup per (point, multipole slot), as a persistent grid walking per-XCD compact work lists,
  * or as a persistent grid walking per-XCD packed lists (two (point, multipole) items whose tracer
- * counts sum to at most 16 share a workgroup), and (if dC is not NULL) the adjoint with 1, 2 or 4
- * times its base number of multipole chunks; keeps the fastest in the plan (a variant other than
+ * counts sum to at most 16 share a workgroup), and (if dC is not NULL) the adjoint with 1, 2, 4 or
+ * 8 times its base number of multipole chunks (base: about 256 workgroups, one round on the chip,
+ * which suits uniform batches; ragged batches run better with more); keeps the fastest in the plan (a variant other than
  * the default, fwd_mode 0 and bwd_chunk_mul 1, must be at least 2% faster).  With cache_path (may
  * be NULL) the choice is read from, or appended to, a file with one JSON object per line keyed by
  * architecture and shape.  `C` (output-shaped scratch, overwritten) and `dC` are device buffers
- * laid out as for swiftcl_cl / swiftcl_cl_backward.  `report` (may be NULL) receives a one-line summary.  Synchronises `stream`;
- * call it outside graph capture, then capture or call swiftcl_cl / swiftcl_cl_backward as usual. */
+ * laid out as for swiftcl_cl / swiftcl_cl_backward.  `report` (may be NULL) receives a one-line
+ * summary.  Synchronises `stream`; call it outside graph capture, then capture or call swiftcl_cl /
+ * swiftcl_cl_backward as usual. */
 swiftcl_status swiftcl_autotune(swiftcl_plan_t plan, const swiftcl_inputs* in, void* C, const void* dC,
                                 void* stream, const char* cache_path, char* report, int32_t report_len);
 
 /* Set (values < 0 leave a field unchanged) or read the launch configuration the autotuner chooses:
  * fwd_mode 0 = one workgroup per (point, multipole slot), 1 = persistent grid over per-XCD compact
  * work lists, 2 = persistent grid over per-XCD packed lists (plans whose projection is fused; the
- * others run mode 0 whatever is set); bwd_chunk_mul in {1, 2, 4} scales the adjoint's number of multipole chunks.  Every
- * configuration computes the same C_l bit for bit. */
+ * others run mode 0 whatever is set); bwd_chunk_mul in {1, 2, 4, 8} scales the adjoint's number of
+ * multipole chunks.  Every configuration computes the same C_l bit for bit. */
 swiftcl_status swiftcl_set_launch(swiftcl_plan_t plan, int32_t fwd_mode, int32_t bwd_chunk_mul);
 swiftcl_status swiftcl_get_launch(swiftcl_plan_t plan, int32_t* fwd_mode, int32_t* bwd_chunk_mul);
 

@@ -35,10 +35,12 @@ template <> struct bmfma<double> {
 
 __device__ __forceinline__ int clampb(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// number of multipole chunks per point: enough workgroups to fill the chip
+// number of multipole chunks per point: about 256 x bwd_chunk_mul workgroups (one 1024-thread
+// workgroup fills a CU; uniform batches run best with one round, ragged ones with more, smaller
+// chunks dispatched heaviest first)
 int backward_chunks(const plan_dev& p, int batch) {
   const int mul = p.bwd_chunk_mul > 0 ? p.bwd_chunk_mul : 1;
-  int c = (2 * 256 * mul + batch - 1) / batch;
+  int c = (256 * mul + batch - 1) / batch;
   if (c > p.max_ell) c = p.max_ell;
   return c < 1 ? 1 : c;
 }

@@ -84,7 +84,7 @@ struct plan_dev {
   int fwd_mode;       // 0: one workgroup per (point, multipole slot); 1: persistent, per-XCD lists;
                       // 2: persistent, packed per-XCD lists (two items of few tracers per task)
   int persist_blocks; // grid of the persistent launch (a multiple of 8)
-  int bwd_chunk_mul;  // multiplier of the backward multipole-chunk count (1, 2 or 4)
+  int bwd_chunk_mul;  // multiplier of the backward multipole-chunk count (1, 2, 4 or 8)
   int* sched;         // sched_ints(sched_stride): per-XCD work lists of the persistent launch
   int sched_stride;
   // projection path: fused (windows in LDS, <= 16 tracers) or through the workspace below

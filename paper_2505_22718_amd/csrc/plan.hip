@@ -550,7 +550,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     // multiplier ask for
     long slots = 0;
     plan_dev probe = p->d;
-    probe.bwd_chunk_mul = 4;
+    probe.bwd_chunk_mul = 8;
     long grid = 0;
     for (int bb = 1; bb <= B; ++bb) {
       slots = std::max(slots, (long)bb * backward_chunks(probe, bb));
@@ -1007,7 +1007,7 @@ extern "C" swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t p, const swif
 // ---------------------------------------------------------------------------------------------
 // Autotuner: times the launch variants on the caller's inputs and keeps the fastest in the plan.
 // Choices: fwd_mode (one workgroup per slot / persistent per-XCD lists / persistent packed lists)
-// and bwd_chunk_mul (1, 2, 4 x the base multipole-chunk count of the adjoint).  Results are cached, one JSON object per
+// and bwd_chunk_mul (1, 2, 4, 8 x the base multipole-chunk count of the adjoint).  Results are cached, one JSON object per
 // line, keyed by device architecture and shape.
 // ---------------------------------------------------------------------------------------------
 static std::string tune_key(const swiftcl_plan_s* p, int batch) {
@@ -1036,7 +1036,8 @@ static bool cache_lookup(const char* path, const std::string& key, int* fwd_mode
     if (a && b) {
       *fwd_mode = atoi(a + 12);
       *chunk_mul = atoi(b + 17);
-      found = (*fwd_mode >= 0 && *fwd_mode <= 2) && (*chunk_mul == 1 || *chunk_mul == 2 || *chunk_mul == 4);
+      found = (*fwd_mode >= 0 && *fwd_mode <= 2) &&
+              (*chunk_mul == 1 || *chunk_mul == 2 || *chunk_mul == 4 || *chunk_mul == 8);
     }
   }
   fclose(f);
@@ -1095,16 +1096,16 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
     for (int m = 1; m < 3; ++m)
       if (tf[m] < tf[fb]) fb = m;
     p->d.fwd_mode = tf[fb] < 0.98f * tf[0] ? fb : 0;
-    float tb[3] = {1e30f, 1e30f, 1e30f};
-    const int muls[3] = {1, 2, 4};
+    float tb[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+    const int muls[4] = {1, 2, 4, 8};
     if (dC && p->d.fused && p->d.precision != SWIFTCL_SPLIT_BF16) {
-      for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+      for (int i = 0; i < 4 && e == hipSuccess; ++i) {
         p->d.bwd_chunk_mul = muls[i];
         tb[i] = time_ms(s, [&]() { return launch_backward(p->d, in, dC, nullptr, nullptr, nullptr, nullptr, s); }, &e);
       }
       if (e != hipSuccess) { p->d.bwd_chunk_mul = 1; return hip_check(e, "autotune backward"); }
       int bi = 0;
-      for (int i = 1; i < 3; ++i)
+      for (int i = 1; i < 4; ++i)
         if (tb[i] < tb[bi]) bi = i;
       if (tb[bi] >= 0.98f * tb[0]) bi = 0;
       p->d.bwd_chunk_mul = muls[bi];
@@ -1112,9 +1113,9 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
     char buf[512];
     snprintf(buf, sizeof(buf),
              "{\"key\": \"%s\", \"fwd_mode\": %d, \"bwd_chunk_mul\": %d, \"fwd_ms\": [%.4f, %.4f, %.4f], "
-             "\"bwd_ms\": [%.4f, %.4f, %.4f]}",
+             "\"bwd_ms\": [%.4f, %.4f, %.4f, %.4f]}",
              key.c_str(), p->d.fwd_mode, p->d.bwd_chunk_mul, tf[0], tf[1], tf[2], dC ? tb[0] : 0.f, dC ? tb[1] : 0.f,
-             dC ? tb[2] : 0.f);
+             dC ? tb[2] : 0.f, dC ? tb[3] : 0.f);
     rep = buf;
     if (cache_path) {
       FILE* f = fopen(cache_path, "a");
@@ -1138,8 +1139,8 @@ extern "C" swiftcl_status swiftcl_set_launch(swiftcl_plan_t p, int32_t fwd_mode,
     p->d.fwd_mode = fwd_mode;
   }
   if (bwd_chunk_mul >= 0) {
-    if (bwd_chunk_mul != 1 && bwd_chunk_mul != 2 && bwd_chunk_mul != 4) {
-      set_error("bwd_chunk_mul must be 1, 2 or 4");
+    if (bwd_chunk_mul != 1 && bwd_chunk_mul != 2 && bwd_chunk_mul != 4 && bwd_chunk_mul != 8) {
+      set_error("bwd_chunk_mul must be 1, 2, 4 or 8");
       return SWIFTCL_E_INVALID;
     }
     p->d.bwd_chunk_mul = bwd_chunk_mul;

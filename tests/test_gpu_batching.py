@@ -5,7 +5,8 @@
   persistent launch (two items of few tracers per workgroup) in every precision, on counts that
   include points with no multipoles, one tracer, and pairs that fill all 16 rows (a point
   without tracers is an input error, flagged; the host test of the list builder covers it).
-* The autotuner picks a configuration, reports it, and reads it back from its cache.
+* The autotuner picks a configuration, reports it, and reads it back from its cache; the adjoint's
+  multipole chunkings agree.
 * forward + backward captured in a hipGraph (torch.cuda.CUDAGraph) and replayed several times,
   with eager work between the replays: every replay reproduces the eager forward bit for bit and
   the eager gradients to roundoff (the geometry adjoint sums with FP64 atomics).
@@ -83,6 +84,35 @@ def test_packed_matches_per_slot(dev, precision):
     assert torch.equal(C0, C2)
     assert torch.equal(C0, C2b)
     assert C0.abs().sum().item() > 0
+
+
+def test_adjoint_chunkings_agree(dev):
+    """The adjoint's multipole chunking (bwd_chunk_mul 1, 2, 4, 8) changes only the order of the
+    FP32 partial sums: the gradients of a ragged batch agree to the FP32 bar; other values are
+    refused."""
+    from paper_2505_22718_amd.binding import SwiftclError, SWIFTCL_E_INVALID
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    B = 24
+    wl = synth.make_workload("cfg3", batch=B)
+    plan = Plan.for_workload(wl)
+    t = device_inputs(wl, dev)
+    dC = torch.as_tensor(np.random.default_rng(17).standard_normal((B, plan.max_ell, plan.n_pairs)),
+                         dtype=torch.float32, device=dev)
+    ref = None
+    for m in (1, 2, 4, 8):
+        plan.set_launch(bwd_chunk_mul=m)
+        g = {k: v.cpu().numpy() for k, v in plan.backward(t, dC).items()}
+        assert plan.device_flags() == 0
+        if ref is None:
+            ref = g
+            continue
+        for k in g:
+            e = float(np.max(np.abs(g[k] - ref[k])) / np.max(np.abs(ref[k])))
+            _say(f"  bwd_chunk_mul {m}: {k} differs from 1 by {e:.2e}")
+            assert e < 1e-4
+    with pytest.raises(SwiftclError) as ei:
+        plan.set_launch(bwd_chunk_mul=3)
+    assert ei.value.status == SWIFTCL_E_INVALID
 
 
 def test_autotune_and_cache(dev, tmp_path):
