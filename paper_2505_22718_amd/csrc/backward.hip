@@ -5,6 +5,7 @@
 // C = W diag(s) W^T, s = (2/pi) w k^3 P:
 //   Y = G W,   dP_k = sum_l (2/pi) w_k k_k^3 sum_t W_tk Y_tk,   dW = 2 s Y                (a5)
 //   W = c(l) k^{-1-b} x, x = c2r(conj(c U)) -> dc_n = sum_l h_n conj(r2c(dx)_n) conj(U_l(n))  (a6)
+//      (the real prefactor c(l) is folded into the U table, so dx carries 2 s k^{-1-b} Y only)
 //      (h_0 = 1, h_n = 2: the Hermitian half counts every n > 0 twice)
 //   c_n = alpha_n r2c(g)_n, alpha_n = (k_0 chi_0)^{-i eta_n} chi_0^{-b} / N
 //      -> dg_m = Re sum_{n<N/2} conj(alpha_n) dc_n e^{+2 pi i n m / N}
@@ -245,11 +246,10 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       ln &= SWIFTCL_WAVE - 1;  // the compiler may assume 0 <= ln < 64 again
       wave_c2r<R, M>(v, mine, stw, ln);
       wave_sync();
-      const R* ks = kscale + ((size_t)kind * nb + band) * nk;
-      const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
+      const R* ks = kscale + ((size_t)kind * nb + band) * nk;  // (F(l) is folded into U)
       auto w_pair = [&](int k0, int e) {
         const C2<R> kk = *(const C2<R>*)(ks + k0);
-        *(C2<R>*)(WY + t * vs + k0) = mk<R>(F * kk.x * v[e].x, F * kk.y * v[e].y);
+        *(C2<R>*)(WY + t * vs + k0) = mk<R>(kk.x * v[e].x, kk.y * v[e].y);
       };
       if (2 * M <= nk) {  // every pair inside the row: no guard between the loads
 #pragma unroll
@@ -316,7 +316,6 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
     for (int t = wave; t < Tb; t += NW) {
       const int kind = tracer_kind(in, T, b, t);
       const R* ks = kscale + ((size_t)kind * nb + band) * nk;
-      const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
       C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)t * vs) : fbuf + (size_t)wave * FL;
       C2<R> v[RL];
       // 2 s F k^{-1-b} Y per output pair; when every pair lies inside the row (N <= nk) the loads
@@ -326,10 +325,10 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
         const C2<R> kk = *(const C2<R>*)(ks + k0);
         if constexpr (COMPACT) {
           const C2<R> s2 = *(const C2<R>*)(sq2 + k0);
-          return mk<R>(F * kk.x * s2.x * y2.x, F * kk.y * s2.y * y2.y);
+          return mk<R>(kk.x * s2.x * y2.x, kk.y * s2.y * y2.y);
         } else {
           const C2<R> s2 = *(const C2<R>*)(sq + k0);
-          return mk<R>((R)2 * s2.x * s2.x * F * kk.x * y2.x, (R)2 * s2.y * s2.y * F * kk.y * y2.y);
+          return mk<R>((R)2 * s2.x * s2.x * kk.x * y2.x, (R)2 * s2.y * s2.y * kk.y * y2.y);
         }
       };
       if (2 * M <= nk) {
@@ -645,7 +644,6 @@ __global__ __launch_bounds__(256) void k_bwd_adj(plan_dev P, swiftcl_inputs in, 
     }
     const float* y = (const float*)P.vbuf + (((size_t)bl * Lm + li) * 32 + t) * nk;
     const float* ks = (const float*)P.kscale + ((size_t)kind * nb + band) * nk;
-    const float F = (float)P.fell[(size_t)kind * P.n_ell + ei];
     C2<float> v[RL];
 #pragma unroll
     for (int e = 0; e < RL; ++e) {
@@ -654,7 +652,7 @@ __global__ __launch_bounds__(256) void k_bwd_adj(plan_dev P, swiftcl_inputs in, 
         const C2<float> y2 = *(const C2<float>*)(y + k0);
         const C2<float> kk = *(const C2<float>*)(ks + k0);
         const C2<float> s2 = *(const C2<float>*)(sq + k0);
-        v[e] = mk<float>(2.f * s2.x * s2.x * F * kk.x * y2.x, 2.f * s2.y * s2.y * F * kk.y * y2.y);
+        v[e] = mk<float>(2.f * s2.x * s2.x * kk.x * y2.x, 2.f * s2.y * s2.y * kk.y * y2.y);
       } else {
         v[e] = mk<float>(0.f, 0.f);
       }

@@ -206,8 +206,7 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
     // the row, nk is even; only the stores are guarded)
     const R* kscl = DO_CL ? (const R*)P.kss + (((size_t)bt * SWIFTCL_NKINDS + kind) * nb + band) * nk
                           : (const R*)P.kscale + ((size_t)kind * nb + band) * nk;
-    const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
-    constexpr int KG = RL < 4 ? RL : 4;
+    constexpr int KG = RL < 4 ? RL : 4;  // (the prefactor F(l) is folded into U)
 #pragma unroll
     for (int e0 = 0; e0 < RL; e0 += KG) {
       C2<R> kk[KG];
@@ -217,7 +216,7 @@ __device__ __forceinline__ void windows_cl_item(const plan_dev& P, const swiftcl
       for (int e = 0; e < KG; ++e) {
         const int k0 = 2 * (ln + SWIFTCL_WAVE * (e0 + e));
         if (k0 < nk) {
-          const C2<R> x = mk<R>(F * kk[e].x * v[e0 + e].x, F * kk[e].y * v[e0 + e].y);
+          const C2<R> x = mk<R>(kk[e].x * v[e0 + e].x, kk[e].y * v[e0 + e].y);
           if (WRITE_W) *(C2<R>*)(Wout + (((size_t)b * Lm + li) * T + t) * nk + k0) = x;
           if (DO_CL) *(C2<R>*)(V + r * vs + k0) = x;  // V = sqrt(s) W
         }
@@ -600,7 +599,6 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
     wave_c2r<R, M>(v, mine, stw, ln);
     const R* kq = w_only ? (const R*)P.kscale + ((size_t)kind * nb + band) * nk
                          : (const R*)P.kss + (((size_t)b * SWIFTCL_NKINDS + kind) * nb + band) * nk;  // kscale sqrt(s)
-    const R F = (R)P.fell[(size_t)kind * P.n_ell + ei];
     constexpr int KG = RL < 4 ? RL : 4;  // loads issued in groups (index clamped into the row, nk even)
 #pragma unroll
     for (int e0 = 0; e0 < RL; e0 += KG) {
@@ -611,7 +609,7 @@ __global__ __launch_bounds__(NW * 64) void k_windows_v(plan_dev P, swiftcl_input
     for (int e = 0; e < KG; ++e) {
       const int k0 = 2 * (ln + SWIFTCL_WAVE * (e0 + e));
       if (k0 < nk) {
-        const float x0 = F * kk[e].x * v[e0 + e].x, x1 = F * kk[e].y * v[e0 + e].y;
+        const float x0 = kk[e].x * v[e0 + e].x, x1 = kk[e].y * v[e0 + e].y;
         if (SPLIT) {
           unsigned short h0, l0, h1, l1;
           split_bf16(x0, &h0, &l0);

@@ -414,8 +414,7 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
       const int r = 16 * rt + 4 * kq + q;
       if (r >= cnt) continue;
       const int li = lis[r];
-      const float F = (float)P.fell[(size_t)kind * P.n_ell + eis[r]];
-      const float x = F * kqv * acc[rt][q];
+      const float x = kqv * acc[rt][q];  // (F(l) is folded into U, hence into the operand table)
       const size_t o = (((size_t)bl * Lm + li) * 32 + t) * nk + j;
       if (SPLIT) {
         const unsigned short hi = bf16_rne_kg(x);

@@ -103,11 +103,14 @@ __device__ inline double taper_of(int n, int M, double taper_frac) {
   return x > x0 ? 0.5 * (1.0 + cos(M_PI * fmin((x - x0) / taper_frac, 1.0))) : 1.0;
 }
 
-// U_l(n) * taper(n) for every kind at eta_n = 2 pi n / (N Delta), n = 0..M-1, with the bias of the
-// kind's row in l's band.
+// F(l) U_l(n) * taper(n) for every kind at eta_n = 2 pi n / (N Delta), n = 0..M-1, with the bias of
+// the kind's row in l's band.  The kind's multipole prefactor F(l) (fell: 1, the shear factor, or
+// l(l+1)) is real and multiplies the whole window, so it is folded into the table once here rather
+// than into every window element (forward, adjoint and k-dependent-growth paths alike).
 template <typename R>
 __global__ void k_u_table(C2<R>* __restrict__ U, const double* __restrict__ ell, const int* __restrict__ band,
-                          bias_table bt, int n_ell, int M, double delta, double taper_frac) {
+                          const double* __restrict__ fell, bias_table bt, int n_ell, int M, double delta,
+                          double taper_frac) {
   const int li = blockIdx.x;
   const int n = blockIdx.y * blockDim.x + threadIdx.x;
   if (li >= n_ell || n >= M) return;
@@ -117,9 +120,10 @@ __global__ void k_u_table(C2<R>* __restrict__ U, const double* __restrict__ ell,
   const double tap = taper_of(n, M, taper_frac);
   for (int kind = 0; kind < SWIFTCL_NKINDS; ++kind) {
     const zd u = u_value(l, bt.b[kind][bi], eta);
+    const double f = fell[(size_t)kind * n_ell + li] * tap;
     C2<R> v;
-    v.x = (R)(u.x * tap);
-    v.y = (R)(n == 0 ? 0.0 : u.y * tap);
+    v.x = (R)(u.x * f);
+    v.y = (R)(n == 0 ? 0.0 : u.y * f);
     U[((size_t)kind * n_ell + li) * M + n] = v;
   }
 }
@@ -176,11 +180,11 @@ hipError_t launch_u_table(const plan_dev& pd, const double* d_ell, hipStream_t s
   for (int k = 0; k < SWIFTCL_NKINDS; ++k)
     for (int j = 0; j < SWIFTCL_MAX_BANDS; ++j) bt.b[k][j] = p->fftlog_b[k][j];
   if (p->precision == SWIFTCL_FP64)
-    hipLaunchKernelGGL(k_u_table<double>, grid, dim3(128), 0, s, (double2*)p->U, d_ell, p->ell_band, bt, p->n_ell,
-                       p->M, p->delta, p->taper_frac);
+    hipLaunchKernelGGL(k_u_table<double>, grid, dim3(128), 0, s, (double2*)p->U, d_ell, p->ell_band, p->fell, bt,
+                       p->n_ell, p->M, p->delta, p->taper_frac);
   else
-    hipLaunchKernelGGL(k_u_table<float>, grid, dim3(128), 0, s, (float2*)p->U, d_ell, p->ell_band, bt, p->n_ell,
-                       p->M, p->delta, p->taper_frac);
+    hipLaunchKernelGGL(k_u_table<float>, grid, dim3(128), 0, s, (float2*)p->U, d_ell, p->ell_band, p->fell, bt,
+                       p->n_ell, p->M, p->delta, p->taper_frac);
   if (p->rsd)  // RSD and magnification plans are FP32 / split
     hipLaunchKernelGGL(k_u_rsd<float>, grid, dim3(128), 0, s, (float2*)p->UR, d_ell, p->ell_band, bt, p->n_ell, p->M,
                        p->delta, p->taper_frac);
