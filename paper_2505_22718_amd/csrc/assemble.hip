@@ -22,8 +22,9 @@
 
 // tracers whose n(z) rows sit in LDS at once
 #define GEOM_GROUP 16
-// threads per point (with 512, 256 VGPRs per lane hold the per-node state without spilling)
-#define GEOM_THREADS 512
+// threads per point: two chi nodes of state per thread (n_chi <= 2048) fit 128 VGPRs without
+// spilling, and the n(z) splines of up to 16 tracers run in one round of wavefronts
+#define GEOM_THREADS 1024
 
 size_t geometry_lds_bytes(const plan_dev& p) {
   const size_t tg = p.max_tracers < GEOM_GROUP ? p.max_tracers : GEOM_GROUP;
