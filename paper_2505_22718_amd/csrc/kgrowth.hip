@@ -245,8 +245,10 @@ template <bool SPLIT, bool W_ONLY = false, bool STAGE = false>
 __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
   __shared__ __align__(16) float Xs[4][16][KG_XP];
   __shared__ __align__(16) float Us[2][KG_TILE][KG_UP];
-  __shared__ __align__(16) float2 Cs[STAGE ? 2 : 1][STAGE ? KG_NA : 1][KG_KC];  // node coefficients
-  __shared__ __align__(16) float2 Ms[STAGE ? 2 : 1][STAGE ? KG_NA : 1][KG_KC];  // and moments
+  // node coefficients and moments; rows of 17 entries, so that the rows a half-wave reads (a few
+  // consecutive node intervals, two coefficients) fall on distinct 8-byte LDS slots
+  __shared__ __align__(16) float2 Cs[STAGE ? 2 : 1][STAGE ? KG_NA : 1][KG_KC + 1];
+  __shared__ __align__(16) float2 Ms[STAGE ? 2 : 1][STAGE ? KG_NA : 1][KG_KC + 1];
   __shared__ int eis[KG_TILE];
   __shared__ int lis[KG_TILE];
   const int T = P.max_tracers, Lm = P.max_ell, nk = P.n_k, nb = P.n_bands, M = P.M, A = P.n_interp;
