@@ -14,7 +14,8 @@
 //   k_kg_slots    multipole slots of every point grouped by band, cut into tiles of <= 64
 //   k_kg_fft      per (point, node): D(kappa_a, z) splined in z and sampled on the chi nodes, every
 //                 (tracer, band) row of kernel samples (assembled with D = 1) times it, r2c
-//   k_kg_cspline  per (point, tracer, band, n): the node spline along ln k (Thomas, FP32)
+//   k_kg_cspline  per (point, tracer, band, n): the node spline along ln k (Thomas, FP32,
+//                 one pass, the back substitution restarted per 16-node segment)
 //   k_kg_windows  the GEMM above, one workgroup per (point, tracer, slot tile, 64 k nodes)
 //   k_contract    C = V V^T per (point, multipole) from the workspace (forward.hip)
 #include <type_traits>
@@ -149,7 +150,17 @@ __global__ __launch_bounds__(256) void k_kg_fft(plan_dev P, swiftcl_inputs in, c
 
 // Natural cubic spline of the node coefficients along ln k: one thread per (row, n), the
 // tridiagonal system M_{a-1} + 4 M_a + M_{a+1} = 6/h^2 (c_{a+1} - 2 c_a + c_{a-1}), M_0 = M_{A-1} = 0,
-// by the Thomas recurrences (1/pivots in kg_ip).
+// by the Thomas recurrences (1/pivots in kg_ip), in one pass over the coefficient rows.  The
+// elimination d_a = (r_a - d_{a-1}) / p_a runs forward in registers, 16 nodes at a time, one
+// segment ahead of the back substitution M_a = d_a - M_{a+1} / p_a.  That substitution starts
+// afresh for every segment from M = 0 at the far end of the next segment: the 1/pivots rise from
+// 1/4 to 2 - sqrt(3) and no further, so a moment computed at least 17 nodes before the restart
+// differs from the full sweep's by at most (2 - sqrt(3))^17 < 2e-10 times the true moment at the
+// restart node, and the moments of the last two segments are exact (the sweep then starts at
+// M_{A-1} = 0).  The coefficient rows are read once and the moments written once (the two full
+// sweeps read c, wrote d, read d, wrote M).
+constexpr int KG_SEG = 16;
+
 __global__ __launch_bounds__(256) void k_kg_cspline(plan_dev P, swiftcl_inputs in, int b0, int nbp, float s6) {
   const int M = P.M, A = P.n_interp, T = P.max_tracers, nb = P.n_bands;
   const int n = blockIdx.y * blockDim.x + threadIdx.x;
@@ -160,43 +171,60 @@ __global__ __launch_bounds__(256) void k_kg_cspline(plan_dev P, swiftcl_inputs i
   if (bl >= nbp || t >= clamp_i(in.n_tracers[b0 + bl], 0, T)) return;
   const float2* c = (const float2*)P.kg_c + (size_t)row * A * M + n;
   float2* m = (float2*)P.kg_m + (size_t)row * A * M + n;
+  const float* ip = P.kg_ip;
   m[0] = make_float2(0.f, 0.f);
   m[(size_t)(A - 1) * M] = make_float2(0.f, 0.f);
-  // each recurrence step waits on one load: the loads of KG_PF steps are issued together
-  constexpr int KG_PF = 8;
+  // elimination state: c_{a-1}, c_a and d_{a-1} for the next node a
   float2 cm = c[0], c0 = c[(size_t)M];
   float2 d = make_float2(0.f, 0.f);
-  for (int a0 = 1; a0 + 1 < A; a0 += KG_PF) {
-    float2 cps[KG_PF];
+  // d of the interior nodes a0 .. a0 + 15 (0 past A - 2); the segment's 16 loads are issued together
+  auto eliminate = [&](int a0, float2(&out)[KG_SEG]) {
+    float2 cps[KG_SEG];
 #pragma unroll
-    for (int i = 0; i < KG_PF; ++i)
+    for (int i = 0; i < KG_SEG; ++i)
       cps[i] = a0 + i + 1 < A ? c[(size_t)(a0 + i + 1) * M] : make_float2(0.f, 0.f);
 #pragma unroll
-    for (int i = 0; i < KG_PF; ++i) {
+    for (int i = 0; i < KG_SEG; ++i) {
       const int a = a0 + i;
-      if (a + 1 >= A) break;
-      const float2 cp = cps[i];
-      const float ip = P.kg_ip[a];
-      d.x = (s6 * (cp.x - 2.f * c0.x + cm.x) - d.x) * ip;
-      d.y = (s6 * (cp.y - 2.f * c0.y + cm.y) - d.y) * ip;
-      m[(size_t)a * M] = d;
-      cm = c0;
-      c0 = cp;
+      if (a + 1 < A) {
+        const float2 cp = cps[i];
+        const float ipa = ip[a];
+        d.x = (s6 * (cp.x - 2.f * c0.x + cm.x) - d.x) * ipa;
+        d.y = (s6 * (cp.y - 2.f * c0.y + cm.y) - d.y) * ipa;
+        cm = c0;
+        c0 = cp;
+        out[i] = d;
+      } else {
+        out[i] = make_float2(0.f, 0.f);
+      }
     }
-  }
-  float2 mn = make_float2(0.f, 0.f);
-  for (int a0 = A - 2; a0 >= 1; a0 -= KG_PF) {
-    float2 ds[KG_PF];
+  };
+  float2 dcur[KG_SEG], dnext[KG_SEG];
+  eliminate(1, dcur);
+  for (int a0 = 1; a0 + 1 < A; a0 += KG_SEG) {
+    eliminate(a0 + KG_SEG, dnext);
+    // back substitution through the next segment from M = 0 past its end (moments discarded) ...
+    float2 mn = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int i = 0; i < KG_PF; ++i) ds[i] = a0 - i >= 1 ? m[(size_t)(a0 - i) * M] : make_float2(0.f, 0.f);
-#pragma unroll
-    for (int i = 0; i < KG_PF; ++i) {
-      const int a = a0 - i;
-      if (a < 1) break;
-      const float ip = P.kg_ip[a];
-      mn = make_float2(ds[i].x - ip * mn.x, ds[i].y - ip * mn.y);
-      m[(size_t)a * M] = mn;
+    for (int i = KG_SEG - 1; i >= 0; --i) {
+      const int a = a0 + KG_SEG + i;
+      if (a + 1 < A) {
+        const float ipa = ip[a];
+        mn = make_float2(dnext[i].x - ipa * mn.x, dnext[i].y - ipa * mn.y);
+      }
     }
+    // ... then through this one, storing its moments
+#pragma unroll
+    for (int i = KG_SEG - 1; i >= 0; --i) {
+      const int a = a0 + i;
+      if (a + 1 < A) {
+        const float ipa = ip[a];
+        mn = make_float2(dcur[i].x - ipa * mn.x, dcur[i].y - ipa * mn.y);
+        m[(size_t)a * M] = mn;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < KG_SEG; ++i) dcur[i] = dnext[i];
   }
 }
 
