@@ -33,32 +33,53 @@ __device__ __forceinline__ int clamp_i(int v, int lo, int hi) { return v < lo ? 
 constexpr int KG_TILE = 64;   // slots and k nodes per GEMM workgroup
 constexpr int KG_KC = 16;     // coefficients n per K chunk (32 real K rows)
 
-// One thread per point: slot permutation (stable, grouped by band) and the tile list.
-__global__ void k_kg_slots(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
-  const int bl = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per point: slot permutation (stable, grouped by band) and the tile list.  The
+// slots are taken 64 at a time, one per lane; a ballot per band counts them and places each at its
+// band's running offset plus the number of lower lanes of the same band.
+__global__ __launch_bounds__(SWIFTCL_WAVE) void k_kg_slots(plan_dev P, swiftcl_inputs in, int b0, int nbp) {
+  const int bl = blockIdx.x, lane = threadIdx.x;
   if (bl >= nbp) return;
   const int b = b0 + bl;
   const int Lm = P.max_ell, nb = P.n_bands;
   const int Lb = clamp_i(in.n_ell[b], 0, Lm);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  // band of slot li (-1 past the point's slots); a bad index is flagged and read as 0
+  auto band_of = [&](int li) {
+    if (li >= Lb) return -1;
+    int ei = in.ell_idx[(size_t)b * Lm + li];
+    if (ei < 0 || ei >= P.n_ell) {
+      atomicOr(P.flags, FLAG_BAD_INDEX);
+      ei = 0;
+    }
+    return P.ell_band[ei];
+  };
   int cnt[SWIFTCL_MAX_BANDS] = {0, 0, 0, 0};
-  bool bad = false;
-  for (int li = 0; li < Lb; ++li) {
-    int ei = in.ell_idx[(size_t)b * Lm + li];
-    if (ei < 0 || ei >= P.n_ell) { bad = true; ei = 0; }
-    ++cnt[P.ell_band[ei]];
+  for (int l0 = 0; l0 < Lb; l0 += SWIFTCL_WAVE) {
+    const int bd = band_of(l0 + lane);
+    for (int bi = 0; bi < nb; ++bi) cnt[bi] += __popcll(__ballot(bd == bi));
   }
-  if (bad) atomicOr(P.flags, FLAG_BAD_INDEX);
-  int off[SWIFTCL_MAX_BANDS];
+  int off[SWIFTCL_MAX_BANDS], pos[SWIFTCL_MAX_BANDS];
   int acc = 0;
-  for (int bi = 0; bi < nb; ++bi) { off[bi] = acc; acc += cnt[bi]; }
-  int* perm = P.kg_perm + (size_t)bl * Lm;
-  int pos[SWIFTCL_MAX_BANDS];
-  for (int bi = 0; bi < nb; ++bi) pos[bi] = off[bi];
-  for (int li = 0; li < Lb; ++li) {
-    int ei = in.ell_idx[(size_t)b * Lm + li];
-    if (ei < 0 || ei >= P.n_ell) ei = 0;
-    perm[pos[P.ell_band[ei]]++] = li;
+  for (int bi = 0; bi < nb; ++bi) {
+    off[bi] = acc;
+    pos[bi] = acc;
+    acc += cnt[bi];
   }
+  int* perm = P.kg_perm + (size_t)bl * Lm;
+  for (int l0 = 0; l0 < Lb; l0 += SWIFTCL_WAVE) {
+    const int li = l0 + lane;
+    int bd = -1;
+    if (li < Lb) {
+      const int ei = in.ell_idx[(size_t)b * Lm + li];
+      bd = P.ell_band[ei < 0 || ei >= P.n_ell ? 0 : ei];
+    }
+    for (int bi = 0; bi < nb; ++bi) {
+      const unsigned long long mask = __ballot(bd == bi);
+      if (bd == bi) perm[pos[bi] + __popcll(mask & below)] = li;
+      pos[bi] += __popcll(mask);
+    }
+  }
+  if (lane != 0) return;
   int4* tile = (int4*)P.kg_tile + (size_t)bl * P.kg_ntile;
   int nt = 0;
   for (int bi = 0; bi < nb; ++bi)
@@ -512,7 +533,7 @@ hipError_t launch_kg_t(const plan_dev& p, const swiftcl_inputs* in, const double
   const bool split = p.precision == SWIFTCL_SPLIT_BF16;
   for (int b0 = 0; b0 < in->batch; b0 += p.vchunk) {
     const int nbp = in->batch - b0 < p.vchunk ? in->batch - b0 : p.vchunk;
-    hipLaunchKernelGGL(k_kg_slots, dim3((nbp + 63) / 64), dim3(64), 0, s, p, *in, b0, nbp);
+    hipLaunchKernelGGL(k_kg_slots, dim3(nbp), dim3(SWIFTCL_WAVE), 0, s, p, *in, b0, nbp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_kg_fft<M>, dim3((unsigned)((size_t)nbp * A)), dim3(256), kg_fft_lds<M>(p.n_zg), s, p, *in,
@@ -550,7 +571,7 @@ hipError_t launch_kg_bwd_t(const plan_dev& p, const swiftcl_inputs* in, const do
   if (dpk) {
     for (int b0 = 0; b0 < in->batch; b0 += p.vchunk) {
       const int nbp = in->batch - b0 < p.vchunk ? in->batch - b0 : p.vchunk;
-      hipLaunchKernelGGL(k_kg_slots, dim3((nbp + 63) / 64), dim3(64), 0, s, p, *in, b0, nbp);
+      hipLaunchKernelGGL(k_kg_slots, dim3(nbp), dim3(SWIFTCL_WAVE), 0, s, p, *in, b0, nbp);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL(k_kg_fft<M>, dim3((unsigned)((size_t)nbp * A)), dim3(256), kg_fft_lds<M>(p.n_zg), s, p,
                          *in, D_kz, b0, nbp);
