@@ -381,6 +381,13 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
     }
     __syncthreads();
     int buf = 0;
+    // e^{-2 pi i n0 j / N} of the chunk, advanced by one chunk's rotation in FP64 (no table load
+    // inside the loop, where its wait would also wait for the prefetches above; 32 FP64 steps stay
+    // far below FP32 rounding)
+    double2 ed = make_double2(1.0, 0.0);
+    double2 wd;
+    sincospi(2.0 * (double)((KG_KC * j) & Nmask) / (double)(2 * M), &wd.y, &wd.x);
+    wd.y = -wd.y;
     for (int n0 = 0; n0 < M; n0 += KG_KC) {
       // next chunk's U rows (and staged node rows), in flight during this chunk
       float4 un0 = make_float4(0.f, 0.f, 0.f, 0.f), un1 = un0;
@@ -394,7 +401,8 @@ __global__ __launch_bounds__(256) void k_kg_windows(plan_dev P, swiftcl_inputs i
           mn = sm[n0 + KG_KC];
         }
       }
-      const float2 e0 = twid(n0 * j);
+      const float2 e0 = make_float2((float)ed.x, (float)ed.y);
+      ed = make_double2(ed.x * wd.x - ed.y * wd.y, ed.x * wd.y + ed.y * wd.x);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int nl = kq + 4 * q;
