@@ -223,8 +223,9 @@ swiftcl_status swiftcl_cl_backward(swiftcl_plan_t plan, const swiftcl_inputs* in
  * or as a persistent grid walking per-XCD packed lists (two (point, multipole) items whose tracer
  * counts sum to at most 16 share a workgroup), and (if dC is not NULL) the adjoint with 1, 2, 4 or
  * 8 times its base number of multipole chunks (base: about 256 workgroups, one round on the chip,
- * which suits uniform batches; ragged batches run better with more); keeps the fastest in the plan (a variant other than
- * the default, fwd_mode 0 and bwd_chunk_mul 1, must be at least 2% faster).  With cache_path (may
+ * which suits uniform batches; ragged batches run better with more) and, on FP32 plans, the packed
+ * adjoint at 1, 2 and 4; keeps the fastest in the plan (a variant other than the default, fwd_mode
+ * 0, bwd_chunk_mul 1 and bwd_pack 0, must be at least 2% faster).  With cache_path (may
  * be NULL) the choice is read from, or appended to, a file with one JSON object per line keyed by
  * architecture and shape.  `C` (output-shaped scratch, overwritten) and `dC` are device buffers
  * laid out as for swiftcl_cl / swiftcl_cl_backward.  `report` (may be NULL) receives a one-line
@@ -237,9 +238,14 @@ swiftcl_status swiftcl_autotune(swiftcl_plan_t plan, const swiftcl_inputs* in, v
  * fwd_mode 0 = one workgroup per (point, multipole slot), 1 = persistent grid over per-XCD compact
  * work lists, 2 = persistent grid over per-XCD packed lists (plans whose projection is fused; the
  * others run mode 0 whatever is set); bwd_chunk_mul in {1, 2, 4, 8} scales the adjoint's number of
- * multipole chunks.  Every configuration computes the same C_l bit for bit. */
-swiftcl_status swiftcl_set_launch(swiftcl_plan_t plan, int32_t fwd_mode, int32_t bwd_chunk_mul);
-swiftcl_status swiftcl_get_launch(swiftcl_plan_t plan, int32_t* fwd_mode, int32_t* bwd_chunk_mul);
+ * multipole chunks; bwd_pack 1 (FP32 plans with a fused adjoint; FP64 plans run unpacked whatever
+ * is set) splits each chunk into two halves with partial rows of their own, which a point of at
+ * most 8 tracers runs side by side on the two halves of the workgroup's 16 wavefronts (needs
+ * bwd_chunk_mul <= 4).  A combination outside these sets returns SWIFTCL_E_INVALID and changes
+ * nothing.  Every configuration computes the same C_l bit for bit; the gradients differ only in
+ * the order of their FP32 partial sums.  get: every pointer must be non-NULL. */
+swiftcl_status swiftcl_set_launch(swiftcl_plan_t plan, int32_t fwd_mode, int32_t bwd_chunk_mul, int32_t bwd_pack);
+swiftcl_status swiftcl_get_launch(swiftcl_plan_t plan, int32_t* fwd_mode, int32_t* bwd_chunk_mul, int32_t* bwd_pack);
 
 /* What a built plan runs (host only, no device work): *fused = 1 when the C_l projection keeps the
  * windows of a (point, multipole) in one workgroup's LDS, 0 when it goes through the device

@@ -114,8 +114,9 @@ def load(path: str = LIB_PATH):
     lib.swiftcl_cl_kgrowth_backward.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp, vp]
     lib.swiftcl_autotune.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, ctypes.c_char_p,
                                      ctypes.c_char_p, ctypes.c_int32]
-    lib.swiftcl_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
-    lib.swiftcl_get_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.swiftcl_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.swiftcl_get_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]
     lib.swiftcl_plan_info.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 3
     lib.swiftcl_cl_backward_timed.argtypes = [vp, ctypes.POINTER(swiftcl_inputs), vp, vp, vp, vp, vp,
                                               ctypes.c_uint32, vp, ctypes.POINTER(ctypes.c_float)]
@@ -227,8 +228,8 @@ def swiftcl_autotune(plan, inputs: swiftcl_inputs, C: int, dC: int = 0, stream: 
     return buf.value.decode()
 
 
-def swiftcl_set_launch(plan, fwd_mode: int = -1, bwd_chunk_mul: int = -1):
-    _check(load().swiftcl_set_launch(plan, fwd_mode, bwd_chunk_mul))
+def swiftcl_set_launch(plan, fwd_mode: int = -1, bwd_chunk_mul: int = -1, bwd_pack: int = -1):
+    _check(load().swiftcl_set_launch(plan, fwd_mode, bwd_chunk_mul, bwd_pack))
 
 
 def swiftcl_plan_info(plan):
@@ -238,9 +239,9 @@ def swiftcl_plan_info(plan):
 
 
 def swiftcl_get_launch(plan):
-    a, b = ctypes.c_int32(), ctypes.c_int32()
-    _check(load().swiftcl_get_launch(plan, ctypes.byref(a), ctypes.byref(b)))
-    return {"fwd_mode": a.value, "bwd_chunk_mul": b.value}
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().swiftcl_get_launch(plan, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return {"fwd_mode": a.value, "bwd_chunk_mul": b.value, "bwd_pack": c.value}
 
 
 def raw_status(fn_name: str, *args) -> int:

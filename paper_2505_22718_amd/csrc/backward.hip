@@ -128,11 +128,18 @@ __global__ __launch_bounds__(1024) void k_bwd_order(plan_dev P, swiftcl_inputs i
 // per-wave scratch [NW][FL] and WY[16][n_k + 2].  The dc accumulators held in registers across the
 // multipole loop need ~126 VGPRs, so one 1024-thread workgroup runs per CU (forcing two costs more
 // in spills than the occupancy gains).
-template <typename R, int M, int NW, bool TW_LDS>
+// PACK (FP32, one wavefront per tracer slot): the chunk's slots form two sub-chunks [l0, lm) and
+// [lm, l1) with partial rows of their own (the reduction then sums 2 nchunk rows per point).  A
+// point of at most 8 tracers runs the two side by side, waves 0-7 on the first and waves 8-15 on
+// the second: rows 0-7 of the W tile hold the tracers of the first sub-chunk's multipole, rows
+// 8-15 those of the second's, and G is block-diagonal, so one Y = G W product serves both and all
+// 16 wavefronts transform.  Any other point runs the two sub-chunks one after the other.
+template <typename R, int M, int NW, bool TW_LDS, bool PACK = false>
 __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inputs in, const R* __restrict__ dC,
                                                          int nchunk, int ordered) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr bool COMPACT = sizeof(R) == 4 && NW == 16;
+  static_assert(!PACK || COMPACT, "sub-chunk packing needs one wavefront per tracer slot");
   constexpr int RL = M / SWIFTCL_WAVE;
   constexpr int N = 2 * M;
   constexpr int FL = fft_lds_size(M, sizeof(R));
@@ -160,13 +167,20 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   const int Lb = clampb(in.n_ell[b], 0, Lm);
   const int l0 = (int)(((long)chunk * Lb) / nchunk), l1 = (int)(((long)(chunk + 1) * Lb) / nchunk);
   const int npair = T * (T + 1) / 2;
+  // PACK: the sub-chunk split; this wavefront's half, tracer and slots
+  const int lm = PACK ? l0 + (l1 - l0) / 2 : l1;
+  const bool pk = PACK && Tb <= 8;
+  const int hh = pk ? wave >> 3 : 0;
+  const int tt = pk ? (wave & 7) : wave;
+  const int ml0 = (pk && hh) ? lm : l0, ml1 = (pk && !hh) ? lm : l1;
+  const int nsteps = pk ? (lm - l0 > l1 - lm ? lm - l0 : l1 - lm) : l1 - l0;
   const C2<R>* stw = TW_LDS ? stw_l : (const C2<R>*)P.tw;
   if constexpr (TW_LDS) {
     const C2<R>* gtw = (const C2<R>*)P.tw;
     for (int i = threadIdx.x; i < N; i += NW * 64) stw_l[i] = gtw[i];
   }
   const size_t slot = (size_t)b * nchunk + chunk;
-  C2<R>* part = (C2<R>*)P.dchat_part + slot * T * nb * M;
+  C2<R>* part = (C2<R>*)P.dchat_part + slot * (PACK ? 2 : 1) * T * nb * M;
   if (!COMPACT)  // (COMPACT: every (tracer, band) row of the slot is stored once, below)
     for (size_t i = threadIdx.x; i < (size_t)T * nb * M; i += NW * 64) part[i] = mk<R>(0, 0);
   const R* sq = (const R*)P.sqrt_s + (size_t)b * nk;
@@ -186,17 +200,30 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
 #pragma unroll
   for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
   int cur_band = -1;
-  unsigned flushed = 0;  // bands whose partial rows this workgroup has written
+  int cur_sub = 0;       // (PACK) sub-chunk of the accumulators
+  unsigned flushed = 0;  // bands (PACK: sub-chunk x 4 + band) whose partial rows this wavefront has written
   // add the accumulators of band cur_band to the partial rows (store on the first visit)
   auto flush = [&]() {
-    const bool again = (flushed >> cur_band) & 1u;
-    for (int t = wave; t < Tb; t += NW) {
-      C2<R>* dst = part + ((size_t)t * nb + cur_band) * M;
+    if constexpr (PACK) {
+      const int bit = cur_sub * SWIFTCL_MAX_BANDS + cur_band;
+      const bool again = (flushed >> bit) & 1u;
+      if (tt < Tb) {
+        C2<R>* dst = part + (((size_t)cur_sub * T + tt) * nb + cur_band) * M;
 #pragma unroll
-      for (int e = 0; e < RL; ++e)
-        dst[lane + SWIFTCL_WAVE * e] = again ? cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]) : acc[e];
+        for (int e = 0; e < RL; ++e)
+          dst[lane + SWIFTCL_WAVE * e] = again ? cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]) : acc[e];
+      }
+      flushed |= 1u << bit;
+    } else {
+      const bool again = (flushed >> cur_band) & 1u;
+      for (int t = wave; t < Tb; t += NW) {
+        C2<R>* dst = part + ((size_t)t * nb + cur_band) * M;
+#pragma unroll
+        for (int e = 0; e < RL; ++e)
+          dst[lane + SWIFTCL_WAVE * e] = again ? cadd(dst[lane + SWIFTCL_WAVE * e], acc[e]) : acc[e];
+      }
+      flushed |= 1u << cur_band;
     }
-    flushed |= 1u << cur_band;
   };
   __syncthreads();
 
@@ -204,7 +231,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
   auto ell_of = [&](int li, int& ei, int& band) {
     ei = in.ell_idx[(size_t)b * Lm + li];
     if (ei < 0 || ei >= P.n_ell) {
-      if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
+      if (PACK ? lane == 0 : threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
       ei = 0;
     }
     band = P.ell_band[ei];
@@ -223,17 +250,38 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       Gp[j & 3][16 * (j >> 2) + i] = gv;
     }
   };
-  // (1) W of every tracer of multipole (ei, band) into its LDS row
-  auto windows = [&](int ei, int band) {
-    for (int t = wave; t < 16; t += NW) {
-      if (t >= Tb) {
-        for (int j = lane; j < nk; j += SWIFTCL_WAVE) WY[t * vs + j] = (R)0;
-        continue;
+  // (PACK) G of step s: block-diagonal over the halves of a packed point
+  auto load_G_pk = [&](int s) {
+    for (int gi = threadIdx.x; gi < 256; gi += NW * 64) {
+      const int i = gi / 16, j = gi % 16;
+      int li = -1, ii = i, jj = j;
+      if (pk) {
+        if ((i >> 3) == (j >> 3)) {
+          const int a0 = (i >> 3) ? lm : l0, a1 = (i >> 3) ? l1 : lm;
+          if (a0 + s < a1) li = a0 + s;
+          ii = i & 7;
+          jj = j & 7;
+        }
+      } else {
+        li = l0 + s;
       }
+      R gv = (R)0;
+      if (li >= 0 && ii < Tb && jj < Tb) {
+        const int a = ii < jj ? ii : jj, c = ii < jj ? jj : ii;
+        const int p = a * T - a * (a - 1) / 2 + (c - a);
+        gv = dC[((size_t)b * Lm + li) * npair + p];
+        if (ii != jj) gv *= (R)0.5;
+      }
+      Gp[j & 3][16 * (j >> 2) + i] = gv;
+    }
+  };
+  // (1) W of tracer t of multipole (ei, band) into LDS row `row`
+  auto win_row = [&](int row, int t, int ei, int band) {
+    {
       const int kind = tracer_kind(in, T, b, t);
       const C2<R>* ch = (const C2<R>*)P.chat + (((size_t)b * T + t) * nb + band) * M;
       const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
-      C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)t * vs) : fbuf + (size_t)wave * FL;
+      C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)row * vs) : fbuf + (size_t)wave * FL;
       C2<R> v[RL];
       wave_sync();
 #pragma unroll
@@ -249,7 +297,7 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       const R* ks = kscale + ((size_t)kind * nb + band) * nk;  // (F(l) is folded into U)
       auto w_pair = [&](int k0, int e) {
         const C2<R> kk = *(const C2<R>*)(ks + k0);
-        *(C2<R>*)(WY + t * vs + k0) = mk<R>(kk.x * v[e].x, kk.y * v[e].y);
+        *(C2<R>*)(WY + row * vs + k0) = mk<R>(kk.x * v[e].x, kk.y * v[e].y);
       };
       if (2 * M <= nk) {  // every pair inside the row: no guard between the loads
 #pragma unroll
@@ -263,19 +311,30 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
       }
     }
   };
+  // (1) W of every tracer of multipole (ei, band) into its LDS row
+  auto windows = [&](int ei, int band) {
+    for (int t = wave; t < 16; t += NW) {
+      if (t >= Tb) {
+        for (int j = lane; j < nk; j += SWIFTCL_WAVE) WY[t * vs + j] = (R)0;
+        continue;
+      }
+      win_row(t, t, ei, band);
+    }
+  };
+  // (PACK) this wavefront's row at step s; its slot's multipole and band go to (nei, nband)
+  int nei = 0, nband = 0;
+  auto windows_pk = [&](int s) {
+    const int li = ml0 + s;
+    if (li >= ml1 || tt >= Tb) {
+      for (int j = lane; j < nk; j += SWIFTCL_WAVE) WY[wave * vs + j] = (R)0;
+      return;
+    }
+    ell_of(li, nei, nband);
+    win_row(wave, tt, nei, nband);
+  };
 
-  // Software pipeline over the multipoles of this chunk, two barriers per multipole: the adjoint
-  // transforms of slot li share a barrier interval with the windows of slot li + 1 (each wavefront
-  // only touches its own LDS rows there).
-  int ei = 0, band = 0;
-  if (l0 < l1) {
-    ell_of(l0, ei, band);
-    load_G(l0);
-    windows(ei, band);
-  }
-  __syncthreads();
-  for (int li = l0; li < l1; ++li) {
-    // (2) Y = G W on MFMA, tile by tile of 16 k (each tile owned by one wavefront, in place)
+  // (2) Y = G W on MFMA, tile by tile of 16 k (each tile owned by one wavefront, in place)
+  auto products = [&]() {
     using acc_t = typename bmfma<R>::type;
     for (int tile = wave; tile < ntiles; tile += NW) {
       const int col = tile * 16 + (lane & 15);
@@ -305,90 +364,152 @@ __global__ __launch_bounds__(NW * 64) void k_bwd_windows(plan_dev P, swiftcl_inp
         if (col < nk) WY[row * vs + col] = y[r];
       }
     }
+  };
+  // (3) dx = 2 s F k^{-1-b} Y of LDS row `row` (tracer t, multipole (ei, band)), r2c,
+  // dc += h_n conj(X_n) conj(U_l(n))
+  auto adj_row = [&](int row, int t, int ei, int band) {
+    const int kind = tracer_kind(in, T, b, t);
+    const R* ks = kscale + ((size_t)kind * nb + band) * nk;
+    C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)row * vs) : fbuf + (size_t)wave * FL;
+    C2<R> v[RL];
+    // 2 s F k^{-1-b} Y per output pair; when every pair lies inside the row (N <= nk) the loads
+    // carry no guard, so they are issued together
+    auto dx_pair = [&](int k0) {
+      const C2<R> y2 = *(const C2<R>*)(WY + row * vs + k0);
+      const C2<R> kk = *(const C2<R>*)(ks + k0);
+      if constexpr (COMPACT) {
+        const C2<R> s2 = *(const C2<R>*)(sq2 + k0);
+        return mk<R>(kk.x * s2.x * y2.x, kk.y * s2.y * y2.y);
+      } else {
+        const C2<R> s2 = *(const C2<R>*)(sq + k0);
+        return mk<R>((R)2 * s2.x * s2.x * kk.x * y2.x, (R)2 * s2.y * s2.y * kk.y * y2.y);
+      }
+    };
+    if (2 * M <= nk) {
+#pragma unroll
+      for (int e = 0; e < RL; ++e) v[e] = dx_pair(2 * (lane + SWIFTCL_WAVE * e));
+    } else {
+#pragma unroll
+      for (int e = 0; e < RL; ++e) {
+        const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
+        v[e] = k0 < nk ? dx_pair(k0) : mk<R>(0, 0);
+      }
+    }
+    const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
+    C2<R> ur[NW >= 16 ? RL : 1];
+    if constexpr (NW >= 16) {
+      // issued before the transform, used after it
+#pragma unroll
+      for (int e = 0; e < RL; ++e) ur[e] = Ur[lane + SWIFTCL_WAVE * e];
+    }
+    wave_sync();
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    ln &= SWIFTCL_WAVE - 1;  // the compiler may assume 0 <= ln < 64 again
+    wave_r2c<R, M>(v, mine, stw, ln);
+    if constexpr (NW >= 16) {
+      // one tracer per wavefront: accumulate in registers, flushed when the band changes
+#pragma unroll
+      for (int e = 0; e < RL; ++e) {
+        const int n = lane + SWIFTCL_WAVE * e;
+        const R h = n == 0 ? (R)1 : (R)2;
+        acc[e] = cadd(acc[e], cscale(cmul(cconj(v[e]), cconj(ur[e])), h));
+      }
+    } else {
+      // a wavefront serves several tracers: add into this workgroup's partial slot directly
+      C2<R>* dst = part + ((size_t)t * nb + band) * M;
+#pragma unroll
+      for (int e = 0; e < RL; ++e) {
+        const int n = lane + SWIFTCL_WAVE * e;
+        const R h = n == 0 ? (R)1 : (R)2;
+        dst[n] = cadd(dst[n], cscale(cmul(cconj(v[e]), cconj(Ur[n])), h));
+      }
+    }
+  };
+
+  if constexpr (PACK) {
+    // the same pipeline over the steps of the two sub-chunks; each wavefront keeps its own band,
+    // sub-chunk and accumulators
+    if (nsteps > 0) {
+      load_G_pk(0);
+      windows_pk(0);
+    }
     __syncthreads();
-    if (NW >= 16 && band != cur_band) {
-      if (cur_band >= 0) flush();
+    for (int s = 0; s < nsteps; ++s) {
+      products();
+      __syncthreads();
+      const int li = ml0 + s;
+      if (li < ml1 && tt < Tb) {
+        const int ei = nei, band = nband;  // set by windows_pk(s)
+        const int sub = pk ? hh : (li >= lm ? 1 : 0);
+        if (band != cur_band || sub != cur_sub) {
+          if (cur_band >= 0) flush();
 #pragma unroll
-      for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
-      cur_band = band;
+          for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
+          cur_band = band;
+          cur_sub = sub;
+        }
+        adj_row(wave, tt, ei, band);
+      }
+      if (s + 1 < nsteps) {
+        load_G_pk(s + 1);
+        windows_pk(s + 1);
+      }
+      __syncthreads();
     }
-    // (3) dx = 2 s F k^{-1-b} Y, r2c, dc += h_n conj(X_n) conj(U_l(n))
-    for (int t = wave; t < Tb; t += NW) {
-      const int kind = tracer_kind(in, T, b, t);
-      const R* ks = kscale + ((size_t)kind * nb + band) * nk;
-      C2<R>* mine = COMPACT ? (C2<R>*)(WY + (size_t)t * vs) : fbuf + (size_t)wave * FL;
-      C2<R> v[RL];
-      // 2 s F k^{-1-b} Y per output pair; when every pair lies inside the row (N <= nk) the loads
-      // carry no guard, so they are issued together
-      auto dx_pair = [&](int k0) {
-        const C2<R> y2 = *(const C2<R>*)(WY + t * vs + k0);
-        const C2<R> kk = *(const C2<R>*)(ks + k0);
-        if constexpr (COMPACT) {
-          const C2<R> s2 = *(const C2<R>*)(sq2 + k0);
-          return mk<R>(kk.x * s2.x * y2.x, kk.y * s2.y * y2.y);
-        } else {
-          const C2<R> s2 = *(const C2<R>*)(sq + k0);
-          return mk<R>((R)2 * s2.x * s2.x * kk.x * y2.x, (R)2 * s2.y * s2.y * kk.y * y2.y);
-        }
-      };
-      if (2 * M <= nk) {
+    if (cur_band >= 0) flush();
+    // (sub-chunk, band) rows this wavefront never wrote: zeros (the reduction sums every row)
+    if (tt < Tb) {
+      for (int sb = 0; sb < 2; ++sb) {
+        if (pk && sb != hh) continue;
+        for (int bi = 0; bi < nb; ++bi) {
+          if ((flushed >> (sb * SWIFTCL_MAX_BANDS + bi)) & 1u) continue;
+          C2<R>* dst = part + (((size_t)sb * T + tt) * nb + bi) * M;
 #pragma unroll
-        for (int e = 0; e < RL; ++e) v[e] = dx_pair(2 * (lane + SWIFTCL_WAVE * e));
-      } else {
-#pragma unroll
-        for (int e = 0; e < RL; ++e) {
-          const int k0 = 2 * (lane + SWIFTCL_WAVE * e);
-          v[e] = k0 < nk ? dx_pair(k0) : mk<R>(0, 0);
-        }
-      }
-      const C2<R>* Ur = (const C2<R>*)P.U + ((size_t)kind * P.n_ell + ei) * M;
-      C2<R> ur[NW >= 16 ? RL : 1];
-      if constexpr (NW >= 16) {
-        // issued before the transform, used after it
-#pragma unroll
-        for (int e = 0; e < RL; ++e) ur[e] = Ur[lane + SWIFTCL_WAVE * e];
-      }
-      wave_sync();
-      int ln = lane;
-      asm volatile("" : "+v"(ln));
-      ln &= SWIFTCL_WAVE - 1;  // the compiler may assume 0 <= ln < 64 again
-      wave_r2c<R, M>(v, mine, stw, ln);
-      if constexpr (NW >= 16) {
-        // one tracer per wavefront: accumulate in registers, flushed when the band changes
-#pragma unroll
-        for (int e = 0; e < RL; ++e) {
-          const int n = lane + SWIFTCL_WAVE * e;
-          const R h = n == 0 ? (R)1 : (R)2;
-          acc[e] = cadd(acc[e], cscale(cmul(cconj(v[e]), cconj(ur[e])), h));
-        }
-      } else {
-        // a wavefront serves several tracers: add into this workgroup's partial slot directly
-        C2<R>* dst = part + ((size_t)t * nb + band) * M;
-#pragma unroll
-        for (int e = 0; e < RL; ++e) {
-          const int n = lane + SWIFTCL_WAVE * e;
-          const R h = n == 0 ? (R)1 : (R)2;
-          dst[n] = cadd(dst[n], cscale(cmul(cconj(v[e]), cconj(Ur[n])), h));
+          for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = mk<R>(0, 0);
         }
       }
     }
-    // (1) for the next slot
-    if (li + 1 < l1) {
-      ell_of(li + 1, ei, band);
-      load_G(li + 1);
+  } else {
+    // Software pipeline over the multipoles of this chunk, two barriers per multipole: the adjoint
+    // transforms of slot li share a barrier interval with the windows of slot li + 1 (each wavefront
+    // only touches its own LDS rows there).
+    int ei = 0, band = 0;
+    if (l0 < l1) {
+      ell_of(l0, ei, band);
+      load_G(l0);
       windows(ei, band);
     }
     __syncthreads();
-  }
-  if (NW >= 16) {
-    if (cur_band >= 0) flush();
-    // bands this chunk never reached: zero rows (the reduction sums every chunk's row)
-    for (int bi = 0; bi < nb; ++bi) {
-      if ((flushed >> bi) & 1u) continue;
-      for (int t = wave; t < Tb; t += NW) {
-        C2<R>* dst = part + ((size_t)t * nb + bi) * M;
+    for (int li = l0; li < l1; ++li) {
+      products();
+      __syncthreads();
+      if (NW >= 16 && band != cur_band) {
+        if (cur_band >= 0) flush();
 #pragma unroll
-        for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = mk<R>(0, 0);
+        for (int e = 0; e < RL; ++e) acc[e] = mk<R>(0, 0);
+        cur_band = band;
+      }
+      // (3) the adjoint transforms
+      for (int t = wave; t < Tb; t += NW) adj_row(t, t, ei, band);
+      // (1) for the next slot
+      if (li + 1 < l1) {
+        ell_of(li + 1, ei, band);
+        load_G(li + 1);
+        windows(ei, band);
+      }
+      __syncthreads();
+    }
+    if (NW >= 16) {
+      if (cur_band >= 0) flush();
+      // bands this chunk never reached: zero rows (the reduction sums every chunk's row)
+      for (int bi = 0; bi < nb; ++bi) {
+        if ((flushed >> bi) & 1u) continue;
+        for (int t = wave; t < Tb; t += NW) {
+          C2<R>* dst = part + ((size_t)t * nb + bi) * M;
+#pragma unroll
+          for (int e = 0; e < RL; ++e) dst[lane + SWIFTCL_WAVE * e] = mk<R>(0, 0);
+        }
       }
     }
   }
@@ -1006,7 +1127,9 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   constexpr bool TW = !dp;
   const int nchunk = backward_chunks(p, in->batch);
   const size_t lds = bwd_windows_lds(p);
-  auto k1 = k_bwd_windows<R, M, NW, TW>;
+  // the packed adjoint writes two sub-chunks of partial rows per chunk
+  const bool pack = !dp && p.bwd_pack && p.bwd_chunk_mul <= 4;
+  auto k1 = pack ? k_bwd_windows<R, M, NW, TW, !dp> : k_bwd_windows<R, M, NW, TW>;
   hipError_t e;
   const size_t groups = (size_t)(in->batch + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD;
   const long n = (long)groups * nchunk * SWIFTCL_NXCD;
@@ -1019,7 +1142,8 @@ static hipError_t launch_bwd_t(const plan_dev& p, const swiftcl_inputs* in, cons
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
   const long rows = (long)in->batch * p.max_tracers * p.n_bands;
-  hipLaunchKernelGGL((k_bwd_coeffs<R, M>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in, nchunk);
+  hipLaunchKernelGGL((k_bwd_coeffs<R, M>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, p, *in,
+                     pack ? 2 * nchunk : nchunk);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   if ((dbias || dnz || dD) && (e = launch_bwd_tracer<R>(p, in, dbias, dnz, s)) != hipSuccess) return e;

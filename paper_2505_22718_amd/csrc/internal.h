@@ -85,6 +85,8 @@ struct plan_dev {
                       // 2: persistent, packed per-XCD lists (two items of few tracers per task)
   int persist_blocks; // grid of the persistent launch (a multiple of 8)
   int bwd_chunk_mul;  // multiplier of the backward multipole-chunk count (1, 2, 4 or 8)
+  int bwd_pack;       // FP32 fused adjoint: two sub-chunks per chunk, side by side for points of <= 8
+                      // tracers (0 or 1; with bwd_chunk_mul <= 4)
   int* sched;         // sched_ints(sched_stride): per-XCD work lists of the persistent launch
   int sched_stride;
   // projection path: fused (windows in LDS, <= 16 tracers) or through the workspace below

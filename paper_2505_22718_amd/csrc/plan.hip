@@ -415,6 +415,7 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
     p->d.persist_blocks = (ncu / SWIFTCL_NXCD) * SWIFTCL_NXCD;
     p->d.fwd_mode = 0;
     p->d.bwd_chunk_mul = 1;
+    p->d.bwd_pack = 0;
   }
   for (int j = 0; j < SWIFTCL_MAX_BANDS; ++j) {
     p->d.band_ell_lo[j] = j < d->n_bands ? d->band_ell_lo[j] : 1e300;
@@ -551,13 +552,15 @@ extern "C" swiftcl_status swiftcl_plan(const swiftcl_plan_desc* d, void* stream,
   ALLOC(flags, int, 1);
   {
     // (point, chunk) slots of the backward partials: the most any batch size and chunk
-    // multiplier ask for
+    // multiplier ask for (the packed adjoint, bwd_chunk_mul <= 4, writes two per chunk)
     long slots = 0;
-    plan_dev probe = p->d;
+    plan_dev probe = p->d, probe4 = p->d;
     probe.bwd_chunk_mul = 8;
+    probe4.bwd_chunk_mul = 4;
     long grid = 0;
     for (int bb = 1; bb <= B; ++bb) {
       slots = std::max(slots, (long)bb * backward_chunks(probe, bb));
+      slots = std::max(slots, (long)bb * 2 * backward_chunks(probe4, bb));
       grid = std::max(grid, (long)((bb + SWIFTCL_NXCD - 1) / SWIFTCL_NXCD) * SWIFTCL_NXCD * backward_chunks(probe, bb));
     }
     p->d.bwd_slots = (int)slots;
@@ -1026,7 +1029,7 @@ static std::string tune_key(const swiftcl_plan_s* p, int batch) {
   return buf;
 }
 
-static bool cache_lookup(const char* path, const std::string& key, int* fwd_mode, int* chunk_mul) {
+static bool cache_lookup(const char* path, const std::string& key, int* fwd_mode, int* chunk_mul, int* pack) {
   if (!path) return false;
   FILE* f = fopen(path, "r");
   if (!f) return false;
@@ -1037,11 +1040,14 @@ static bool cache_lookup(const char* path, const std::string& key, int* fwd_mode
     if (!strstr(line, needle.c_str())) continue;
     const char* a = strstr(line, "\"fwd_mode\": ");
     const char* b = strstr(line, "\"bwd_chunk_mul\": ");
+    const char* c = strstr(line, "\"bwd_pack\": ");
     if (a && b) {
       *fwd_mode = atoi(a + 12);
       *chunk_mul = atoi(b + 17);
+      *pack = c ? atoi(c + 12) : 0;
       found = (*fwd_mode >= 0 && *fwd_mode <= 2) &&
-              (*chunk_mul == 1 || *chunk_mul == 2 || *chunk_mul == 4 || *chunk_mul == 8);
+              (*chunk_mul == 1 || *chunk_mul == 2 || *chunk_mul == 4 || *chunk_mul == 8) &&
+              (*pack == 0 || (*pack == 1 && *chunk_mul <= 4));
     }
   }
   fclose(f);
@@ -1079,11 +1085,13 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
   hipStream_t s = (hipStream_t)stream;
   const std::string key = tune_key(p, in->batch);
   std::string rep;
-  int fm = 0, cm = 1;
-  if (cache_lookup(cache_path, key, &fm, &cm)) {
+  int fm = 0, cm = 1, pk = 0;
+  if (cache_lookup(cache_path, key, &fm, &cm, &pk)) {
     p->d.fwd_mode = fm;
     p->d.bwd_chunk_mul = cm;
-    rep = "cached " + key + ": fwd_mode=" + std::to_string(fm) + " bwd_chunk_mul=" + std::to_string(cm);
+    p->d.bwd_pack = pk;
+    rep = "cached " + key + ": fwd_mode=" + std::to_string(fm) + " bwd_chunk_mul=" + std::to_string(cm) +
+          " bwd_pack=" + std::to_string(pk);
   } else {
     p->fwd_valid = false;
     hipError_t e = launch_assemble(p->d, in, s);
@@ -1100,26 +1108,36 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
     for (int m = 1; m < 3; ++m)
       if (tf[m] < tf[fb]) fb = m;
     p->d.fwd_mode = tf[fb] < 0.98f * tf[0] ? fb : 0;
-    float tb[4] = {1e30f, 1e30f, 1e30f, 1e30f};
-    const int muls[4] = {1, 2, 4, 8};
+    // the adjoint: chunk multipliers 1, 2, 4, 8 unpacked, then 1, 2, 4 packed (FP32 plans)
+    float tb[7] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
+    const int muls[7] = {1, 2, 4, 8, 1, 2, 4};
+    const int packs[7] = {0, 0, 0, 0, 1, 1, 1};
     if (dC && p->d.fused && p->d.precision != SWIFTCL_SPLIT_BF16) {
-      for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+      const int nv = p->d.precision == SWIFTCL_FP32 ? 7 : 4;
+      for (int i = 0; i < nv && e == hipSuccess; ++i) {
         p->d.bwd_chunk_mul = muls[i];
+        p->d.bwd_pack = packs[i];
         tb[i] = time_ms(s, [&]() { return launch_backward(p->d, in, dC, nullptr, nullptr, nullptr, nullptr, s); }, &e);
       }
-      if (e != hipSuccess) { p->d.bwd_chunk_mul = 1; return hip_check(e, "autotune backward"); }
+      if (e != hipSuccess) {
+        p->d.bwd_chunk_mul = 1;
+        p->d.bwd_pack = 0;
+        return hip_check(e, "autotune backward");
+      }
       int bi = 0;
-      for (int i = 1; i < 4; ++i)
+      for (int i = 1; i < nv; ++i)
         if (tb[i] < tb[bi]) bi = i;
       if (tb[bi] >= 0.98f * tb[0]) bi = 0;
       p->d.bwd_chunk_mul = muls[bi];
+      p->d.bwd_pack = packs[bi];
     }
-    char buf[512];
+    auto tv = [&](int i) { return dC && tb[i] < 1e29f ? tb[i] : 0.f; };
+    char buf[640];
     snprintf(buf, sizeof(buf),
-             "{\"key\": \"%s\", \"fwd_mode\": %d, \"bwd_chunk_mul\": %d, \"fwd_ms\": [%.4f, %.4f, %.4f], "
-             "\"bwd_ms\": [%.4f, %.4f, %.4f, %.4f]}",
-             key.c_str(), p->d.fwd_mode, p->d.bwd_chunk_mul, tf[0], tf[1], tf[2], dC ? tb[0] : 0.f, dC ? tb[1] : 0.f,
-             dC ? tb[2] : 0.f, dC ? tb[3] : 0.f);
+             "{\"key\": \"%s\", \"fwd_mode\": %d, \"bwd_chunk_mul\": %d, \"bwd_pack\": %d, "
+             "\"fwd_ms\": [%.4f, %.4f, %.4f], \"bwd_ms\": [%.4f, %.4f, %.4f, %.4f], \"bwd_pack_ms\": [%.4f, %.4f, %.4f]}",
+             key.c_str(), p->d.fwd_mode, p->d.bwd_chunk_mul, p->d.bwd_pack, tf[0], tf[1], tf[2], tv(0), tv(1), tv(2),
+             tv(3), tv(4), tv(5), tv(6));
     rep = buf;
     if (cache_path) {
       FILE* f = fopen(cache_path, "a");
@@ -1136,19 +1154,21 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
   return SWIFTCL_OK;
 }
 
-extern "C" swiftcl_status swiftcl_set_launch(swiftcl_plan_t p, int32_t fwd_mode, int32_t bwd_chunk_mul) {
+extern "C" swiftcl_status swiftcl_set_launch(swiftcl_plan_t p, int32_t fwd_mode, int32_t bwd_chunk_mul,
+                                             int32_t bwd_pack) {
   if (!p) { set_error("plan is NULL"); return SWIFTCL_E_INVALID; }
-  if (fwd_mode >= 0) {
-    if (fwd_mode > 2) { set_error("fwd_mode must be 0, 1 or 2"); return SWIFTCL_E_INVALID; }
-    p->d.fwd_mode = fwd_mode;
+  if (fwd_mode > 2) { set_error("fwd_mode must be 0, 1 or 2"); return SWIFTCL_E_INVALID; }
+  if (bwd_chunk_mul >= 0 && bwd_chunk_mul != 1 && bwd_chunk_mul != 2 && bwd_chunk_mul != 4 && bwd_chunk_mul != 8) {
+    set_error("bwd_chunk_mul must be 1, 2, 4 or 8");
+    return SWIFTCL_E_INVALID;
   }
-  if (bwd_chunk_mul >= 0) {
-    if (bwd_chunk_mul != 1 && bwd_chunk_mul != 2 && bwd_chunk_mul != 4 && bwd_chunk_mul != 8) {
-      set_error("bwd_chunk_mul must be 1, 2, 4 or 8");
-      return SWIFTCL_E_INVALID;
-    }
-    p->d.bwd_chunk_mul = bwd_chunk_mul;
-  }
+  if (bwd_pack > 1) { set_error("bwd_pack must be 0 or 1"); return SWIFTCL_E_INVALID; }
+  const int cm = bwd_chunk_mul >= 0 ? bwd_chunk_mul : p->d.bwd_chunk_mul;
+  const int pk = bwd_pack >= 0 ? bwd_pack : p->d.bwd_pack;
+  if (pk && cm > 4) { set_error("the packed adjoint takes bwd_chunk_mul 1, 2 or 4"); return SWIFTCL_E_INVALID; }
+  if (fwd_mode >= 0) p->d.fwd_mode = fwd_mode;
+  p->d.bwd_chunk_mul = cm;
+  p->d.bwd_pack = pk;
   return SWIFTCL_OK;
 }
 
@@ -1160,9 +1180,11 @@ extern "C" swiftcl_status swiftcl_plan_info(swiftcl_plan_t p, int32_t* fused, in
   return SWIFTCL_OK;
 }
 
-extern "C" swiftcl_status swiftcl_get_launch(swiftcl_plan_t p, int32_t* fwd_mode, int32_t* bwd_chunk_mul) {
-  if (!p || !fwd_mode || !bwd_chunk_mul) { set_error("NULL argument"); return SWIFTCL_E_INVALID; }
+extern "C" swiftcl_status swiftcl_get_launch(swiftcl_plan_t p, int32_t* fwd_mode, int32_t* bwd_chunk_mul,
+                                             int32_t* bwd_pack) {
+  if (!p || !fwd_mode || !bwd_chunk_mul || !bwd_pack) { set_error("NULL argument"); return SWIFTCL_E_INVALID; }
   *fwd_mode = p->d.fwd_mode;
   *bwd_chunk_mul = p->d.bwd_chunk_mul;
+  *bwd_pack = p->d.bwd_pack;
   return SWIFTCL_OK;
 }

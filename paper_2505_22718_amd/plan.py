@@ -361,10 +361,11 @@ class Plan:
         return bd.swiftcl_autotune(self.handle, s, C.data_ptr(), dC.data_ptr() if dC is not None else 0,
                                    self._stream(), cache_path)
 
-    def set_launch(self, fwd_mode=None, bwd_chunk_mul=None):
+    def set_launch(self, fwd_mode=None, bwd_chunk_mul=None, bwd_pack=None):
         """Force a launch configuration (what swiftcl_autotune would choose)."""
         bd.swiftcl_set_launch(self.handle, -1 if fwd_mode is None else fwd_mode,
-                              -1 if bwd_chunk_mul is None else bwd_chunk_mul)
+                              -1 if bwd_chunk_mul is None else bwd_chunk_mul,
+                              -1 if bwd_pack is None else int(bwd_pack))
 
     def launch_config(self):
         return bd.swiftcl_get_launch(self.handle)

@@ -6,7 +6,8 @@
   include points with no multipoles, one tracer, and pairs that fill all 16 rows (a point
   without tracers is an input error, flagged; the host test of the list builder covers it).
 * The autotuner picks a configuration, reports it, and reads it back from its cache; the adjoint's
-  multipole chunkings agree.
+  multipole chunkings agree, and so does the packed adjoint (two half-chunks side by side for
+  points of at most 8 tracers).
 * forward + backward captured in a hipGraph (torch.cuda.CUDAGraph) and replayed several times,
   with eager work between the replays: every replay reproduces the eager forward bit for bit and
   the eager gradients to roundoff (the geometry adjoint sums with FP64 atomics).
@@ -112,6 +113,55 @@ def test_adjoint_chunkings_agree(dev):
             assert e < 1e-4
     with pytest.raises(SwiftclError) as ei:
         plan.set_launch(bwd_chunk_mul=3)
+    assert ei.value.status == SWIFTCL_E_INVALID
+
+
+def test_packed_adjoint_agrees(dev):
+    """The packed adjoint (each multipole chunk split into two halves with partial rows of their
+    own, run side by side by the two halves of the workgroup for points of at most 8 tracers, one
+    after the other otherwise) changes only the order of the FP32 partial sums: on a ragged batch
+    with points of 1, 2, 7, 8 and 9 tracers and of 0, 1 and 2 multipoles, its gradients agree with
+    the unpacked adjoint's to the FP32 bar at chunk multipliers 1, 2 and 4.  Packing with chunk
+    multiplier 8 is refused."""
+    from paper_2505_22718_amd.binding import SwiftclError, SWIFTCL_E_INVALID
+    from paper_2505_22718_amd.plan import Plan, device_inputs
+    B = 24
+    wl = synth.make_workload("cfg3", batch=B)
+    plan = Plan.for_workload(wl)
+    t = device_inputs(wl, dev)
+    nt, nl = t["n_tracers"], t["n_ell"]
+    # lower the tracer count of points that have at least 10 (a slot past a point's own tracers
+    # holds no n(z)); the others keep 6, 10 or 15
+    big = [i for i in range(B) if int(nt[i]) >= 10]
+    for i, want in zip(big, [1, 2, 7, 8, 9, 8, 7, 9]):
+        nt[i] = want
+    nl[big[0]] = 0
+    nl[big[1]] = 1
+    nl[big[2]] = 2
+    _say(f"packed adjoint, cfg3 B={B}: T={nt.tolist()}, L={nl.tolist()}")
+    dC = torch.as_tensor(np.random.default_rng(23).standard_normal((B, plan.max_ell, plan.n_pairs)),
+                         dtype=torch.float32, device=dev)
+    plan.set_launch(bwd_chunk_mul=1, bwd_pack=0)
+    ref = {k: v.cpu().numpy() for k, v in plan.backward(t, dC).items()}
+    assert plan.device_flags() == 0
+    for m in (1, 2, 4):
+        plan.set_launch(bwd_chunk_mul=m, bwd_pack=1)
+        assert plan.launch_config()["bwd_pack"] == 1
+        g = {k: v.cpu().numpy() for k, v in plan.backward(t, dC).items()}
+        assert plan.device_flags() == 0
+        for k in g:
+            assert np.all(np.isfinite(g[k]))
+            e = float(np.max(np.abs(g[k] - ref[k])) / np.max(np.abs(ref[k])))
+            _say(f"  packed, bwd_chunk_mul {m}: {k} differs from the unpacked adjoint by {e:.2e}")
+            assert e < 1e-4
+    with pytest.raises(SwiftclError) as ei:
+        plan.set_launch(bwd_chunk_mul=8)
+    assert ei.value.status == SWIFTCL_E_INVALID
+    assert plan.launch_config()["bwd_chunk_mul"] == 4
+    plan.set_launch(bwd_pack=0)
+    plan.set_launch(bwd_chunk_mul=8)
+    with pytest.raises(SwiftclError) as ei:
+        plan.set_launch(bwd_pack=1)
     assert ei.value.status == SWIFTCL_E_INVALID
 
 
