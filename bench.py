@@ -113,7 +113,8 @@ def traffic_bytes(batch, launch):
     (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain copy of known
     size), or None if there is none, if the kernel's sources changed since it was taken, or if the
     launch being timed is not the one it was taken on: the batch and the launch shape (the number
-    of multipole chunks per point, set by bwd_chunk_mul, sets how many partial rows are written)."""
+    of multipole chunks per point, set by bwd_chunk_mul, and the packed adjoint's two halves per
+    chunk, bwd_pack, set how many partial rows are written)."""
     if not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = None
@@ -124,6 +125,8 @@ def traffic_bytes(batch, launch):
     if not rec or rec.get("sources_sha256") != sources_digest():
         return None
     if rec.get("batch") != batch or rec.get("launch", {}).get("bwd_chunk_mul") != launch["bwd_chunk_mul"]:
+        return None
+    if rec.get("launch", {}).get("bwd_pack", 0) != launch.get("bwd_pack", 0):
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -205,15 +208,15 @@ def profile_split_pass(B):
 
 def profile_ragged_pass(B, steps=2):
     """Forward + backward steps of the ragged batch (B points of 6, 10 or 15 tracers and 50..103
-    multipoles) in launch shapes the autotuner picks for it in the bench (per-slot forward, two
-    times the base multipole chunks of the adjoint); run under rocprofv3."""
+    multipoles) in launch shapes the autotuner picks for it in the bench (per-slot forward, the
+    packed adjoint at two times the base multipole chunks); run under rocprofv3."""
     import numpy as np
     import torch
     import synth
     from paper_2505_22718_amd.plan import Plan, device_inputs
     wl = synth.make_workload("cfg3", batch=B)
     plan = Plan.for_workload(wl)
-    plan.set_launch(fwd_mode=0, bwd_chunk_mul=2)
+    plan.set_launch(fwd_mode=0, bwd_chunk_mul=2, bwd_pack=1)
     inp = device_inputs(wl, "cuda:0")
     C = torch.empty((B, plan.max_ell, plan.n_pairs), dtype=torch.float32, device="cuda:0")
     dC = torch.as_tensor(np.random.default_rng(0).standard_normal(tuple(C.shape)), dtype=torch.float32, device="cuda:0")

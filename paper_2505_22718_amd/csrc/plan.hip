@@ -1097,11 +1097,22 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
     hipError_t e = launch_assemble(p->d, in, s);
     if (e == hipSuccess) e = launch_forward_fft(p->d, in, s);
     if (e == hipSuccess) note_forward(p, in);
-    float tf[3] = {1e30f, 1e30f, 1e30f};
-    for (int m = 0; m < (p->d.fused ? 3 : 1) && e == hipSuccess; ++m) {
-      p->d.fwd_mode = m;
-      tf[m] = time_ms(s, [&]() { return launch_windows_cl(p->d, in, nullptr, C, s); }, &e);
+    const bool tune_bwd = dC && p->d.fused && p->d.precision != SWIFTCL_SPLIT_BF16;
+    // warm-up in the default shapes: the clock ramps up over the first milliseconds of work, which
+    // would favour the variants timed last; then two rounds over the variants, keeping each one's best
+    p->d.fwd_mode = 0;
+    p->d.bwd_chunk_mul = 1;
+    p->d.bwd_pack = 0;
+    for (int r = 0; r < 10 && e == hipSuccess; ++r) {
+      e = launch_windows_cl(p->d, in, nullptr, C, s);
+      if (e == hipSuccess && tune_bwd) e = launch_backward(p->d, in, dC, nullptr, nullptr, nullptr, nullptr, s);
     }
+    float tf[3] = {1e30f, 1e30f, 1e30f};
+    for (int round = 0; round < 2; ++round)
+      for (int m = 0; m < (p->d.fused ? 3 : 1) && e == hipSuccess; ++m) {
+        p->d.fwd_mode = m;
+        tf[m] = std::min(tf[m], time_ms(s, [&]() { return launch_windows_cl(p->d, in, nullptr, C, s); }, &e));
+      }
     if (e != hipSuccess) { p->d.fwd_mode = 0; return hip_check(e, "autotune forward"); }
     // a variant other than the default must win by 2% (run-to-run noise is ~1%)
     int fb = 0;
@@ -1112,13 +1123,16 @@ extern "C" swiftcl_status swiftcl_autotune(swiftcl_plan_t p, const swiftcl_input
     float tb[7] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
     const int muls[7] = {1, 2, 4, 8, 1, 2, 4};
     const int packs[7] = {0, 0, 0, 0, 1, 1, 1};
-    if (dC && p->d.fused && p->d.precision != SWIFTCL_SPLIT_BF16) {
+    if (tune_bwd) {
       const int nv = p->d.precision == SWIFTCL_FP32 ? 7 : 4;
-      for (int i = 0; i < nv && e == hipSuccess; ++i) {
-        p->d.bwd_chunk_mul = muls[i];
-        p->d.bwd_pack = packs[i];
-        tb[i] = time_ms(s, [&]() { return launch_backward(p->d, in, dC, nullptr, nullptr, nullptr, nullptr, s); }, &e);
-      }
+      for (int round = 0; round < 2; ++round)
+        for (int i = 0; i < nv && e == hipSuccess; ++i) {
+          p->d.bwd_chunk_mul = muls[i];
+          p->d.bwd_pack = packs[i];
+          tb[i] = std::min(tb[i], time_ms(s, [&]() {
+            return launch_backward(p->d, in, dC, nullptr, nullptr, nullptr, nullptr, s);
+          }, &e));
+        }
       if (e != hipSuccess) {
         p->d.bwd_chunk_mul = 1;
         p->d.bwd_pack = 0;

@@ -47,12 +47,15 @@ def test_traffic_record_is_dropped_when_the_sources_change(monkeypatch):
 
 
 def test_traffic_record_is_dropped_for_another_launch(monkeypatch):
-    """Another batch or chunk multiplier writes another number of partial rows."""
+    """Another batch, chunk multiplier or packing writes another number of partial rows."""
     rec = _record()
     monkeypatch.setattr(bench, "sources_digest", lambda: rec["sources_sha256"])
     assert bench.traffic_bytes(rec["batch"] // 16, rec["launch"]) is None
     other = 2 if rec["launch"]["bwd_chunk_mul"] != 2 else 4
     assert bench.traffic_bytes(rec["batch"], dict(rec["launch"], bwd_chunk_mul=other)) is None
+    pack = rec["launch"].get("bwd_pack", 0)
+    assert bench.traffic_bytes(rec["batch"], dict(rec["launch"], bwd_pack=1 - pack)) is None
+    assert bench.traffic_bytes(rec["batch"], dict(rec["launch"], bwd_pack=pack)) is not None
 
 
 def test_forward_traffic_record(monkeypatch):
