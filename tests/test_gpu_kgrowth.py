@@ -64,6 +64,22 @@ def test_kgrowth_cfg0_fp32(dev):
     assert e.max() < 1e-4
 
 
+@pytest.mark.parametrize("n_nodes", [2, 3, 17, 18, 19, 34])
+def test_kgrowth_node_count_edges(dev, n_nodes):
+    """Node counts at the edges of the node spline's 16-node segments (no interior node, one, a
+    segment filled exactly, one node past it, two segments and a remainder): parity with the
+    oracle's natural spline at the FP32 bar."""
+    wl = synth.make_workload("cfg0")
+    synth.scale_dependent_growth(wl, n_nodes, f_nu=0.3)
+    _say(f"kgrowth cfg0 fp32, {n_nodes} nodes")
+    p, C = _run(wl, dev)
+    assert p.device_flags() == 0
+    slots = np.arange(wl["n_ell"][0])
+    e = _eps(C[0], _oracle(wl, 0, slots), slots, 2)
+    _say(f"  max eps {e.max():.3e}")
+    assert e.max() < 1e-4
+
+
 def test_kgrowth_dense_nodes(dev):
     """200 nodes over 256 k nodes: a 64-node k tile spans more node rows than the windows GEMM
     stages in LDS, so the plan runs the GEMM that gathers them per lane."""
