@@ -269,7 +269,8 @@ swiftcl_status swiftcl_cl_backward_timed(swiftcl_plan_t plan, const swiftcl_inpu
  * P(k, z_fid) D(k, z(chi)) D(k, z(chi')), FFTLog coefficients c_n(k) of f(chi) D(k, chi)).  The
  * coefficients are computed at the plan's n_interp nodes kappa_a = k_0 (k_max / k_0)^{a / (n_interp-1)}
  * (uniform in ln k, both ends included) and continued to every k node by the natural cubic spline in
- * ln k through the node values; the window at k_j uses c_n(k_j), so the inverse transform becomes a
+ * ln k through the node values (its second derivatives within 2e-10 of the exact solve, relative to
+ * the moments 17 nodes on, in FP32 arithmetic); the window at k_j uses c_n(k_j), so the inverse transform becomes a
  * dense sum over n per k (run as a GEMM on MFMA).  Growth at a node is continued in z by the natural
  * cubic spline, like D(z).
  *   D_kz  device, double, [B][n_interp][n_zg]: D(kappa_a, z_geom) of every point; it replaces
