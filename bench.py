@@ -484,7 +484,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; a multi-GPU run is not part of it "
+        print("bench.py: the benchmark runs on one GPU only; a multi-GPU run is not supported "
               "(points would shard across GPUs with no exchange).", file=sys.stderr)
         sys.exit(2)
 

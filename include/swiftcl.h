@@ -44,7 +44,7 @@ typedef enum {
   SWIFTCL_E_DOMAIN = -2,      /* a value outside the method's domain (b range, k spacing) */
   SWIFTCL_E_NOMEM = -3,       /* device or host allocation failed (swiftcl_plan only) */
   SWIFTCL_E_DEVICE = -4,      /* a HIP runtime error */
-  SWIFTCL_E_UNSUPPORTED = -5  /* a size this build does not handle (e.g. n_chi) */
+  SWIFTCL_E_UNSUPPORTED = -5  /* a size the library does not handle (e.g. n_chi) */
 } swiftcl_status;
 
 /* Tracer kinds.  The CMB-lensing kernel ends at chi_* = chi(z_geom[n_zg-1]): the top of the geometry
