@@ -39,38 +39,54 @@ __global__ __launch_bounds__(64) void k_limber_pk(plan_dev P, swiftcl_inputs in)
   }
 }
 
-// One block per (point, multipole slot).  Per chunk of chi nodes: the weights
-// s_m = Delta P(nu / chi_m) / (chi_m w_m) and H_t(m) = w_m f_t(chi_m) [chi_m^2 for the lensing kinds]
-// in LDS (w_m f_t is the band-0 kernel sample without its tilt; the CMB-lensing sample of the last
-// node, which carries the linear-end weight, is brought to w_m), then every thread sums its tracer
-// pairs; the factor c(l) / nu^2 (F(l) or l(l+1)) per lensing-kind tracer of the pair is applied at
-// the end.
+// One block per (point, group of LB_LG multipole slots).  Per chunk of chi nodes: H_t(m) =
+// w_m f_t(chi_m) [chi_m^2 for the lensing kinds] in LDS, once for the whole group (it does not
+// depend on the multipole; w_m f_t is the band-0 kernel sample without its tilt; the CMB-lensing
+// sample of the last node, which carries the linear-end weight, is brought to w_m), and the
+// weights s_l(m) = Delta P(nu_l / chi_m) / (chi_m w_m) of every slot of the group, stored node by
+// node so that a lane reads the group's weights of one node in one go; then every thread sums its
+// tracer pairs for all slots of the group.  The factor c(l) / nu^2 (F(l) or l(l+1)) per
+// lensing-kind tracer of the pair is applied at the end.
+constexpr int LB_LG = 8;  // multipole slots per block
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R* __restrict__ Cout) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int T = P.max_tracers, Lm = P.max_ell, N = P.N, nb = P.n_bands, nk = P.n_k;
-  R* H = (R*)smem;             // [T][LB_CH]
-  R* s = H + (size_t)T * LB_CH;  // [LB_CH]
-  int* kinds = (int*)(s + LB_CH);  // [T] tracer kinds
-  const int b = blockIdx.x / Lm, li = blockIdx.x % Lm;
+  R* H = (R*)smem;                              // [T][LB_CH]
+  R* s = H + (size_t)T * LB_CH;                 // [LB_CH][LB_LG]
+  double* lnus = (double*)(s + LB_CH * LB_LG);  // [LB_LG] ln(l + 1/2) of the group's slots
+  int* kinds = (int*)(lnus + LB_LG);            // [T] tracer kinds
+  int* eis = kinds + T;                         // [LB_LG] multipole of each slot
+  const int ngrp = (Lm + LB_LG - 1) / LB_LG;
+  const int b = blockIdx.x / ngrp, l0 = (blockIdx.x % ngrp) * LB_LG;
   if (b >= in.batch) return;
   const int npair = T * (T + 1) / 2;
-  R* c = Cout + ((size_t)b * Lm + li) * npair;
   const int Tb = clamp_l(in.n_tracers[b], 0, T);
   const int Lb = clamp_l(in.n_ell[b], 0, Lm);
-  if (li >= Lb) {
-    for (int p = threadIdx.x; p < npair; p += blockDim.x) c[p] = (R)0;
-    return;
+  // slots of the group past the point's multipoles: zeros
+  for (int e = threadIdx.x; e < LB_LG * npair; e += blockDim.x) {
+    const int l = l0 + e / npair;
+    if (l < Lm && l >= Lb) Cout[((size_t)b * Lm + l) * npair + e % npair] = (R)0;
   }
-  int ei = in.ell_idx[(size_t)b * Lm + li];
-  if (ei < 0 || ei >= P.n_ell) {
-    if (threadIdx.x == 0) atomicOr(P.flags, FLAG_BAD_INDEX);
-    ei = 0;
+  const int nl = Lb - l0 < LB_LG ? Lb - l0 : LB_LG;  // slots of the group this point has
+  if (nl <= 0) return;
+  if (threadIdx.x < LB_LG) {
+    int ei = 0;
+    if ((int)threadIdx.x < nl) {
+      ei = in.ell_idx[(size_t)b * Lm + l0 + threadIdx.x];
+      if (ei < 0 || ei >= P.n_ell) {
+        atomicOr(P.flags, FLAG_BAD_INDEX);
+        ei = 0;
+      }
+    }
+    eis[threadIdx.x] = ei;
+    lnus[threadIdx.x] = log(P.ell_v[ei] + 0.5);
   }
   for (int t = threadIdx.x; t < T; t += blockDim.x) kinds[t] = t < Tb ? tracer_kind(in, T, b, t) : 0;
+  // weights of the slots the point does not have stay zero
+  for (int e = threadIdx.x; e < LB_CH * LB_LG; e += blockDim.x) s[e] = (R)0;
   __syncthreads();
-  const double nu = P.ell_v[ei] + 0.5;
-  const double lnu = log(nu);
   const double* pt = P.pt + (size_t)b * PT_STRIDE;
   const double chi0 = pt[PT_CHI0], lchi0 = log(chi0), theta = pt[PT_THETA];
   const int m0 = P.m0, m1 = (int)pt[PT_M1];
@@ -80,7 +96,7 @@ __global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R
   // this thread's tracer pairs (row-major upper triangle)
   constexpr int MAXP = (32 * 33 / 2 + 255) / 256;
   int pi[MAXP], pj[MAXP];
-  R acc[MAXP];
+  R acc[MAXP][LB_LG];
 #pragma unroll
   for (int q = 0; q < MAXP; ++q) {
     const int p = threadIdx.x + 256 * q;
@@ -88,24 +104,26 @@ __global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R
     while (i < T && rem >= T - i) { rem -= T - i; ++i; }
     pi[q] = p < npair ? i : 0;
     pj[q] = p < npair ? i + rem : 0;
-    acc[q] = (R)0;
+#pragma unroll
+    for (int l = 0; l < LB_LG; ++l) acc[q][l] = (R)0;
   }
   for (int mc = m0; mc <= m1; mc += LB_CH) {
     __syncthreads();  // the previous chunk's readers are done
-    for (int idx = threadIdx.x; idx < LB_CH; idx += blockDim.x) {
+    for (int e = threadIdx.x; e < nl * LB_CH; e += blockDim.x) {
+      const int l = e / LB_CH, idx = e % LB_CH;
       const int m = mc + idx;
       double sv = 0.0;
       if (m <= m1) {
         const double lchi = lchi0 + (double)m * P.delta;
         const double w = m == m0 ? 0.5 : (m == m1 ? 0.5 + theta : 1.0);
-        const double x = lnu - lchi;  // ln k of the Limber node
+        const double x = lnus[l] - lchi;  // ln k of the Limber node
         if (x >= lnk[0] && x <= lnk[nk - 1]) {
           const int iv = clamp_l((int)floor((x - lnk[0]) / P.delta), 0, nk - 2);
           const double lv = spline_at(lnk, lkih, lnp, lnp + nk, iv, x, nullptr);
           sv = P.delta * exp(lv - lchi) / w;
         }
       }
-      s[idx] = (R)sv;
+      s[idx * LB_LG + l] = (R)sv;
     }
     for (int e = threadIdx.x; e < T * LB_CH; e += blockDim.x) {
       const int t = e / LB_CH, idx = e % LB_CH;
@@ -130,25 +148,40 @@ __global__ __launch_bounds__(256) void k_limber(plan_dev P, swiftcl_inputs in, R
       if (threadIdx.x + 256 * q >= npair) continue;
       const R* hi = H + (size_t)pi[q] * LB_CH;
       const R* hj = H + (size_t)pj[q] * LB_CH;
-      R a = acc[q];
-      for (int idx = 0; idx < cnt; ++idx) a += hi[idx] * hj[idx] * s[idx];
-      acc[q] = a;
+      R a[LB_LG];
+#pragma unroll
+      for (int l = 0; l < LB_LG; ++l) a[l] = acc[q][l];
+      for (int idx = 0; idx < cnt; ++idx) {
+        const R h = hi[idx] * hj[idx];
+        const R* sw = s + idx * LB_LG;
+#pragma unroll
+        for (int l = 0; l < LB_LG; ++l) a[l] += h * sw[l];
+      }
+#pragma unroll
+      for (int l = 0; l < LB_LG; ++l) acc[q][l] = a[l];
     }
   }
-  const double inu2 = 1.0 / (nu * nu);
 #pragma unroll
-  for (int q = 0; q < MAXP; ++q) {
-    const int p = threadIdx.x + 256 * q;
-    if (p >= npair) continue;
-    const int i = pi[q], j = pj[q];
-    R v = (R)0;
-    if (i < Tb && j < Tb) {
-      double f = (double)acc[q];
-      if (kinds[i]) f *= P.fell[(size_t)kinds[i] * P.n_ell + ei] * inu2;
-      if (kinds[j]) f *= P.fell[(size_t)kinds[j] * P.n_ell + ei] * inu2;
-      v = (R)f;
+  for (int l = 0; l < LB_LG; ++l) {
+    if (l >= nl) break;
+    const int ei = eis[l];
+    const double nu = P.ell_v[ei] + 0.5;
+    const double inu2 = 1.0 / (nu * nu);
+    R* c = Cout + ((size_t)b * Lm + l0 + l) * npair;
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+      const int p = threadIdx.x + 256 * q;
+      if (p >= npair) continue;
+      const int i = pi[q], j = pj[q];
+      R v = (R)0;
+      if (i < Tb && j < Tb) {
+        double f = (double)acc[q][l];
+        if (kinds[i]) f *= P.fell[(size_t)kinds[i] * P.n_ell + ei] * inu2;
+        if (kinds[j]) f *= P.fell[(size_t)kinds[j] * P.n_ell + ei] * inu2;
+        v = (R)f;
+      }
+      c[p] = v;
     }
-    c[p] = v;
   }
 }
 
@@ -340,14 +373,15 @@ size_t limber_bwd_lds_bytes(const plan_dev& p) {
 
 size_t limber_lds_bytes(const plan_dev& p) {
   const size_t rs = p.precision == SWIFTCL_FP64 ? 8 : 4;
-  return rs * ((size_t)p.max_tracers * LB_CH + LB_CH) + sizeof(int) * (size_t)p.max_tracers;
+  return rs * ((size_t)p.max_tracers * LB_CH + (size_t)LB_CH * LB_LG) + sizeof(double) * LB_LG +
+         sizeof(int) * ((size_t)p.max_tracers + LB_LG);
 }
 
 hipError_t launch_limber(const plan_dev& p, const swiftcl_inputs* in, void* C, hipStream_t s) {
   hipLaunchKernelGGL(k_limber_pk, dim3(in->batch), dim3(64), sizeof(double) * 2 * (size_t)p.n_k, s, p, *in);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)((size_t)in->batch * p.max_ell));
+  const dim3 grid((unsigned)((size_t)in->batch * ((p.max_ell + LB_LG - 1) / LB_LG)));
   if (p.precision == SWIFTCL_FP64)
     hipLaunchKernelGGL(k_limber<double>, grid, dim3(256), limber_lds_bytes(p), s, p, *in, (double*)C);
   else
